@@ -1,0 +1,78 @@
+"""Seeded synthetic FP64x2 operands.
+
+This module only draws random numbers and lays them out; it holds none of the
+cascade's arithmetic, so both the HIP path's tests and the CPU oracle can take
+their inputs from here.
+
+Workload recipe (Sec. 5.2, "uniformly random data" and "wide-range data"):
+
+* ``uniform``: ``hi ~ U[-1, 1)`` and ``lo = (hi * 2**-53) * U[-1, 1)``, so the
+  pair carries about 106 significant bits and ``|lo| < ulp(hi)``.
+* ``ill``: as ``uniform``, but every row of A and every column of B is first
+  multiplied by ``2**e`` with ``e`` a uniform integer in ``[-30, 30]``; C is
+  multiplied by ``2**(e_i + f_j)`` so that it lives on the same scale as the
+  product.
+
+All arrays are float64 in Fortran (column-major) order, matching the BLAS
+layout of the C ABI.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEED_ROOT = 230304353
+VARIANTS = {"uniform": 0, "ill": 1}
+
+
+def _rng(cfg: int, variant: str, m: int, n: int, k: int, salt: int = 0):
+    return np.random.default_rng(
+        np.random.SeedSequence([SEED_ROOT, int(cfg), VARIANTS[variant],
+                                int(m), int(n), int(k), int(salt)]))
+
+
+def _pair(rng, shape):
+    hi = np.asfortranarray(rng.uniform(-1.0, 1.0, size=shape))
+    u = np.asfortranarray(rng.uniform(-1.0, 1.0, size=shape))
+    lo = np.asfortranarray((hi * 2.0 ** -53) * u)
+    return hi, lo
+
+
+def make_problem(m: int, n: int, k: int, *, cfg: int = 0, variant: str = "uniform",
+                 salt: int = 0):
+    """Return ``dict(A=(hi, lo), B=(hi, lo), C=(hi, lo))`` with A m×k, B k×n, C m×n."""
+    rng = _rng(cfg, variant, m, n, k, salt)
+    Ahi = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(m, k)))
+    Au = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(m, k)))
+    Bhi = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(k, n)))
+    Bu = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(k, n)))
+    Chi = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(m, n)))
+    Cu = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(m, n)))
+    if variant == "ill":
+        eA = rng.integers(-30, 31, size=m)
+        fB = rng.integers(-30, 31, size=n)
+        Ahi *= np.ldexp(1.0, eA)[:, None]
+        Bhi *= np.ldexp(1.0, fB)[None, :]
+        Chi *= np.ldexp(1.0, eA[:, None] + fB[None, :])
+    Alo = np.asfortranarray((Ahi * 2.0 ** -53) * Au)
+    Blo = np.asfortranarray((Bhi * 2.0 ** -53) * Bu)
+    Clo = np.asfortranarray((Chi * 2.0 ** -53) * Cu)
+    return {"A": (Ahi, Alo), "B": (Bhi, Blo), "C": (Chi, Clo)}
+
+
+def make_pair(shape, *, seed: int):
+    """A single FP64x2 matrix of the ``uniform`` recipe (used by the autograd chain)."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 99, int(seed)] + list(shape)))
+    return _pair(rng, tuple(shape))
+
+
+def batched_shapes(count: int = 512, lo: int = 32, hi: int = 1024, *, seed: int = 3):
+    """Shapes of the uneven batch: m, n, k each ``round(exp(U[ln lo, ln hi]))``."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 3, int(seed), count]))
+    draw = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size=(count, 3)))).astype(np.int64)
+    return [tuple(int(v) for v in row) for row in draw]
+
+
+def sample_entries(m: int, n: int, count: int, *, seed: int = 7):
+    """Seeded (i, j) output positions for sampled checks at full size."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 5, int(seed), m, n, count]))
+    return rng.integers(0, m, size=count), rng.integers(0, n, size=count)

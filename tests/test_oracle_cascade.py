@@ -1,0 +1,274 @@
+"""Pins of the numpy cascade model (CPU only).
+
+Against: the split widths printed in Sec. 3.3; exact rounding to the digit
+grid (Appendix A) computed with rationals; exact reconstruction and the
+conversion bound (eq. error_scalar); exactness of bins 0-2 (Sec. 3.3-3.4)
+against integer arithmetic, including worst-case digits; the worked example of
+Sec. 3.6; integer matrices; the forward bound eq. (cascerr) against exact
+results; row/column power-of-two invariance; identity.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import cascade as cz
+from oracle.ref import dd_gemm_ref
+from paper_2303_04353_amd.inputs import make_problem
+from tests.exact import abs_gemm, dd_value, exact_gemm
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U2 = 2.0 ** -106
+
+
+def test_split_widths_printed_values():
+    # Sec. 3.3: k = 256 gives (22, 21, 21), 117 bits with c3 = 53; k = 64 allows c0 = 23
+    assert cz.split_widths(256) == (22, 21, 21)
+    assert sum(cz.split_widths(256)) + 53 == 117
+    assert cz.split_widths(64)[0] == 23
+
+
+@pytest.mark.parametrize("kc", [1, 2, 3, 17, 64, 100, 128, 256, 257, 512, 1024, 4096])
+def test_split_widths_are_the_largest_feasible(kc):
+    L = (kc - 1).bit_length()
+
+    def ok(c0, c1, c2):
+        return (2 * c0 + L <= 53 and c0 + c1 + L + 1 <= 53 and 2 * c1 + L + 2 <= 53
+                and c0 + c2 + L + 2 <= 53)
+    c0, c1, c2 = cz.split_widths(kc)
+    assert ok(c0, c1, c2)
+    assert not ok(c0 + 1, 0, 0) or not ok(c0 + 1, c1, 0)
+    assert not ok(c0, c1 + 1, c2)
+    assert not ok(c0, c1, c2 + 1)
+
+
+def _round_to_grid(x: Fraction, g: Fraction) -> Fraction:
+    return round(x / g) * g  # Fraction.__round__ rounds half to even
+
+
+def _scalar_values():
+    rng = np.random.default_rng(11)
+    v = list(rng.uniform(-1, 1, 400))
+    v += [0.0, 1.0 - 2.0 ** -53, -(1.0 - 2.0 ** -53), 0.5, -0.5, 2.0 ** -22, 2.0 ** -21,
+          3 * 2.0 ** -23, 2.0 ** -60, -2.0 ** -300, 0.75 + 2.0 ** -52]
+    v += list(rng.uniform(-1, 1, 100) * 2.0 ** rng.integers(-70, 0, 100))
+    return np.array(v)
+
+
+@pytest.mark.parametrize("kc", [64, 128, 256, 512])
+def test_split_digits_are_grid_roundings(kc):
+    c = cz.split_widths(kc)
+    x = _scalar_values()
+    d = cz.split_fp64(x, c)
+    for idx in range(x.size):
+        v = Fraction(float(x[idx]))
+        for t in range(3):
+            g = Fraction(2) ** (1 - c[t])
+            want = _round_to_grid(v, g)
+            assert Fraction(float(d[t][idx])) == want
+            assert abs(want) <= 1
+            v = (v - want) * Fraction(2) ** c[t]
+        assert Fraction(float(d[3][idx])) == v  # the last digit is the exact remainder
+
+
+@pytest.mark.parametrize("kc", [128, 256])
+def test_split_reconstructs_fp64_exactly(kc):
+    c = cz.split_widths(kc)
+    s = [Fraction(1)] + [Fraction(2) ** -sum(c[:t]) for t in range(1, 4)]
+    x = _scalar_values()
+    d = cz.split_fp64(x, c)
+    for idx in range(x.size):
+        tot = sum(s[t] * Fraction(float(d[t][idx])) for t in range(4))
+        assert tot == Fraction(float(x[idx]))
+
+
+@pytest.mark.parametrize("kc", [128, 256])
+def test_fp64x2_conversion_error_bound(kc):
+    # eq. (error_scalar): the only error is the rounding of the last digit,
+    # |delta| <= 2^-53 |d3| sigma_3 <= 2^-(D2+53) when |d3| <= 1
+    c = cz.split_widths(kc)
+    P = make_problem(6, 1, 50, cfg=80)
+    hi, lo = P["A"]
+    Ap, e = cz.cascade_A(hi, lo, c)
+    D2 = sum(c)
+    for i in range(hi.shape[0]):
+        for p in range(hi.shape[1]):
+            x = (Fraction(float(hi[i, p])) + Fraction(float(lo[i, p]))) * Fraction(2) ** -int(e[i])
+            tot = sum(Fraction(float(Ap[t][i, p])) for t in range(4))
+            d3 = abs(Fraction(float(Ap[3][i, p]))) * Fraction(2) ** D2
+            err = abs(x - tot)
+            assert err <= Fraction(2) ** (-53 - D2) * d3
+            assert err <= Fraction(2) ** (-52 - D2)
+    # matrix form (Sec. 3.4): |Sigma Delta A| <= 2 eps~ D_A J up to the same factor 2
+    ell = Fraction(2) ** -(D2 + 53)
+    for i in range(hi.shape[0]):
+        rowmax = max(abs(Fraction(float(h))) for h in hi[i])
+        for p in range(hi.shape[1]):
+            val = Fraction(float(hi[i, p])) + Fraction(float(lo[i, p]))
+            rec = sum(Fraction(float(Ap[t][i, p])) for t in range(4))
+            err = abs(val - rec * Fraction(2) ** int(e[i]))
+            assert err <= 4 * ell * rowmax
+
+
+def test_exponents_bracket_the_row_max():
+    P = make_problem(9, 7, 13, cfg=81, variant="ill")
+    e = cz.exponents(P["A"][0], axis=1)
+    f = cz.exponents(P["B"][0], axis=0)
+    for i in range(9):
+        mx = np.max(np.abs(P["A"][0][i]))
+        assert 2.0 ** (e[i] - 1) <= mx < 2.0 ** e[i]
+    for j in range(7):
+        mx = np.max(np.abs(P["B"][0][:, j]))
+        assert 2.0 ** (f[j] - 1) <= mx < 2.0 ** f[j]
+    z = np.zeros((3, 4))
+    assert np.all(cz.exponents(z, axis=1) == 0)
+
+
+@pytest.mark.parametrize("kc", [64, 128, 256, 512])
+@pytest.mark.parametrize("worst", [False, True])
+def test_bins_0_to_2_are_exact(kc, worst):
+    # Sec. 3.3-3.4: with the widths chosen from kc, bins 0, 1 and 2 are
+    # computed without error in FP64.  Checked against exact sums of the
+    # digit products, with random and with worst-case (all-maximal,
+    # same-sign) digits.
+    c = cz.split_widths(kc)
+    m = n = 3
+    if worst:
+        # scaled values just below 1 and with every later digit at its largest
+        hi = np.full((m, kc), 1.0 - 2.0 ** -53)
+        hi[:, ::2] = 0.5 + 0.5 * (1.0 - 2.0 ** -30)
+        lo = hi * 2.0 ** -54
+        Bh, Bl = np.asfortranarray(hi.T.copy()), np.asfortranarray(lo.T.copy())
+        A = (hi, lo)
+        B = (Bh, Bl)
+    else:
+        P = make_problem(m, n, kc, cfg=82)
+        A, B = P["A"], P["B"]
+    _, _, parts = cz.cascade_gemm(A, B, kc=kc, return_parts=True)
+    Ap, Bp = parts["A"], parts["B"]
+    bin0, bin1, bin2, _ = parts["bins"][0]
+    pairs = {0: [(0, 0)], 1: [(0, 1), (1, 0)], 2: [(0, 2), (1, 1), (2, 0)]}
+    for which, got in ((0, bin0), (1, bin1), (2, bin2)):
+        for i in range(m):
+            for j in range(n):
+                s = Fraction(0)
+                for (ta, tb) in pairs[which]:
+                    for p in range(kc):
+                        s += Fraction(float(Ap[ta][i, p])) * Fraction(float(Bp[tb][p, j]))
+                assert Fraction(float(got[i, j])) == s, (which, i, j)
+
+
+def _load_hex(mat):
+    return np.array([[float.fromhex(v) for v in row] for row in mat])
+
+
+def test_worked_example_sec3_6():
+    with open(os.path.join(GOLDEN, "worked_example_sec3_6.json")) as fh:
+        g = json.load(fh)
+    for case in g["cases"]:
+        A = (_load_hex(case["A"]["hi"]), _load_hex(case["A"]["lo"]))
+        B = (_load_hex(case["B"]["hi"]), _load_hex(case["B"]["lo"]))
+        hi, lo = cz.cascade_gemm(A, B, kc=256, c=case["c"])
+        assert hi[0, 0] == float.fromhex(case["cascade_result"]["hi"])
+        assert lo[0, 0] == float.fromhex(case["cascade_result"]["lo"])
+        rh, rl, _ = dd_gemm_ref(A, B)
+        assert rh[0, 0] == float.fromhex(case["fp64x2_result"]["hi"])
+        assert rl[0, 0] == float.fromhex(case["fp64x2_result"]["lo"])
+
+
+def test_integer_matrices_exact_over_several_blocks():
+    # integers of at most 21 bits land entirely in digit 0 (grid 2^(1-c0) after
+    # scaling by 2^-e with e <= 21), bins 1-6 vanish and bin 0 is exact
+    rng = np.random.default_rng(5)
+    m, n, k = 6, 5, 1000
+    A = rng.integers(-2 ** 20, 2 ** 20 + 1, size=(m, k)).astype(float)
+    B = rng.integers(-2 ** 20, 2 ** 20 + 1, size=(k, n)).astype(float)
+    hi, lo = cz.cascade_gemm((A, 0 * A), (B, 0 * B), kc=256)
+    want = A.astype(object) @ B.astype(object)
+    assert np.all(hi.astype(object) == want) and np.all(lo == 0)
+
+
+@pytest.mark.parametrize("m,n,k,variant", [(4, 3, 9, "uniform"), (5, 4, 40, "ill"), (3, 3, 70, "uniform")])
+def test_forward_bound_vs_exact(m, n, k, variant):
+    # eq. (cascerr) per entry, with the rank-kc blocks accumulated in FP64x2:
+    # |G - X| <= (1 + 2 nb) 2^-106 (|A||B|)_ij + 40 kc k eps~ ||a_i|| ||b_j|| (+ C rounding)
+    kc = 16
+    P = make_problem(m, n, k, cfg=83, variant=variant)
+    hi, lo = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc)
+    X = exact_gemm(P["A"], P["B"], P["C"])
+    S = abs_gemm(P["A"], P["B"])
+    Cabs = np.abs(dd_value(*P["C"]))
+    c = cz.split_widths(kc)
+    eps_t = Fraction(2) ** -(sum(c) + 53)
+    nb = -(-k // kc)
+    a = dd_value(*P["A"])
+    b = dd_value(*P["B"])
+    G = dd_value(hi, lo)
+    for i in range(m):
+        ai = max(abs(v) for v in a[i])
+        for j in range(n):
+            bj = max(abs(v) for v in b[:, j])
+            bound = ((1 + 2 * nb) * Fraction(U2) * S[i, j] + 40 * kc * k * eps_t * ai * bj
+                     + 4 * Fraction(U2) * (Cabs[i, j] + S[i, j]))
+            assert abs(G[i, j] - X[i, j]) <= bound
+
+
+def test_row_and_column_power_of_two_invariance_bitwise():
+    P = make_problem(12, 9, 300, cfg=84)
+    A, B, C = P["A"], P["B"], P["C"]
+    r = np.arange(12) % 7 - 3
+    s = np.arange(9) % 5 - 2
+    h0, l0 = cz.cascade_gemm(A, B, C, kc=128)
+    Ar = (np.ldexp(A[0], r[:, None]), np.ldexp(A[1], r[:, None]))
+    Bs = (np.ldexp(B[0], s[None, :]), np.ldexp(B[1], s[None, :]))
+    sh = r[:, None] + s[None, :]
+    Cs = (np.ldexp(C[0], sh), np.ldexp(C[1], sh))
+    h1, l1 = cz.cascade_gemm(Ar, Bs, Cs, kc=128)
+    assert np.array_equal(h1, np.ldexp(h0, sh)) and np.array_equal(l1, np.ldexp(l0, sh))
+
+
+def test_identity_within_conversion_error():
+    k, n = 8, 6
+    P = make_problem(k, n, k, cfg=85)
+    B = P["B"]
+    hi, lo = cz.cascade_gemm((np.eye(k), np.zeros((k, k))), B, kc=256)
+    c = cz.split_widths(k)
+    ell = Fraction(2) ** -(sum(c) + 53)
+    got = dd_value(hi, lo)
+    want = dd_value(*B)
+    for j in range(n):
+        bj = max(abs(v) for v in want[:, j])
+        for i in range(k):
+            assert abs(got[i, j] - want[i, j]) <= 8 * ell * bj
+
+
+def test_agrees_with_fp64x2_oracle_within_tolerance():
+    m = n = k = 128
+    P = make_problem(m, n, k, cfg=0)
+    hi, lo = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=256)
+    rh, rl, _ = dd_gemm_ref(P["A"], P["B"], P["C"])
+    diff = (hi - rh) + (lo - rl)
+    AB = np.abs(P["A"][0]) @ np.abs(P["B"][0])
+    assert np.all(np.abs(diff) <= 64 * k * 2.0 ** -104 * AB)
+
+
+def test_derived_B_planes_are_single_roundings():
+    # B4' = sigma_2 B4 = B2' + B3', B5' = sigma_1 B5 = B1' + B2' + B3' (through
+    # B4'), B6 = the scaled FP64x2 entry itself (Sec. 3.4); each is the exact
+    # sum rounded once to FP64 (Python's float(Fraction) rounds correctly).
+    P = make_problem(5, 40, 33, cfg=86)
+    hi, lo = P["B"]
+    c = cz.split_widths(256)
+    Bp, f = cz.cascade_B(hi, lo, c)
+    nb6 = 0
+    for p in range(hi.shape[0]):
+        for j in range(hi.shape[1]):
+            q = [Fraction(float(Bp[t][p, j])) for t in range(7)]
+            assert q[4] == Fraction(float(q[2] + q[3]))
+            assert q[5] == Fraction(float(q[1] + q[4]))
+            y = (Fraction(float(hi[p, j])) + Fraction(float(lo[p, j]))) * Fraction(2) ** -int(f[j])
+            assert q[6] == Fraction(float(y))
+            nb6 += q[6] != Fraction(float(hi[p, j])) * Fraction(2) ** -int(f[j])
+    assert nb6 > 0  # the low word changes B6' for some entries
