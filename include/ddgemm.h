@@ -1,0 +1,139 @@
+/*
+ * ddgemm -- double-double (FP64x2) GEMM for AMD Instinct MI355X (gfx950),
+ * computed as a cascade of FP64 matrix products.
+ *
+ * Method: Parikh, van de Geijn, Henry, "Cascading GEMM: High Precision from
+ * Low Precision" (arXiv 2303.04353).  An FP64x2 number is the unevaluated sum
+ * hi + lo of two FP64 numbers (Sec. 3.1, eq. doubledouble).  Each row of A and
+ * each column of B is scaled by a power of two and cut into four FP64 digits
+ * of bounded width (Sec. 3.3-3.4, Appendix A); the ten digit products of
+ * eq. (Gemm10) are accumulated in four FP64 bins per rank-kc update, bins 0-2
+ * exactly (Sec. 3.3, exactness constraints), and the bins are added in FP64x2
+ * from the least significant one (Sec. 3.3, 3.6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are column-major (BLAS) with a leading dimension; an FP64x2
+ *   matrix is two separate FP64 arrays ("planes") hi and lo with the same
+ *   leading dimension.  The value of entry (i, j) is hi[i + j*ld] + lo[i + j*ld]
+ *   taken exactly; the pair need not be normalised.
+ * - All matrix pointers are DEVICE pointers owned by the caller; the library
+ *   never frees them.  A and B are read only, C is read and written.  C must
+ *   not overlap A or B.
+ * - Every call is stream ordered and asynchronous on `stream` (NULL = the
+ *   default stream).  Argument errors are detected on the host and returned
+ *   before anything is launched; a launch error is returned as DD_ERR_HIP.
+ *   No C++ exception and no process exit crosses this interface.
+ * - Non-finite inputs: an output entry whose row of op(A) or column of op(B)
+ *   holds an Inf or NaN becomes NaN (the split has no finite digits for it).
+ *   Entries whose inputs are finite are unaffected.
+ * - The library runs on gfx950 only; other devices get DD_ERR_UNSUPPORTED.
+ */
+#ifndef DDGEMM_H
+#define DDGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* 0 = success; a negative value -i means that argument i (1-based, in the
+ * order of the prototype) is invalid, LAPACK "info" style. */
+typedef int32_t dd_status;
+#define DD_OK 0
+#define DD_ERR_HIP 1          /* a HIP runtime call or kernel launch failed      */
+#define DD_ERR_WORKSPACE 2    /* workspace too small, or device memory exhausted */
+#define DD_ERR_UNSUPPORTED 3  /* the current device is not gfx950                */
+#define DD_ERR_INTERNAL 4     /* internal invariant violated (a library bug)     */
+
+typedef enum { DD_OP_N = 0, DD_OP_T = 1 } dd_op;
+
+typedef enum {
+  /* The paper's method: four FP64 digits per operand, ten FP64 products on
+   * the FP64 matrix cores, bins combined in FP64x2 (Sec. 3.4, eq. Gemm10). */
+  DD_ALGO_CASCADE_F64 = 0,
+  /* Plain software double-double GEMM on the FP64 vector units: the "FP64x2
+   * arithmetic" triple loop the paper compares against (Sec. 5.2); per entry
+   * acc += a*b in DD arithmetic, inner index ascending, C added last. */
+  DD_ALGO_DD_VALU = 1
+} dd_algo;
+
+/* Options of dd_gemm_ex / dd_gemm_batched.  A NULL pointer means all zero. */
+typedef struct {
+  int32_t algo;        /* dd_algo                                                  */
+  int32_t kc;          /* inner block of one rank-kc update (Sec. 3.5); 0 = 256.
+                          Must be a multiple of 4 in [4, 4096].  The split widths
+                          follow from min(kc, k) by the constraints of Sec. 3.3. */
+  int32_t tile;        /* cascade tile configuration, 0 = chosen by the library  */
+  int32_t reserved0;   /* must be 0                                                */
+  int64_t reserved1;   /* must be 0                                                */
+} dd_gemm_opts;
+
+/*
+ * C := A*B + C  (Sec. 1 problem statement; C added last, Sec. 6).
+ * A is m x k (lda >= max(1, m)), B is k x n (ldb >= max(1, k)), C is m x n
+ * (ldc >= max(1, m)), all FP64x2 as hi/lo planes.  Uses the cascade with
+ * kc = 256 and a workspace that the library allocates and keeps per device
+ * and stream (grown on demand; calls that overlap on one stream are ordered
+ * by the stream).  m = 0 or n = 0 is a no-op; k = 0 leaves C unchanged.
+ */
+dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
+                  const double* A_hi, const double* A_lo, int64_t lda,
+                  const double* B_hi, const double* B_lo, int64_t ldb,
+                  double* C_hi, double* C_lo, int64_t ldc,
+                  hipStream_t stream);
+
+/* Bytes of device workspace dd_gemm_ex needs for this problem and options
+ * (0 for DD_ALGO_DD_VALU).  Returns 0 as well for invalid arguments. */
+size_t dd_gemm_workspace_size(dd_op transa, dd_op transb,
+                              int64_t m, int64_t n, int64_t k,
+                              const dd_gemm_opts* opts);
+
+/*
+ * C := op(A)*op(B) + C with op(X) = X or X^T.  op(A) is m x k, op(B) is k x n.
+ * lda >= max(1, rows of A as stored), likewise ldb; ldc >= max(1, m).
+ * `workspace` is caller-owned device memory of at least
+ * dd_gemm_workspace_size(...) bytes, 256-byte aligned; passing NULL with
+ * ws_bytes = 0 makes the library use its own cached workspace (which may
+ * allocate, so not under graph capture).  The workspace is in use until the
+ * call's work on `stream` has finished.
+ */
+dd_status dd_gemm_ex(dd_op transa, dd_op transb,
+                     int64_t m, int64_t n, int64_t k,
+                     const double* A_hi, const double* A_lo, int64_t lda,
+                     const double* B_hi, const double* B_lo, int64_t ldb,
+                     double* C_hi, double* C_lo, int64_t ldc,
+                     void* workspace, size_t ws_bytes,
+                     const dd_gemm_opts* opts, hipStream_t stream);
+
+/*
+ * The split of Appendix A on its own (phase one of Sec. 4), for inspection
+ * and testing.  `side` = 0: X is op(A), rows x cols = m x k, one exponent per
+ * row, 4 planes A0'..A3'.  `side` = 1: X is op(B), rows x cols = k x n, one
+ * exponent per column, 7 planes B0'..B6'.  Planes are pre-weighted
+ * (A_t' = sigma_t A_t, B4' = B2' + B3', B5' = B1' + B4', B6' = the scaled
+ * entry rounded to FP64) and written column-major, plane t at
+ * planes + t*rows*cols with leading dimension rows.  exps receives e (int32)
+ * with max |hi| of the row/column in [2^(e-1), 2^e), 0 for an all-zero one.
+ * kc has the meaning of dd_gemm_opts.kc, with the inner size k = cols
+ * (side 0) or rows (side 1).  exps and planes are device pointers.
+ */
+dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
+                           const double* X_hi, const double* X_lo, int64_t ldx,
+                           int32_t kc, int32_t* exps, double* planes,
+                           hipStream_t stream);
+
+/* Short English description of a status code (static storage). */
+const char* dd_status_string(dd_status status);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t dd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDGEMM_H */

@@ -1,0 +1,166 @@
+// Phases two and three of the cascade (Sec. 4), fused: the ten FP64 digit
+// products of eq. (Gemm10) on the FP64 matrix cores, accumulated per rank-kc
+// update into bins 0, 1, 2 and 3-6 (bins 0-2 exact, Sec. 3.3), the bins added
+// in FP64x2 from the least significant one (Sec. 3.3, 3.6), the rank-kc
+// results accumulated in FP64x2, Sigma and T applied and C added last.
+//
+// Work decomposition (gfx950): a workgroup of 4 waves owns a 64x64 tile of C,
+// each wave a 32x32 quarter.  The products use v_mfma_f64_4x4x4_4b_f64, which
+// runs at the full FP64 matrix rate on gfx950 (the 16x16x4 form does not):
+// one instruction multiplies a 4-row sub-block of A (the same 16 values in
+// all four MFMA blocks) by a 16-column group of B (four 4-column blocks).  A
+// wave therefore holds, per group of 4 inner indices, 8 A registers and
+// 2 B registers per plane, and 4 bins x 8 x 2 accumulator registers.
+// Operands stream from the packed planes in global memory (L2) straight into
+// registers, one group of 4 inner indices ahead of the matrix cores.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dd_device.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace ddk {
+
+namespace {
+
+constexpr int kWaveRB = 2;              // 16-row blocks per wave
+constexpr int kWaveCB = 2;              // 16-column groups per wave
+constexpr int kSub = 4 * kWaveRB;       // 4-row sub-blocks per wave
+constexpr int kTile = 64;               // workgroup tile (rows and columns)
+
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+struct Frags {
+  double a[4][kSub];      // plane, 4-row sub-block
+  double b[7][kWaveCB];   // plane, 16-column group
+};
+
+__device__ __forceinline__ void load_frags(Frags& f, const double* __restrict__ Abase,
+                                           const double* __restrict__ Bbase, int64_t q,
+                                           int64_t rbstride, int64_t cbstride) {
+#pragma unroll
+  for (int r = 0; r < kWaveRB; ++r)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        f.a[t][r * 4 + s] = Abase[r * rbstride + q * (kFragA * kLanes) + t * kLanes + s * 16];
+#pragma unroll
+  for (int g = 0; g < kWaveCB; ++g)
+#pragma unroll
+    for (int t = 0; t < 7; ++t)
+      f.b[t][g] = Bbase[g * cbstride + q * (kFragB * kLanes) + t * kLanes];
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(256)
+cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpack,
+               const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax,
+               int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_n,
+               double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t tm = (int64_t)blockIdx.x / tiles_n;
+  const int64_t tn = (int64_t)blockIdx.x - tm * tiles_n;
+  const int64_t rb0 = tm * 4 + wm * kWaveRB;   // first 16-row block of this wave
+  const int64_t cb0 = tn * 4 + wn * kWaveCB;   // first 16-column group
+
+  const int64_t rbstride = K4 * (kFragA * kLanes);
+  const int64_t cbstride = K4 * (kFragB * kLanes);
+  // A lane 16k + 4b + i reads position s*16 + k*4 + i of its sub-block (the
+  // same for every MFMA block b); B lane l reads position l.
+  const double* Abase = Apack + rb0 * rbstride + (lane >> 4) * 4 + (lane & 3);
+  const double* Bbase = Bpack + cb0 * cbstride + lane;
+
+  double bin0[kSub][kWaveCB], bin1[kSub][kWaveCB], bin2[kSub][kWaveCB], bin36[kSub][kWaveCB];
+  double acc_h[kSub][kWaveCB], acc_l[kSub][kWaveCB];
+#pragma unroll
+  for (int i = 0; i < kSub; ++i)
+#pragma unroll
+    for (int g = 0; g < kWaveCB; ++g) {
+      bin0[i][g] = bin1[i][g] = bin2[i][g] = bin36[i][g] = 0.0;
+      acc_h[i][g] = acc_l[i][g] = 0.0;
+    }
+
+  Frags cur, nxt;
+  load_frags(cur, Abase, Bbase, 0, rbstride, cbstride);
+  int32_t inblk = 0;
+  for (int64_t q = 0; q < K4; ++q) {
+    const int64_t qn = q + 1 < K4 ? q + 1 : q;
+    load_frags(nxt, Abase, Bbase, qn, rbstride, cbstride);
+
+#define DD_PRODUCT(BIN, TA, TB)                                                  \
+  _Pragma("unroll") for (int i = 0; i < kSub; ++i)                               \
+  _Pragma("unroll") for (int g = 0; g < kWaveCB; ++g)                            \
+      BIN[i][g] = mfma4(cur.a[TA][i], cur.b[TB][g], BIN[i][g]);
+    DD_PRODUCT(bin0, 0, 0)
+    DD_PRODUCT(bin1, 0, 1)
+    DD_PRODUCT(bin1, 1, 0)
+    DD_PRODUCT(bin2, 0, 2)
+    DD_PRODUCT(bin2, 1, 1)
+    DD_PRODUCT(bin2, 2, 0)
+    DD_PRODUCT(bin36, 0, 3)
+    DD_PRODUCT(bin36, 1, 4)
+    DD_PRODUCT(bin36, 2, 5)
+    DD_PRODUCT(bin36, 3, 6)
+#undef DD_PRODUCT
+
+    if (++inblk == kcq || q + 1 == K4) {
+      inblk = 0;
+      // bin0 + (bin1 + (bin2 + bin36)) in FP64x2, then into the accumulator
+#pragma unroll
+      for (int i = 0; i < kSub; ++i)
+#pragma unroll
+        for (int g = 0; g < kWaveCB; ++g) {
+          double s, e;
+          two_sum(bin2[i][g], bin36[i][g], s, e);
+          dd_add_d(s, e, bin1[i][g], s, e);
+          dd_add_d(s, e, bin0[i][g], s, e);
+          dd_add(acc_h[i][g], acc_l[i][g], s, e, acc_h[i][g], acc_l[i][g]);
+          bin0[i][g] = bin1[i][g] = bin2[i][g] = bin36[i][g] = 0.0;
+        }
+    }
+    cur = nxt;
+  }
+
+  // Epilogue: D lane 16i + 4b + j of (sub-block, group) holds row 4*sub + i,
+  // column 16*group + 4b + j, i.e. row lane/16 and column lane%16.
+#pragma unroll
+  for (int i = 0; i < kSub; ++i) {
+    const int64_t row = rb0 * 16 + i * 4 + (lane >> 4);
+    if (row >= m) continue;
+    const int er = exp_of_bits(amax[row]);
+#pragma unroll
+    for (int g = 0; g < kWaveCB; ++g) {
+      const int64_t col = (cb0 + g) * 16 + (lane & 15);
+      if (col >= n) continue;
+      const int sh = er + exp_of_bits(bmax[col]);
+      const double h = __builtin_ldexp(acc_h[i][g], sh);
+      const double l = __builtin_ldexp(acc_l[i][g], sh);
+      const int64_t idx = row + col * ldc;
+      double rh, rl;
+      dd_add(Chi[idx], Clo[idx], h, l, rh, rl);
+      Chi[idx] = rh;
+      Clo[idx] = rl;
+    }
+  }
+}
+
+hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,
+                          const uint64_t* amax, const uint64_t* bmax,
+                          double* Chi, double* Clo, int64_t ldc, hipStream_t s) {
+  if (L.tile_m != kTile || L.tile_n != kTile) return hipErrorInvalidValue;
+  const int64_t tiles_m = L.mpad / kTile, tiles_n = L.npad / kTile;
+  const int64_t tiles = tiles_m * tiles_n;
+  if (tiles <= 0 || tiles > 0x7fffffff) return hipErrorInvalidValue;
+  cascade_kernel<<<(unsigned)tiles, 256, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
+                                                 tiles_n, Chi, Clo, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace ddk

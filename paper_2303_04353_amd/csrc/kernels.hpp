@@ -1,0 +1,36 @@
+// Host-side launchers of the library's kernels (each defined next to its
+// kernel in a .hip file).  All launches are asynchronous on `s` and return
+// the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace ddk {
+
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int64_t so, int64_t sr,
+                               uint64_t* out, hipStream_t s);
+hipError_t launch_pack_a(const double* Ahi, const double* Alo, int64_t si, int64_t sp,
+                         const CascadeLayout& L, const uint64_t* amax, double* Apack, hipStream_t s);
+hipError_t launch_pack_b(const double* Bhi, const double* Blo, int64_t sp, int64_t sj,
+                         const CascadeLayout& L, const uint64_t* bmax, double* Bpack, hipStream_t s);
+hipError_t launch_unpack(const double* pack, int side, int64_t rows, int64_t cols, int64_t K4,
+                         double* planes, hipStream_t s);
+hipError_t launch_exps(const uint64_t* bits, int64_t n, int32_t* e, hipStream_t s);
+
+// The fused product kernel: ten FP64 MFMA products per rank-kc block, bins
+// combined in FP64x2, Sigma/T applied, C := C + result.
+hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,
+                          const uint64_t* amax, const uint64_t* bmax,
+                          double* Chi, double* Clo, int64_t ldc, hipStream_t s);
+
+// Plain software double-double GEMM on the vector units.
+hipError_t launch_dd_valu(int64_t m, int64_t n, int64_t k,
+                          const double* Ahi, const double* Alo, int64_t a_si, int64_t a_sp,
+                          const double* Bhi, const double* Blo, int64_t b_sp, int64_t b_sj,
+                          double* Chi, double* Clo, int64_t ldc, hipStream_t s);
+
+}  // namespace ddk

@@ -1,0 +1,77 @@
+// Workspace layout of one cascaded FP64x2 GEMM, shared by the host runtime
+// and the kernels.
+//
+// Packed digit planes (the "cascaded" operands of Sec. 3.4, pre-weighted),
+// laid out for v_mfma_f64_4x4x4_4b_f64 (four independent 4x4x4 blocks; A lane
+// 16k+4b+i holds row i / inner index k of block b, B lane 16k+4b+j holds inner
+// index k / column j, D lane 16i+4b+j holds row i / column j):
+//   A: for each 16-row block rb and each group of 4 inner indices kq, the
+//      four planes A0'..A3'; within a plane the 4-row sub-block s, inner
+//      index kk and row i sit at s*16 + kk*4 + i (16 values per 4-row
+//      sub-block, read by all four MFMA blocks at once):
+//        Apack[((rb*K4 + kq)*4 + t)*64 + s*16 + kk*4 + i]
+//   B: for each 16-column block cb, the seven planes B0'..B6', one 64-lane
+//      operand each (lane kk*16 + c holds inner index kk, column c):
+//        Bpack[((cb*K4 + kq)*7 + t)*64 + kk*16 + c]
+// Rows/columns are padded with zeros up to the workgroup tile and the inner
+// dimension up to a multiple of 4, so the product kernel needs no bounds
+// checks in its main loop.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ddk {
+
+constexpr int kFragA = 4;   // planes of op(A)
+constexpr int kFragB = 7;   // planes of op(B)
+constexpr int kLanes = 64;
+
+struct CascadeLayout {
+  int64_t m, n, k;
+  int64_t mpad, npad, kpad, K4;  // padded sizes, K4 = kpad / 4
+  int64_t tile_m, tile_n;        // workgroup tile of the product kernel
+  int32_t kc;                    // rank-kc block actually used (min(kc, k))
+  int32_t kcq;                   // kc in groups of four inner indices
+  int32_t c[3];                  // split widths c0, c1, c2
+  size_t off_amax, off_bmax, off_apack, off_bpack, bytes;
+};
+
+inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+// ceil(log2 kc) and the widths of Sec. 3.3 (bins 0-2 exact for kc terms).
+inline void split_widths(int64_t kc, int32_t c[3]) {
+  int L = 0;
+  while ((int64_t(1) << L) < kc) ++L;
+  int c0 = (53 - L) / 2;
+  int c1a = 53 - L - 1 - c0, c1b = (53 - L - 2) / 2;
+  c[0] = c0;
+  c[1] = c1a < c1b ? c1a : c1b;
+  c[2] = 53 - L - 2 - c0;
+}
+
+inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
+                                 int64_t tile_m, int64_t tile_n) {
+  CascadeLayout L{};
+  L.m = m; L.n = n; L.k = k;
+  L.tile_m = tile_m; L.tile_n = tile_n;
+  L.mpad = round_up(m > 0 ? m : 1, tile_m);
+  L.npad = round_up(n > 0 ? n : 1, tile_n);
+  L.kpad = round_up(k > 0 ? k : 1, 4);
+  L.K4 = L.kpad / 4;
+  int64_t kce = k < kc ? k : kc;
+  if (kce < 1) kce = 1;
+  L.kc = (int32_t)kce;
+  L.kcq = (int32_t)((kce + 3) / 4);
+  split_widths(kce, L.c);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up((int64_t)(off + bytes), 256); return o; };
+  L.off_amax = take(sizeof(uint64_t) * (size_t)L.mpad);
+  L.off_bmax = take(sizeof(uint64_t) * (size_t)L.npad);
+  L.off_apack = take(sizeof(double) * (size_t)kFragA * (size_t)L.mpad * (size_t)L.kpad);
+  L.off_bpack = take(sizeof(double) * (size_t)kFragB * (size_t)L.npad * (size_t)L.kpad);
+  L.bytes = off;
+  return L;
+}
+
+}  // namespace ddk

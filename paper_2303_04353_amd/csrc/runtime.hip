@@ -1,0 +1,303 @@
+// Host runtime and C ABI of the library: argument checks, workspace, and the
+// launch sequence of the cascade (phase one: Sigma/T and split; phases two
+// and three: the fused product/combine kernel) or of the plain double-double
+// kernel.  See include/ddgemm.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "../../include/ddgemm.h"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace {
+
+using ddk::CascadeLayout;
+
+constexpr int64_t kTileM = 64, kTileN = 64;
+constexpr int32_t kDefaultKc = 256;
+
+// ------------------------------------------------------------ device checks
+std::mutex g_mu;
+std::map<int, int> g_arch_ok;  // device -> 1 gfx950, 0 other
+
+dd_status check_device(int* dev_out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return DD_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_arch_ok.find(dev);
+  if (it == g_arch_ok.end()) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DD_ERR_HIP;
+    int ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+    it = g_arch_ok.emplace(dev, ok).first;
+  }
+  if (dev_out) *dev_out = dev;
+  return it->second ? DD_OK : DD_ERR_UNSUPPORTED;
+}
+
+// ------------------------------------------------------ cached workspaces
+struct WsKey { int dev; hipStream_t stream; bool operator<(const WsKey& o) const {
+  return dev != o.dev ? dev < o.dev : (uintptr_t)stream < (uintptr_t)o.stream; } };
+struct WsBuf { void* ptr = nullptr; size_t bytes = 0; };
+std::map<WsKey, WsBuf> g_ws;
+
+dd_status cached_workspace(int dev, hipStream_t stream, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  WsBuf& b = g_ws[WsKey{dev, stream}];
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      // earlier work on this stream may still use the old buffer
+      if (hipStreamSynchronize(stream) != hipSuccess) return DD_ERR_HIP;
+      (void)hipFree(b.ptr);
+      b.ptr = nullptr;
+      b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+      (void)hipGetLastError();
+      b.ptr = nullptr;
+      return DD_ERR_WORKSPACE;
+    }
+    b.bytes = want;
+  }
+  *out = b.ptr;
+  return DD_OK;
+}
+
+// ------------------------------------------------------------ arguments
+struct Problem {
+  int transa, transb;
+  int64_t m, n, k;
+  const double *Ahi, *Alo; int64_t lda;
+  const double *Bhi, *Blo; int64_t ldb;
+  double *Chi, *Clo; int64_t ldc;
+};
+
+// Which logical argument failed; mapped to the position in each prototype.
+enum Arg { ARG_OK = 0, ARG_TRANSA, ARG_TRANSB, ARG_M, ARG_N, ARG_K, ARG_AHI, ARG_ALO, ARG_LDA,
+           ARG_BHI, ARG_BLO, ARG_LDB, ARG_CHI, ARG_CLO, ARG_LDC, ARG_OPTS };
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return (size_t)((cols - 1) * ld + rows) * sizeof(double);
+}
+
+Arg validate(const Problem& p) {
+  if (p.transa != DD_OP_N && p.transa != DD_OP_T) return ARG_TRANSA;
+  if (p.transb != DD_OP_N && p.transb != DD_OP_T) return ARG_TRANSB;
+  if (p.m < 0) return ARG_M;
+  if (p.n < 0) return ARG_N;
+  if (p.k < 0) return ARG_K;
+  const int64_t arows = p.transa ? p.k : p.m, acols = p.transa ? p.m : p.k;
+  const int64_t brows = p.transb ? p.n : p.k, bcols = p.transb ? p.k : p.n;
+  if (p.lda < (arows > 1 ? arows : 1)) return ARG_LDA;
+  if (p.ldb < (brows > 1 ? brows : 1)) return ARG_LDB;
+  if (p.ldc < (p.m > 1 ? p.m : 1)) return ARG_LDC;
+  if (p.m == 0 || p.n == 0) return ARG_OK;
+  if (!p.Chi) return ARG_CHI;
+  if (!p.Clo) return ARG_CLO;
+  if (p.k == 0) return ARG_OK;
+  if (!p.Ahi) return ARG_AHI;
+  if (!p.Alo) return ARG_ALO;
+  if (!p.Bhi) return ARG_BHI;
+  if (!p.Blo) return ARG_BLO;
+  const size_t cb = span_bytes(p.m, p.n, p.ldc);
+  const size_t ab = span_bytes(arows, acols, p.lda), bb = span_bytes(brows, bcols, p.ldb);
+  if (overlaps(p.Chi, cb, p.Clo, cb)) return ARG_CLO;
+  for (const double* c : {(const double*)p.Chi, (const double*)p.Clo}) {
+    const Arg which = c == p.Chi ? ARG_CHI : ARG_CLO;
+    if (overlaps(c, cb, p.Ahi, ab) || overlaps(c, cb, p.Alo, ab) ||
+        overlaps(c, cb, p.Bhi, bb) || overlaps(c, cb, p.Blo, bb)) return which;
+  }
+  return ARG_OK;
+}
+
+// Strides of op(A)(i, p) and op(B)(p, j) in elements.
+void strides(const Problem& p, int64_t& a_si, int64_t& a_sp, int64_t& b_sp, int64_t& b_sj) {
+  if (p.transa) { a_si = p.lda; a_sp = 1; } else { a_si = 1; a_sp = p.lda; }
+  if (p.transb) { b_sp = p.ldb; b_sj = 1; } else { b_sp = 1; b_sj = p.ldb; }
+}
+
+bool valid_kc(int32_t kc) { return kc >= 4 && kc <= 4096 && kc % 4 == 0; }
+
+dd_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return DD_OK;
+  if (e == hipErrorOutOfMemory) return DD_ERR_WORKSPACE;
+  return DD_ERR_HIP;
+}
+
+#define DD_TRY(expr) do { dd_status st_ = hip_status(expr); if (st_ != DD_OK) return st_; } while (0)
+
+// Phase one into the workspace described by L.
+dd_status run_split(const Problem& p, const CascadeLayout& L, char* ws, hipStream_t s) {
+  int64_t a_si, a_sp, b_sp, b_sj;
+  strides(p, a_si, a_sp, b_sp, b_sj);
+  uint64_t* amax = (uint64_t*)(ws + L.off_amax);
+  uint64_t* bmax = (uint64_t*)(ws + L.off_bmax);
+  DD_TRY(ddk::launch_fill_u64(amax, L.mpad, 0, s));
+  DD_TRY(ddk::launch_fill_u64(bmax, L.npad, 0, s));
+  // rows of op(A): outer i, reduced p;  columns of op(B): outer j, reduced p
+  DD_TRY(ddk::launch_max_abs_bits(p.Ahi, p.m, p.k, a_si, a_sp, amax, s));
+  DD_TRY(ddk::launch_max_abs_bits(p.Bhi, p.n, p.k, b_sj, b_sp, bmax, s));
+  DD_TRY(ddk::launch_pack_a(p.Ahi, p.Alo, a_si, a_sp, L, amax, (double*)(ws + L.off_apack), s));
+  DD_TRY(ddk::launch_pack_b(p.Bhi, p.Blo, b_sp, b_sj, L, bmax, (double*)(ws + L.off_bpack), s));
+  return DD_OK;
+}
+
+dd_status run(const Problem& p, int32_t algo, int32_t kc, void* workspace, size_t ws_bytes,
+              bool internal_ws, hipStream_t s) {
+  int dev = 0;
+  dd_status st = check_device(&dev);
+  if (st != DD_OK) return st;
+  if (p.m == 0 || p.n == 0 || p.k == 0) return DD_OK;
+  if (algo == DD_ALGO_DD_VALU) {
+    int64_t a_si, a_sp, b_sp, b_sj;
+    strides(p, a_si, a_sp, b_sp, b_sj);
+    return hip_status(ddk::launch_dd_valu(p.m, p.n, p.k, p.Ahi, p.Alo, a_si, a_sp, p.Bhi, p.Blo,
+                                          b_sp, b_sj, p.Chi, p.Clo, p.ldc, s));
+  }
+  const CascadeLayout L = ddk::make_layout(p.m, p.n, p.k, kc, kTileM, kTileN);
+  char* ws = (char*)workspace;
+  if (internal_ws) {
+    void* w = nullptr;
+    st = cached_workspace(dev, s, L.bytes, &w);
+    if (st != DD_OK) return st;
+    ws = (char*)w;
+  } else if (ws_bytes < L.bytes || ((uintptr_t)ws & 255u) != 0) {
+    return DD_ERR_WORKSPACE;
+  }
+  st = run_split(p, L, ws, s);
+  if (st != DD_OK) return st;
+  return hip_status(ddk::launch_cascade(L, (const double*)(ws + L.off_apack),
+                                        (const double*)(ws + L.off_bpack),
+                                        (const uint64_t*)(ws + L.off_amax),
+                                        (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
+                  const double* A_hi, const double* A_lo, int64_t lda,
+                  const double* B_hi, const double* B_lo, int64_t ldb,
+                  double* C_hi, double* C_lo, int64_t ldc, hipStream_t stream) {
+  static const int pos[] = {0, 0, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 0};
+  Problem p{DD_OP_N, DD_OP_N, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc};
+  Arg a = validate(p);
+  if (a != ARG_OK) return -pos[a];
+  return run(p, DD_ALGO_CASCADE_F64, kDefaultKc, nullptr, 0, true, stream);
+}
+
+static bool read_opts(const dd_gemm_opts* o, int32_t* algo, int32_t* kc) {
+  *algo = DD_ALGO_CASCADE_F64;
+  *kc = kDefaultKc;
+  if (!o) return true;
+  if (o->algo != DD_ALGO_CASCADE_F64 && o->algo != DD_ALGO_DD_VALU) return false;
+  if (o->kc != 0 && !valid_kc(o->kc)) return false;
+  if (o->tile != 0 || o->reserved0 != 0 || o->reserved1 != 0) return false;
+  *algo = o->algo;
+  if (o->kc != 0) *kc = o->kc;
+  return true;
+}
+
+size_t dd_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+                              const dd_gemm_opts* opts) {
+  int32_t algo, kc;
+  if (!read_opts(opts, &algo, &kc)) return 0;
+  if ((transa != DD_OP_N && transa != DD_OP_T) || (transb != DD_OP_N && transb != DD_OP_T)) return 0;
+  if (m <= 0 || n <= 0 || k <= 0 || algo == DD_ALGO_DD_VALU) return 0;
+  return ddk::make_layout(m, n, k, kc, kTileM, kTileN).bytes;
+}
+
+dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+                     const double* A_hi, const double* A_lo, int64_t lda,
+                     const double* B_hi, const double* B_lo, int64_t ldb,
+                     double* C_hi, double* C_lo, int64_t ldc,
+                     void* workspace, size_t ws_bytes, const dd_gemm_opts* opts,
+                     hipStream_t stream) {
+  static const int pos[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 17};
+  Problem p{(int)transa, (int)transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc};
+  Arg a = validate(p);
+  if (a != ARG_OK) return -pos[a];
+  int32_t algo, kc;
+  if (!read_opts(opts, &algo, &kc)) return -17;
+  const bool internal = workspace == nullptr && ws_bytes == 0;
+  if (!internal && workspace == nullptr) return -15;
+  return run(p, algo, kc, workspace, ws_bytes, internal, stream);
+}
+
+dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
+                           const double* X_hi, const double* X_lo, int64_t ldx,
+                           int32_t kc, int32_t* exps, double* planes, hipStream_t stream) {
+  if (side != 0 && side != 1) return -1;
+  if (trans != DD_OP_N && trans != DD_OP_T) return -2;
+  if (rows < 0) return -3;
+  if (cols < 0) return -4;
+  const int64_t srows = trans ? cols : rows;
+  if (ldx < (srows > 1 ? srows : 1)) return -7;
+  if (kc != 0 && !valid_kc(kc)) return -8;
+  if (rows == 0 || cols == 0) return DD_OK;
+  if (!X_hi) return -5;
+  if (!X_lo) return -6;
+  if (!exps) return -9;
+  if (!planes) return -10;
+  int dev = 0;
+  dd_status st = check_device(&dev);
+  if (st != DD_OK) return st;
+  // Present X as op(A) (side 0, m x k = rows x cols) or op(B) (side 1, k x n).
+  Problem p{};
+  p.transa = p.transb = (int)trans;
+  int64_t m = 1, n = 1, k;
+  if (side == 0) { m = rows; k = cols; p.Ahi = X_hi; p.Alo = X_lo; p.lda = ldx; }
+  else { k = rows; n = cols; p.Bhi = X_hi; p.Blo = X_lo; p.ldb = ldx; }
+  p.m = m; p.n = n; p.k = k;
+  const CascadeLayout L = ddk::make_layout(m, n, k, kc ? kc : kDefaultKc, kTileM, kTileN);
+  void* w = nullptr;
+  st = cached_workspace(dev, stream, L.bytes, &w);
+  if (st != DD_OK) return st;
+  char* ws = (char*)w;
+  int64_t a_si, a_sp, b_sp, b_sj;
+  strides(p, a_si, a_sp, b_sp, b_sj);
+  if (side == 0) {
+    uint64_t* amax = (uint64_t*)(ws + L.off_amax);
+    DD_TRY(ddk::launch_fill_u64(amax, L.mpad, 0, stream));
+    DD_TRY(ddk::launch_max_abs_bits(p.Ahi, m, k, a_si, a_sp, amax, stream));
+    DD_TRY(ddk::launch_pack_a(p.Ahi, p.Alo, a_si, a_sp, L, amax, (double*)(ws + L.off_apack), stream));
+    DD_TRY(ddk::launch_unpack((const double*)(ws + L.off_apack), 0, m, k, L.K4, planes, stream));
+    DD_TRY(ddk::launch_exps(amax, m, exps, stream));
+  } else {
+    uint64_t* bmax = (uint64_t*)(ws + L.off_bmax);
+    DD_TRY(ddk::launch_fill_u64(bmax, L.npad, 0, stream));
+    DD_TRY(ddk::launch_max_abs_bits(p.Bhi, n, k, b_sj, b_sp, bmax, stream));
+    DD_TRY(ddk::launch_pack_b(p.Bhi, p.Blo, b_sp, b_sj, L, bmax, (double*)(ws + L.off_bpack), stream));
+    DD_TRY(ddk::launch_unpack((const double*)(ws + L.off_bpack), 1, k, n, L.K4, planes, stream));
+    DD_TRY(ddk::launch_exps(bmax, n, exps, stream));
+  }
+  return DD_OK;
+}
+
+const char* dd_status_string(dd_status s) {
+  switch (s) {
+    case DD_OK: return "success";
+    case DD_ERR_HIP: return "HIP runtime error or kernel launch failure";
+    case DD_ERR_WORKSPACE: return "workspace too small, misaligned, or device memory exhausted";
+    case DD_ERR_UNSUPPORTED: return "unsupported device (the library runs on gfx950 only)";
+    case DD_ERR_INTERNAL: return "internal error";
+    default: return s < 0 ? "invalid argument (-status is its 1-based position)" : "unknown status";
+  }
+}
+
+int32_t dd_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+// Phase one of the cascade (Sec. 4): Sigma and T, then the split of
+// Appendix A into pre-weighted, MFMA-fragment-packed digit planes.
+//
+//  * max_abs_bits_*: per row of op(A) / column of op(B), the largest |hi| as a
+//    bit pattern (non-negative doubles order like their bits), reduced with
+//    atomicMax; the exponent e = frexp_exp(max) is taken where it is used.
+//  * pack_a / pack_b: one wave per 64-lane fragment, each lane splits one
+//    entry and writes its 4 (A) or 7 (B) planes; zero padding outside m, n, k.
+//  * unpack_*: diagnostic copy of the packed planes into plain column-major
+//    planes (used by dd_cascade_split).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dd_device.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace ddk {
+
+__global__ void fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Element (o, r) at X[o + r*ld]: consecutive threads take consecutive o.
+__global__ void __launch_bounds__(256)
+max_abs_bits_outer_contig(const double* __restrict__ X, int64_t outer, int64_t red, int64_t ld,
+                          int64_t chunk, uint64_t* __restrict__ out) {
+  int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (o >= outer) return;
+  int64_t r0 = (int64_t)blockIdx.y * chunk;
+  int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
+  uint64_t mx = 0;
+  for (int64_t r = r0; r < r1; ++r) {
+    uint64_t b = __builtin_bit_cast(uint64_t, X[o + r * ld]) & 0x7fffffffffffffffull;
+    mx = b > mx ? b : mx;
+  }
+  if (r1 > r0) atomicMax((unsigned long long*)&out[o], (unsigned long long)mx);
+}
+
+// Element (o, r) at X[r + o*ld]: one wave per o, lanes stride over r.
+__global__ void __launch_bounds__(256)
+max_abs_bits_red_contig(const double* __restrict__ X, int64_t outer, int64_t red, int64_t ld,
+                        int64_t chunk, uint64_t* __restrict__ out) {
+  int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (o >= outer) return;
+  int64_t r0 = (int64_t)blockIdx.y * chunk;
+  int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
+  uint64_t mx = 0;
+  const double* col = X + o * ld;
+  for (int64_t r = r0 + lane; r < r1; r += 64) {
+    uint64_t b = __builtin_bit_cast(uint64_t, col[r]) & 0x7fffffffffffffffull;
+    mx = b > mx ? b : mx;
+  }
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    uint64_t y = __shfl_xor(mx, s, 64);
+    mx = y > mx ? y : mx;
+  }
+  if (lane == 0 && r1 > r0) atomicMax((unsigned long long*)&out[o], (unsigned long long)mx);
+}
+
+__device__ __forceinline__ SplitParams make_params(int c0, int c1, int c2) {
+  SplitParams sp;
+  int c[3] = {c0, c1, c2};
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    sp.K[t] = __builtin_ldexp(1.0, 53 - c[t]) + __builtin_ldexp(1.0, 52 - c[t]);
+    sp.P[t] = __builtin_ldexp(1.0, c[t]);
+  }
+  sp.sig[0] = 1.0;
+  sp.sig[1] = __builtin_ldexp(1.0, -c0);
+  sp.sig[2] = __builtin_ldexp(1.0, -(c0 + c1));
+  sp.sig[3] = __builtin_ldexp(1.0, -(c0 + c1 + c2));
+  return sp;
+}
+
+// op(A)(i, p) = A[i*si + p*sp_].  One wave per fragment (rb, kq).
+__global__ void __launch_bounds__(256)
+pack_a(const double* __restrict__ Ahi, const double* __restrict__ Alo, int64_t si, int64_t sp_,
+       int64_t m, int64_t k, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ amax,
+       int c0, int c1, int c2, double* __restrict__ Apack) {
+  int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (frag >= nfrag) return;
+  int lane = threadIdx.x & 63;
+  int64_t rb = frag / K4, kq = frag - rb * K4;
+  // position lane = s*16 + kk*4 + ii holds row rb*16 + s*4 + ii, inner index kq*4 + kk
+  int64_t i = rb * 16 + (lane >> 4) * 4 + (lane & 3), p = kq * 4 + ((lane >> 2) & 3);
+  double w[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < m && p < k) {
+    SplitParams spar = make_params(c0, c1, c2);
+    int64_t idx = i * si + p * sp_;
+    double xh, xl;
+    split_entry(Ahi[idx], Alo[idx], exp_of_bits(amax[i]), spar, w, xh, xl);
+  }
+  double* dst = Apack + frag * (kFragA * kLanes) + lane;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) dst[t * kLanes] = w[t];
+}
+
+// op(B)(p, j) = B[p*sp_ + j*sj].  One wave per fragment (cb, kq).
+__global__ void __launch_bounds__(256)
+pack_b(const double* __restrict__ Bhi, const double* __restrict__ Blo, int64_t sp_, int64_t sj,
+       int64_t k, int64_t n, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ bmax,
+       int c0, int c1, int c2, double* __restrict__ Bpack) {
+  int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (frag >= nfrag) return;
+  int lane = threadIdx.x & 63;
+  int64_t cb = frag / K4, kq = frag - cb * K4;
+  int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
+  double w[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (j < n && p < k) {
+    SplitParams spar = make_params(c0, c1, c2);
+    int64_t idx = p * sp_ + j * sj;
+    double yh, yl;
+    split_entry(Bhi[idx], Blo[idx], exp_of_bits(bmax[j]), spar, w, yh, yl);
+    w[4] = w[2] + w[3];   // sigma_2 B4 = B2' + B3'
+    w[5] = w[1] + w[4];   // sigma_1 B5 = B1' + B2' + B3'
+    w[6] = yh + yl;       // B6: the scaled entry itself, rounded once
+  }
+  double* dst = Bpack + frag * (kFragB * kLanes) + lane;
+#pragma unroll
+  for (int t = 0; t < 7; ++t) dst[t * kLanes] = w[t];
+}
+
+// Plain planes from the packed layout (diagnostics).  side 0: element (i, p)
+// of a rows x cols = m x k operand; side 1: element (p, j) of k x n.
+__global__ void __launch_bounds__(256)
+unpack_planes(const double* __restrict__ pack, int side, int64_t rows, int64_t cols, int64_t K4,
+              double* __restrict__ planes) {
+  int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= rows * cols) return;
+  int64_t r = idx % rows, cidx = idx / rows;
+  int nt = side == 0 ? kFragA : kFragB;
+  int64_t blk, q, kk, lanepos;
+  if (side == 0) { blk = r / 16; q = cidx / 4; kk = cidx % 4; lanepos = ((r % 16) / 4) * 16 + kk * 4 + (r % 4); }
+  else { blk = cidx / 16; q = r / 4; kk = r % 4; lanepos = kk * 16 + (cidx % 16); }
+  const double* src = pack + (blk * K4 + q) * (int64_t)(nt * kLanes) + lanepos;
+  for (int t = 0; t < nt; ++t) planes[(int64_t)t * rows * cols + idx] = src[t * kLanes];
+}
+
+__global__ void exps_from_bits(const uint64_t* __restrict__ bits, int64_t n, int32_t* __restrict__ e) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) e[i] = exp_of_bits(bits[i]);
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned blocks_for(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_u64<<<blocks_for(n, 256), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+// max |X(o, r)| bits over r for o < outer, X(o, r) = X[o*so + r*sr]; one of
+// so, sr is 1.  out must be zero on entry.
+hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int64_t so, int64_t sr,
+                               uint64_t* out, hipStream_t s) {
+  if (outer <= 0 || red <= 0) return hipSuccess;
+  if (so == 1) {
+    int64_t chunk = 256;
+    int64_t gy = (red + chunk - 1) / chunk;
+    while (gy > 65535) { chunk *= 2; gy = (red + chunk - 1) / chunk; }
+    dim3 grid(blocks_for(outer, 256), (unsigned)gy);
+    max_abs_bits_outer_contig<<<grid, 256, 0, s>>>(X, outer, red, sr, chunk, out);
+  } else {
+    int64_t chunk = 4096;
+    int64_t gy = (red + chunk - 1) / chunk;
+    while (gy > 65535) { chunk *= 2; gy = (red + chunk - 1) / chunk; }
+    dim3 grid(blocks_for(outer, 4), (unsigned)gy);
+    max_abs_bits_red_contig<<<grid, 256, 0, s>>>(X, outer, red, so, chunk, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_a(const double* Ahi, const double* Alo, int64_t si, int64_t sp,
+                         const CascadeLayout& L, const uint64_t* amax, double* Apack, hipStream_t s) {
+  int64_t nfrag = (L.mpad / 16) * L.K4;
+  pack_a<<<blocks_for(nfrag, 4), 256, 0, s>>>(Ahi, Alo, si, sp, L.m, L.k, L.K4, nfrag, amax,
+                                              L.c[0], L.c[1], L.c[2], Apack);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_b(const double* Bhi, const double* Blo, int64_t sp, int64_t sj,
+                         const CascadeLayout& L, const uint64_t* bmax, double* Bpack, hipStream_t s) {
+  int64_t nfrag = (L.npad / 16) * L.K4;
+  pack_b<<<blocks_for(nfrag, 4), 256, 0, s>>>(Bhi, Blo, sp, sj, L.k, L.n, L.K4, nfrag, bmax,
+                                              L.c[0], L.c[1], L.c[2], Bpack);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const double* pack, int side, int64_t rows, int64_t cols, int64_t K4,
+                         double* planes, hipStream_t s) {
+  if (rows * cols <= 0) return hipSuccess;
+  unpack_planes<<<blocks_for(rows * cols, 256), 256, 0, s>>>(pack, side, rows, cols, K4, planes);
+  return hipGetLastError();
+}
+
+hipError_t launch_exps(const uint64_t* bits, int64_t n, int32_t* e, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  exps_from_bits<<<blocks_for(n, 256), 256, 0, s>>>(bits, n, e);
+  return hipGetLastError();
+}
+
+}  // namespace ddk

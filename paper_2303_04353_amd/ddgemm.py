@@ -1,0 +1,148 @@
+"""ctypes binding of ``libddgemm.so``: the C ABI of include/ddgemm.h, same names.
+
+Only argument marshalling happens here: device pointers are taken from torch
+tensors (``.data_ptr()``) or passed as integers, the stream defaults to
+torch's current stream.  Every step of the computation runs in the HIP
+library; if it is not built, :func:`lib` raises.
+
+Matrices are column-major as in BLAS.  A column-major ``rows x cols`` matrix
+is held in a contiguous torch tensor of shape ``(cols, rows)`` (its
+transpose), see :func:`colmajor_to_device` / :func:`colmajor_from_device`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddgemm.so")
+
+DD_OK = 0
+DD_ERR_HIP = 1
+DD_ERR_WORKSPACE = 2
+DD_ERR_UNSUPPORTED = 3
+DD_ERR_INTERNAL = 4
+DD_OP_N = 0
+DD_OP_T = 1
+DD_ALGO_CASCADE_F64 = 0
+DD_ALGO_DD_VALU = 1
+
+EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split",
+            "dd_status_string", "dd_version")
+
+
+class dd_gemm_opts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("kc", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int64)]
+
+
+class DDError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s failed: status %d (%s)" % (where, status, dd_status_string(status)))
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libddgemm.so is not built: run `python -c 'import __graft_entry__ as g; "
+                               "g.build()'` (hipcc, gfx950) first")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp, i32, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        L.dd_gemm.argtypes = [i64, i64, i64, vp, vp, i64, vp, vp, i64, vp, vp, i64, vp]
+        L.dd_gemm.restype = i32
+        L.dd_gemm_workspace_size.argtypes = [i32, i32, i64, i64, i64, ctypes.POINTER(dd_gemm_opts)]
+        L.dd_gemm_workspace_size.restype = sz
+        L.dd_gemm_ex.argtypes = [i32, i32, i64, i64, i64, vp, vp, i64, vp, vp, i64, vp, vp, i64,
+                                 vp, sz, ctypes.POINTER(dd_gemm_opts), vp]
+        L.dd_gemm_ex.restype = i32
+        L.dd_cascade_split.argtypes = [i32, i32, i64, i64, vp, vp, i64, i32, vp, vp, vp]
+        L.dd_cascade_split.restype = i32
+        L.dd_status_string.argtypes = [i32]
+        L.dd_status_string.restype = ctypes.c_char_p
+        L.dd_version.argtypes = []
+        L.dd_version.restype = i32
+        _lib = L
+    return _lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _opts(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, dd_gemm_opts):
+        return ctypes.byref(opts)
+    o = dd_gemm_opts()
+    for key, val in dict(opts).items():
+        setattr(o, key, int(val))
+    return ctypes.byref(o)
+
+
+# ------------------------------------------------------------ the C entry points
+def dd_status_string(status: int) -> str:
+    return lib().dd_status_string(int(status)).decode()
+
+
+def dd_version() -> int:
+    return int(lib().dd_version())
+
+
+def dd_gemm(m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc, stream=None) -> int:
+    return int(lib().dd_gemm(m, n, k, _ptr(A_hi), _ptr(A_lo), lda, _ptr(B_hi), _ptr(B_lo), ldb,
+                             _ptr(C_hi), _ptr(C_lo), ldc, _stream(stream)))
+
+
+def dd_gemm_workspace_size(transa, transb, m, n, k, opts=None) -> int:
+    return int(lib().dd_gemm_workspace_size(int(transa), int(transb), m, n, k, _opts(opts)))
+
+
+def dd_gemm_ex(transa, transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc,
+               workspace=None, ws_bytes=0, opts=None, stream=None) -> int:
+    return int(lib().dd_gemm_ex(int(transa), int(transb), m, n, k, _ptr(A_hi), _ptr(A_lo), lda,
+                                _ptr(B_hi), _ptr(B_lo), ldb, _ptr(C_hi), _ptr(C_lo), ldc,
+                                _ptr(workspace), int(ws_bytes), _opts(opts), _stream(stream)))
+
+
+def dd_cascade_split(side, trans, rows, cols, X_hi, X_lo, ldx, kc, exps, planes, stream=None) -> int:
+    return int(lib().dd_cascade_split(int(side), int(trans), rows, cols, _ptr(X_hi), _ptr(X_lo), ldx,
+                                      int(kc), _ptr(exps), _ptr(planes), _stream(stream)))
+
+
+def check(status: int, where: str = "ddgemm") -> None:
+    if status != DD_OK:
+        raise DDError(status, where)
+
+
+# ------------------------------------------------------------ layout helpers
+def colmajor_to_device(a, device="cuda"):
+    """numpy (rows x cols, any order) -> contiguous torch tensor (cols, rows) on ``device``."""
+    import numpy as np
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T)).to(device)
+
+
+def colmajor_from_device(t):
+    """Inverse of :func:`colmajor_to_device`: a Fortran-ordered numpy array."""
+    import numpy as np
+    return np.asfortranarray(t.detach().cpu().numpy().T)

@@ -1,0 +1,80 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and rejects invalid arguments on the host before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2303_04353_amd import ddgemm as dg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ddgemm.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_names():
+    assert set(declared_symbols()) == set(dg.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(dg.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_version():
+    assert dg.dd_version() >= 100
+    assert "success" in dg.dd_status_string(0)
+    assert "gfx950" in dg.dd_status_string(dg.DD_ERR_UNSUPPORTED)
+    assert "invalid" in dg.dd_status_string(-4)
+
+
+@pytest.mark.parametrize("args,want", [
+    ((-1, 2, 3, 0, 0, 1, 0, 0, 3, 0, 0, 1), -1),
+    ((2, -1, 3, 0, 0, 2, 0, 0, 3, 0, 0, 2), -2),
+    ((2, 2, -3, 0, 0, 2, 0, 0, 1, 0, 0, 2), -3),
+    ((4, 4, 4, 8, 8, 3, 16, 16, 4, 32, 40, 4), -6),     # lda < m
+    ((4, 4, 4, 8, 8, 4, 16, 16, 3, 32, 40, 4), -9),     # ldb < k
+    ((4, 4, 4, 8, 8, 4, 16, 16, 4, 32, 40, 3), -12),    # ldc < m
+    ((4, 4, 4, 0, 8, 4, 16, 16, 4, 1 << 30, 1 << 31, 4), -4),     # A_hi NULL
+    ((4, 4, 4, 8, 8, 4, 16, 16, 4, 0, 1 << 31, 4), -10),          # C_hi NULL
+    ((4, 4, 4, 8, 16, 4, 1 << 20, 1 << 21, 4, 8, 1 << 22, 4), -10),  # C_hi overlaps A_hi
+    ((4, 4, 4, 8, 16, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 22, 4), -11),  # C_lo overlaps C_hi
+])
+def test_invalid_arguments_rejected_on_host(args, want):
+    assert dg.dd_gemm(*args, stream=0) == want
+
+
+def test_ex_rejects_bad_ops_and_options():
+    base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
+    assert dg.dd_gemm_ex(2, 0, *base, stream=0) == -1
+    assert dg.dd_gemm_ex(0, 7, *base, stream=0) == -2
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"kc": 6}, stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"algo": 9}, stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"tile": 3}, stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, workspace=None, ws_bytes=64, stream=0) == -15
+
+
+def test_without_a_gpu_valid_calls_fail_cleanly():
+    # No device in this container: a valid call must return an error status,
+    # never crash or compute on the host.
+    base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
+    st = dg.dd_gemm(*base, stream=0)
+    if st != dg.DD_OK:
+        assert st in (dg.DD_ERR_HIP, dg.DD_ERR_UNSUPPORTED)
+
+
+def test_workspace_size_formula():
+    ws = dg.dd_gemm_workspace_size(0, 0, 100, 70, 300)
+    mpad, npad, kpad = 128, 128, 300
+    need = 8 * (mpad + npad) + 8 * 4 * mpad * kpad + 8 * 7 * npad * kpad
+    assert need <= ws <= need + 4 * 256
+    assert dg.dd_gemm_workspace_size(0, 0, 100, 70, 300, {"algo": dg.DD_ALGO_DD_VALU}) == 0
+    assert dg.dd_gemm_workspace_size(3, 0, 100, 70, 300) == 0
+    assert dg.dd_gemm_workspace_size(0, 0, 0, 70, 300) == 0

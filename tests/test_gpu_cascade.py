@@ -1,0 +1,222 @@
+"""GPU parity of the cascade (C ABI) against the oracle.
+
+* split planes and exponents: bit for bit against the oracle's Appendix A
+  split (one correct result: round-to-nearest-even, no free choice);
+* the cascaded product: against the oracle's cascade within the bound on a
+  different summation order of bin 3-6 (bins 0-2 are exact, so only that
+  order differs), and against the FP64x2 oracle within 64 k 2^-104 (|A||B|)_ij;
+* transposed storage gives bit-identical results (same packed planes);
+* worked example of Sec. 3.6, integer matrices, edge cases.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cascade as cz
+from oracle.ref import dd_gemm_ref, dd_gemm_ref_entries
+from paper_2303_04353_amd import ddgemm as dg
+from paper_2303_04353_amd.inputs import make_problem, sample_entries
+from tests.gpuhelp import (cascade_order_bound, dd_diff, down, log, north_star_bound, run_gemm, up)
+
+pytestmark = pytest.mark.gpu
+
+
+def _split_gpu(side, X, trans, kc):
+    import torch
+    hi, lo = X
+    rows, cols = (hi.shape[1], hi.shape[0]) if trans else hi.shape
+    nexp = rows if side == 0 else cols
+    npl = 4 if side == 0 else 7
+    exps = torch.zeros(max(nexp, 1), dtype=torch.int32, device="cuda")
+    planes = torch.zeros(npl * rows * cols, dtype=torch.float64, device="cuda")
+    st = dg.dd_cascade_split(side, int(trans), rows, cols, up(hi), up(lo), max(1, hi.shape[0]), kc,
+                             exps, planes)
+    dg.check(st, "dd_cascade_split")
+    torch.cuda.synchronize()
+    P = planes.cpu().numpy().reshape(npl, cols, rows)
+    return [np.asfortranarray(P[t].T) for t in range(npl)], exps.cpu().numpy()[:nexp]
+
+
+@pytest.mark.parametrize("shape", [(37, 50), (64, 256), (129, 300), (1, 1), (16, 5)])
+@pytest.mark.parametrize("variant", ["uniform", "ill"])
+@pytest.mark.parametrize("trans", [False, True])
+def test_split_planes_bitwise(shape, variant, trans):
+    rows, cols = shape
+    log(f"split side=0/1 shape={shape} variant={variant} trans={trans}")
+    P = make_problem(rows, cols, cols, cfg=10, variant=variant)
+    for side in (0, 1):
+        X = P["A"]
+        # the logical operand is rows x cols; store it transposed when trans
+        stored = (np.asfortranarray(X[0].T), np.asfortranarray(X[1].T)) if trans else X
+        kc = 256
+        kin = cols if side == 0 else rows
+        c = cz.split_widths(min(kc, kin))
+        if side == 0:
+            want, e = cz.cascade_A(X[0], X[1], c)
+        else:
+            want, e = cz.cascade_B(X[0], X[1], c)
+        got, ge = _split_gpu(side, stored, trans, kc)
+        assert np.array_equal(ge, e)
+        for t in range(len(want)):
+            assert np.array_equal(got[t].view(np.int64), np.asarray(want[t]).view(np.int64)), (side, t)
+
+
+CASES = [(128, 128, 128, "uniform", 256), (100, 70, 300, "uniform", 256), (65, 33, 17, "ill", 256),
+         (1, 1, 1, "uniform", 256), (200, 96, 520, "ill", 128), (64, 64, 1000, "uniform", 64),
+         (3, 130, 257, "uniform", 256)]
+
+
+@pytest.mark.parametrize("m,n,k,variant,kc", CASES)
+def test_cascade_matches_oracles(m, n, k, variant, kc):
+    log(f"cascade m={m} n={n} k={k} variant={variant} kc={kc}")
+    P = make_problem(m, n, k, cfg=11, variant=variant)
+    G = run_gemm(P["A"], P["B"], P["C"], kc=kc)
+    O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc)
+    assert np.all(dd_diff(G, O) <= cascade_order_bound(P["A"], P["B"], O, k, kc))
+    R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
+    assert np.all(dd_diff(G, R) <= north_star_bound(P["A"], P["B"], k))
+
+
+def test_plain_entry_point_equals_ex_default():
+    P = make_problem(96, 80, 300, cfg=12)
+    G1 = run_gemm(P["A"], P["B"], P["C"], plain=True)
+    G2 = run_gemm(P["A"], P["B"], P["C"])
+    assert np.array_equal(G1[0], G2[0]) and np.array_equal(G1[1], G2[1])
+
+
+@pytest.mark.parametrize("ta,tb", [(True, False), (False, True), (True, True)])
+def test_transposed_storage_is_bit_identical(ta, tb):
+    log(f"transposes ta={ta} tb={tb}")
+    P = make_problem(70, 90, 333, cfg=13)
+    A, B, C = P["A"], P["B"], P["C"]
+    G0 = run_gemm(A, B, C)
+    At = (np.asfortranarray(A[0].T), np.asfortranarray(A[1].T)) if ta else A
+    Bt = (np.asfortranarray(B[0].T), np.asfortranarray(B[1].T)) if tb else B
+    G1 = run_gemm(At, Bt, C, transa=ta, transb=tb)
+    assert np.array_equal(G0[0], G1[0]) and np.array_equal(G0[1], G1[1])
+
+
+def test_deterministic():
+    P = make_problem(130, 70, 600, cfg=14)
+    G1 = run_gemm(P["A"], P["B"], P["C"])
+    G2 = run_gemm(P["A"], P["B"], P["C"])
+    assert np.array_equal(G1[0], G2[0]) and np.array_equal(G1[1], G2[1])
+
+
+def test_worked_example_sec3_6_on_gpu():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_sec3_6.json")) as fh:
+        g = json.load(fh)
+    case = [c for c in g["cases"] if c["c"] is None][0]
+    hexm = lambda M: np.asfortranarray([[float.fromhex(v) for v in row] for row in M])
+    A = (hexm(case["A"]["hi"]), hexm(case["A"]["lo"]))
+    B = (hexm(case["B"]["hi"]), hexm(case["B"]["lo"]))
+    C = (np.zeros((1, 1), order="F"), np.zeros((1, 1), order="F"))
+    G = run_gemm(A, B, C)
+    assert G[0][0, 0] == float.fromhex(case["cascade_result"]["hi"])
+    assert G[1][0, 0] == float.fromhex(case["cascade_result"]["lo"])
+
+
+def test_integer_matrices_exact():
+    rng = np.random.default_rng(21)
+    m, n, k = 70, 50, 1500
+    A = np.asfortranarray(rng.integers(-2 ** 20, 2 ** 20 + 1, size=(m, k)).astype(float))
+    B = np.asfortranarray(rng.integers(-2 ** 20, 2 ** 20 + 1, size=(k, n)).astype(float))
+    z = lambda s: np.zeros(s, order="F")
+    G = run_gemm((A, z(A.shape)), (B, z(B.shape)), (z((m, n)), z((m, n))))
+    want = A.astype(object) @ B.astype(object)
+    assert np.all(G[0].astype(object) == want) and np.all(G[1] == 0)
+
+
+def test_k_zero_and_empty_are_noops():
+    import torch
+    P = make_problem(5, 4, 0, cfg=15)
+    G = run_gemm(P["A"], P["B"], P["C"])
+    assert np.array_equal(G[0], P["C"][0]) and np.array_equal(G[1], P["C"][1])
+    z = torch.zeros(1, dtype=torch.float64, device="cuda")
+    assert dg.dd_gemm(0, 5, 7, z, z, 1, z, z, 7, z, z, 1) == dg.DD_OK
+    assert dg.dd_gemm(5, 0, 7, z, z, 5, z, z, 7, z, z, 5) == dg.DD_OK
+
+
+def test_non_finite_rows_become_nan_only_there():
+    P = make_problem(20, 12, 40, cfg=16)
+    A = (P["A"][0].copy(order="F"), P["A"][1].copy(order="F"))
+    A[0][3, 7] = np.inf
+    A[0][11, 2] = np.nan
+    G = run_gemm(A, P["B"], P["C"])
+    bad = np.zeros(20, bool)
+    bad[[3, 11]] = True
+    assert np.all(np.isnan(G[0][bad]))
+    assert np.all(np.isfinite(G[0][~bad]))
+    R = dd_gemm_ref((A[0][~bad], A[1][~bad]), P["B"], (P["C"][0][~bad], P["C"][1][~bad]))[:2]
+    Ag = (A[0][~bad], A[1][~bad])
+    assert np.all(dd_diff((G[0][~bad], G[1][~bad]), R) <= north_star_bound(Ag, P["B"], 40))
+
+
+def test_workspace_variant_and_errors():
+    import torch
+    P = make_problem(90, 60, 200, cfg=17)
+    A, B, C = P["A"], P["B"], P["C"]
+    ws_bytes = dg.dd_gemm_workspace_size(0, 0, 90, 60, 200)
+    assert ws_bytes > 0
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    Ah, Al, Bh, Bl = up(A[0]), up(A[1]), up(B[0]), up(B[1])
+    Ch, Cl = up(C[0]), up(C[1])
+    st = dg.dd_gemm_ex(0, 0, 90, 60, 200, Ah, Al, 90, Bh, Bl, 200, Ch, Cl, 90, ws, ws_bytes)
+    dg.check(st)
+    torch.cuda.synchronize()
+    G0 = run_gemm(A, B, C)
+    assert np.array_equal(down(Ch), G0[0]) and np.array_equal(down(Cl), G0[1])
+    # too small a workspace is refused before any launch
+    assert dg.dd_gemm_ex(0, 0, 90, 60, 200, Ah, Al, 90, Bh, Bl, 200, Ch, Cl, 90, ws, 1024) == dg.DD_ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("m,n,k", [(128, 128, 128), (77, 45, 300), (1, 1, 1), (64, 3, 17)])
+@pytest.mark.parametrize("trans", [(False, False), (True, True)])
+def test_dd_valu_equals_fp64x2_oracle_bitwise(m, n, k, trans):
+    log(f"dd_valu m={m} n={n} k={k} trans={trans}")
+    P = make_problem(m, n, k, cfg=18)
+    A, B, C = P["A"], P["B"], P["C"]
+    ta, tb = trans
+    At = (np.asfortranarray(A[0].T), np.asfortranarray(A[1].T)) if ta else A
+    Bt = (np.asfortranarray(B[0].T), np.asfortranarray(B[1].T)) if tb else B
+    G = run_gemm(At, Bt, C, transa=ta, transb=tb, algo=dg.DD_ALGO_DD_VALU)
+    R = dd_gemm_ref(At, Bt, C, transa=ta, transb=tb)[:2]
+    assert np.array_equal(G[0], R[0]) and np.array_equal(G[1], R[1])
+
+
+def test_full_size_sampled_parity_8192():
+    """m = n = k = 8192 in the benchmark's launch configuration: sampled
+    entries against the FP64x2 oracle, all entries against the GPU
+    double-double kernel (itself bit-identical to the oracle at small sizes)."""
+    import torch
+    N = 8192
+    log("full size 8192: generating inputs")
+    P = make_problem(N, N, N, cfg=1, variant="uniform")
+    A, B, C = P["A"], P["B"], P["C"]
+    d = {key: (up(v[0]), up(v[1])) for key, v in P.items()}
+    Cc = (d["C"][0].clone(), d["C"][1].clone())
+    log("full size 8192: cascade")
+    dg.check(dg.dd_gemm(N, N, N, d["A"][0], d["A"][1], N, d["B"][0], d["B"][1], N, Cc[0], Cc[1], N))
+    torch.cuda.synchronize()
+    I, J = sample_entries(N, N, 512)
+    Gs = (Cc[0].T[I, J].cpu().numpy(), Cc[1].T[I, J].cpu().numpy())
+    log("full size 8192: oracle entries")
+    Rs = dd_gemm_ref_entries(A, B, C, I, J)[:2]
+    AB = np.array([np.abs(A[0][i]) @ np.abs(B[0][:, j]) for i, j in zip(I, J)])
+    assert np.all(dd_diff(Gs, Rs) <= 64 * N * 2.0 ** -104 * AB)
+    log("full size 8192: dd_valu")
+    Cv = (d["C"][0].clone(), d["C"][1].clone())
+    dg.check(dg.dd_gemm_ex(0, 0, N, N, N, d["A"][0], d["A"][1], N, d["B"][0], d["B"][1], N, Cv[0], Cv[1],
+                           N, opts={"algo": dg.DD_ALGO_DD_VALU}))
+    torch.cuda.synchronize()
+    Vs = (Cv[0].T[I, J].cpu().numpy(), Cv[1].T[I, J].cpu().numpy())
+    assert np.array_equal(Vs[0], Rs[0]) and np.array_equal(Vs[1], Rs[1])
+    # every entry: cascade vs double-double within the tolerance
+    absA = torch.abs(d["A"][0])
+    absB = torch.abs(d["B"][0])
+    ABfull = absB @ absA  # (|A||B|)^T in the transposed storage
+    diff = torch.abs((Cc[0] - Cv[0]) + (Cc[1] - Cv[1]))
+    assert bool(torch.all(diff <= 64 * N * 2.0 ** -104 * ABfull))
+    log("full size 8192: done")
