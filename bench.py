@@ -1,0 +1,209 @@
+"""Benchmark: cascaded FP64x2 GEMM C := A*B + C on one MI355X.
+
+One step = one ``dd_gemm`` over the whole hot path (row/column exponents,
+Appendix A split, ten FP64-MFMA products per rank-256 block, FP64x2 combine,
+Sigma/T and C added last) at m = n = k = 8192 on seeded synthetic FP64x2
+inputs (hi ~ U[-1, 1), lo = hi * 2^-53 * U[-1, 1)), resident in HBM.
+
+Prints ONE JSON line with the effective FP64x2 rate 2mnk/t, the fused
+product kernel against the FP64 matrix-core peak (timed live with HIP events
+on the GEMM's stream), the software double-double kernel on the same GPU and
+inputs, the max / median relative error against the FP64x2 oracle on sampled
+entries, and the oracle itself timed on this host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_MFMA_TFLOPS = 78.6   # MI355X, dense FP64 matrix
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=8192, help="m = n = k")
+    ap.add_argument("--variant", default="uniform", choices=["uniform", "ill"])
+    ap.add_argument("--oracle-seconds", type=float, default=15.0,
+                    help="CPU time budget of the sampled oracle run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with measured HBM bytes per launch of the product kernel")
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the GEMM shards over output tiles without communication; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2303_04353_amd import ddgemm as dg
+    from paper_2303_04353_amd.inputs import make_problem, sample_entries
+
+    torch.cuda.set_device(0)
+    dg.lib()  # fails loudly if the HIP library is missing
+    N = args.size
+    m = n = k = N
+    log(f"generating inputs m=n=k={N} variant={args.variant}")
+    P = make_problem(m, n, k, cfg=1, variant=args.variant)
+    dev = {key: (dg.colmajor_to_device(v[0]), dg.colmajor_to_device(v[1])) for key, v in P.items()}
+    Ah, Al = dev["A"]
+    Bh, Bl = dev["B"]
+    C0h, C0l = dev["C"]
+    Ch, Cl = C0h.clone(), C0l.clone()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        dg.check(dg.dd_gemm(m, n, k, Ah, Al, m, Bh, Bl, k, Ch, Cl, m, stream), "dd_gemm")
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    dg.dd_profile_enable(1)
+    dg.dd_phase_times()
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st, split_ms, prod_ms, calls = dg.dd_phase_times()
+    dg.dd_profile_enable(0)
+    dg.check(st, "dd_phase_times")
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    flops_eff = 2.0 * m * n * k
+    value = flops_eff / (ms_per_step * 1e-3) / 1e9
+    prod_avg_ms = prod_ms / max(calls, 1)
+    split_avg_ms = split_ms / max(calls, 1)
+    mfma_flops = 20.0 * m * n * k
+    achieved = mfma_flops / (prod_avg_ms * 1e-3) / 1e12
+    log(f"{ms_per_step:.2f} ms/step, {value:.1f} GFLOP/s effective; product kernel {prod_avg_ms:.2f} ms "
+        f"({achieved:.2f} TFLOP/s FP64 MFMA), phase one {split_avg_ms:.2f} ms")
+
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as fh:
+            tr = json.load(fh)
+        if tr.get("m") == m and tr.get("n") == n and tr.get("k") == k:
+            traffic = tr.get("bytes_per_launch")
+
+    # ---- accuracy on sampled entries: one more GEMM on a fresh copy of C
+    Ch.copy_(C0h)
+    Cl.copy_(C0l)
+    step()
+    torch.cuda.synchronize()
+    result = {
+        "metric": "effective FP64x2 GFLOP/s (2mnk/t) & % FP64 MFMA peak at 8192^3, max rel err vs oracle",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"FP64x2 GEMM C := A*B + C, m=n=k={N}, {args.variant} "
+                               "(hi ~ U[-1,1), lo = hi*2^-53*U[-1,1)), column-major hi/lo planes in HBM",
+                   "m": m, "n": n, "k": k, "kc": 256, "algo": "cascade_f64 (10 FP64 MFMA products)",
+                   "parallelism": "single GPU"},
+        "fp64_mfma_util_pct_of_peak": round(100.0 * (20.0 * m * n * k) / (ms_per_step * 1e-3) / 1e12
+                                            / PEAK_FP64_MFMA_TFLOPS, 2),
+        "phases_ms": {"split": round(split_avg_ms, 3), "product": round(prod_avg_ms, 3)},
+        "roofline": {"bound": "mfma", "kernel": "cascade_kernel",
+                     "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": traffic,
+                     "algorithmic": "20*m*n*k FP64 flops per launch (10 products)"},
+    }
+
+    I, J = sample_entries(m, n, 1 << 20, seed=7)
+    Gh = Ch.T[torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()].cpu().numpy()
+    Gl = Cl.T[torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()].cpu().numpy()
+
+    if not args.no_comparator:
+        log("software double-double kernel")
+        Vh, Vl = C0h.clone(), C0l.clone()
+        opts = {"algo": dg.DD_ALGO_DD_VALU}
+        dg.check(dg.dd_gemm_ex(0, 0, m, n, k, Ah, Al, m, Bh, Bl, k, Vh, Vl, m, opts=opts, stream=stream))
+        torch.cuda.synchronize()
+        Vh.copy_(C0h)
+        Vl.copy_(C0l)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        dg.check(dg.dd_gemm_ex(0, 0, m, n, k, Ah, Al, m, Bh, Bl, k, Vh, Vl, m, opts=opts, stream=stream))
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        vms = ev0.elapsed_time(ev1)
+        result["comparator"] = {"kernel": "dd_valu (software FP64x2 on FP64 VALU)",
+                                "ms": round(vms, 3), "value": round(flops_eff / (vms * 1e-3) / 1e9, 2),
+                                "unit": "GFLOP/s", "cascade_speedup": round(vms / ms_per_step, 3)}
+        Vs = (Vh.T[torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()].cpu().numpy(),
+              Vl.T[torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()].cpu().numpy())
+        del Vh, Vl
+
+    if not args.no_cpu_baseline:
+        from oracle.ref import dd_gemm_ref_entries  # CPU baseline leg only
+        A, B, C = P["A"], P["B"], P["C"]
+        probe = 2048
+        t = time.perf_counter()
+        dd_gemm_ref_entries(A, B, C, I[:probe], J[:probe])
+        dt = time.perf_counter() - t
+        S = int(min(len(I), max(probe, probe * args.oracle_seconds / max(dt, 1e-3))))
+        log(f"oracle on {S} sampled entries (~{args.oracle_seconds:.0f} s)")
+        t = time.perf_counter()
+        Rh, Rl, used = dd_gemm_ref_entries(A, B, C, I[:S], J[:S])
+        dt = time.perf_counter() - t
+        result["cpu_baseline"] = {
+            "value": round(2.0 * k * S / dt / 1e9, 4), "unit": "GFLOP/s", "cores": int(used),
+            "kind": "oracle",
+            "sample": f"{S} seeded output entries (i, j) of the same {N}^3 problem, each a full "
+                      f"length-{k} FP64x2 dot product plus C; {dt:.1f} s wall",
+            "projected_full_s": round(dt * (m * n) / S, 1)}
+        diff = np.abs((Gh[:S] - Rh) + (Gl[:S] - Rl))
+        denom = np.abs(Rh)
+        nz = denom > 0
+        rel = diff[nz] / denom[nz]
+        ABs = np.array([np.abs(A[0][i]) @ np.abs(B[0][:, j]) for i, j in zip(I[:min(S, 4096)], J[:min(S, 4096)])])
+        normed = diff[:len(ABs)] / ABs
+        result["accuracy"] = {
+            "sampled_entries": S, "max_rel_err": float(np.max(rel)), "median_rel_err": float(np.median(rel)),
+            "excluded_zero": int(np.sum(~nz)),
+            "max_err_over_absAabsB": float(np.max(normed)),
+            "tolerance_over_absAabsB": 64 * k * 2.0 ** -104,
+            "within_tolerance": bool(np.all(normed <= 64 * k * 2.0 ** -104))}
+        if "comparator" in result:
+            result["comparator"]["bitwise_equal_to_oracle_on_sample"] = bool(
+                np.array_equal(Vs[0][:S], Rh) and np.array_equal(Vs[1][:S], Rl))
+            vdiff = np.abs((Vs[0][:S] - Rh) + (Vs[1][:S] - Rl))
+            result["comparator"]["max_rel_err"] = float(np.max(vdiff[nz] / denom[nz]))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

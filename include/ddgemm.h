@@ -126,6 +126,20 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
                            int32_t kc, int32_t* exps, double* planes,
                            hipStream_t stream);
 
+/*
+ * Phase timing (Fig. breakdown of Sec. 5.1 measures the same split).  While
+ * enabled, every cascaded GEMM records HIP events on its own stream before
+ * phase one (exponents and split), between the phases, and after the fused
+ * product kernel (phases two and three).  dd_phase_times waits for those
+ * events and returns the milliseconds summed since the last call (or since
+ * enabling) and the number of GEMMs they cover, then starts a new sum.  Any
+ * pointer may be NULL.  Enabling costs two event records per call; it is
+ * meant for measurement, not production.  Not thread safe against
+ * concurrent GEMM calls.
+ */
+dd_status dd_profile_enable(int32_t enable);
+dd_status dd_phase_times(double* split_ms, double* product_ms, int64_t* calls);
+
 /* Short English description of a status code (static storage). */
 const char* dd_status_string(dd_status status);
 

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "../../include/ddgemm.h"
 #include "kernels.hpp"
@@ -67,6 +68,23 @@ dd_status cached_workspace(int dev, hipStream_t stream, size_t bytes, void** out
   }
   *out = b.ptr;
   return DD_OK;
+}
+
+// ------------------------------------------------------------ phase timing
+struct PhaseEvents { hipEvent_t e0, e1, e2; };
+bool g_prof = false;
+std::vector<PhaseEvents> g_prof_events;
+
+PhaseEvents prof_begin(hipStream_t s) {
+  PhaseEvents pe{nullptr, nullptr, nullptr};
+  if (!g_prof) return pe;
+  if (hipEventCreate(&pe.e0) != hipSuccess || hipEventCreate(&pe.e1) != hipSuccess ||
+      hipEventCreate(&pe.e2) != hipSuccess) {
+    (void)hipGetLastError();
+    return PhaseEvents{nullptr, nullptr, nullptr};
+  }
+  (void)hipEventRecord(pe.e0, s);
+  return pe;
 }
 
 // ------------------------------------------------------------ arguments
@@ -176,12 +194,20 @@ dd_status run(const Problem& p, int32_t algo, int32_t kc, void* workspace, size_
   } else if (ws_bytes < L.bytes || ((uintptr_t)ws & 255u) != 0) {
     return DD_ERR_WORKSPACE;
   }
+  PhaseEvents pe = prof_begin(s);
   st = run_split(p, L, ws, s);
   if (st != DD_OK) return st;
-  return hip_status(ddk::launch_cascade(L, (const double*)(ws + L.off_apack),
-                                        (const double*)(ws + L.off_bpack),
-                                        (const uint64_t*)(ws + L.off_amax),
-                                        (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, s));
+  if (pe.e1) (void)hipEventRecord(pe.e1, s);
+  st = hip_status(ddk::launch_cascade(L, (const double*)(ws + L.off_apack),
+                                      (const double*)(ws + L.off_bpack),
+                                      (const uint64_t*)(ws + L.off_amax),
+                                      (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, s));
+  if (pe.e2) {
+    (void)hipEventRecord(pe.e2, s);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof_events.push_back(pe);
+  }
+  return st;
 }
 
 }  // namespace
@@ -285,6 +311,37 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
     DD_TRY(ddk::launch_exps(bmax, n, exps, stream));
   }
   return DD_OK;
+}
+
+dd_status dd_profile_enable(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof = enable != 0;
+  return DD_OK;
+}
+
+dd_status dd_phase_times(double* split_ms, double* product_ms, int64_t* calls) {
+  std::vector<PhaseEvents> evs;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    evs.swap(g_prof_events);
+  }
+  double a = 0.0, b = 0.0;
+  dd_status st = DD_OK;
+  for (const PhaseEvents& pe : evs) {
+    float t1 = 0.f, t2 = 0.f;
+    if (hipEventSynchronize(pe.e2) != hipSuccess ||
+        hipEventElapsedTime(&t1, pe.e0, pe.e1) != hipSuccess ||
+        hipEventElapsedTime(&t2, pe.e1, pe.e2) != hipSuccess) st = DD_ERR_HIP;
+    a += t1;
+    b += t2;
+    (void)hipEventDestroy(pe.e0);
+    (void)hipEventDestroy(pe.e1);
+    (void)hipEventDestroy(pe.e2);
+  }
+  if (split_ms) *split_ms = a;
+  if (product_ms) *product_ms = b;
+  if (calls) *calls = (int64_t)evs.size();
+  return st;
 }
 
 const char* dd_status_string(dd_status s) {

@@ -28,7 +28,7 @@ DD_ALGO_CASCADE_F64 = 0
 DD_ALGO_DD_VALU = 1
 
 EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split",
-            "dd_status_string", "dd_version")
+            "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version")
 
 
 class dd_gemm_opts(ctypes.Structure):
@@ -63,6 +63,11 @@ def lib():
         L.dd_gemm_ex.restype = i32
         L.dd_cascade_split.argtypes = [i32, i32, i64, i64, vp, vp, i64, i32, vp, vp, vp]
         L.dd_cascade_split.restype = i32
+        L.dd_profile_enable.argtypes = [i32]
+        L.dd_profile_enable.restype = i32
+        L.dd_phase_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]
+        L.dd_phase_times.restype = i32
         L.dd_status_string.argtypes = [i32]
         L.dd_status_string.restype = ctypes.c_char_p
         L.dd_version.argtypes = []
@@ -127,6 +132,17 @@ def dd_gemm_ex(transa, transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, 
 def dd_cascade_split(side, trans, rows, cols, X_hi, X_lo, ldx, kc, exps, planes, stream=None) -> int:
     return int(lib().dd_cascade_split(int(side), int(trans), rows, cols, _ptr(X_hi), _ptr(X_lo), ldx,
                                       int(kc), _ptr(exps), _ptr(planes), _stream(stream)))
+
+
+def dd_profile_enable(enable) -> int:
+    return int(lib().dd_profile_enable(int(bool(enable))))
+
+
+def dd_phase_times():
+    """Returns ``(status, split_ms, product_ms, calls)`` summed since the last call."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    st = int(lib().dd_phase_times(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return st, a.value, b.value, int(c.value)
 
 
 def check(status: int, where: str = "ddgemm") -> None:
