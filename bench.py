@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--traffic", default=None,
                     help="JSON file with measured HBM bytes per launch of the product kernel")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain elementwise copy of MIB MiB (reads and writes that many "
+                         "bytes once), the reference for scaling HBM byte counters")
     return ap.parse_args()
 
 
@@ -103,6 +106,15 @@ def main():
     achieved = mfma_flops / (prod_avg_ms * 1e-3) / 1e12
     log(f"{ms_per_step:.2f} ms/step, {value:.1f} GFLOP/s effective; product kernel {prod_avg_ms:.2f} ms "
         f"({achieved:.2f} TFLOP/s FP64 MFMA), phase one {split_avg_ms:.2f} ms")
+
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nel * 8} bytes read and written by one elementwise kernel")
+        del src, dst
 
     traffic = None
     if args.traffic and os.path.exists(args.traffic):

@@ -38,21 +38,86 @@ struct Frags {
   double b[7][kWaveCB];   // plane, 16-column group
 };
 
-__device__ __forceinline__ void load_frags(Frags& f, const double* __restrict__ Abase,
-                                           const double* __restrict__ Bbase, int64_t q,
-                                           int64_t rbstride, int64_t cbstride) {
+// Operands of one group of 4 inner indices: A at Ap[r] + t*64 + s*16, B at
+// Bp[g] + t*64 (all offsets are immediates of the load instructions).
+__device__ __forceinline__ void load_frags(Frags& f, const double* const* Ap,
+                                           const double* const* Bp, int64_t q) {
 #pragma unroll
-  for (int r = 0; r < kWaveRB; ++r)
+  for (int r = 0; r < kWaveRB; ++r) {
+    const double* a = Ap[r] + q * (kFragA * kLanes);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-        f.a[t][r * 4 + s] = Abase[r * rbstride + q * (kFragA * kLanes) + t * kLanes + s * 16];
+      for (int s = 0; s < 4; ++s) f.a[t][r * 4 + s] = a[t * kLanes + s * 16];
+  }
 #pragma unroll
-  for (int g = 0; g < kWaveCB; ++g)
+  for (int g = 0; g < kWaveCB; ++g) {
+    const double* b = Bp[g] + q * (kFragB * kLanes);
 #pragma unroll
-    for (int t = 0; t < 7; ++t)
-      f.b[t][g] = Bbase[g * cbstride + q * (kFragB * kLanes) + t * kLanes];
+    for (int t = 0; t < 7; ++t) f.b[t][g] = b[t * kLanes];
+  }
+}
+
+struct Bins {
+  double b0[kSub][kWaveCB], b1[kSub][kWaveCB], b2[kSub][kWaveCB], b36[kSub][kWaveCB];
+};
+
+// The ten products of eq. (Gemm10) for one group of 4 inner indices.  Each
+// product is 16 independent MFMAs, so consecutive updates of one accumulator
+// are 16 instructions apart.
+__device__ __forceinline__ void ten_products(Bins& B, const Frags& f) {
+#define DD_PRODUCT(BIN, TA, TB)                                 \
+  _Pragma("unroll") for (int i = 0; i < kSub; ++i)              \
+  _Pragma("unroll") for (int g = 0; g < kWaveCB; ++g)           \
+      B.BIN[i][g] = mfma4(f.a[TA][i], f.b[TB][g], B.BIN[i][g]);
+  DD_PRODUCT(b0, 0, 0)
+  DD_PRODUCT(b1, 0, 1)
+  DD_PRODUCT(b1, 1, 0)
+  DD_PRODUCT(b2, 0, 2)
+  DD_PRODUCT(b2, 1, 1)
+  DD_PRODUCT(b2, 2, 0)
+  DD_PRODUCT(b36, 0, 3)
+  DD_PRODUCT(b36, 1, 4)
+  DD_PRODUCT(b36, 2, 5)
+  DD_PRODUCT(b36, 3, 6)
+#undef DD_PRODUCT
+}
+
+// bin0 + (bin1 + (bin2 + bin36)) in FP64x2, added to the accumulator; bins reset.
+__device__ __forceinline__ void combine(Bins& B, double (&acc_h)[kSub][kWaveCB],
+                                        double (&acc_l)[kSub][kWaveCB]) {
+#pragma unroll
+  for (int i = 0; i < kSub; ++i)
+#pragma unroll
+    for (int g = 0; g < kWaveCB; ++g) {
+      double s, e;
+      two_sum(B.b2[i][g], B.b36[i][g], s, e);
+      dd_add_d(s, e, B.b1[i][g], s, e);
+      dd_add_d(s, e, B.b0[i][g], s, e);
+      dd_add(acc_h[i][g], acc_l[i][g], s, e, acc_h[i][g], acc_l[i][g]);
+      B.b0[i][g] = B.b1[i][g] = B.b2[i][g] = B.b36[i][g] = 0.0;
+    }
+}
+
+// Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD b % 8)
+// and each XCD has its own L2.  Give every XCD a contiguous range of tiles
+// and walk that range in groups of kGroupM tile rows, so the workgroups that
+// run together on one XCD share a few A and B strips in its L2.
+constexpr int64_t kXcds = 8;
+constexpr int64_t kGroupM = 8;
+
+__device__ __forceinline__ void tile_of_block(int64_t b, int64_t tiles_m, int64_t tiles_n,
+                                              int64_t& tm, int64_t& tn) {
+  const int64_t T = tiles_m * tiles_n;
+  int64_t L = b;
+  if (T % kXcds == 0) L = (b % kXcds) * (T / kXcds) + b / kXcds;
+  const int64_t per_group = kGroupM * tiles_n;
+  const int64_t g = L / per_group;
+  const int64_t first_m = g * kGroupM;
+  const int64_t gm = tiles_m - first_m < kGroupM ? tiles_m - first_m : kGroupM;
+  const int64_t r = L - g * per_group;
+  tm = first_m + r % gm;
+  tn = r / gm;
 }
 
 }  // namespace
@@ -60,13 +125,13 @@ __device__ __forceinline__ void load_frags(Frags& f, const double* __restrict__ 
 __global__ void __launch_bounds__(256)
 cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpack,
                const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax,
-               int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_n,
+               int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_m, int64_t tiles_n,
                double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t tm = (int64_t)blockIdx.x / tiles_n;
-  const int64_t tn = (int64_t)blockIdx.x - tm * tiles_n;
+  int64_t tm, tn;
+  tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
   const int64_t rb0 = tm * 4 + wm * kWaveRB;   // first 16-row block of this wave
   const int64_t cb0 = tn * 4 + wn * kWaveCB;   // first 16-column group
 
@@ -74,58 +139,37 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
   const int64_t cbstride = K4 * (kFragB * kLanes);
   // A lane 16k + 4b + i reads position s*16 + k*4 + i of its sub-block (the
   // same for every MFMA block b); B lane l reads position l.
-  const double* Abase = Apack + rb0 * rbstride + (lane >> 4) * 4 + (lane & 3);
-  const double* Bbase = Bpack + cb0 * cbstride + lane;
+  const double* Ap[kWaveRB];
+  const double* Bp[kWaveCB];
+#pragma unroll
+  for (int r = 0; r < kWaveRB; ++r) Ap[r] = Apack + (rb0 + r) * rbstride + (lane >> 4) * 4 + (lane & 3);
+#pragma unroll
+  for (int g = 0; g < kWaveCB; ++g) Bp[g] = Bpack + (cb0 + g) * cbstride + lane;
 
-  double bin0[kSub][kWaveCB], bin1[kSub][kWaveCB], bin2[kSub][kWaveCB], bin36[kSub][kWaveCB];
+  Bins bins;
   double acc_h[kSub][kWaveCB], acc_l[kSub][kWaveCB];
 #pragma unroll
   for (int i = 0; i < kSub; ++i)
 #pragma unroll
     for (int g = 0; g < kWaveCB; ++g) {
-      bin0[i][g] = bin1[i][g] = bin2[i][g] = bin36[i][g] = 0.0;
+      bins.b0[i][g] = bins.b1[i][g] = bins.b2[i][g] = bins.b36[i][g] = 0.0;
       acc_h[i][g] = acc_l[i][g] = 0.0;
     }
 
-  Frags cur, nxt;
-  load_frags(cur, Abase, Bbase, 0, rbstride, cbstride);
+  // Two operand sets used alternately: the loads for one group of inner
+  // indices are in flight while the matrix cores work on the previous one.
+  Frags fx, fy;
+  load_frags(fx, Ap, Bp, 0);
   int32_t inblk = 0;
-  for (int64_t q = 0; q < K4; ++q) {
-    const int64_t qn = q + 1 < K4 ? q + 1 : q;
-    load_frags(nxt, Abase, Bbase, qn, rbstride, cbstride);
-
-#define DD_PRODUCT(BIN, TA, TB)                                                  \
-  _Pragma("unroll") for (int i = 0; i < kSub; ++i)                               \
-  _Pragma("unroll") for (int g = 0; g < kWaveCB; ++g)                            \
-      BIN[i][g] = mfma4(cur.a[TA][i], cur.b[TB][g], BIN[i][g]);
-    DD_PRODUCT(bin0, 0, 0)
-    DD_PRODUCT(bin1, 0, 1)
-    DD_PRODUCT(bin1, 1, 0)
-    DD_PRODUCT(bin2, 0, 2)
-    DD_PRODUCT(bin2, 1, 1)
-    DD_PRODUCT(bin2, 2, 0)
-    DD_PRODUCT(bin36, 0, 3)
-    DD_PRODUCT(bin36, 1, 4)
-    DD_PRODUCT(bin36, 2, 5)
-    DD_PRODUCT(bin36, 3, 6)
-#undef DD_PRODUCT
-
-    if (++inblk == kcq || q + 1 == K4) {
-      inblk = 0;
-      // bin0 + (bin1 + (bin2 + bin36)) in FP64x2, then into the accumulator
-#pragma unroll
-      for (int i = 0; i < kSub; ++i)
-#pragma unroll
-        for (int g = 0; g < kWaveCB; ++g) {
-          double s, e;
-          two_sum(bin2[i][g], bin36[i][g], s, e);
-          dd_add_d(s, e, bin1[i][g], s, e);
-          dd_add_d(s, e, bin0[i][g], s, e);
-          dd_add(acc_h[i][g], acc_l[i][g], s, e, acc_h[i][g], acc_l[i][g]);
-          bin0[i][g] = bin1[i][g] = bin2[i][g] = bin36[i][g] = 0.0;
-        }
-    }
-    cur = nxt;
+  for (int64_t q = 0; q < K4; q += 2) {
+    const bool two = q + 1 < K4;
+    load_frags(fy, Ap, Bp, two ? q + 1 : q);
+    ten_products(bins, fx);
+    if (++inblk == kcq || q + 1 == K4) { inblk = 0; combine(bins, acc_h, acc_l); }
+    if (!two) break;
+    load_frags(fx, Ap, Bp, q + 2 < K4 ? q + 2 : q + 1);
+    ten_products(bins, fy);
+    if (++inblk == kcq || q + 2 == K4) { inblk = 0; combine(bins, acc_h, acc_l); }
   }
 
   // Epilogue: D lane 16i + 4b + j of (sub-block, group) holds row 4*sub + i,
@@ -159,7 +203,7 @@ hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const dou
   const int64_t tiles = tiles_m * tiles_n;
   if (tiles <= 0 || tiles > 0x7fffffff) return hipErrorInvalidValue;
   cascade_kernel<<<(unsigned)tiles, 256, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
-                                                 tiles_n, Chi, Clo, ldc);
+                                                 tiles_m, tiles_n, Chi, Clo, ldc);
   return hipGetLastError();
 }
 
