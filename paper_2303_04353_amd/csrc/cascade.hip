@@ -11,8 +11,13 @@
 // all four MFMA blocks) by a 16-column group of B (four 4-column blocks).  A
 // wave therefore holds, per group of 4 inner indices, 8 A registers and
 // 2 B registers per plane, and 4 bins x 8 x 2 accumulator registers.
-// Operands stream from the packed planes in global memory (L2) straight into
-// registers, one group of 4 inner indices ahead of the matrix cores.
+// Operand staging: per LDS stage (2 groups of 4 inner indices) the
+// workgroup's 64 rows of A (4 planes) and 64 columns of B (5 stored planes)
+// are copied from the packed planes into LDS with global_load_lds_dwordx4
+// (each wave moves one 16-row block of A and one 16-column block of B), four
+// stages deep, so three stages are in flight while the matrix cores work on
+// one.  The copies are waited for with explicit vmcnt counts and a plain
+// s_barrier; waves then read their operands from LDS.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,16 +40,41 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
 
 struct Frags {
   double a[4][kSub];      // plane, 4-row sub-block
-  double b[7][kWaveCB];   // plane, 16-column group
+  double b[7][kWaveCB];   // plane B0'..B6', 16-column group
 };
 
-// Operands of one group of 4 inner indices: A at Ap[r] + t*64 + s*16, B at
-// Bp[g] + t*64 (all offsets are immediates of the load instructions).
-__device__ __forceinline__ void load_frags(Frags& f, const double* const* Ap,
-                                           const double* const* Bp, int64_t q) {
+// LDS stage: A [16-row block 0..3][group h][plane 4][64], B [16-col block][h][plane 5][64]
+constexpr int kStageQ = 2;                                 // groups of 4 inner indices per stage
+constexpr int kNStage = 4;                                 // stages resident in LDS
+constexpr int kAStage = 4 * kStageQ * kFragA * kLanes;     // doubles
+constexpr int kBStage = 4 * kStageQ * kFragB * kLanes;
+constexpr int kStage = kAStage + kBStage;                  // 36 KiB
+constexpr int kDmaA = kStageQ * kFragA * kLanes / 128;     // 1 KiB copies per wave per stage
+constexpr int kDmaB = kStageQ * kFragB * kLanes / 128;
+constexpr int kDmaPerStage = kDmaA + kDmaB;
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void dma_1k(const double* src, double* lds_dst) {
+  __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)lds_dst, 16, 0, 0);
+}
+
+// Waits until at most `ahead` stages of this wave's copies are outstanding.
+__device__ __forceinline__ void wait_stages(int ahead) {
+  static_assert(kNStage == 4 && kDmaPerStage == 9, "vmcnt immediates assume 4 stages of 9 copies");
+  if (ahead >= 2) asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
+  else if (ahead == 1) asm volatile("s_waitcnt vmcnt(9)" ::: "memory");
+  else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// Operands of group h of a stage, from LDS.  A register (sub-block i = 4r+s,
+// plane t) of lane 16k + 4b + i' holds position s*16 + k*4 + i' of its block.
+__device__ __forceinline__ void read_frags(Frags& f, const double* sA, const double* sB, int h) {
 #pragma unroll
   for (int r = 0; r < kWaveRB; ++r) {
-    const double* a = Ap[r] + q * (kFragA * kLanes);
+    const double* a = sA + (r * kStageQ + h) * (kFragA * kLanes);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -52,9 +82,14 @@ __device__ __forceinline__ void load_frags(Frags& f, const double* const* Ap,
   }
 #pragma unroll
   for (int g = 0; g < kWaveCB; ++g) {
-    const double* b = Bp[g] + q * (kFragB * kLanes);
-#pragma unroll
-    for (int t = 0; t < 7; ++t) f.b[t][g] = b[t * kLanes];
+    const double* b = sB + (g * kStageQ + h) * (kFragB * kLanes);
+    f.b[0][g] = b[0 * kLanes];
+    f.b[1][g] = b[1 * kLanes];
+    f.b[2][g] = b[2 * kLanes];
+    f.b[3][g] = b[3 * kLanes];
+    f.b[6][g] = b[4 * kLanes];
+    f.b[4][g] = f.b[2][g] + f.b[3][g];   // sigma_2 B4 = B2' + B3'
+    f.b[5][g] = f.b[1][g] + f.b[4][g];   // sigma_1 B5 = B1' + B2' + B3'
   }
 }
 
@@ -135,16 +170,7 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
   const int64_t rb0 = tm * 4 + wm * kWaveRB;   // first 16-row block of this wave
   const int64_t cb0 = tn * 4 + wn * kWaveCB;   // first 16-column group
 
-  const int64_t rbstride = K4 * (kFragA * kLanes);
-  const int64_t cbstride = K4 * (kFragB * kLanes);
-  // A lane 16k + 4b + i reads position s*16 + k*4 + i of its sub-block (the
-  // same for every MFMA block b); B lane l reads position l.
-  const double* Ap[kWaveRB];
-  const double* Bp[kWaveCB];
-#pragma unroll
-  for (int r = 0; r < kWaveRB; ++r) Ap[r] = Apack + (rb0 + r) * rbstride + (lane >> 4) * 4 + (lane & 3);
-#pragma unroll
-  for (int g = 0; g < kWaveCB; ++g) Bp[g] = Bpack + (cb0 + g) * cbstride + lane;
+  __shared__ __attribute__((aligned(16))) double lds[kNStage * kStage];
 
   Bins bins;
   double acc_h[kSub][kWaveCB], acc_l[kSub][kWaveCB];
@@ -156,21 +182,44 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
       acc_h[i][g] = acc_l[i][g] = 0.0;
     }
 
-  // Two operand sets used alternately: the loads for one group of inner
-  // indices are in flight while the matrix cores work on the previous one.
+  // This wave copies 16-row block tm*4 + wave of A and 16-column block
+  // tn*4 + wave of B; the packed planes of one block are contiguous over k.
+  const double* gA = Apack + ((tm * 4 + wave) * K4) * (kFragA * kLanes) + lane * 2;
+  const double* gB = Bpack + ((tn * 4 + wave) * K4) * (kFragB * kLanes) + lane * 2;
+  const int64_t nst = K4 / kStageQ;
+  auto issue = [&](int64_t st) {
+    double* dA = lds + (int)(st % kNStage) * kStage + wave * (kStageQ * kFragA * kLanes);
+    double* dB = lds + (int)(st % kNStage) * kStage + kAStage + wave * (kStageQ * kFragB * kLanes);
+    const double* sA = gA + st * (kStageQ * kFragA * kLanes);
+    const double* sB = gB + st * (kStageQ * kFragB * kLanes);
+#pragma unroll
+    for (int i = 0; i < kDmaA; ++i) dma_1k(sA + i * 128, dA + i * 128);
+#pragma unroll
+    for (int i = 0; i < kDmaB; ++i) dma_1k(sB + i * 128, dB + i * 128);
+  };
+#pragma unroll
+  for (int st = 0; st < kNStage - 1; ++st)
+    if (st < nst) issue(st);
+
   Frags fx, fy;
-  load_frags(fx, Ap, Bp, 0);
   int32_t inblk = 0;
-  for (int64_t q = 0; q < K4; q += 2) {
-    const bool two = q + 1 < K4;
-    load_frags(fy, Ap, Bp, two ? q + 1 : q);
+  for (int64_t st = 0; st < nst; ++st) {
+    const int64_t last = nst - 1;
+    wait_stages((int)((last - st) < (kNStage - 2) ? (last - st) : (kNStage - 2)));
+    lds_barrier();  // stage st is in LDS for every wave; stage st-1 is no longer read
+    if (st + kNStage - 1 < nst) issue(st + kNStage - 1);
+    const double* sA = lds + (int)(st % kNStage) * kStage + (wm * kWaveRB) * (kStageQ * kFragA * kLanes)
+                       + (lane >> 4) * 4 + (lane & 3);
+    const double* sB = lds + (int)(st % kNStage) * kStage + kAStage
+                       + (wn * kWaveCB) * (kStageQ * kFragB * kLanes) + lane;
+    read_frags(fx, sA, sB, 0);
+    read_frags(fy, sA, sB, 1);
     ten_products(bins, fx);
-    if (++inblk == kcq || q + 1 == K4) { inblk = 0; combine(bins, acc_h, acc_l); }
-    if (!two) break;
-    load_frags(fx, Ap, Bp, q + 2 < K4 ? q + 2 : q + 1);
+    if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
     ten_products(bins, fy);
-    if (++inblk == kcq || q + 2 == K4) { inblk = 0; combine(bins, acc_h, acc_l); }
+    if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
   }
+  if (inblk != 0) combine(bins, acc_h, acc_l);
 
   // Epilogue: D lane 16i + 4b + j of (sub-block, group) holds row 4*sub + i,
   // column 16*group + 4b + j, i.e. row lane/16 and column lane%16.

@@ -10,12 +10,15 @@
 //      index kk and row i sit at s*16 + kk*4 + i (16 values per 4-row
 //      sub-block, read by all four MFMA blocks at once):
 //        Apack[((rb*K4 + kq)*4 + t)*64 + s*16 + kk*4 + i]
-//   B: for each 16-column block cb, the seven planes B0'..B6', one 64-lane
-//      operand each (lane kk*16 + c holds inner index kk, column c):
-//        Bpack[((cb*K4 + kq)*7 + t)*64 + kk*16 + c]
+//   B: for each 16-column block cb, five planes B0', B1', B2', B3', B6' (in
+//      that order), one 64-lane operand each (lane kk*16 + c holds inner index
+//      kk, column c); B4' = B2' + B3' and B5' = B1' + B4' are formed where
+//      they are used, with the same two FP64 additions:
+//        Bpack[((cb*K4 + kq)*5 + t)*64 + kk*16 + c]
 // Rows/columns are padded with zeros up to the workgroup tile and the inner
-// dimension up to a multiple of 4, so the product kernel needs no bounds
-// checks in its main loop.
+// dimension up to a multiple of 8 (two groups of 4, one LDS stage of the
+// product kernel), so the product kernel needs no bounds checks in its main
+// loop.
 #pragma once
 
 #include <stddef.h>
@@ -24,7 +27,8 @@
 namespace ddk {
 
 constexpr int kFragA = 4;   // planes of op(A)
-constexpr int kFragB = 7;   // planes of op(B)
+constexpr int kFragB = 5;   // stored planes of op(B): B0', B1', B2', B3', B6'
+constexpr int kPlanesB = 7; // planes of op(B) in the products (with B4', B5')
 constexpr int kLanes = 64;
 
 struct CascadeLayout {
@@ -57,7 +61,7 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
   L.tile_m = tile_m; L.tile_n = tile_n;
   L.mpad = round_up(m > 0 ? m : 1, tile_m);
   L.npad = round_up(n > 0 ? n : 1, tile_n);
-  L.kpad = round_up(k > 0 ? k : 1, 4);
+  L.kpad = round_up(k > 0 ? k : 1, 8);
   L.K4 = L.kpad / 4;
   int64_t kce = k < kc ? k : kc;
   if (kce < 1) kce = 1;

@@ -109,19 +109,17 @@ pack_b(const double* __restrict__ Bhi, const double* __restrict__ Blo, int64_t s
   int lane = threadIdx.x & 63;
   int64_t cb = frag / K4, kq = frag - cb * K4;
   int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
-  double w[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (j < n && p < k) {
     SplitParams spar = make_params(c0, c1, c2);
     int64_t idx = p * sp_ + j * sj;
     double yh, yl;
     split_entry(Bhi[idx], Blo[idx], exp_of_bits(bmax[j]), spar, w, yh, yl);
-    w[4] = w[2] + w[3];   // sigma_2 B4 = B2' + B3'
-    w[5] = w[1] + w[4];   // sigma_1 B5 = B1' + B2' + B3'
-    w[6] = yh + yl;       // B6: the scaled entry itself, rounded once
+    w[4] = yh + yl;       // B6: the scaled entry itself, rounded once
   }
   double* dst = Bpack + frag * (kFragB * kLanes) + lane;
 #pragma unroll
-  for (int t = 0; t < 7; ++t) dst[t * kLanes] = w[t];
+  for (int t = 0; t < 5; ++t) dst[t * kLanes] = w[t];
 }
 
 // Plain planes from the packed layout (diagnostics).  side 0: element (i, p)
@@ -132,12 +130,27 @@ unpack_planes(const double* __restrict__ pack, int side, int64_t rows, int64_t c
   int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= rows * cols) return;
   int64_t r = idx % rows, cidx = idx / rows;
-  int nt = side == 0 ? kFragA : kFragB;
-  int64_t blk, q, kk, lanepos;
-  if (side == 0) { blk = r / 16; q = cidx / 4; kk = cidx % 4; lanepos = ((r % 16) / 4) * 16 + kk * 4 + (r % 4); }
-  else { blk = cidx / 16; q = r / 4; kk = r % 4; lanepos = kk * 16 + (cidx % 16); }
-  const double* src = pack + (blk * K4 + q) * (int64_t)(nt * kLanes) + lanepos;
-  for (int t = 0; t < nt; ++t) planes[(int64_t)t * rows * cols + idx] = src[t * kLanes];
+  const int64_t plane = rows * cols;
+  if (side == 0) {
+    int64_t blk = r / 16, q = cidx / 4, kk = cidx % 4;
+    int64_t lanepos = ((r % 16) / 4) * 16 + kk * 4 + (r % 4);
+    const double* src = pack + (blk * K4 + q) * (int64_t)(kFragA * kLanes) + lanepos;
+    for (int t = 0; t < kFragA; ++t) planes[t * plane + idx] = src[t * kLanes];
+  } else {
+    int64_t blk = cidx / 16, q = r / 4, kk = r % 4;
+    const double* src = pack + (blk * K4 + q) * (int64_t)(kFragB * kLanes) + kk * 16 + (cidx % 16);
+    double b[5];
+    for (int t = 0; t < kFragB; ++t) b[t] = src[t * kLanes];
+    const double b4 = b[2] + b[3];   // the same additions as the product kernel
+    const double b5 = b[1] + b4;
+    planes[0 * plane + idx] = b[0];
+    planes[1 * plane + idx] = b[1];
+    planes[2 * plane + idx] = b[2];
+    planes[3 * plane + idx] = b[3];
+    planes[4 * plane + idx] = b4;
+    planes[5 * plane + idx] = b5;
+    planes[6 * plane + idx] = b[4];
+  }
 }
 
 __global__ void exps_from_bits(const uint64_t* __restrict__ bits, int64_t n, int32_t* __restrict__ e) {
