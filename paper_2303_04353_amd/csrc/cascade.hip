@@ -163,7 +163,7 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
                int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_m, int64_t tiles_n,
                double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   int64_t tm, tn;
   tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
@@ -201,7 +201,7 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
   for (int st = 0; st < kNStage - 1; ++st)
     if (st < nst) issue(st);
 
-  Frags fx, fy;
+  Frags fx;
   int32_t inblk = 0;
   for (int64_t st = 0; st < nst; ++st) {
     const int64_t last = nst - 1;
@@ -212,12 +212,12 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
                        + (lane >> 4) * 4 + (lane & 3);
     const double* sB = lds + (int)(st % kNStage) * kStage + kAStage
                        + (wn * kWaveCB) * (kStageQ * kFragB * kLanes) + lane;
-    read_frags(fx, sA, sB, 0);
-    read_frags(fy, sA, sB, 1);
-    ten_products(bins, fx);
-    if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
-    ten_products(bins, fy);
-    if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
+#pragma unroll
+    for (int h = 0; h < kStageQ; ++h) {
+      read_frags(fx, sA, sB, h);
+      ten_products(bins, fx);
+      if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
+    }
   }
   if (inblk != 0) combine(bins, acc_h, acc_l);
 
