@@ -4,20 +4,24 @@
 // in FP64x2 from the least significant one (Sec. 3.3, 3.6), the rank-kc
 // results accumulated in FP64x2, Sigma and T applied and C added last.
 //
-// Work decomposition (gfx950): a workgroup of 4 waves owns a 64x64 tile of C,
-// each wave a 32x32 quarter.  The products use v_mfma_f64_4x4x4_4b_f64, which
-// runs at the full FP64 matrix rate on gfx950 (the 16x16x4 form does not):
-// one instruction multiplies a 4-row sub-block of A (the same 16 values in
-// all four MFMA blocks) by a 16-column group of B (four 4-column blocks).  A
-// wave therefore holds, per group of 4 inner indices, 8 A registers and
-// 2 B registers per plane, and 4 bins x 8 x 2 accumulator registers.
+// Work decomposition (gfx950): a workgroup of 8 waves (two per SIMD) owns a
+// 64x64 tile of C, each wave a 16x32 piece.  The products use
+// v_mfma_f64_4x4x4_4b_f64, which runs at the full FP64 matrix rate on gfx950
+// (the 16x16x4 form does not): one instruction multiplies a 4-row sub-block
+// of A (the same 16 values in all four MFMA blocks) by a 16-column group of B
+// (four 4-column blocks).  A wave holds, per group of 4 inner indices, 4 A
+// registers per plane and 2 B registers per plane, and 4 bins x 4 x 2
+// accumulator registers; with two waves per SIMD one wave's products cover
+// the other's LDS reads.
+//
 // Operand staging: per LDS stage (2 groups of 4 inner indices) the
 // workgroup's 64 rows of A (4 planes) and 64 columns of B (5 stored planes)
-// are copied from the packed planes into LDS with global_load_lds_dwordx4
-// (each wave moves one 16-row block of A and one 16-column block of B), four
-// stages deep, so three stages are in flight while the matrix cores work on
-// one.  The copies are waited for with explicit vmcnt counts and a plain
-// s_barrier; waves then read their operands from LDS.
+// are copied from the packed planes into LDS with global_load_lds_dwordx4,
+// 36 copies of 1 KiB dealt round robin to the 8 waves.  Four stage buffers
+// rotate, three stages in flight while one is multiplied.  Copies are waited
+// for with explicit vmcnt counts and a plain s_barrier.  FP64 vector work
+// does not overlap the matrix cores on gfx950, so the loop keeps vector
+// instructions to the two additions that form B4' and B5'.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,67 +33,82 @@ namespace ddk {
 
 namespace {
 
-constexpr int kWaveRB = 2;              // 16-row blocks per wave
+constexpr int kWaves = 8;               // waves per workgroup
 constexpr int kWaveCB = 2;              // 16-column groups per wave
-constexpr int kSub = 4 * kWaveRB;       // 4-row sub-blocks per wave
+constexpr int kSub = 4;                 // 4-row sub-blocks per wave (one 16-row block)
 constexpr int kTile = 64;               // workgroup tile (rows and columns)
+
+// LDS stage: A [16-row block 0..3][group h][plane 4][64], B [16-col block][h][plane 5][64]
+constexpr int kStageQ = 2;                                 // groups of 4 inner indices per stage
+constexpr int kNStage = 4;                                 // stage buffers in LDS
+constexpr int kAStage = 4 * kStageQ * kFragA * kLanes;     // doubles
+constexpr int kBStage = 4 * kStageQ * kFragB * kLanes;
+constexpr int kStage = kAStage + kBStage;                  // 36 KiB
+constexpr int kDmaA = 4 * kStageQ * kFragA * kLanes / 128; // 1 KiB copies per stage, A (16)
+constexpr int kDmaB = 4 * kStageQ * kFragB * kLanes / 128; // and B (20)
+constexpr int kDma = kDmaA + kDmaB;                        // 36, copy d goes to wave d % 8
+constexpr int kDmaHi = (kDma + kWaves - 1) / kWaves;       // copies of waves 0..3
+constexpr int kDmaLo = kDma / kWaves;                      // copies of waves 4..7
+static_assert(kDma % kWaves == 4 && kDmaHi == 5 && kDmaLo == 4, "copy split assumed below");
+
+typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-struct Frags {
-  double a[4][kSub];      // plane, 4-row sub-block
-  double b[7][kWaveCB];   // plane B0'..B6', 16-column group
-};
-
-// LDS stage: A [16-row block 0..3][group h][plane 4][64], B [16-col block][h][plane 5][64]
-constexpr int kStageQ = 2;                                 // groups of 4 inner indices per stage
-constexpr int kNStage = 4;                                 // stages resident in LDS
-constexpr int kAStage = 4 * kStageQ * kFragA * kLanes;     // doubles
-constexpr int kBStage = 4 * kStageQ * kFragB * kLanes;
-constexpr int kStage = kAStage + kBStage;                  // 36 KiB
-constexpr int kDmaA = kStageQ * kFragA * kLanes / 128;     // 1 KiB copies per wave per stage
-constexpr int kDmaB = kStageQ * kFragB * kLanes / 128;
-constexpr int kDmaPerStage = kDmaA + kDmaB;
-
-typedef __attribute__((address_space(3))) void lds_void;
-
 __device__ __forceinline__ void dma_1k(const double* src, double* lds_dst) {
   __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)lds_dst, 16, 0, 0);
 }
 
-// Waits until at most `ahead` stages of this wave's copies are outstanding.
-__device__ __forceinline__ void wait_stages(int ahead) {
-  static_assert(kNStage == 4 && kDmaPerStage == 9, "vmcnt immediates assume 4 stages of 9 copies");
-  if (ahead >= 2) asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
-  else if (ahead == 1) asm volatile("s_waitcnt vmcnt(9)" ::: "memory");
-  else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+// Waits until at most `ahead` stages of this wave's copies are outstanding
+// (vector memory operations complete in order); `hi` selects 5 or 4 copies
+// per stage.
+__device__ __forceinline__ void wait_stages(int ahead, bool hi) {
+  if (hi) {
+    if (ahead >= 3) asm volatile("s_waitcnt vmcnt(15)" ::: "memory");
+    else if (ahead == 2) asm volatile("s_waitcnt vmcnt(10)" ::: "memory");
+    else if (ahead == 1) asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  } else {
+    if (ahead >= 3) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+    else if (ahead == 2) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+    else if (ahead == 1) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
 }
 
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
-// Operands of group h of a stage, from LDS.  A register (sub-block i = 4r+s,
-// plane t) of lane 16k + 4b + i' holds position s*16 + k*4 + i' of its block.
-__device__ __forceinline__ void read_frags(Frags& f, const double* sA, const double* sB, int h) {
+// Operands of one group of 4 inner indices.  A register (sub-block s, plane
+// t) of lane 16k + 4b + i holds position s*16 + k*4 + i of the wave's 16-row
+// block; B registers hold the planes B0'..B6' (B4', B5' formed here).
+struct Ops {
+  double a[4][kSub];
+  double b[7][kWaveCB];
+};
+
+__device__ __forceinline__ void read_ops(Ops& o, const double* sA, const double* sB, int h) {
 #pragma unroll
-  for (int r = 0; r < kWaveRB; ++r) {
-    const double* a = sA + (r * kStageQ + h) * (kFragA * kLanes);
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) f.a[t][r * 4 + s] = a[t * kLanes + s * 16];
-  }
+    for (int s = 0; s < kSub; ++s) o.a[t][s] = sA[h * (kFragA * kLanes) + t * kLanes + s * 16];
 #pragma unroll
   for (int g = 0; g < kWaveCB; ++g) {
     const double* b = sB + (g * kStageQ + h) * (kFragB * kLanes);
-    f.b[0][g] = b[0 * kLanes];
-    f.b[1][g] = b[1 * kLanes];
-    f.b[2][g] = b[2 * kLanes];
-    f.b[3][g] = b[3 * kLanes];
-    f.b[6][g] = b[4 * kLanes];
-    f.b[4][g] = f.b[2][g] + f.b[3][g];   // sigma_2 B4 = B2' + B3'
-    f.b[5][g] = f.b[1][g] + f.b[4][g];   // sigma_1 B5 = B1' + B2' + B3'
+    o.b[0][g] = b[0 * kLanes];
+    o.b[1][g] = b[1 * kLanes];
+    o.b[2][g] = b[2 * kLanes];
+    o.b[3][g] = b[3 * kLanes];
+    o.b[6][g] = b[4 * kLanes];
+  }
+}
+
+__device__ __forceinline__ void derive_b(Ops& o) {
+#pragma unroll
+  for (int g = 0; g < kWaveCB; ++g) {
+    o.b[4][g] = o.b[2][g] + o.b[3][g];   // sigma_2 B4 = B2' + B3'
+    o.b[5][g] = o.b[1][g] + o.b[4][g];   // sigma_1 B5 = B1' + B2' + B3'
   }
 }
 
@@ -97,14 +116,13 @@ struct Bins {
   double b0[kSub][kWaveCB], b1[kSub][kWaveCB], b2[kSub][kWaveCB], b36[kSub][kWaveCB];
 };
 
-// The ten products of eq. (Gemm10) for one group of 4 inner indices.  Each
-// product is 16 independent MFMAs, so consecutive updates of one accumulator
-// are 16 instructions apart.
-__device__ __forceinline__ void ten_products(Bins& B, const Frags& f) {
+// The ten products of eq. (Gemm10) for one group of 4 inner indices; each
+// product is 8 independent MFMAs.
+__device__ __forceinline__ void ten_products(Bins& B, const Ops& o) {
 #define DD_PRODUCT(BIN, TA, TB)                                 \
   _Pragma("unroll") for (int i = 0; i < kSub; ++i)              \
   _Pragma("unroll") for (int g = 0; g < kWaveCB; ++g)           \
-      B.BIN[i][g] = mfma4(f.a[TA][i], f.b[TB][g], B.BIN[i][g]);
+      B.BIN[i][g] = mfma4(o.a[TA][i], o.b[TB][g], B.BIN[i][g]);
   DD_PRODUCT(b0, 0, 0)
   DD_PRODUCT(b1, 0, 1)
   DD_PRODUCT(b1, 1, 0)
@@ -155,22 +173,24 @@ __device__ __forceinline__ void tile_of_block(int64_t b, int64_t tiles_m, int64_
   tn = r / gm;
 }
 
+__device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+
 }  // namespace
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kWaves * 64)
 cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpack,
                const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax,
                int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_m, int64_t tiles_n,
                double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc) {
+  __shared__ __attribute__((aligned(16))) double lds[kNStage * kStage];
+
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave >> 1, wn = wave & 1;     // 16-row block wm, 32-column half wn
   int64_t tm, tn;
   tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  const int64_t rb0 = tm * 4 + wm * kWaveRB;   // first 16-row block of this wave
+  const int64_t rb0 = tm * 4 + wm;             // this wave's 16-row block
   const int64_t cb0 = tn * 4 + wn * kWaveCB;   // first 16-column group
-
-  __shared__ __attribute__((aligned(16))) double lds[kNStage * kStage];
 
   Bins bins;
   double acc_h[kSub][kWaveCB], acc_l[kSub][kWaveCB];
@@ -182,42 +202,65 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
       acc_h[i][g] = acc_l[i][g] = 0.0;
     }
 
-  // This wave copies 16-row block tm*4 + wave of A and 16-column block
-  // tn*4 + wave of B; the packed planes of one block are contiguous over k.
-  const double* gA = Apack + ((tm * 4 + wave) * K4) * (kFragA * kLanes) + lane * 2;
-  const double* gB = Bpack + ((tn * 4 + wave) * K4) * (kFragB * kLanes) + lane * 2;
+  // Copy d of a stage (d = wave, wave + 8, ...): d < 16 is chunk d%4 of
+  // 16-row block d/4 of A, otherwise chunk e%5 of 16-column block e/5 of B
+  // (e = d - 16).  The packed planes of one block are contiguous over k.
+  const bool hi = wave < (kDma % kWaves);
+  const int ncopy = hi ? kDmaHi : kDmaLo;
   const int64_t nst = K4 / kStageQ;
   auto issue = [&](int64_t st) {
-    double* dA = lds + (int)(st % kNStage) * kStage + wave * (kStageQ * kFragA * kLanes);
-    double* dB = lds + (int)(st % kNStage) * kStage + kAStage + wave * (kStageQ * kFragB * kLanes);
-    const double* sA = gA + st * (kStageQ * kFragA * kLanes);
-    const double* sB = gB + st * (kStageQ * kFragB * kLanes);
+    double* buf = lds + (int)(st % kNStage) * kStage;
 #pragma unroll
-    for (int i = 0; i < kDmaA; ++i) dma_1k(sA + i * 128, dA + i * 128);
-#pragma unroll
-    for (int i = 0; i < kDmaB; ++i) dma_1k(sB + i * 128, dB + i * 128);
+    for (int c = 0; c < kDmaHi; ++c) {
+      if (c == kDmaHi - 1 && !hi) break;
+      const int d = wave + c * kWaves;
+      const double* src;
+      double* dst;
+      if (d < kDmaA) {
+        const int blk = d >> 2, i = d & 3;
+        src = Apack + (((tm * 4 + blk) * K4) + st * kStageQ) * (kFragA * kLanes) + i * 128;
+        dst = buf + blk * (kStageQ * kFragA * kLanes) + i * 128;
+      } else {
+        const int e = d - kDmaA, blk = e / 5, i = e % 5;
+        src = Bpack + (((tn * 4 + blk) * K4) + st * kStageQ) * (kFragB * kLanes) + i * 128;
+        dst = buf + kAStage + blk * (kStageQ * kFragB * kLanes) + i * 128;
+      }
+      dma_1k(src + lane * 2, dst);
+    }
   };
+  (void)ncopy;
+
+  auto a_ptr = [&](int64_t st) {
+    return lds + (int)(st % kNStage) * kStage + wm * (kStageQ * kFragA * kLanes)
+           + (lane >> 4) * 4 + (lane & 3);
+  };
+  auto b_ptr = [&](int64_t st) {
+    return lds + (int)(st % kNStage) * kStage + kAStage + (wn * kWaveCB) * (kStageQ * kFragB * kLanes)
+           + lane;
+  };
+
+  // Prologue: stages 0..2 in flight.
 #pragma unroll
   for (int st = 0; st < kNStage - 1; ++st)
     if (st < nst) issue(st);
 
-  Frags fx;
   int32_t inblk = 0;
+  Ops ox, oy;
   for (int64_t st = 0; st < nst; ++st) {
     const int64_t last = nst - 1;
-    wait_stages((int)((last - st) < (kNStage - 2) ? (last - st) : (kNStage - 2)));
+    wait_stages((int)(last - st < kNStage - 2 ? last - st : kNStage - 2), hi);
     lds_barrier();  // stage st is in LDS for every wave; stage st-1 is no longer read
     if (st + kNStage - 1 < nst) issue(st + kNStage - 1);
-    const double* sA = lds + (int)(st % kNStage) * kStage + (wm * kWaveRB) * (kStageQ * kFragA * kLanes)
-                       + (lane >> 4) * 4 + (lane & 3);
-    const double* sB = lds + (int)(st % kNStage) * kStage + kAStage
-                       + (wn * kWaveCB) * (kStageQ * kFragB * kLanes) + lane;
-#pragma unroll
-    for (int h = 0; h < kStageQ; ++h) {
-      read_frags(fx, sA, sB, h);
-      ten_products(bins, fx);
-      if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
-    }
+    const double* sA = a_ptr(st);
+    const double* sB = b_ptr(st);
+    read_ops(ox, sA, sB, 0);
+    read_ops(oy, sA, sB, 1);
+    derive_b(ox);
+    ten_products(bins, ox);
+    if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
+    derive_b(oy);
+    ten_products(bins, oy);
+    if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
   }
   if (inblk != 0) combine(bins, acc_h, acc_l);
 
@@ -247,11 +290,11 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
 hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,
                           const uint64_t* amax, const uint64_t* bmax,
                           double* Chi, double* Clo, int64_t ldc, hipStream_t s) {
-  if (L.tile_m != kTile || L.tile_n != kTile) return hipErrorInvalidValue;
+  if (L.tile_m != kTile || L.tile_n != kTile || L.K4 % kStageQ != 0) return hipErrorInvalidValue;
   const int64_t tiles_m = L.mpad / kTile, tiles_n = L.npad / kTile;
   const int64_t tiles = tiles_m * tiles_n;
   if (tiles <= 0 || tiles > 0x7fffffff) return hipErrorInvalidValue;
-  cascade_kernel<<<(unsigned)tiles, 256, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
+  cascade_kernel<<<(unsigned)tiles, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
                                                  tiles_m, tiles_n, Chi, Clo, ldc);
   return hipGetLastError();
 }
