@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size", type=int, default=8192, help="m = n = k")
+    ap.add_argument("--shape", default=None, metavar="M,N,K",
+                    help="time another shape instead (exploration; not the headline workload)")
     ap.add_argument("--variant", default="uniform", choices=["uniform", "ill"])
     ap.add_argument("--oracle-seconds", type=float, default=15.0,
                     help="CPU time budget of the sampled oracle run")
@@ -69,7 +71,9 @@ def main():
     dg.lib()  # fails loudly if the HIP library is missing
     N = args.size
     m = n = k = N
-    log(f"generating inputs m=n=k={N} variant={args.variant}")
+    if args.shape:
+        m, n, k = (int(v) for v in args.shape.split(","))
+    log(f"generating inputs m={m} n={n} k={k} variant={args.variant}")
     P = make_problem(m, n, k, cfg=1, variant=args.variant)
     dev = {key: (dg.colmajor_to_device(v[0]), dg.colmajor_to_device(v[1])) for key, v in P.items()}
     Ah, Al = dev["A"]
@@ -141,7 +145,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"FP64x2 GEMM C := A*B + C, m=n=k={N}, {args.variant} "
+        "config": {"workload": f"FP64x2 GEMM C := A*B + C, m={m} n={n} k={k}, {args.variant} "
                                "(hi ~ U[-1,1), lo = hi*2^-53*U[-1,1)), column-major hi/lo planes in HBM",
                    "m": m, "n": n, "k": k, "kc": 256, "algo": "cascade_f64 (10 FP64 MFMA products)",
                    "parallelism": "single GPU"},
@@ -194,7 +198,7 @@ def main():
         result["cpu_baseline"] = {
             "value": round(2.0 * k * S / dt / 1e9, 4), "unit": "GFLOP/s", "cores": int(used),
             "kind": "oracle",
-            "sample": f"{S} seeded output entries (i, j) of the same {N}^3 problem, each a full "
+            "sample": f"{S} seeded output entries (i, j) of the same {m}x{n}x{k} problem, each a full "
                       f"length-{k} FP64x2 dot product plus C; {dt:.1f} s wall",
             "projected_full_s": round(dt * (m * n) / S, 1)}
         diff = np.abs((Gh[:S] - Rh) + (Gl[:S] - Rl))

@@ -15,13 +15,17 @@
 // the other's LDS reads.
 //
 // Operand staging: per LDS stage (2 groups of 4 inner indices) the
-// workgroup's 64 rows of A (4 planes) and 64 columns of B (5 stored planes)
-// are copied from the packed planes into LDS with global_load_lds_dwordx4,
-// 36 copies of 1 KiB dealt round robin to the 8 waves.  Four stage buffers
-// rotate, three stages in flight while one is multiplied.  Copies are waited
-// for with explicit vmcnt counts and a plain s_barrier.  FP64 vector work
-// does not overlap the matrix cores on gfx950, so the loop keeps vector
-// instructions to the two additions that form B4' and B5'.
+// workgroup's 64 rows of A (4 planes) and 64 columns of B (5 stored planes),
+// 36 KiB, are loaded from the packed planes into registers (16-byte loads,
+// 36 pieces of 1 KiB dealt round robin to the 8 waves) one stage ahead, then
+// written to the other of two LDS buffers; one barrier per stage.  (Direct
+// global-to-LDS copies would save the registers, but their completion is
+// tracked with the LDS counter as well, so every wait for an operand read
+// would also wait for the copies in flight.)  Waves read their operands from
+// LDS; the reads of the next group are spread over the current group's
+// MFMAs.  FP64 vector work does not overlap the matrix cores on gfx950, so
+// the loop keeps vector instructions to the two additions that form B4' and
+// B5'.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -40,45 +44,34 @@ constexpr int kTile = 64;               // workgroup tile (rows and columns)
 
 // LDS stage: A [16-row block 0..3][group h][plane 4][64], B [16-col block][h][plane 5][64]
 constexpr int kStageQ = 2;                                 // groups of 4 inner indices per stage
-constexpr int kNStage = 4;                                 // stage buffers in LDS
+constexpr int kNBuf = 2;                                   // stage buffers in LDS
 constexpr int kAStage = 4 * kStageQ * kFragA * kLanes;     // doubles
 constexpr int kBStage = 4 * kStageQ * kFragB * kLanes;
 constexpr int kStage = kAStage + kBStage;                  // 36 KiB
-constexpr int kDmaA = 4 * kStageQ * kFragA * kLanes / 128; // 1 KiB copies per stage, A (16)
-constexpr int kDmaB = 4 * kStageQ * kFragB * kLanes / 128; // and B (20)
-constexpr int kDma = kDmaA + kDmaB;                        // 36, copy d goes to wave d % 8
-constexpr int kDmaHi = (kDma + kWaves - 1) / kWaves;       // copies of waves 0..3
-constexpr int kDmaLo = kDma / kWaves;                      // copies of waves 4..7
-static_assert(kDma % kWaves == 4 && kDmaHi == 5 && kDmaLo == 4, "copy split assumed below");
+constexpr int kPieceA = 4 * kStageQ * kFragA * kLanes / 128; // 1 KiB pieces per stage, A (16)
+constexpr int kPieceB = 4 * kStageQ * kFragB * kLanes / 128; // and B (20)
+constexpr int kPieces = kPieceA + kPieceB;                   // 36, piece d goes to wave d % 8
+constexpr int kPiecesMax = (kPieces + kWaves - 1) / kWaves;  // 5 (waves 0..3; waves 4..7 take 4)
 
-typedef __attribute__((address_space(3))) void lds_void;
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ void dma_1k(const double* src, double* lds_dst) {
-  __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)lds_dst, 16, 0, 0);
-}
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
+__device__ __forceinline__ void lds_reads_done() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-// Waits until at most `ahead` stages of this wave's copies are outstanding
-// (vector memory operations complete in order); `hi` selects 5 or 4 copies
-// per stage.
-__device__ __forceinline__ void wait_stages(int ahead, bool hi) {
-  if (hi) {
-    if (ahead >= 3) asm volatile("s_waitcnt vmcnt(15)" ::: "memory");
-    else if (ahead == 2) asm volatile("s_waitcnt vmcnt(10)" ::: "memory");
-    else if (ahead == 1) asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  } else {
-    if (ahead >= 3) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
-    else if (ahead == 2) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
-    else if (ahead == 1) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+// Ask the scheduler to spread the LDS reads of the next operand set (13
+// two-word reads) over the 80 MFMAs of the current set: one read, then six
+// MFMAs, repeated.
+__device__ __forceinline__ void interleave_reads() {
+#pragma unroll
+  for (int i = 0; i < 13; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
+    __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);   // MFMA
   }
 }
-
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
 // Operands of one group of 4 inner indices.  A register (sub-block s, plane
 // t) of lane 16k + 4b + i holds position s*16 + k*4 + i of the wave's 16-row
@@ -117,22 +110,24 @@ struct Bins {
 };
 
 // The ten products of eq. (Gemm10) for one group of 4 inner indices; each
-// product is 8 independent MFMAs.
+// product is 8 independent MFMAs.  The products are ordered so that no two
+// consecutive ones update the same bin: an MFMA then depends on one issued at
+// least 16 instructions earlier, which keeps the matrix core busy.
 __device__ __forceinline__ void ten_products(Bins& B, const Ops& o) {
 #define DD_PRODUCT(BIN, TA, TB)                                 \
   _Pragma("unroll") for (int i = 0; i < kSub; ++i)              \
   _Pragma("unroll") for (int g = 0; g < kWaveCB; ++g)           \
       B.BIN[i][g] = mfma4(o.a[TA][i], o.b[TB][g], B.BIN[i][g]);
-  DD_PRODUCT(b0, 0, 0)
-  DD_PRODUCT(b1, 0, 1)
-  DD_PRODUCT(b1, 1, 0)
-  DD_PRODUCT(b2, 0, 2)
-  DD_PRODUCT(b2, 1, 1)
-  DD_PRODUCT(b2, 2, 0)
   DD_PRODUCT(b36, 0, 3)
+  DD_PRODUCT(b2, 0, 2)
   DD_PRODUCT(b36, 1, 4)
+  DD_PRODUCT(b2, 1, 1)
   DD_PRODUCT(b36, 2, 5)
+  DD_PRODUCT(b1, 0, 1)
   DD_PRODUCT(b36, 3, 6)
+  DD_PRODUCT(b1, 1, 0)
+  DD_PRODUCT(b2, 2, 0)
+  DD_PRODUCT(b0, 0, 0)
 #undef DD_PRODUCT
 }
 
@@ -182,7 +177,7 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
                const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax,
                int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_m, int64_t tiles_n,
                double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc) {
-  __shared__ __attribute__((aligned(16))) double lds[kNStage * kStage];
+  __shared__ __attribute__((aligned(16))) double lds[kNBuf * kStage];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -202,64 +197,85 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
       acc_h[i][g] = acc_l[i][g] = 0.0;
     }
 
-  // Copy d of a stage (d = wave, wave + 8, ...): d < 16 is chunk d%4 of
+  // Piece d of a stage (d = wave, wave + 8, ...): d < 16 is chunk d%4 of
   // 16-row block d/4 of A, otherwise chunk e%5 of 16-column block e/5 of B
   // (e = d - 16).  The packed planes of one block are contiguous over k.
-  const bool hi = wave < (kDma % kWaves);
-  const int ncopy = hi ? kDmaHi : kDmaLo;
-  const int64_t nst = K4 / kStageQ;
-  auto issue = [&](int64_t st) {
-    double* buf = lds + (int)(st % kNStage) * kStage;
+  const int npiece = wave < (kPieces % kWaves) ? kPiecesMax : kPiecesMax - 1;
+  const double* psrc[kPiecesMax];
+  int pdst[kPiecesMax];
 #pragma unroll
-    for (int c = 0; c < kDmaHi; ++c) {
-      if (c == kDmaHi - 1 && !hi) break;
-      const int d = wave + c * kWaves;
-      const double* src;
-      double* dst;
-      if (d < kDmaA) {
-        const int blk = d >> 2, i = d & 3;
-        src = Apack + (((tm * 4 + blk) * K4) + st * kStageQ) * (kFragA * kLanes) + i * 128;
-        dst = buf + blk * (kStageQ * kFragA * kLanes) + i * 128;
-      } else {
-        const int e = d - kDmaA, blk = e / 5, i = e % 5;
-        src = Bpack + (((tn * 4 + blk) * K4) + st * kStageQ) * (kFragB * kLanes) + i * 128;
-        dst = buf + kAStage + blk * (kStageQ * kFragB * kLanes) + i * 128;
+  for (int c = 0; c < kPiecesMax; ++c) {
+    const int d = c < npiece ? wave + c * kWaves : wave;   // unused slots repeat piece 0
+    if (d < kPieceA) {
+      const int blk = d >> 2, i = d & 3;
+      psrc[c] = Apack + ((tm * 4 + blk) * K4) * (kFragA * kLanes) + i * 128 + lane * 2;
+      pdst[c] = blk * (kStageQ * kFragA * kLanes) + i * 128 + lane * 2;
+    } else {
+      const int e = d - kPieceA, blk = e / 5, i = e % 5;
+      psrc[c] = Bpack + ((tn * 4 + blk) * K4) * (kFragB * kLanes) + i * 128 + lane * 2;
+      pdst[c] = kAStage + blk * (kStageQ * kFragB * kLanes) + i * 128 + lane * 2;
+    }
+  }
+  const int64_t strideA = kStageQ * kFragA * kLanes, strideB = kStageQ * kFragB * kLanes;
+  d2 stg[kPiecesMax];
+  auto load_stage = [&](int64_t st) {
+#pragma unroll
+    for (int c = 0; c < kPiecesMax; ++c) {
+      if (c < npiece) {
+        const bool isA = pdst[c] < kAStage;
+        stg[c] = *(const d2*)(psrc[c] + st * (isA ? strideA : strideB));
       }
-      dma_1k(src + lane * 2, dst);
     }
   };
-  (void)ncopy;
+  auto store_stage = [&](int64_t st) {
+    double* buf = lds + (int)(st % kNBuf) * kStage;
+#pragma unroll
+    for (int c = 0; c < kPiecesMax; ++c)
+      if (c < npiece) *(d2*)(buf + pdst[c]) = stg[c];
+  };
 
   auto a_ptr = [&](int64_t st) {
-    return lds + (int)(st % kNStage) * kStage + wm * (kStageQ * kFragA * kLanes)
+    return lds + (int)(st % kNBuf) * kStage + wm * (kStageQ * kFragA * kLanes)
            + (lane >> 4) * 4 + (lane & 3);
   };
   auto b_ptr = [&](int64_t st) {
-    return lds + (int)(st % kNStage) * kStage + kAStage + (wn * kWaveCB) * (kStageQ * kFragB * kLanes)
+    return lds + (int)(st % kNBuf) * kStage + kAStage + (wn * kWaveCB) * (kStageQ * kFragB * kLanes)
            + lane;
   };
 
-  // Prologue: stages 0..2 in flight.
-#pragma unroll
-  for (int st = 0; st < kNStage - 1; ++st)
-    if (st < nst) issue(st);
-
-  int32_t inblk = 0;
+  // Prologue: stage 0 into LDS, stage 1 into the staging registers.
+  const int64_t nst = K4 / kStageQ;
+  load_stage(0);
+  store_stage(0);
+  if (nst > 1) load_stage(1);
+  lds_reads_done();
+  lds_barrier();
   Ops ox, oy;
+  read_ops(ox, a_ptr(0), b_ptr(0), 0);
+
+  // Per stage st: the products of group 0 (ox) run while group 1 is read
+  // into oy; the staged stage st+1 is written to the other buffer (last read
+  // during stage st-1) and the loads of stage st+2 are issued; after the
+  // barrier the products of group 1 run while group 0 of stage st+1 is read
+  // into ox.
+  int32_t inblk = 0;
   for (int64_t st = 0; st < nst; ++st) {
     const int64_t last = nst - 1;
-    wait_stages((int)(last - st < kNStage - 2 ? last - st : kNStage - 2), hi);
-    lds_barrier();  // stage st is in LDS for every wave; stage st-1 is no longer read
-    if (st + kNStage - 1 < nst) issue(st + kNStage - 1);
-    const double* sA = a_ptr(st);
-    const double* sB = b_ptr(st);
-    read_ops(ox, sA, sB, 0);
-    read_ops(oy, sA, sB, 1);
+    read_ops(oy, a_ptr(st), b_ptr(st), 1);
     derive_b(ox);
     ten_products(bins, ox);
+    interleave_reads();
     if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
     derive_b(oy);
+    if (st < last) {
+      store_stage(st + 1);
+      if (st + 2 <= last) load_stage(st + 2);
+      lds_reads_done();
+      lds_barrier();
+      read_ops(ox, a_ptr(st + 1), b_ptr(st + 1), 0);
+    }
     ten_products(bins, oy);
+    interleave_reads();
     if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
   }
   if (inblk != 0) combine(bins, acc_h, acc_l);
