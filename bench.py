@@ -42,8 +42,9 @@ def parse():
                     help="CPU time budget of the sampled oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with measured HBM bytes per launch of the product kernel")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "cascade_kernel_8192_traffic.json"),
+                    help="JSON file with measured HBM bytes per launch of the product kernel "
+                         "(used only while the kernel source is unchanged since the measurement)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy of MIB MiB (reads and writes that many "
                          "bytes once), the reference for scaling HBM byte counters")
@@ -120,12 +121,8 @@ def main():
         log(f"copy calibration: {nel * 8} bytes read and written by one elementwise kernel")
         del src, dst
 
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as fh:
-            tr = json.load(fh)
-        if tr.get("m") == m and tr.get("n") == n and tr.get("k") == k:
-            traffic = tr.get("bytes_per_launch")
+    from paper_2303_04353_amd.profiling import load_traffic
+    traffic = load_traffic(args.traffic, m, n, k)
 
     # ---- accuracy on sampled entries: one more GEMM on a fresh copy of C
     Ch.copy_(C0h)
@@ -154,8 +151,10 @@ def main():
         "phases_ms": {"split": round(split_avg_ms, 3), "product": round(prod_avg_ms, 3)},
         "roofline": {"bound": "mfma", "kernel": "cascade_kernel",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": traffic,
-                     "algorithmic": "20*m*n*k FP64 flops per launch (10 products)"},
+                     "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "algorithmic": "20*m*n*k FP64 flops per launch (10 products)",
+                     "algorithmic_bytes": (4 + 5) * 8 * (m * k + k * n) + 32 * m * n},
     }
 
     I, J = sample_entries(m, n, 1 << 20, seed=7)
