@@ -127,6 +127,28 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
                            hipStream_t stream);
 
 /*
+ * FP64x2 dot product: result[0] + result[1] = sum_i x_i y_i, computed in
+ * double-double arithmetic (each product by TwoProd with FMA plus the two
+ * cross terms, sums by the accurate FP64x2 addition, a fixed reduction tree:
+ * the result does not change between runs).  x and y are FP64x2 vectors of
+ * n entries with strides incx, incy >= 1 (elements); `result` is device
+ * memory for two doubles, written (not accumulated).  Uses the library's
+ * cached per-stream scratch of 16 KiB.  n = 0 gives 0.
+ */
+dd_status dd_dot(int64_t n, const double* x_hi, const double* x_lo, int64_t incx,
+                 const double* y_hi, const double* y_lo, int64_t incy,
+                 double* result, hipStream_t stream);
+
+/*
+ * y := alpha * x in FP64x2 (alpha = alpha_hi + alpha_lo given on the host),
+ * entry by entry with the double-double product.  y may equal x (same
+ * pointers and stride); otherwise they must not overlap.
+ */
+dd_status dd_scal(int64_t n, double alpha_hi, double alpha_lo,
+                  const double* x_hi, const double* x_lo, int64_t incx,
+                  double* y_hi, double* y_lo, int64_t incy, hipStream_t stream);
+
+/*
  * Phase timing (Fig. breakdown of Sec. 5.1 measures the same split).  While
  * enabled, every cascaded GEMM records HIP events on its own stream before
  * phase one (exponents and split), between the phases, and after the fused

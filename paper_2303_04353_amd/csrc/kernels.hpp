@@ -33,4 +33,13 @@ hipError_t launch_dd_valu(int64_t m, int64_t n, int64_t k,
                           const double* Bhi, const double* Blo, int64_t b_sp, int64_t b_sj,
                           double* Chi, double* Clo, int64_t ldc, hipStream_t s);
 
+// FP64x2 dot product (two passes; `part` holds 2*dd_dot_blocks(n) doubles)
+// and scaling y = alpha x.
+int dd_dot_blocks(int64_t n);
+hipError_t launch_dd_dot(int64_t n, const double* xh, const double* xl, int64_t incx,
+                         const double* yh, const double* yl, int64_t incy,
+                         double* part, double* res, hipStream_t s);
+hipError_t launch_dd_scal(int64_t n, double ah, double al, const double* xh, const double* xl, int64_t incx,
+                          double* yh, double* yl, int64_t incy, hipStream_t s);
+
 }  // namespace ddk

@@ -313,6 +313,49 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
   return DD_OK;
 }
 
+dd_status dd_dot(int64_t n, const double* x_hi, const double* x_lo, int64_t incx,
+                 const double* y_hi, const double* y_lo, int64_t incy,
+                 double* result, hipStream_t stream) {
+  if (n < 0) return -1;
+  if (n > 0 && !x_hi) return -2;
+  if (n > 0 && !x_lo) return -3;
+  if (incx < 1) return -4;
+  if (n > 0 && !y_hi) return -5;
+  if (n > 0 && !y_lo) return -6;
+  if (incy < 1) return -7;
+  if (!result) return -8;
+  int dev = 0;
+  dd_status st = check_device(&dev);
+  if (st != DD_OK) return st;
+  void* part = nullptr;
+  st = cached_workspace(dev, stream, sizeof(double) * 2 * 1024, &part);
+  if (st != DD_OK) return st;
+  return hip_status(ddk::launch_dd_dot(n, x_hi, x_lo, incx, y_hi, y_lo, incy, (double*)part, result, stream));
+}
+
+dd_status dd_scal(int64_t n, double alpha_hi, double alpha_lo,
+                  const double* x_hi, const double* x_lo, int64_t incx,
+                  double* y_hi, double* y_lo, int64_t incy, hipStream_t stream) {
+  if (n < 0) return -1;
+  if (n == 0) return DD_OK;
+  if (!x_hi) return -4;
+  if (!x_lo) return -5;
+  if (incx < 1) return -6;
+  if (!y_hi) return -7;
+  if (!y_lo) return -8;
+  if (incy < 1) return -9;
+  const bool same = x_hi == y_hi && x_lo == y_lo && incx == incy;
+  if (!same) {
+    const size_t xb = (size_t)((n - 1) * incx + 1) * sizeof(double);
+    const size_t yb = (size_t)((n - 1) * incy + 1) * sizeof(double);
+    if (overlaps(y_hi, yb, x_hi, xb) || overlaps(y_hi, yb, x_lo, xb)) return -7;
+    if (overlaps(y_lo, yb, x_hi, xb) || overlaps(y_lo, yb, x_lo, xb) || overlaps(y_lo, yb, y_hi, yb)) return -8;
+  }
+  dd_status st = check_device(nullptr);
+  if (st != DD_OK) return st;
+  return hip_status(ddk::launch_dd_scal(n, alpha_hi, alpha_lo, x_hi, x_lo, incx, y_hi, y_lo, incy, stream));
+}
+
 dd_status dd_profile_enable(int32_t enable) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_prof = enable != 0;

@@ -27,8 +27,8 @@ DD_OP_T = 1
 DD_ALGO_CASCADE_F64 = 0
 DD_ALGO_DD_VALU = 1
 
-EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split",
-            "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version")
+EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_dot",
+            "dd_scal", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version")
 
 
 class dd_gemm_opts(ctypes.Structure):
@@ -63,6 +63,10 @@ def lib():
         L.dd_gemm_ex.restype = i32
         L.dd_cascade_split.argtypes = [i32, i32, i64, i64, vp, vp, i64, i32, vp, vp, vp]
         L.dd_cascade_split.restype = i32
+        L.dd_dot.argtypes = [i64, vp, vp, i64, vp, vp, i64, vp, vp]
+        L.dd_dot.restype = i32
+        L.dd_scal.argtypes = [i64, ctypes.c_double, ctypes.c_double, vp, vp, i64, vp, vp, i64, vp]
+        L.dd_scal.restype = i32
         L.dd_profile_enable.argtypes = [i32]
         L.dd_profile_enable.restype = i32
         L.dd_phase_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -132,6 +136,16 @@ def dd_gemm_ex(transa, transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, 
 def dd_cascade_split(side, trans, rows, cols, X_hi, X_lo, ldx, kc, exps, planes, stream=None) -> int:
     return int(lib().dd_cascade_split(int(side), int(trans), rows, cols, _ptr(X_hi), _ptr(X_lo), ldx,
                                       int(kc), _ptr(exps), _ptr(planes), _stream(stream)))
+
+
+def dd_dot(n, x_hi, x_lo, incx, y_hi, y_lo, incy, result, stream=None) -> int:
+    return int(lib().dd_dot(n, _ptr(x_hi), _ptr(x_lo), incx, _ptr(y_hi), _ptr(y_lo), incy, _ptr(result),
+                            _stream(stream)))
+
+
+def dd_scal(n, alpha_hi, alpha_lo, x_hi, x_lo, incx, y_hi, y_lo, incy, stream=None) -> int:
+    return int(lib().dd_scal(n, float(alpha_hi), float(alpha_lo), _ptr(x_hi), _ptr(x_lo), incx,
+                             _ptr(y_hi), _ptr(y_lo), incy, _stream(stream)))
 
 
 def dd_profile_enable(enable) -> int:
