@@ -110,6 +110,57 @@ dd_status dd_gemm_ex(dd_op transa, dd_op transb,
                      const dd_gemm_opts* opts, hipStream_t stream);
 
 /*
+ * Batches of independent GEMMs of uneven shapes, C_p := A_p B_p + C_p for
+ * p < count (each as dd_gemm, no transposes; kc from opts as in dd_gemm_ex).
+ * The cascade is the one of dd_gemm; the whole batch runs as one phase-one
+ * pass and one persistent product launch over all output tiles (Sec. 3.5:
+ * the number of products is independent of the shapes, so uneven problems
+ * mix freely in one launch).
+ *
+ * A plan fixes count and the shapes (host arrays m, n, k, lda, ldb, ldc) and
+ * owns the device memory for descriptors, tile list and packed operands
+ * (dd_batched_plan_info reports its size).  Creating a plan allocates and
+ * uploads (synchronously).  dd_gemm_batched_exec then launches three
+ * kernels on `stream`, allocates nothing and may be captured in a HIP
+ * graph; A_hi .. C_lo are DEVICE arrays of `count` device pointers, read
+ * when the kernels run.  Calls of one plan that overlap (on different
+ * streams) race on its workspace.  Problems with m, n or k = 0 are no-ops.
+ *
+ * Schedule of the persistent kernel: tiles in decreasing cost (LPT) or
+ * problem order, taken with a fixed stride or from an atomic counter.  The
+ * default is LPT with a counter, unless the tuning cache (file named by
+ * DDGEMM_TUNE_CACHE) holds a choice for these shapes.  dd_batched_plan_tune
+ * times every candidate `repeats` times with the given operands (C is
+ * updated by every run!), keeps the fastest and appends it to the cache.
+ */
+typedef struct dd_batched_plan_s* dd_batched_plan;
+dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                                 const int64_t* lda, const int64_t* ldb, const int64_t* ldc,
+                                 const dd_gemm_opts* opts, dd_batched_plan* plan);
+dd_status dd_gemm_batched_exec(dd_batched_plan plan,
+                               const double* const* A_hi, const double* const* A_lo,
+                               const double* const* B_hi, const double* const* B_lo,
+                               double* const* C_hi, double* const* C_lo, hipStream_t stream);
+dd_status dd_batched_plan_tune(dd_batched_plan plan,
+                               const double* const* A_hi, const double* const* A_lo,
+                               const double* const* B_hi, const double* const* B_lo,
+                               double* const* C_hi, double* const* C_lo, int32_t repeats,
+                               hipStream_t stream);
+/* Sets the schedule directly (dynamic: 1 = atomic counter, lpt: 1 = decreasing cost). */
+dd_status dd_batched_plan_schedule(dd_batched_plan plan, int32_t dynamic, int32_t lpt, hipStream_t stream);
+dd_status dd_batched_plan_info(dd_batched_plan plan, int64_t* ntiles, int32_t* dynamic, int32_t* lpt,
+                               size_t* device_bytes);
+/* Waits for the device, then frees the plan and its memory. */
+dd_status dd_batched_plan_destroy(dd_batched_plan plan);
+
+/* One-shot form: plan, execute, wait, free.  Synchronous. */
+dd_status dd_gemm_batched(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                          const double* const* A_hi, const double* const* A_lo, const int64_t* lda,
+                          const double* const* B_hi, const double* const* B_lo, const int64_t* ldb,
+                          double* const* C_hi, double* const* C_lo, const int64_t* ldc,
+                          const dd_gemm_opts* opts, hipStream_t stream);
+
+/*
  * The split of Appendix A on its own (phase one of Sec. 4), for inspection
  * and testing.  `side` = 0: X is op(A), rows x cols = m x k, one exponent per
  * row, 4 planes A0'..A3'.  `side` = 1: X is op(B), rows x cols = k x n, one

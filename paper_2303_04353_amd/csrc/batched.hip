@@ -1,0 +1,371 @@
+// Batches of independent cascaded FP64x2 GEMMs of uneven shapes, run as one
+// phase-one pass and one persistent product launch.
+//
+// A plan fixes the shapes: it numbers the units of work of every problem
+// (prefix sums), lists the 64x64 output tiles of all problems in decreasing
+// cost (LPT order), lays out one workspace for all packed operands and
+// uploads all of it once.  Executing a plan launches three kernels and
+// allocates nothing, so it can be captured in a HIP graph.  The schedule of
+// the persistent kernel (fixed stride or atomic counter, LPT or problem
+// order) is chosen by timing the candidates (dd_batched_plan_tune); choices
+// are kept in a small cache file keyed by the shapes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ddgemm.h"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+using ddk::BatchDesc;
+using ddk::BatchTile;
+
+struct dd_batched_plan_s {
+  int device = -1;
+  int32_t count = 0;
+  int32_t kc = 256;
+  std::vector<BatchDesc> desc;
+  std::vector<BatchTile> tiles_lpt, tiles_natural;
+  uint64_t key = 0;
+  char* dmem = nullptr;          // one device allocation for everything below
+  size_t dmem_bytes = 0;
+  BatchDesc* d_desc = nullptr;
+  int64_t *d_pexpA = nullptr, *d_pexpB = nullptr, *d_ppackA = nullptr, *d_ppackB = nullptr;
+  BatchTile* d_tiles = nullptr;
+  uint32_t* d_counter = nullptr;
+  char* d_ws = nullptr;
+  int64_t nexps = 0, units_exp = 0, units_pack = 0, ntiles = 0;
+  int grid = 256;
+  int dynamic = 1;
+  int lpt = 1;
+};
+
+namespace {
+
+constexpr int64_t kTile = 64;
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) { h ^= p[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+std::mutex g_cache_mu;
+
+std::string cache_path() {
+  const char* e = std::getenv("DDGEMM_TUNE_CACHE");
+  return e ? std::string(e) : std::string();
+}
+
+// Cache file lines: "<key hex> <dynamic> <lpt>".
+bool cache_lookup(uint64_t key, int* dynamic, int* lpt) {
+  std::string path = cache_path();
+  if (path.empty()) return false;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  unsigned long long k;
+  int d, l;
+  bool found = false;
+  while (std::fscanf(f, "%llx %d %d", &k, &d, &l) == 3)
+    if (k == key) { *dynamic = d; *lpt = l; found = true; }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(uint64_t key, int dynamic, int lpt) {
+  std::string path = cache_path();
+  if (path.empty()) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%016llx %d %d\n", (unsigned long long)key, dynamic, lpt);
+  std::fclose(f);
+}
+
+dd_status hip_st(hipError_t e) {
+  if (e == hipSuccess) return DD_OK;
+  if (e == hipErrorOutOfMemory) return DD_ERR_WORKSPACE;
+  return DD_ERR_HIP;
+}
+
+dd_status upload_tiles(dd_batched_plan_s* P, hipStream_t s) {
+  const std::vector<BatchTile>& t = P->lpt ? P->tiles_lpt : P->tiles_natural;
+  if (t.empty()) return DD_OK;
+  return hip_st(hipMemcpyAsync(P->d_tiles, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                                 const int64_t* lda, const int64_t* ldb, const int64_t* ldc,
+                                 const dd_gemm_opts* opts, dd_batched_plan* plan) {
+  if (count < 0) return -1;
+  if (count > 0 && (!m)) return -2;
+  if (count > 0 && (!n)) return -3;
+  if (count > 0 && (!k)) return -4;
+  if (count > 0 && (!lda)) return -5;
+  if (count > 0 && (!ldb)) return -6;
+  if (count > 0 && (!ldc)) return -7;
+  if (!plan) return -9;
+  *plan = nullptr;
+  int32_t kc = 256;
+  if (opts) {
+    if (opts->algo != DD_ALGO_CASCADE_F64 || opts->tile != 0 || opts->reserved0 != 0 || opts->reserved1 != 0)
+      return -8;
+    if (opts->kc != 0) {
+      if (opts->kc < 4 || opts->kc > 4096 || opts->kc % 4 != 0) return -8;
+      kc = opts->kc;
+    }
+  }
+  for (int32_t p = 0; p < count; ++p) {
+    if (m[p] < 0 || n[p] < 0 || k[p] < 0) return -2;
+    if (lda[p] < std::max<int64_t>(1, m[p])) return -5;
+    if (ldb[p] < std::max<int64_t>(1, k[p])) return -6;
+    if (ldc[p] < std::max<int64_t>(1, m[p])) return -7;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DD_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DD_ERR_HIP;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return DD_ERR_UNSUPPORTED;
+
+  dd_batched_plan_s* P = new (std::nothrow) dd_batched_plan_s();
+  if (!P) return DD_ERR_WORKSPACE;
+  P->device = dev;
+  P->count = count;
+  P->kc = kc;
+  P->desc.resize(count);
+  std::vector<int64_t> pexpA(count + 1, 0), pexpB(count + 1, 0), ppackA(count + 1, 0), ppackB(count + 1, 0);
+  // workspace: all exponent words first (zeroed with one fill), then the packed planes
+  int64_t nexps = 0;
+  for (int32_t p = 0; p < count; ++p) {
+    const int64_t mp = m[p] > 0 ? ddk::round_up(m[p], kTile) : 0, np = n[p] > 0 ? ddk::round_up(n[p], kTile) : 0;
+    nexps += mp + np;
+  }
+  size_t off = (size_t)ddk::round_up(nexps * 8, 256);
+  int64_t eoff = 0;
+  for (int32_t p = 0; p < count; ++p) {
+    BatchDesc& d = P->desc[p];
+    std::memset(&d, 0, sizeof(d));
+    d.m = m[p]; d.n = n[p]; d.k = k[p];
+    d.lda = lda[p]; d.ldb = ldb[p]; d.ldc = ldc[p];
+    const bool active = m[p] > 0 && n[p] > 0 && k[p] > 0;
+    if (active) {
+      ddk::CascadeLayout L = ddk::make_layout(m[p], n[p], k[p], kc, kTile, kTile);
+      d.K4 = L.K4; d.mpad = L.mpad; d.npad = L.npad;
+      d.tiles_m = L.mpad / kTile; d.tiles_n = L.npad / kTile;
+      d.kcq = L.kcq; d.c0 = L.c[0]; d.c1 = L.c[1]; d.c2 = L.c[2];
+      d.off_amax = eoff * 8; eoff += d.mpad;
+      d.off_bmax = eoff * 8; eoff += d.npad;
+      d.off_apack = (int64_t)off;
+      off += (size_t)ddk::round_up((int64_t)(sizeof(double) * ddk::kFragA * d.mpad * L.kpad), 256);
+      d.off_bpack = (int64_t)off;
+      off += (size_t)ddk::round_up((int64_t)(sizeof(double) * ddk::kFragB * d.npad * L.kpad), 256);
+    }
+    pexpA[p + 1] = pexpA[p] + (active ? cdiv(d.m, 256) * cdiv(d.k, 256) : 0);
+    pexpB[p + 1] = pexpB[p] + (active ? cdiv(d.n, 4) * cdiv(d.k, 4096) : 0);
+    ppackA[p + 1] = ppackA[p] + (active ? cdiv((d.mpad / 16) * d.K4, 4) : 0);
+    ppackB[p + 1] = ppackB[p] + (active ? cdiv((d.npad / 16) * d.K4, 4) : 0);
+    if (active)
+      for (int64_t tm = 0; tm < d.tiles_m; ++tm)
+        for (int64_t tn = 0; tn < d.tiles_n; ++tn)
+          P->tiles_natural.push_back(BatchTile{p, (int32_t)tm, (int32_t)tn, 0});
+  }
+  P->nexps = eoff;
+  P->units_exp = pexpA[count] + pexpB[count];
+  P->units_pack = ppackA[count] + ppackB[count];
+  P->ntiles = (int64_t)P->tiles_natural.size();
+  P->tiles_lpt = P->tiles_natural;
+  std::stable_sort(P->tiles_lpt.begin(), P->tiles_lpt.end(), [&](const BatchTile& a, const BatchTile& b) {
+    return P->desc[a.p].K4 > P->desc[b.p].K4;
+  });
+  const size_t ws_bytes = off;
+
+  // device memory: descriptors, prefix arrays, tiles, counter, workspace
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = (size_t)ddk::round_up((int64_t)(o + bytes), 256); return r; };
+  const size_t o_desc = take(sizeof(BatchDesc) * std::max(count, 1));
+  const size_t o_pa = take(sizeof(int64_t) * (count + 1)), o_pb = take(sizeof(int64_t) * (count + 1));
+  const size_t o_qa = take(sizeof(int64_t) * (count + 1)), o_qb = take(sizeof(int64_t) * (count + 1));
+  const size_t o_tiles = take(sizeof(BatchTile) * std::max<int64_t>(P->ntiles, 1));
+  const size_t o_ctr = take(sizeof(uint64_t));
+  const size_t o_ws = take(std::max<size_t>(ws_bytes, 256));
+  P->dmem_bytes = o;
+  if (hipMalloc(&P->dmem, P->dmem_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete P;
+    return DD_ERR_WORKSPACE;
+  }
+  P->d_desc = (BatchDesc*)(P->dmem + o_desc);
+  P->d_pexpA = (int64_t*)(P->dmem + o_pa);
+  P->d_pexpB = (int64_t*)(P->dmem + o_pb);
+  P->d_ppackA = (int64_t*)(P->dmem + o_qa);
+  P->d_ppackB = (int64_t*)(P->dmem + o_qb);
+  P->d_tiles = (BatchTile*)(P->dmem + o_tiles);
+  P->d_counter = (uint32_t*)(P->dmem + o_ctr);
+  P->d_ws = P->dmem + o_ws;
+
+  // key of the tuning cache: device, kc and every shape
+  uint64_t key = fnv1a(prop.gcnArchName, std::strlen(prop.gcnArchName));
+  key = fnv1a(&kc, sizeof(kc), key);
+  for (int32_t p = 0; p < count; ++p) {
+    const int64_t s3[3] = {m[p], n[p], k[p]};
+    key = fnv1a(s3, sizeof(s3), key);
+  }
+  P->key = key;
+  P->grid = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  int dyn = 1, lpt = 1;
+  if (cache_lookup(key, &dyn, &lpt)) { P->dynamic = dyn; P->lpt = lpt; }
+
+  dd_status st = DD_OK;
+  if (count > 0) {
+    st = hip_st(hipMemcpy(P->d_desc, P->desc.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice));
+    if (st == DD_OK) st = hip_st(hipMemcpy(P->d_pexpA, pexpA.data(), 8 * (count + 1), hipMemcpyHostToDevice));
+    if (st == DD_OK) st = hip_st(hipMemcpy(P->d_pexpB, pexpB.data(), 8 * (count + 1), hipMemcpyHostToDevice));
+    if (st == DD_OK) st = hip_st(hipMemcpy(P->d_ppackA, ppackA.data(), 8 * (count + 1), hipMemcpyHostToDevice));
+    if (st == DD_OK) st = hip_st(hipMemcpy(P->d_ppackB, ppackB.data(), 8 * (count + 1), hipMemcpyHostToDevice));
+    if (st == DD_OK) st = upload_tiles(P, nullptr);
+    if (st == DD_OK) st = hip_st(hipDeviceSynchronize());
+  }
+  if (st != DD_OK) {
+    (void)hipFree(P->dmem);
+    delete P;
+    return st;
+  }
+  *plan = P;
+  return DD_OK;
+}
+
+dd_status dd_gemm_batched_exec(dd_batched_plan P, const double* const* A_hi, const double* const* A_lo,
+                               const double* const* B_hi, const double* const* B_lo,
+                               double* const* C_hi, double* const* C_lo, hipStream_t stream) {
+  if (!P) return -1;
+  if (P->ntiles == 0) return DD_OK;
+  if (!A_hi) return -2;
+  if (!A_lo) return -3;
+  if (!B_hi) return -4;
+  if (!B_lo) return -5;
+  if (!C_hi) return -6;
+  if (!C_lo) return -7;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return DD_ERR_HIP;
+  if (dev != P->device) return DD_ERR_UNSUPPORTED;
+  hipError_t e = ddk::launch_batched_phase_one(P->d_desc, P->count, P->d_pexpA, P->d_pexpB, P->units_exp,
+                                               P->d_ppackA, P->d_ppackB, P->units_pack, A_hi, A_lo, B_hi, B_lo,
+                                               P->d_ws, (uint64_t*)P->d_ws, P->nexps, stream);
+  if (e != hipSuccess) return hip_st(e);
+  return hip_st(ddk::launch_cascade_batched(P->d_desc, P->d_tiles, P->ntiles, C_hi, C_lo, P->d_ws,
+                                            P->d_counter, P->grid, P->dynamic != 0, stream));
+}
+
+dd_status dd_batched_plan_tune(dd_batched_plan P, const double* const* A_hi, const double* const* A_lo,
+                               const double* const* B_hi, const double* const* B_lo,
+                               double* const* C_hi, double* const* C_lo, int32_t repeats,
+                               hipStream_t stream) {
+  if (!P) return -1;
+  if (repeats < 1) return -8;
+  if (P->ntiles == 0) return DD_OK;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DD_ERR_HIP;
+  float best = 1e30f;
+  int best_dyn = P->dynamic, best_lpt = P->lpt;
+  dd_status st = DD_OK;
+  for (int lpt = 1; lpt >= 0 && st == DD_OK; --lpt) {
+    P->lpt = lpt;
+    st = upload_tiles(P, stream);
+    for (int dyn = 1; dyn >= 0 && st == DD_OK; --dyn) {
+      P->dynamic = dyn;
+      st = dd_gemm_batched_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, stream);  // warm-up
+      std::vector<float> t;
+      for (int r = 0; r < repeats && st == DD_OK; ++r) {
+        (void)hipEventRecord(e0, stream);
+        st = dd_gemm_batched_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, stream);
+        (void)hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess) st = DD_ERR_HIP;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t.push_back(ms);
+      }
+      if (st != DD_OK) break;
+      std::sort(t.begin(), t.end());
+      const float med = t[t.size() / 2];
+      if (med < best) { best = med; best_dyn = dyn; best_lpt = lpt; }
+    }
+  }
+  P->dynamic = best_dyn;
+  P->lpt = best_lpt;
+  if (st == DD_OK) st = upload_tiles(P, stream);
+  if (st == DD_OK) st = hip_st(hipStreamSynchronize(stream));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == DD_OK) cache_store(P->key, best_dyn, best_lpt);
+  return st;
+}
+
+dd_status dd_batched_plan_schedule(dd_batched_plan P, int32_t dynamic, int32_t lpt, hipStream_t stream) {
+  if (!P) return -1;
+  if (dynamic != 0 && dynamic != 1) return -2;
+  if (lpt != 0 && lpt != 1) return -3;
+  P->dynamic = dynamic;
+  P->lpt = lpt;
+  return upload_tiles(P, stream);
+}
+
+dd_status dd_batched_plan_info(dd_batched_plan P, int64_t* ntiles, int32_t* dynamic, int32_t* lpt,
+                               size_t* device_bytes) {
+  if (!P) return -1;
+  if (ntiles) *ntiles = P->ntiles;
+  if (dynamic) *dynamic = P->dynamic;
+  if (lpt) *lpt = P->lpt;
+  if (device_bytes) *device_bytes = P->dmem_bytes;
+  return DD_OK;
+}
+
+dd_status dd_batched_plan_destroy(dd_batched_plan P) {
+  if (!P) return DD_OK;
+  dd_status st = DD_OK;
+  if (P->dmem) {
+    if (hipDeviceSynchronize() != hipSuccess) st = DD_ERR_HIP;
+    if (hipFree(P->dmem) != hipSuccess) st = DD_ERR_HIP;
+  }
+  delete P;
+  return st;
+}
+
+dd_status dd_gemm_batched(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                          const double* const* A_hi, const double* const* A_lo, const int64_t* lda,
+                          const double* const* B_hi, const double* const* B_lo, const int64_t* ldb,
+                          double* const* C_hi, double* const* C_lo, const int64_t* ldc,
+                          const dd_gemm_opts* opts, hipStream_t stream) {
+  if (count < 0) return -1;
+  if (count == 0) return DD_OK;
+  dd_batched_plan P = nullptr;
+  dd_status st = dd_batched_plan_create(count, m, n, k, lda, ldb, ldc, opts, &P);
+  if (st != DD_OK) {
+    // map the plan's argument numbers onto this prototype
+    static const int pos[] = {0, 1, 2, 3, 4, 7, 10, 13, 14, 0};
+    return st < 0 && -st < 10 ? -pos[-st] : st;
+  }
+  st = dd_gemm_batched_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, stream);
+  if (st < 0) {
+    static const int pos2[] = {0, 0, 5, 6, 8, 9, 11, 12};
+    st = -pos2[-st];
+  }
+  dd_status st2 = dd_batched_plan_destroy(P);  // waits for the work to finish
+  return st != DD_OK ? st : st2;
+}
+
+}  // extern "C"

@@ -172,18 +172,18 @@ __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? 
 
 }  // namespace
 
-__global__ void __launch_bounds__(kWaves * 64)
-cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpack,
-               const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax,
-               int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_m, int64_t tiles_n,
-               double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc) {
-  __shared__ __attribute__((aligned(16))) double lds[kNBuf * kStage];
-
+// One 64x64 output tile (tile row tm, tile column tn) of one GEMM, computed
+// by the whole workgroup.  `lds` is the workgroup's staging memory.
+__device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const double* __restrict__ Apack,
+                                             const double* __restrict__ Bpack,
+                                             const uint64_t* __restrict__ amax,
+                                             const uint64_t* __restrict__ bmax, int64_t K4, int32_t kcq,
+                                             int64_t m, int64_t n, int64_t tm, int64_t tn,
+                                             double* __restrict__ Chi, double* __restrict__ Clo,
+                                             int64_t ldc) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 1, wn = wave & 1;     // 16-row block wm, 32-column half wn
-  int64_t tm, tn;
-  tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
   const int64_t rb0 = tm * 4 + wm;             // this wave's 16-row block
   const int64_t cb0 = tn * 4 + wn * kWaveCB;   // first 16-column group
 
@@ -301,6 +301,59 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
       Clo[idx] = rl;
     }
   }
+}
+
+__global__ void __launch_bounds__(kWaves * 64)
+cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpack,
+               const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax,
+               int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_m, int64_t tiles_n,
+               double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc) {
+  __shared__ __attribute__((aligned(16))) double lds[kNBuf * kStage];
+  int64_t tm, tn;
+  tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  cascade_tile(lds, Apack, Bpack, amax, bmax, K4, kcq, m, n, tm, tn, Chi, Clo, ldc);
+}
+
+// Persistent form for a batch of GEMMs: every workgroup takes tiles from the
+// list (in list order: the list is sorted by decreasing cost) until none is
+// left, either with a fixed stride or from an atomic counter.
+__global__ void __launch_bounds__(kWaves * 64)
+cascade_batched_kernel(const BatchDesc* __restrict__ desc, const BatchTile* __restrict__ tiles,
+                       int64_t ntiles, double* const* __restrict__ Chi, double* const* __restrict__ Clo,
+                       const char* __restrict__ ws, unsigned long long* __restrict__ counter, int dynamic) {
+  __shared__ __attribute__((aligned(16))) double lds[kNBuf * kStage];
+  __shared__ unsigned long long next;
+  int64_t w = blockIdx.x;
+  for (;;) {
+    if (dynamic) {
+      if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);
+      __syncthreads();
+      w = (int64_t)next;
+      __syncthreads();
+    }
+    if (w >= ntiles) break;
+    const BatchTile t = tiles[w];
+    const BatchDesc d = desc[t.p];
+    cascade_tile(lds, (const double*)(ws + d.off_apack), (const double*)(ws + d.off_bpack),
+                 (const uint64_t*)(ws + d.off_amax), (const uint64_t*)(ws + d.off_bmax), d.K4, d.kcq,
+                 d.m, d.n, t.tm, t.tn, Chi[t.p], Clo[t.p], d.ldc);
+    __syncthreads();  // the next tile reuses the staging buffers
+    if (!dynamic) w += gridDim.x;
+  }
+}
+
+hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles, int64_t ntiles,
+                                  double* const* Chi, double* const* Clo, const char* ws,
+                                  uint32_t* counter, int grid, bool dynamic, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (grid < 1) return hipErrorInvalidValue;
+  if (dynamic) {
+    hipError_t e = launch_fill_u64((uint64_t*)counter, 1, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  cascade_batched_kernel<<<grid, kWaves * 64, 0, s>>>(desc, tiles, ntiles, Chi, Clo, ws,
+                                                      (unsigned long long*)counter, dynamic ? 1 : 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,

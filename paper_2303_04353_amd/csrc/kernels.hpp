@@ -21,6 +21,23 @@ hipError_t launch_unpack(const double* pack, int side, int64_t rows, int64_t col
                          double* planes, hipStream_t s);
 hipError_t launch_exps(const uint64_t* bits, int64_t n, int32_t* e, hipStream_t s);
 
+// Phase one of a batch: zero the exponent words, reduce max |hi| per row of
+// every A and column of every B, then split all operands.  Units of work are
+// numbered through the prefix arrays (prefix[count] = total).
+hipError_t launch_batched_phase_one(const BatchDesc* desc, int count, const int64_t* prefExpA,
+                                   const int64_t* prefExpB, int64_t units_exp, const int64_t* prefPackA,
+                                   const int64_t* prefPackB, int64_t units_pack,
+                                   const double* const* Ahi, const double* const* Alo,
+                                   const double* const* Bhi, const double* const* Blo,
+                                   char* ws, uint64_t* exps, int64_t nexps, hipStream_t s);
+
+// The product kernel over a list of tiles of a batch, `grid` persistent
+// workgroups; `dynamic` takes tiles from an atomic counter (zeroed here)
+// instead of a fixed stride.
+hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles, int64_t ntiles,
+                                  double* const* Chi, double* const* Clo, const char* ws,
+                                  uint32_t* counter, int grid, bool dynamic, hipStream_t s);
+
 // The fused product kernel: ten FP64 MFMA products per rank-kc block, bins
 // combined in FP64x2, Sigma/T applied, C := C + result.
 hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,

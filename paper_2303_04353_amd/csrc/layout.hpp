@@ -43,6 +43,21 @@ struct CascadeLayout {
 
 inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
+// One problem of a batch, as the batched kernels see it (device memory).
+// Offsets are bytes into the batch's workspace, laid out per problem as in
+// CascadeLayout.  Operand pointers come from the caller's device arrays.
+struct BatchDesc {
+  int64_t m, n, k, K4, mpad, npad, tiles_m, tiles_n;
+  int64_t lda, ldb, ldc;
+  int64_t off_amax, off_bmax, off_apack, off_bpack;
+  int32_t kcq, c0, c1, c2;
+};
+
+// A tile of the persistent product kernel: problem p, tile row tm, column tn.
+struct BatchTile {
+  int32_t p, tm, tn, pad;
+};
+
 // ceil(log2 kc) and the widths of Sec. 3.3 (bins 0-2 exact for kc terms).
 inline void split_widths(int64_t kc, int32_t c[3]) {
   int L = 0;

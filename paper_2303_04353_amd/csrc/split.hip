@@ -76,14 +76,11 @@ __device__ __forceinline__ SplitParams make_params(int c0, int c1, int c2) {
   return sp;
 }
 
-// op(A)(i, p) = A[i*si + p*sp_].  One wave per fragment (rb, kq).
-__global__ void __launch_bounds__(256)
-pack_a(const double* __restrict__ Ahi, const double* __restrict__ Alo, int64_t si, int64_t sp_,
-       int64_t m, int64_t k, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ amax,
-       int c0, int c1, int c2, double* __restrict__ Apack) {
-  int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (frag >= nfrag) return;
-  int lane = threadIdx.x & 63;
+// One 64-lane fragment of the packed A planes: op(A)(i, p) = A[i*si + p*sp_].
+__device__ __forceinline__ void pack_a_frag(const double* __restrict__ Ahi, const double* __restrict__ Alo,
+                                            int64_t si, int64_t sp_, int64_t m, int64_t k, int64_t K4,
+                                            int64_t frag, int lane, const uint64_t* __restrict__ amax,
+                                            int c0, int c1, int c2, double* __restrict__ Apack) {
   int64_t rb = frag / K4, kq = frag - rb * K4;
   // position lane = s*16 + kk*4 + ii holds row rb*16 + s*4 + ii, inner index kq*4 + kk
   int64_t i = rb * 16 + (lane >> 4) * 4 + (lane & 3), p = kq * 4 + ((lane >> 2) & 3);
@@ -99,14 +96,11 @@ pack_a(const double* __restrict__ Ahi, const double* __restrict__ Alo, int64_t s
   for (int t = 0; t < 4; ++t) dst[t * kLanes] = w[t];
 }
 
-// op(B)(p, j) = B[p*sp_ + j*sj].  One wave per fragment (cb, kq).
-__global__ void __launch_bounds__(256)
-pack_b(const double* __restrict__ Bhi, const double* __restrict__ Blo, int64_t sp_, int64_t sj,
-       int64_t k, int64_t n, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ bmax,
-       int c0, int c1, int c2, double* __restrict__ Bpack) {
-  int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (frag >= nfrag) return;
-  int lane = threadIdx.x & 63;
+// One 64-lane fragment of the packed B planes: op(B)(p, j) = B[p*sp_ + j*sj].
+__device__ __forceinline__ void pack_b_frag(const double* __restrict__ Bhi, const double* __restrict__ Blo,
+                                            int64_t sp_, int64_t sj, int64_t k, int64_t n, int64_t K4,
+                                            int64_t frag, int lane, const uint64_t* __restrict__ bmax,
+                                            int c0, int c1, int c2, double* __restrict__ Bpack) {
   int64_t cb = frag / K4, kq = frag - cb * K4;
   int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
   double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -120,6 +114,117 @@ pack_b(const double* __restrict__ Bhi, const double* __restrict__ Blo, int64_t s
   double* dst = Bpack + frag * (kFragB * kLanes) + lane;
 #pragma unroll
   for (int t = 0; t < 5; ++t) dst[t * kLanes] = w[t];
+}
+
+// One wave per fragment (rb, kq).
+__global__ void __launch_bounds__(256)
+pack_a(const double* __restrict__ Ahi, const double* __restrict__ Alo, int64_t si, int64_t sp_,
+       int64_t m, int64_t k, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ amax,
+       int c0, int c1, int c2, double* __restrict__ Apack) {
+  int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (frag >= nfrag) return;
+  pack_a_frag(Ahi, Alo, si, sp_, m, k, K4, frag, threadIdx.x & 63, amax, c0, c1, c2, Apack);
+}
+
+// One wave per fragment (cb, kq).
+__global__ void __launch_bounds__(256)
+pack_b(const double* __restrict__ Bhi, const double* __restrict__ Blo, int64_t sp_, int64_t sj,
+       int64_t k, int64_t n, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ bmax,
+       int c0, int c1, int c2, double* __restrict__ Bpack) {
+  int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (frag >= nfrag) return;
+  pack_b_frag(Bhi, Blo, sp_, sj, k, n, K4, frag, threadIdx.x & 63, bmax, c0, c1, c2, Bpack);
+}
+
+// ------------------------------------------------------------ batched phase one
+// Units of work of every problem are numbered consecutively; prefix[p] is the
+// first unit of problem p (prefix[count] = total).  A block finds its problem
+// by binary search.
+__device__ __forceinline__ int find_problem(const int64_t* __restrict__ prefix, int count, int64_t u) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= u) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Units of A: (256-row block, 256-long inner chunk); of B: (4 columns, 4096-long chunk).
+__global__ void __launch_bounds__(256)
+batched_max_abs(const BatchDesc* __restrict__ desc, int count, const int64_t* __restrict__ prefA,
+                const int64_t* __restrict__ prefB, const double* const* __restrict__ Ahi,
+                const double* const* __restrict__ Bhi, char* __restrict__ ws) {
+  const int64_t totA = prefA[count], tot = totA + prefB[count];
+  for (int64_t u = blockIdx.x; u < tot; u += gridDim.x) {
+    if (u < totA) {
+      const int p = find_problem(prefA, count, u);
+      const BatchDesc d = desc[p];
+      const int64_t local = u - prefA[p];
+      const int64_t nchunk = (d.k + 255) / 256;
+      const int64_t rblk = local / nchunk, ch = local - rblk * nchunk;
+      const int64_t o = rblk * 256 + threadIdx.x;
+      if (o >= d.m) continue;
+      const int64_t r0 = ch * 256, r1 = r0 + 256 < d.k ? r0 + 256 : d.k;
+      uint64_t mx = 0;
+      const double* X = Ahi[p];
+      for (int64_t r = r0; r < r1; ++r) {
+        uint64_t b = __builtin_bit_cast(uint64_t, X[o + r * d.lda]) & 0x7fffffffffffffffull;
+        mx = b > mx ? b : mx;
+      }
+      atomicMax((unsigned long long*)((uint64_t*)(ws + d.off_amax) + o), (unsigned long long)mx);
+    } else {
+      const int64_t v = u - totA;
+      const int p = find_problem(prefB, count, v);
+      const BatchDesc d = desc[p];
+      const int64_t local = v - prefB[p];
+      const int64_t nchunk = (d.k + 4095) / 4096;
+      const int64_t cgrp = local / nchunk, ch = local - cgrp * nchunk;
+      const int lane = threadIdx.x & 63;
+      const int64_t o = cgrp * 4 + (threadIdx.x >> 6);
+      if (o >= d.n) continue;
+      const int64_t r0 = ch * 4096, r1 = r0 + 4096 < d.k ? r0 + 4096 : d.k;
+      uint64_t mx = 0;
+      const double* col = Bhi[p] + o * d.ldb;
+      for (int64_t r = r0 + lane; r < r1; r += 64) {
+        uint64_t b = __builtin_bit_cast(uint64_t, col[r]) & 0x7fffffffffffffffull;
+        mx = b > mx ? b : mx;
+      }
+#pragma unroll
+      for (int sft = 32; sft >= 1; sft >>= 1) {
+        uint64_t y = __shfl_xor(mx, sft, 64);
+        mx = y > mx ? y : mx;
+      }
+      if (lane == 0) atomicMax((unsigned long long*)((uint64_t*)(ws + d.off_bmax) + o), (unsigned long long)mx);
+    }
+  }
+}
+
+// Units: 4 fragments (one per wave) of the packed A planes, then of B.
+__global__ void __launch_bounds__(256)
+batched_pack(const BatchDesc* __restrict__ desc, int count, const int64_t* __restrict__ prefA,
+             const int64_t* __restrict__ prefB, const double* const* __restrict__ Ahi,
+             const double* const* __restrict__ Alo, const double* const* __restrict__ Bhi,
+             const double* const* __restrict__ Blo, char* __restrict__ ws) {
+  const int64_t totA = prefA[count], tot = totA + prefB[count];
+  const int lane = threadIdx.x & 63;
+  for (int64_t u = blockIdx.x; u < tot; u += gridDim.x) {
+    if (u < totA) {
+      const int p = find_problem(prefA, count, u);
+      const BatchDesc d = desc[p];
+      const int64_t frag = (u - prefA[p]) * 4 + (threadIdx.x >> 6);
+      if (frag >= (d.mpad / 16) * d.K4) continue;
+      pack_a_frag(Ahi[p], Alo[p], 1, d.lda, d.m, d.k, d.K4, frag, lane,
+                  (const uint64_t*)(ws + d.off_amax), d.c0, d.c1, d.c2, (double*)(ws + d.off_apack));
+    } else {
+      const int64_t v = u - totA;
+      const int p = find_problem(prefB, count, v);
+      const BatchDesc d = desc[p];
+      const int64_t frag = (v - prefB[p]) * 4 + (threadIdx.x >> 6);
+      if (frag >= (d.npad / 16) * d.K4) continue;
+      pack_b_frag(Bhi[p], Blo[p], 1, d.ldb, d.k, d.n, d.K4, frag, lane,
+                  (const uint64_t*)(ws + d.off_bmax), d.c0, d.c1, d.c2, (double*)(ws + d.off_bpack));
+    }
+  }
 }
 
 // Plain planes from the packed layout (diagnostics).  side 0: element (i, p)
@@ -208,6 +313,23 @@ hipError_t launch_unpack(const double* pack, int side, int64_t rows, int64_t col
                          double* planes, hipStream_t s) {
   if (rows * cols <= 0) return hipSuccess;
   unpack_planes<<<blocks_for(rows * cols, 256), 256, 0, s>>>(pack, side, rows, cols, K4, planes);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_phase_one(const BatchDesc* desc, int count, const int64_t* prefExpA,
+                                   const int64_t* prefExpB, int64_t units_exp, const int64_t* prefPackA,
+                                   const int64_t* prefPackB, int64_t units_pack,
+                                   const double* const* Ahi, const double* const* Alo,
+                                   const double* const* Bhi, const double* const* Blo,
+                                   char* ws, uint64_t* exps, int64_t nexps, hipStream_t s) {
+  hipError_t e = launch_fill_u64(exps, nexps, 0, s);
+  if (e != hipSuccess) return e;
+  const unsigned ge = (unsigned)(units_exp < 65536 ? (units_exp > 0 ? units_exp : 1) : 65536);
+  batched_max_abs<<<ge, 256, 0, s>>>(desc, count, prefExpA, prefExpB, Ahi, Bhi, ws);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned gp = (unsigned)(units_pack < 65536 ? (units_pack > 0 ? units_pack : 1) : 65536);
+  batched_pack<<<gp, 256, 0, s>>>(desc, count, prefPackA, prefPackB, Ahi, Alo, Bhi, Blo, ws);
   return hipGetLastError();
 }
 

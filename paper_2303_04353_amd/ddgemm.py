@@ -28,7 +28,9 @@ DD_ALGO_CASCADE_F64 = 0
 DD_ALGO_DD_VALU = 1
 
 EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_dot",
-            "dd_scal", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version")
+            "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",
+            "dd_batched_plan_schedule", "dd_batched_plan_info", "dd_batched_plan_destroy",
+            "dd_gemm_batched", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version")
 
 
 class dd_gemm_opts(ctypes.Structure):
@@ -67,6 +69,24 @@ def lib():
         L.dd_dot.restype = i32
         L.dd_scal.argtypes = [i64, ctypes.c_double, ctypes.c_double, vp, vp, i64, vp, vp, i64, vp]
         L.dd_scal.restype = i32
+        pi64 = ctypes.POINTER(ctypes.c_int64)
+        L.dd_batched_plan_create.argtypes = [i32, pi64, pi64, pi64, pi64, pi64, pi64,
+                                             ctypes.POINTER(dd_gemm_opts), ctypes.POINTER(vp)]
+        L.dd_batched_plan_create.restype = i32
+        L.dd_gemm_batched_exec.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.dd_gemm_batched_exec.restype = i32
+        L.dd_batched_plan_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
+        L.dd_batched_plan_tune.restype = i32
+        L.dd_batched_plan_schedule.argtypes = [vp, i32, i32, vp]
+        L.dd_batched_plan_schedule.restype = i32
+        L.dd_batched_plan_info.argtypes = [vp, pi64, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                           ctypes.POINTER(sz)]
+        L.dd_batched_plan_info.restype = i32
+        L.dd_batched_plan_destroy.argtypes = [vp]
+        L.dd_batched_plan_destroy.restype = i32
+        L.dd_gemm_batched.argtypes = [i32, pi64, pi64, pi64, vp, vp, pi64, vp, vp, pi64, vp, vp, pi64,
+                                      ctypes.POINTER(dd_gemm_opts), vp]
+        L.dd_gemm_batched.restype = i32
         L.dd_profile_enable.argtypes = [i32]
         L.dd_profile_enable.restype = i32
         L.dd_phase_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -146,6 +166,52 @@ def dd_dot(n, x_hi, x_lo, incx, y_hi, y_lo, incy, result, stream=None) -> int:
 def dd_scal(n, alpha_hi, alpha_lo, x_hi, x_lo, incx, y_hi, y_lo, incy, stream=None) -> int:
     return int(lib().dd_scal(n, float(alpha_hi), float(alpha_lo), _ptr(x_hi), _ptr(x_lo), incx,
                              _ptr(y_hi), _ptr(y_lo), incy, _stream(stream)))
+
+
+def _i64arr(v):
+    arr = (ctypes.c_int64 * max(1, len(v)))(*[int(x) for x in v])
+    return arr
+
+
+def dd_batched_plan_create(count, m, n, k, lda, ldb, ldc, opts=None):
+    """Returns ``(status, plan)`` (plan is an opaque integer handle)."""
+    plan = ctypes.c_void_p()
+    st = int(lib().dd_batched_plan_create(int(count), _i64arr(m), _i64arr(n), _i64arr(k), _i64arr(lda),
+                                          _i64arr(ldb), _i64arr(ldc), _opts(opts), ctypes.byref(plan)))
+    return st, plan.value
+
+
+def dd_gemm_batched_exec(plan, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, stream=None) -> int:
+    return int(lib().dd_gemm_batched_exec(plan, _ptr(A_hi), _ptr(A_lo), _ptr(B_hi), _ptr(B_lo),
+                                          _ptr(C_hi), _ptr(C_lo), _stream(stream)))
+
+
+def dd_batched_plan_tune(plan, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, repeats=3, stream=None) -> int:
+    return int(lib().dd_batched_plan_tune(plan, _ptr(A_hi), _ptr(A_lo), _ptr(B_hi), _ptr(B_lo),
+                                          _ptr(C_hi), _ptr(C_lo), int(repeats), _stream(stream)))
+
+
+def dd_batched_plan_schedule(plan, dynamic, lpt, stream=None) -> int:
+    return int(lib().dd_batched_plan_schedule(plan, int(dynamic), int(lpt), _stream(stream)))
+
+
+def dd_batched_plan_info(plan):
+    """Returns ``(status, ntiles, dynamic, lpt, device_bytes)``."""
+    nt, dy, lp, nb = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    st = int(lib().dd_batched_plan_info(plan, ctypes.byref(nt), ctypes.byref(dy), ctypes.byref(lp),
+                                        ctypes.byref(nb)))
+    return st, nt.value, dy.value, lp.value, nb.value
+
+
+def dd_batched_plan_destroy(plan) -> int:
+    return int(lib().dd_batched_plan_destroy(plan))
+
+
+def dd_gemm_batched(count, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc, opts=None,
+                    stream=None) -> int:
+    return int(lib().dd_gemm_batched(int(count), _i64arr(m), _i64arr(n), _i64arr(k), _ptr(A_hi), _ptr(A_lo),
+                                     _i64arr(lda), _ptr(B_hi), _ptr(B_lo), _i64arr(ldb), _ptr(C_hi),
+                                     _ptr(C_lo), _i64arr(ldc), _opts(opts), _stream(stream)))
 
 
 def dd_profile_enable(enable) -> int:

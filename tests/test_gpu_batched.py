@@ -1,0 +1,193 @@
+"""GPU checks of the batched persistent cascade (C ABI).
+
+* every problem of a batch is bit-identical to a single dd_gemm call (same
+  packed planes, same per-tile arithmetic), for every schedule;
+* the uneven batch (512 problems, m, n, k log-uniform in [32, 1024]) against
+  the FP64x2 oracle on sampled entries of every problem;
+* a HIP graph of one execution, replayed several times with eager work in
+  between, reproduces the eager result every time;
+* the tuner picks a schedule and records it in the cache file.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.ref import dd_gemm_ref_entries
+from paper_2303_04353_amd import ddgemm as dg
+from paper_2303_04353_amd.inputs import batched_shapes, make_problem
+from tests.gpuhelp import log, up
+
+pytestmark = pytest.mark.gpu
+
+
+class Batch:
+    """Device copies of a list of problems plus the pointer arrays."""
+
+    def __init__(self, shapes, cfg=30):
+        import torch
+        self.shapes = shapes
+        self.P = [make_problem(m, n, k, cfg=cfg, salt=i) for i, (m, n, k) in enumerate(shapes)]
+        self.A = [(up(p["A"][0]), up(p["A"][1])) for p in self.P]
+        self.B = [(up(p["B"][0]), up(p["B"][1])) for p in self.P]
+        self.C0 = [(up(p["C"][0]), up(p["C"][1])) for p in self.P]
+        self.C = [(c[0].clone(), c[1].clone()) for c in self.C0]
+        ptrs = lambda lst, w: torch.tensor([t[w].data_ptr() for t in lst], dtype=torch.int64, device="cuda")
+        self.pA = (ptrs(self.A, 0), ptrs(self.A, 1))
+        self.pB = (ptrs(self.B, 0), ptrs(self.B, 1))
+        self.pC = (ptrs(self.C, 0), ptrs(self.C, 1))
+        self.m = [s[0] for s in shapes]
+        self.n = [s[1] for s in shapes]
+        self.k = [s[2] for s in shapes]
+        self.lda = [max(1, s[0]) for s in shapes]
+        self.ldb = [max(1, s[2]) for s in shapes]
+        self.ldc = [max(1, s[0]) for s in shapes]
+
+    def reset(self):
+        for c, c0 in zip(self.C, self.C0):
+            c[0].copy_(c0[0])
+            c[1].copy_(c0[1])
+
+    def plan(self, opts=None):
+        st, plan = dg.dd_batched_plan_create(len(self.shapes), self.m, self.n, self.k, self.lda, self.ldb,
+                                             self.ldc, opts)
+        dg.check(st, "dd_batched_plan_create")
+        return plan
+
+    def exec(self, plan):
+        dg.check(dg.dd_gemm_batched_exec(plan, self.pA[0], self.pA[1], self.pB[0], self.pB[1],
+                                         self.pC[0], self.pC[1]), "dd_gemm_batched_exec")
+
+    def results(self):
+        return [(c[0].cpu().numpy().copy(), c[1].cpu().numpy().copy()) for c in self.C]
+
+    def singles(self, opts=None):
+        import torch
+        out = []
+        for i, (m, n, k) in enumerate(self.shapes):
+            ch, cl = self.C0[i][0].clone(), self.C0[i][1].clone()
+            st = dg.dd_gemm_ex(0, 0, m, n, k, self.A[i][0], self.A[i][1], self.lda[i], self.B[i][0],
+                               self.B[i][1], self.ldb[i], ch, cl, self.ldc[i], opts=opts)
+            dg.check(st, "dd_gemm_ex")
+            out.append((ch, cl))
+        torch.cuda.synchronize()
+        return [(c[0].cpu().numpy(), c[1].cpu().numpy()) for c in out]
+
+
+SMALL = [(37, 50, 300), (1, 1, 1), (64, 64, 64), (0, 5, 7), (5, 0, 7), (6, 9, 0), (130, 70, 1000),
+         (17, 200, 33), (128, 3, 257), (65, 65, 65), (200, 128, 520), (3, 3, 3)]
+
+
+@pytest.mark.parametrize("kc", [0, 128])
+def test_batch_equals_single_calls_bitwise_for_every_schedule(kc):
+    import torch
+    b = Batch(SMALL)
+    opts = {"kc": kc}
+    want = b.singles(opts)
+    plan = b.plan(opts)
+    try:
+        for dyn in (1, 0):
+            for lpt in (1, 0):
+                log(f"batched small kc={kc} dynamic={dyn} lpt={lpt}")
+                dg.check(dg.dd_batched_plan_schedule(plan, dyn, lpt))
+                b.reset()
+                b.exec(plan)
+                torch.cuda.synchronize()
+                for i, (g, w) in enumerate(zip(b.results(), want)):
+                    assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1]), (i, dyn, lpt)
+    finally:
+        dg.dd_batched_plan_destroy(plan)
+
+
+def test_one_shot_entry_point():
+    import torch
+    b = Batch(SMALL[:6], cfg=31)
+    want = b.singles()
+    st = dg.dd_gemm_batched(len(b.shapes), b.m, b.n, b.k, b.pA[0], b.pA[1], b.lda, b.pB[0], b.pB[1], b.ldb,
+                            b.pC[0], b.pC[1], b.ldc)
+    dg.check(st, "dd_gemm_batched")
+    torch.cuda.synchronize()
+    for g, w in zip(b.results(), want):
+        assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1])
+
+
+def test_uneven_batch_512_against_oracle_and_singles():
+    import torch
+    shapes = batched_shapes(512)
+    log(f"uneven batch: {len(shapes)} problems")
+    b = Batch(shapes, cfg=3)
+    plan = b.plan()
+    try:
+        b.exec(plan)
+        torch.cuda.synchronize()
+        got = b.results()
+    finally:
+        dg.dd_batched_plan_destroy(plan)
+    want = b.singles()
+    for i, (g, w) in enumerate(zip(got, want)):
+        assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1]), i
+    rng = np.random.default_rng(9)
+    for i, (m, n, k) in enumerate(shapes):
+        P = b.P[i]
+        I = rng.integers(0, m, 8)
+        J = rng.integers(0, n, 8)
+        rh, rl, _ = dd_gemm_ref_entries(P["A"], P["B"], P["C"], I, J)
+        gh, gl = got[i][0].T[I, J], got[i][1].T[I, J]
+        AB = np.array([np.abs(P["A"][0][a]) @ np.abs(P["B"][0][:, c]) for a, c in zip(I, J)])
+        assert np.all(np.abs((gh - rh) + (gl - rl)) <= 64 * k * 2.0 ** -104 * AB), i
+
+
+def test_graph_replays_match_eager():
+    import torch
+    b = Batch(SMALL, cfg=32)
+    plan = b.plan()
+    try:
+        b.exec(plan)
+        torch.cuda.synchronize()
+        eager = b.results()
+        b.reset()
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                dg.check(dg.dd_gemm_batched_exec(plan, b.pA[0], b.pA[1], b.pB[0], b.pB[1], b.pC[0], b.pC[1],
+                                                 stream=s))
+        torch.cuda.synchronize()
+        for r in range(4):
+            b.reset()
+            x = torch.randn(1000, 1000, device="cuda", dtype=torch.float64)   # eager work between replays
+            (x @ x).sum().item()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for i, (gg, w) in enumerate(zip(b.results(), eager)):
+                assert np.array_equal(gg[0], w[0]) and np.array_equal(gg[1], w[1]), (r, i)
+        del g
+    finally:
+        dg.dd_batched_plan_destroy(plan)
+
+
+def test_tuner_records_choice(tmp_path):
+    import torch
+    os.environ["DDGEMM_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+    try:
+        b = Batch(SMALL[:8], cfg=33)
+        plan = b.plan()
+        try:
+            dg.check(dg.dd_batched_plan_tune(plan, b.pA[0], b.pA[1], b.pB[0], b.pB[1], b.pC[0], b.pC[1], 2))
+            st, nt, dyn, lpt, nbytes = dg.dd_batched_plan_info(plan)
+            assert st == 0 and nt > 0 and dyn in (0, 1) and lpt in (0, 1) and nbytes > 0
+            lines = open(tmp_path / "tune.txt").read().split()
+            assert len(lines) == 3 and int(lines[1]) == dyn and int(lines[2]) == lpt
+        finally:
+            dg.dd_batched_plan_destroy(plan)
+        plan2 = b.plan()   # a new plan of the same shapes starts from the recorded choice
+        try:
+            st, nt, dyn2, lpt2, _ = dg.dd_batched_plan_info(plan2)
+            assert (dyn2, lpt2) == (dyn, lpt)
+        finally:
+            dg.dd_batched_plan_destroy(plan2)
+        torch.cuda.synchronize()
+    finally:
+        del os.environ["DDGEMM_TUNE_CACHE"]
