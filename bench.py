@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "cascade_kernel_8192_traffic.json"),
                     help="JSON file with measured HBM bytes per launch of the product kernel "
                          "(used only while the kernel source is unchanged since the measurement)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (512 uneven problems) and differentiation timings")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy of MIB MiB (reads and writes that many "
                          "bytes once), the reference for scaling HBM byte counters")
@@ -53,6 +55,91 @@ def parse():
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def bench_batched(torch, dg, stream):
+    """512 independent FP64x2 GEMMs, m, n, k log-uniform in [32, 1024]: one
+    persistent launch captured in a HIP graph (schedule tuned) against a loop
+    of single dd_gemm calls on the same stream."""
+    from paper_2303_04353_amd.inputs import batched_shapes, make_problem
+    shapes = batched_shapes(512)
+    flops = sum(2.0 * m * n * k for m, n, k in shapes)
+    A, B, C = [], [], []
+    for i, (m, n, k) in enumerate(shapes):
+        P = make_problem(m, n, k, cfg=3, salt=i)
+        A.append(tuple(dg.colmajor_to_device(x) for x in P["A"]))
+        B.append(tuple(dg.colmajor_to_device(x) for x in P["B"]))
+        C.append(tuple(dg.colmajor_to_device(x) for x in P["C"]))
+    ptr = lambda lst, w: torch.tensor([t[w].data_ptr() for t in lst], dtype=torch.int64, device="cuda")
+    pa, pb, pc = (ptr(A, 0), ptr(A, 1)), (ptr(B, 0), ptr(B, 1)), (ptr(C, 0), ptr(C, 1))
+    mm, nn, kk = [s[0] for s in shapes], [s[1] for s in shapes], [s[2] for s in shapes]
+    st, plan = dg.dd_batched_plan_create(len(shapes), mm, nn, kk, mm, kk, mm)
+    dg.check(st, "dd_batched_plan_create")
+    try:
+        dg.check(dg.dd_batched_plan_tune(plan, pa[0], pa[1], pb[0], pb[1], pc[0], pc[1], 3, stream=stream))
+        _, ntiles, dyn, lpt, nbytes = dg.dd_batched_plan_info(plan)
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(g, stream=cap):
+                dg.check(dg.dd_gemm_batched_exec(plan, pa[0], pa[1], pb[0], pb[1], pc[0], pc[1], stream=cap))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        reps = 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(reps):
+                g.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / reps
+
+        def loop():
+            for i, (m, n, k) in enumerate(shapes):
+                dg.check(dg.dd_gemm(m, n, k, A[i][0], A[i][1], m, B[i][0], B[i][1], k, C[i][0], C[i][1], m,
+                                    stream))
+        loop()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            loop()
+        torch.cuda.synchronize()
+        lms = (time.perf_counter() - t0) * 1e3 / reps
+        del g
+    finally:
+        dg.dd_batched_plan_destroy(plan)
+    return {"workload": "512 FP64x2 GEMMs, m, n, k each round(exp(U[ln 32, ln 1024])), uniform inputs",
+            "sum_2mnk": flops, "tiles": ntiles, "schedule": {"atomic_counter": bool(dyn), "lpt": bool(lpt)},
+            "graph_ms": round(gms, 3), "graph_gflops": round(flops / (gms * 1e-3) / 1e9, 1),
+            "loop_of_dd_gemm_ms": round(lms, 3), "loop_gflops": round(flops / (lms * 1e-3) / 1e9, 1),
+            "speedup": round(lms / gms, 2), "plan_device_bytes": nbytes}
+
+
+def bench_autograd(torch):
+    """Forward and cascaded backward of L = sum((W2 (W1 X)) o G), W 2048^2, X, G 2048x512."""
+    from paper_2303_04353_amd import autograd as ag
+    from paper_2303_04353_amd.inputs import make_pair
+    n, b = 2048, 512
+    mk = lambda shape, seed: ag.dd_from_pair(*[torch.from_numpy(v.copy()) for v in make_pair(shape, seed=seed)]).cuda()
+    W1, W2, X, G = mk((n, n), 11), mk((n, n), 12), mk((n, b), 13), mk((n, b), 14)
+    gL = torch.tensor([1.0, 0.0], dtype=torch.float64, device="cuda")
+
+    def run():
+        w1, w2, x = (t.detach().requires_grad_() for t in (W1, W2, X))
+        ag.chain_loss(w1, w2, x, G).backward(gL)
+    run()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    flops = 6 * 2.0 * n * n * b
+    return {"workload": "L = sum((W2 (W1 X)) o G), W1, W2 2048x2048, X, G 2048x512, forward + backward "
+                        "(2 + 4 cascaded GEMMs)", "ms": round(ms, 3), "gflops": round(flops / (ms * 1e-3) / 1e9, 1)}
 
 
 def main():
@@ -217,6 +304,11 @@ def main():
                 np.array_equal(Vs[0][:S], Rh) and np.array_equal(Vs[1][:S], Rl))
             vdiff = np.abs((Vs[0][:S] - Rh) + (Vs[1][:S] - Rl))
             result["comparator"]["max_rel_err"] = float(np.max(vdiff[nz] / denom[nz]))
+    if not args.no_extras:
+        log("batched: 512 uneven problems")
+        result["batched"] = bench_batched(torch, dg, stream)
+        log("differentiation chain")
+        result["autograd"] = bench_autograd(torch)
     print(json.dumps(result), flush=True)
 
 
