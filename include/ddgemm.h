@@ -58,16 +58,37 @@ typedef enum {
   /* Plain software double-double GEMM on the FP64 vector units: the "FP64x2
    * arithmetic" triple loop the paper compares against (Sec. 5.2); per entry
    * acc += a*b in DD arithmetic, inner index ascending, C added last. */
-  DD_ALGO_DD_VALU = 1
+  DD_ALGO_DD_VALU = 1,
+  /* Narrow slices on the BF16 / FP16 matrix cores (the bfloat16 cascade of
+   * Sec. 6.2 carried to FP64x2 with equal-width splits and the product
+   * triangle of Sec. 6.1).  Each row of A and column of B is scaled by the
+   * power of two of its largest |fl(hi + lo)| and cut into `slices` integer
+   * slices of `slice_bits` bits (round to nearest on a fixed grid, the
+   * remainder carried as an FP64 pair), stored exactly in BF16 or FP16.  The
+   * s(s+1)/2 products A_i B_j with i + j < s are summed per level i + j on
+   * v_mfma_f32_32x32x16 with FP32 accumulation, flushed to FP64 before any
+   * partial sum could exceed 2^24, so every level sum is exact; level sums
+   * are gathered in FP64 groups of three (exact below 2^53, which bounds a
+   * chunk of the inner dimension) and the groups are added in FP64x2 from
+   * the least significant.  Accuracy: the dropped products and slice
+   * remainders are below (s+1) 2^-(s w) per inner index relative to the row
+   * and column scales. */
+  DD_ALGO_SLICES_BF16 = 2,
+  DD_ALGO_SLICES_F16 = 3
 } dd_algo;
 
 /* Options of dd_gemm_ex / dd_gemm_batched.  A NULL pointer means all zero. */
 typedef struct {
   int32_t algo;        /* dd_algo                                                  */
-  int32_t kc;          /* inner block of one rank-kc update (Sec. 3.5); 0 = 256.
-                          Must be a multiple of 4 in [4, 4096].  The split widths
-                          follow from min(kc, k) by the constraints of Sec. 3.3. */
-  int32_t tile;        /* cascade tile configuration, 0 = chosen by the library  */
+  int32_t kc;          /* cascade: inner block of one rank-kc update (Sec. 3.5);
+                          0 = 256.  Must be a multiple of 4 in [4, 4096].  The
+                          split widths follow from min(kc, k) by the constraints
+                          of Sec. 3.3.  Must be 0 for the slices variants.      */
+  int32_t tile;        /* must be 0 (tile configuration chosen by the library)    */
+  int32_t slices;      /* slices variants: s in [1, 16]; 0 = 14 (BF16), 12 (FP16) */
+  int32_t slice_bits;  /* slices variants: w; 0 = 8 (BF16), 9 (FP16).  Needs
+                          w - 1 <= 8 (BF16) or 11 (FP16) significant bits and
+                          16 s 2^(2w-2) <= 2^24.  Both must be 0 otherwise.      */
   int32_t reserved0;   /* must be 0                                                */
   int64_t reserved1;   /* must be 0                                                */
 } dd_gemm_opts;
@@ -87,7 +108,10 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
                   hipStream_t stream);
 
 /* Bytes of device workspace dd_gemm_ex needs for this problem and options
- * (0 for DD_ALGO_DD_VALU).  Returns 0 as well for invalid arguments. */
+ * (0 for DD_ALGO_DD_VALU).  Returns 0 as well for invalid arguments.
+ * The slices variants need 2 s (mpad + npad) kpad bytes of packed slices
+ * (mpad, npad rounded up to 64, kpad to 16) plus, for s > 9, 8 mpad npad
+ * (ceil(s/3) - 3) bytes of FP64 group sums. */
 size_t dd_gemm_workspace_size(dd_op transa, dd_op transb,
                               int64_t m, int64_t n, int64_t k,
                               const dd_gemm_opts* opts);
@@ -176,6 +200,22 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
                            const double* X_hi, const double* X_lo, int64_t ldx,
                            int32_t kc, int32_t* exps, double* planes,
                            hipStream_t stream);
+
+/*
+ * The slice split of DD_ALGO_SLICES_BF16 / _F16 on its own, for inspection
+ * and testing.  `side` = 0: X is op(A), rows x cols = m x k, one exponent
+ * per row; `side` = 1: X is op(B), rows x cols = k x n, one per column.
+ * exps receives e (int32) with max |fl(hi + lo)| of the row/column in
+ * [2^(e-1), 2^e) (0 for an all-zero or non-finite one); `out` receives the
+ * 16-bit BF16 (f16 = 0) or FP16 (f16 = 1) patterns of the integer slices,
+ * slice t at out + t*rows*cols, column-major with leading dimension rows.
+ * slices / slice_bits as in dd_gemm_opts (0 = the format's default).
+ * exps and out are device pointers.
+ */
+dd_status dd_slices_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
+                          const double* X_hi, const double* X_lo, int64_t ldx,
+                          int32_t f16, int32_t slices, int32_t slice_bits,
+                          int32_t* exps, uint16_t* out, hipStream_t stream);
 
 /*
  * FP64x2 dot product: result[0] + result[1] = sum_i x_i y_i, computed in

@@ -11,8 +11,9 @@
 namespace ddk {
 
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+// Largest |X| (|fl(X + Xlo)| if Xlo is given) per outer index, as bits.
 hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int64_t so, int64_t sr,
-                               uint64_t* out, hipStream_t s);
+                               uint64_t* out, hipStream_t s, const double* Xlo = nullptr);
 hipError_t launch_pack_a(const double* Ahi, const double* Alo, int64_t si, int64_t sp,
                          const CascadeLayout& L, const uint64_t* amax, double* Apack, hipStream_t s);
 hipError_t launch_pack_b(const double* Bhi, const double* Blo, int64_t sp, int64_t sj,
@@ -58,5 +59,19 @@ hipError_t launch_dd_dot(int64_t n, const double* xh, const double* xl, int64_t 
                          double* part, double* res, hipStream_t s);
 hipError_t launch_dd_scal(int64_t n, double ah, double al, const double* xh, const double* xl, int64_t incx,
                           double* yh, double* yl, int64_t incy, hipStream_t s);
+
+// The narrow-slice variant: split of op(A) (outer = m) or op(B) (outer = n)
+// into packed BF16/FP16 slices, X(o, r) at X[o*so + r*sr] (r the inner index;
+// maxbits from launch_max_abs_bits with the lo plane); the product passes
+// for inner steps [q0, q1) (16 indices each), C := C + result; and a
+// diagnostic unpack of packed slices into plain 16-bit planes.
+hipError_t launch_slices_split(const double* Xhi, const double* Xlo, int64_t so, int64_t sr, int64_t outer,
+                               int64_t red, int64_t opad, const SlicesLayout& L, const uint64_t* maxbits,
+                               void* pack, hipStream_t s);
+hipError_t launch_slices_product(const SlicesLayout& L, const void* Apack, const void* Bpack,
+                                 const uint64_t* amax, const uint64_t* bmax, double* planes, double* Chi,
+                                 double* Clo, int64_t ldc, int64_t q0, int64_t q1, hipStream_t s);
+hipError_t launch_slices_unpack(const void* pack, int64_t outer, int64_t red, const SlicesLayout& L,
+                                int64_t oo, int64_t ro, uint16_t* out, hipStream_t s);
 
 }  // namespace ddk

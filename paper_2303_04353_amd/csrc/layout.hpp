@@ -93,4 +93,69 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
   return L;
 }
 
+// Workspace of the narrow-slice variant.  Slices are 16-bit integers-valued
+// BF16 or FP16 numbers packed for v_mfma_f32_32x32x16_{bf16,f16}: for each
+// 32-row block rb of op(A) (32-column block of op(B)), each step q of 16 inner
+// indices and each slice t, one 64-lane operand of 16 bytes per lane; lane l
+// holds row (column) rb*32 + l%32 and inner indices q*16 + 8*(l/32) + 0..7:
+//   pack[((rb*Q + q)*S + t)*64 + l]   (in 16-byte units)
+// Rows/columns are padded with zeros to the 64 x 64 workgroup tile and the
+// inner dimension to a multiple of 16.
+struct SlicesLayout {
+  int64_t m, n, k;
+  int64_t mpad, npad, kpad, Q;  // Q = kpad / 16 steps
+  int32_t S, w, f16;            // slice count, width, format (1 = FP16)
+  int32_t chunk_q;              // steps per inner-dimension chunk (group sums exact)
+  int32_t flush_mask[16];       // level L is flushed to FP64 every flush_mask[L] + 1 steps
+  size_t off_amax, off_bmax, off_apack, off_bpack, off_planes, bytes;
+};
+
+// Slice counts above this run the levels from it upwards in a pass of their
+// own, whose FP64 group sums go through the workspace.
+constexpr int kSlicesSplit = 9;
+
+// Largest chunk of the inner dimension (a multiple of 16) keeping every FP64
+// level-group sum an exact integer: k s 2^(2w-2) (2^2w + 2^w + 1) <= 2^53.
+inline int64_t slices_chunk_limit(int w, int S) {
+  const double per = (double)S * __builtin_ldexp(1.0, 2 * w - 2) *
+                     (__builtin_ldexp(1.0, 2 * w) + __builtin_ldexp(1.0, w) + 1.0);
+  const int64_t lim = (int64_t)(__builtin_ldexp(1.0, 53) / per);
+  return lim / 16 * 16;
+}
+
+// (w, S) usable in the format: slices (|a| <= 2^(w-1)) exact in it, and the
+// FP32 sums of the top level exact over one 16-deep step.
+inline bool slices_params_ok(int w, int S, bool f16) {
+  const int bits = f16 ? 11 : 8;
+  if (w < 2 || w > bits + 1 || S < 1 || S > 16) return false;
+  return 16.0 * S * __builtin_ldexp(1.0, 2 * w - 2) <= __builtin_ldexp(1.0, 24);
+}
+
+inline SlicesLayout make_slices_layout(int64_t m, int64_t n, int64_t k, int S, int w, bool f16) {
+  SlicesLayout L{};
+  L.m = m; L.n = n; L.k = k;
+  L.S = S; L.w = w; L.f16 = f16 ? 1 : 0;
+  L.mpad = round_up(m > 0 ? m : 1, 64);
+  L.npad = round_up(n > 0 ? n : 1, 64);
+  L.kpad = round_up(k > 0 ? k : 1, 16);
+  L.Q = L.kpad / 16;
+  L.chunk_q = (int32_t)(slices_chunk_limit(w, S) / 16);
+  for (int lv = 0; lv < 16; ++lv) {
+    // largest power-of-two number of steps with 16 * steps * (lv+1) * 2^(2w-2) <= 2^24
+    int64_t steps = 1;
+    while (2.0 * 16 * steps * (lv + 1) * __builtin_ldexp(1.0, 2 * w - 2) <= __builtin_ldexp(1.0, 24)) steps *= 2;
+    L.flush_mask[lv] = (int32_t)(steps - 1);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up((int64_t)(off + bytes), 256); return o; };
+  L.off_amax = take(sizeof(uint64_t) * (size_t)L.mpad);
+  L.off_bmax = take(sizeof(uint64_t) * (size_t)L.npad);
+  L.off_apack = take(2 * (size_t)S * (size_t)L.mpad * (size_t)L.kpad);
+  L.off_bpack = take(2 * (size_t)S * (size_t)L.npad * (size_t)L.kpad);
+  const int upper_groups = S > kSlicesSplit ? (S + 2) / 3 - kSlicesSplit / 3 : 0;
+  L.off_planes = take(sizeof(double) * (size_t)upper_groups * (size_t)L.mpad * (size_t)L.npad);
+  L.bytes = off;
+  return L;
+}
+
 }  // namespace ddk

@@ -172,8 +172,55 @@ dd_status run_split(const Problem& p, const CascadeLayout& L, char* ws, hipStrea
   return DD_OK;
 }
 
-dd_status run(const Problem& p, int32_t algo, int32_t kc, void* workspace, size_t ws_bytes,
-              bool internal_ws, hipStream_t s) {
+// Options after validation.
+struct Opts {
+  int32_t algo = DD_ALGO_CASCADE_F64;
+  int32_t kc = kDefaultKc;
+  int32_t S = 0, w = 0;   // slices variants
+  bool slices() const { return algo == DD_ALGO_SLICES_BF16 || algo == DD_ALGO_SLICES_F16; }
+  bool f16() const { return algo == DD_ALGO_SLICES_F16; }
+};
+
+// Slice count and width with the format's defaults filled in; false if unusable.
+bool slice_params(bool f16, int32_t slices, int32_t bits, int32_t* S, int32_t* w) {
+  *S = slices ? slices : (f16 ? 12 : 14);
+  *w = bits ? bits : (f16 ? 9 : 8);
+  return ddk::slices_params_ok(*w, *S, f16);
+}
+
+ddk::SlicesLayout slices_layout(const Problem& p, const Opts& o) {
+  return ddk::make_slices_layout(p.m, p.n, p.k, o.S, o.w, o.f16());
+}
+
+// Phase one of the slices variant: exponents from max |fl(hi + lo)|, then the split.
+dd_status run_slices_split(const Problem& p, const ddk::SlicesLayout& L, char* ws, hipStream_t s) {
+  int64_t a_si, a_sp, b_sp, b_sj;
+  strides(p, a_si, a_sp, b_sp, b_sj);
+  uint64_t* amax = (uint64_t*)(ws + L.off_amax);
+  uint64_t* bmax = (uint64_t*)(ws + L.off_bmax);
+  DD_TRY(ddk::launch_fill_u64(amax, L.mpad, 0, s));
+  DD_TRY(ddk::launch_fill_u64(bmax, L.npad, 0, s));
+  DD_TRY(ddk::launch_max_abs_bits(p.Ahi, p.m, p.k, a_si, a_sp, amax, s, p.Alo));
+  DD_TRY(ddk::launch_max_abs_bits(p.Bhi, p.n, p.k, b_sj, b_sp, bmax, s, p.Blo));
+  DD_TRY(ddk::launch_slices_split(p.Ahi, p.Alo, a_si, a_sp, p.m, p.k, L.mpad, L, amax, ws + L.off_apack, s));
+  DD_TRY(ddk::launch_slices_split(p.Bhi, p.Blo, b_sj, b_sp, p.n, p.k, L.npad, L, bmax, ws + L.off_bpack, s));
+  return DD_OK;
+}
+
+// The product passes, one inner-dimension chunk after another.
+dd_status run_slices_product(const Problem& p, const ddk::SlicesLayout& L, char* ws, hipStream_t s) {
+  for (int64_t q0 = 0; q0 < L.Q; q0 += L.chunk_q) {
+    const int64_t q1 = q0 + L.chunk_q < L.Q ? q0 + L.chunk_q : L.Q;
+    DD_TRY(ddk::launch_slices_product(L, ws + L.off_apack, ws + L.off_bpack, (const uint64_t*)(ws + L.off_amax),
+                                      (const uint64_t*)(ws + L.off_bmax), (double*)(ws + L.off_planes), p.Chi,
+                                      p.Clo, p.ldc, q0, q1, s));
+  }
+  return DD_OK;
+}
+
+dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes, bool internal_ws,
+              hipStream_t s) {
+  const int32_t algo = o.algo, kc = o.kc;
   int dev = 0;
   dd_status st = check_device(&dev);
   if (st != DD_OK) return st;
@@ -183,6 +230,29 @@ dd_status run(const Problem& p, int32_t algo, int32_t kc, void* workspace, size_
     strides(p, a_si, a_sp, b_sp, b_sj);
     return hip_status(ddk::launch_dd_valu(p.m, p.n, p.k, p.Ahi, p.Alo, a_si, a_sp, p.Bhi, p.Blo,
                                           b_sp, b_sj, p.Chi, p.Clo, p.ldc, s));
+  }
+  if (o.slices()) {
+    const ddk::SlicesLayout L = slices_layout(p, o);
+    char* ws = (char*)workspace;
+    if (internal_ws) {
+      void* w = nullptr;
+      st = cached_workspace(dev, s, L.bytes, &w);
+      if (st != DD_OK) return st;
+      ws = (char*)w;
+    } else if (ws_bytes < L.bytes || ((uintptr_t)ws & 255u) != 0) {
+      return DD_ERR_WORKSPACE;
+    }
+    PhaseEvents pe = prof_begin(s);
+    st = run_slices_split(p, L, ws, s);
+    if (st != DD_OK) return st;
+    if (pe.e1) (void)hipEventRecord(pe.e1, s);
+    st = run_slices_product(p, L, ws, s);
+    if (pe.e2) {
+      (void)hipEventRecord(pe.e2, s);
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_prof_events.push_back(pe);
+    }
+    return st;
   }
   const CascadeLayout L = ddk::make_layout(p.m, p.n, p.k, kc, kTileM, kTileN);
   char* ws = (char*)workspace;
@@ -222,28 +292,33 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
   Problem p{DD_OP_N, DD_OP_N, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc};
   Arg a = validate(p);
   if (a != ARG_OK) return -pos[a];
-  return run(p, DD_ALGO_CASCADE_F64, kDefaultKc, nullptr, 0, true, stream);
+  return run(p, Opts{}, nullptr, 0, true, stream);
 }
 
-static bool read_opts(const dd_gemm_opts* o, int32_t* algo, int32_t* kc) {
-  *algo = DD_ALGO_CASCADE_F64;
-  *kc = kDefaultKc;
+static bool read_opts(const dd_gemm_opts* o, Opts* out) {
+  *out = Opts{};
   if (!o) return true;
-  if (o->algo != DD_ALGO_CASCADE_F64 && o->algo != DD_ALGO_DD_VALU) return false;
-  if (o->kc != 0 && !valid_kc(o->kc)) return false;
+  if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_SLICES_F16) return false;
   if (o->tile != 0 || o->reserved0 != 0 || o->reserved1 != 0) return false;
-  *algo = o->algo;
-  if (o->kc != 0) *kc = o->kc;
+  out->algo = o->algo;
+  if (out->slices()) {
+    if (o->kc != 0) return false;
+    return slice_params(out->f16(), o->slices, o->slice_bits, &out->S, &out->w);
+  }
+  if (o->slices != 0 || o->slice_bits != 0) return false;
+  if (o->kc != 0 && !valid_kc(o->kc)) return false;
+  if (o->kc != 0) out->kc = o->kc;
   return true;
 }
 
 size_t dd_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
                               const dd_gemm_opts* opts) {
-  int32_t algo, kc;
-  if (!read_opts(opts, &algo, &kc)) return 0;
+  Opts o;
+  if (!read_opts(opts, &o)) return 0;
   if ((transa != DD_OP_N && transa != DD_OP_T) || (transb != DD_OP_N && transb != DD_OP_T)) return 0;
-  if (m <= 0 || n <= 0 || k <= 0 || algo == DD_ALGO_DD_VALU) return 0;
-  return ddk::make_layout(m, n, k, kc, kTileM, kTileN).bytes;
+  if (m <= 0 || n <= 0 || k <= 0 || o.algo == DD_ALGO_DD_VALU) return 0;
+  if (o.slices()) return ddk::make_slices_layout(m, n, k, o.S, o.w, o.f16()).bytes;
+  return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN).bytes;
 }
 
 dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
@@ -256,11 +331,11 @@ dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k
   Problem p{(int)transa, (int)transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc};
   Arg a = validate(p);
   if (a != ARG_OK) return -pos[a];
-  int32_t algo, kc;
-  if (!read_opts(opts, &algo, &kc)) return -17;
+  Opts o;
+  if (!read_opts(opts, &o)) return -17;
   const bool internal = workspace == nullptr && ws_bytes == 0;
   if (!internal && workspace == nullptr) return -15;
-  return run(p, algo, kc, workspace, ws_bytes, internal, stream);
+  return run(p, o, workspace, ws_bytes, internal, stream);
 }
 
 dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
@@ -309,6 +384,58 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
     DD_TRY(ddk::launch_pack_b(p.Bhi, p.Blo, b_sp, b_sj, L, bmax, (double*)(ws + L.off_bpack), stream));
     DD_TRY(ddk::launch_unpack((const double*)(ws + L.off_bpack), 1, k, n, L.K4, planes, stream));
     DD_TRY(ddk::launch_exps(bmax, n, exps, stream));
+  }
+  return DD_OK;
+}
+
+dd_status dd_slices_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
+                          const double* X_hi, const double* X_lo, int64_t ldx,
+                          int32_t f16, int32_t slices, int32_t slice_bits,
+                          int32_t* exps, uint16_t* out, hipStream_t stream) {
+  if (side != 0 && side != 1) return -1;
+  if (trans != DD_OP_N && trans != DD_OP_T) return -2;
+  if (rows < 0) return -3;
+  if (cols < 0) return -4;
+  const int64_t srows = trans ? cols : rows;
+  if (ldx < (srows > 1 ? srows : 1)) return -7;
+  if (f16 != 0 && f16 != 1) return -8;
+  Opts o;
+  o.algo = f16 ? DD_ALGO_SLICES_F16 : DD_ALGO_SLICES_BF16;
+  if (!slice_params(f16 != 0, slices, slice_bits, &o.S, &o.w)) return -9;
+  if (rows == 0 || cols == 0) return DD_OK;
+  if (!X_hi) return -5;
+  if (!X_lo) return -6;
+  if (!exps) return -11;
+  if (!out) return -12;
+  int dev = 0;
+  dd_status st = check_device(&dev);
+  if (st != DD_OK) return st;
+  // X as op(A) (side 0: outer = rows) or op(B) (side 1: outer = cols); inner = the other
+  Problem p{};
+  p.transa = p.transb = (int)trans;
+  if (side == 0) { p.m = rows; p.n = 1; p.k = cols; p.Ahi = X_hi; p.Alo = X_lo; p.lda = ldx; }
+  else { p.m = 1; p.n = cols; p.k = rows; p.Bhi = X_hi; p.Blo = X_lo; p.ldb = ldx; }
+  const ddk::SlicesLayout L = slices_layout(p, o);
+  void* w = nullptr;
+  st = cached_workspace(dev, stream, L.bytes, &w);
+  if (st != DD_OK) return st;
+  char* ws = (char*)w;
+  int64_t a_si, a_sp, b_sp, b_sj;
+  strides(p, a_si, a_sp, b_sp, b_sj);
+  if (side == 0) {
+    uint64_t* amax = (uint64_t*)(ws + L.off_amax);
+    DD_TRY(ddk::launch_fill_u64(amax, L.mpad, 0, stream));
+    DD_TRY(ddk::launch_max_abs_bits(p.Ahi, rows, cols, a_si, a_sp, amax, stream, p.Alo));
+    DD_TRY(ddk::launch_slices_split(p.Ahi, p.Alo, a_si, a_sp, rows, cols, L.mpad, L, amax, ws + L.off_apack, stream));
+    DD_TRY(ddk::launch_slices_unpack(ws + L.off_apack, rows, cols, L, 1, rows, out, stream));
+    DD_TRY(ddk::launch_exps(amax, rows, exps, stream));
+  } else {
+    uint64_t* bmax = (uint64_t*)(ws + L.off_bmax);
+    DD_TRY(ddk::launch_fill_u64(bmax, L.npad, 0, stream));
+    DD_TRY(ddk::launch_max_abs_bits(p.Bhi, cols, rows, b_sj, b_sp, bmax, stream, p.Blo));
+    DD_TRY(ddk::launch_slices_split(p.Bhi, p.Blo, b_sj, b_sp, cols, rows, L.npad, L, bmax, ws + L.off_bpack, stream));
+    DD_TRY(ddk::launch_slices_unpack(ws + L.off_bpack, cols, rows, L, rows, 1, out, stream));
+    DD_TRY(ddk::launch_exps(bmax, cols, exps, stream));
   }
   return DD_OK;
 }

@@ -1,0 +1,366 @@
+// The narrow-slice variant: FP64x2 GEMM from BF16/FP16 matrix-core products
+// with exact FP32 level sums (the bfloat16 cascade of Sec. 6.2 carried to
+// FP64x2, with equal-width splits and the product triangle of Sec. 6.1).
+//
+//  * slices_split: per entry of op(A) (op(B)), scaled by the power of two of
+//    its row (column), s slices of w bits: the running remainder, an
+//    unevaluated FP64 pair, is rounded to the grid u_t = 2^-((t+1)w-1) with
+//    (r + K) - K and renormalised by TwoSum.  Each slice a_t = d_t / u_t is an
+//    integer with |a_t| <= 2^(w-1), stored exactly as BF16 or FP16 and packed
+//    as MFMA operands (one 16-byte chunk per lane and slice).
+//  * slices_product: one 64 x 64 output tile per workgroup, a 32 x 32 block
+//    per wave.  For every 16-deep step, the products A_i B_j with
+//    i + j = L < s go to the FP32 accumulator of level L
+//    (v_mfma_f32_32x32x16).  All operands are integers, so FP32 sums are
+//    exact while below 2^24: level L is flushed to its FP64 group every
+//    2^n steps with 16 * 2^n * (L+1) * 2^(2w-2) <= 2^24.  Groups of three
+//    levels share one FP64 accumulator (the lower levels shifted up by w and
+//    2w bits; exact below 2^53, which bounds the inner-dimension chunk).
+//    The epilogue adds the groups in FP64x2 from the least significant,
+//    applies the row and column powers of two and adds C.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dd_device.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace ddk {
+
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kGroup = 3;     // levels per FP64 accumulator
+constexpr int kXcds = 8;      // XCDs of the MI355X; workgroups go round-robin over them
+constexpr int kGroupM = 8;    // tile rows per group of the tile order
+
+__device__ __forceinline__ void tile_order(int64_t b, int64_t tiles_m, int64_t tiles_n, int64_t& tm,
+                                           int64_t& tn) {
+  // consecutive workgroups of one XCD take neighbouring tiles (shared L2)
+  const int64_t T = tiles_m * tiles_n;
+  int64_t L = b;
+  if (T % kXcds == 0) L = (b % kXcds) * (T / kXcds) + b / kXcds;
+  const int64_t per_group = kGroupM * tiles_n;
+  const int64_t g = L / per_group;
+  const int64_t first_m = g * kGroupM;
+  const int64_t gm = tiles_m - first_m < kGroupM ? tiles_m - first_m : kGroupM;
+  const int64_t r = L - g * per_group;
+  tm = first_m + r % gm;
+  tn = r / gm;
+}
+
+// Exact 16-bit pattern of an integer-valued double with |a| <= 2^8 (BF16) or
+// 2^11 (FP16); NaN and Inf map to NaN and Inf.
+template <bool F16>
+__device__ __forceinline__ uint32_t slice_bits(double a) {
+  const float f = (float)a;
+  if constexpr (F16) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
+  } else {
+    return __builtin_bit_cast(uint32_t, f) >> 16;
+  }
+}
+
+// One thread per (outer index o, group of 8 inner indices r8): the 8 entries
+// X(o, 8 r8 + e) = X[o*so + r*sr] are split and written as one 16-byte chunk
+// per slice.
+template <bool F16>
+__global__ void __launch_bounds__(256)
+slices_split(const double* __restrict__ Xhi, const double* __restrict__ Xlo, int64_t so, int64_t sr,
+             int64_t outer, int64_t red, int64_t opad, int64_t Q, int S, int w,
+             const uint64_t* __restrict__ maxbits, u32x4* __restrict__ pack) {
+  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (u >= opad * Q * 2) return;
+  const int64_t o = u % opad, r8 = u / opad;
+  const int ex = o < outer ? exp_of_bits(maxbits[o]) : 0;
+  uint32_t words[16][4];
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+#pragma unroll
+    for (int h = 0; h < 4; ++h) words[t][h] = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t r = r8 * 8 + e;
+    double xh = 0.0, xl = 0.0;
+    if (o < outer && r < red) {
+      xh = __builtin_ldexp(Xhi[o * so + r * sr], -ex);
+      xl = __builtin_ldexp(Xlo[o * so + r * sr], -ex);
+    }
+    double rem, rho;
+    two_sum(xh, xl, rem, rho);
+    for (int t = 0; t < S; ++t) {
+      const double K = __builtin_ldexp(3.0, 52 - (t + 1) * w);
+      const double d = (rem + K) - K;
+      const uint32_t bits = slice_bits<F16>(d * __builtin_ldexp(1.0, (t + 1) * w - 1));
+      const double left = rem - d;
+      two_sum(left, rho, rem, rho);
+      // constant-index stores keep `words` in registers
+#pragma unroll
+      for (int tt = 0; tt < 16; ++tt)
+        if (tt == t) words[tt][e >> 1] |= bits << (16 * (e & 1));
+    }
+  }
+  const int64_t rb = o / 32, q = r8 / 2;
+  const int lane = (int)(o % 32) + 32 * (int)(r8 % 2);
+  u32x4* dst = pack + ((rb * Q + q) * S) * 64 + lane;
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+    if (t < S) dst[t * 64] = u32x4{words[t][0], words[t][1], words[t][2], words[t][3]};
+}
+
+template <bool F16>
+__device__ __forceinline__ f32x16 mma(u32x4 a, u32x4 b, f32x16 c) {
+  if constexpr (F16) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b),
+                                                   c, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                    c, 0, 0, 0);
+  }
+}
+
+struct ProductArgs {
+  const u32x4* Apack;
+  const u32x4* Bpack;
+  const uint64_t* amax;
+  const uint64_t* bmax;
+  double* Chi;
+  double* Clo;
+  double* planes;    // FP64 group sums of the upper pass (NGU groups per wave and tile)
+  int64_t ldc, m, n, tiles_m, tiles_n, Q;
+  int32_t S, NG, NGU;  // slices (operand stride), groups in total, groups of the upper pass
+  int32_t q0, q1, w;
+  int32_t flush_mask[16];
+};
+
+// Levels [LB, LE) of the product triangle for one 64 x 64 tile.  With LB == 0
+// the epilogue combines every group (groups at or above LE/3 are read from
+// `planes`) and updates C; otherwise it writes its groups to `planes`.
+template <int LB, int LE, bool F16>
+__global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
+  static_assert(LB % kGroup == 0, "a pass owns whole level groups");
+  constexpr int NL = LE - LB;
+  constexpr int G0 = LB / kGroup, NGP = (LE + kGroup - 1) / kGroup - G0;   // groups of this pass
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t tm, tn;
+  tile_order(blockIdx.x, a.tiles_m, a.tiles_n, tm, tn);
+  const int64_t rb = tm * 2 + (wv >> 1), cb = tn * 2 + (wv & 1);
+  const int64_t step = (int64_t)a.S * 64;
+  const u32x4* __restrict__ Ap = a.Apack + rb * a.Q * step + lane;
+  const u32x4* __restrict__ Bp = a.Bpack + cb * a.Q * step + lane;
+
+  f32x16 acc[NL];
+  double grp[NGP][16];
+#pragma unroll
+  for (int L = 0; L < NL; ++L)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[L][v] = 0.0f;
+#pragma unroll
+  for (int g = 0; g < NGP; ++g)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) grp[g][v] = 0.0;
+  const double up1 = __builtin_ldexp(1.0, a.w), up2 = __builtin_ldexp(1.0, 2 * a.w);
+
+  // slices 0 .. LE-1 of both operands take part (every one reaches level LE-1)
+  u32x4 fa[LE], fb[LE];
+  {
+    const int64_t base = (int64_t)a.q0 * step;
+#pragma unroll
+    for (int t = 0; t < LE; ++t) {
+      fa[t] = Ap[base + t * 64];
+      fb[t] = Bp[base + t * 64];
+    }
+  }
+  for (int q = a.q0; q < a.q1; ++q) {
+    const bool more = q + 1 < a.q1;
+    // next step's operands (the current step's again on the last step)
+    const int64_t nxt = (int64_t)(more ? q + 1 : q) * step;
+#pragma unroll
+    for (int i = 0; i < LE; ++i) {
+      // j descending: the low B slices, used by most i, come last
+#pragma unroll
+      for (int j = LE - 1 - i; j >= 0 && i + j >= LB; --j) acc[i + j - LB] = mma<F16>(fa[i], fb[j], acc[i + j - LB]);
+      // A_i and B_{LE-1-i} are not needed again in this step
+      fa[i] = Ap[nxt + i * 64];
+      fb[LE - 1 - i] = Bp[nxt + (LE - 1 - i) * 64];
+    }
+    const uint32_t done = (uint32_t)(q - a.q0 + 1);
+#pragma unroll
+    for (int L = LB; L < LE; ++L) {
+      if ((done & (uint32_t)a.flush_mask[L]) == 0 || !more) {
+        const int g = L / kGroup - G0, shift = kGroup - 1 - L % kGroup;
+        const double sc = shift == 2 ? up2 : (shift == 1 ? up1 : 1.0);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          grp[g][v] = __builtin_fma((double)acc[L - LB][v], sc, grp[g][v]);
+          acc[L - LB][v] = 0.0f;
+        }
+      }
+    }
+  }
+
+  // group sums of the upper pass: per tile, wave, group and register, 64 lanes
+  const int64_t tile = tm * a.tiles_n + tn;
+  double* plane = a.planes + ((tile * 4 + wv) * (int64_t)a.NGU * 16) * 64 + lane;
+  if constexpr (LB > 0) {
+#pragma unroll
+    for (int g = 0; g < NGP; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) plane[(g * 16 + v) * 64] = grp[g][v];
+    return;
+  } else {
+    // epilogue: lane holds rows 8*(v/4) + 4*(lane/32) + v%4, column lane%32 of its block
+    const int64_t j = cb * 32 + (lane & 31);
+    if (j >= a.n) return;
+    const int fj = exp_of_bits(a.bmax[j]);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t i = rb * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      if (i < a.m) {
+        double h = 0.0, l = 0.0;
+        for (int g = a.NG - 1; g >= NGP; --g) {
+          const double W = __builtin_ldexp(1.0, 2 - (kGroup * g + kGroup + 1) * a.w);
+          dd_add_d(h, l, plane[((g - NGP) * 16 + v) * 64] * W, h, l);
+        }
+#pragma unroll
+        for (int g = NGP - 1; g >= 0; --g) {
+          const double W = __builtin_ldexp(1.0, 2 - (kGroup * g + kGroup + 1) * a.w);
+          dd_add_d(h, l, grp[g][v] * W, h, l);
+        }
+        const int sh = exp_of_bits(a.amax[i]) + fj;
+        h = __builtin_ldexp(h, sh);
+        l = __builtin_ldexp(l, sh);
+        double* ch = a.Chi + i + j * a.ldc;
+        double* cl = a.Clo + i + j * a.ldc;
+        double rh, rl;
+        dd_add(*ch, *cl, h, l, rh, rl);
+        *ch = rh;
+        *cl = rl;
+      }
+    }
+  }
+}
+
+template <int LB, int LE, bool F16>
+hipError_t launch_pass(const ProductArgs& a, int64_t blocks, hipStream_t s) {
+  slices_product<LB, LE, F16><<<(unsigned)blocks, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// Levels below kSplit run in the final pass; slice counts above it add an
+// upper pass for levels kSplit .. S-1 that runs first.
+constexpr int kSplit = kSlicesSplit;
+static_assert(kSplit % kGroup == 0, "the passes split between level groups");
+
+template <bool F16>
+hipError_t launch_lower(int S, const ProductArgs& a, int64_t blocks, hipStream_t s) {
+  switch (S < kSplit ? S : kSplit) {
+    case 1: return launch_pass<0, 1, F16>(a, blocks, s);
+    case 2: return launch_pass<0, 2, F16>(a, blocks, s);
+    case 3: return launch_pass<0, 3, F16>(a, blocks, s);
+    case 4: return launch_pass<0, 4, F16>(a, blocks, s);
+    case 5: return launch_pass<0, 5, F16>(a, blocks, s);
+    case 6: return launch_pass<0, 6, F16>(a, blocks, s);
+    case 7: return launch_pass<0, 7, F16>(a, blocks, s);
+    case 8: return launch_pass<0, 8, F16>(a, blocks, s);
+    case 9: return launch_pass<0, 9, F16>(a, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <bool F16>
+hipError_t launch_upper(int S, const ProductArgs& a, int64_t blocks, hipStream_t s) {
+  switch (S) {
+    case 10: return launch_pass<kSplit, 10, F16>(a, blocks, s);
+    case 11: return launch_pass<kSplit, 11, F16>(a, blocks, s);
+    case 12: return launch_pass<kSplit, 12, F16>(a, blocks, s);
+    case 13: return launch_pass<kSplit, 13, F16>(a, blocks, s);
+    case 14: return launch_pass<kSplit, 14, F16>(a, blocks, s);
+    case 15: return launch_pass<kSplit, 15, F16>(a, blocks, s);
+    case 16: return launch_pass<kSplit, 16, F16>(a, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_slices_split(const double* Xhi, const double* Xlo, int64_t so, int64_t sr, int64_t outer,
+                               int64_t red, int64_t opad, const SlicesLayout& L, const uint64_t* maxbits,
+                               void* pack, hipStream_t s) {
+  const int64_t units = opad * L.Q * 2;
+  const unsigned blocks = (unsigned)((units + 255) / 256);
+  if (L.f16) {
+    slices_split<true><<<blocks, 256, 0, s>>>(Xhi, Xlo, so, sr, outer, red, opad, L.Q, L.S, L.w, maxbits,
+                                              (u32x4*)pack);
+  } else {
+    slices_split<false><<<blocks, 256, 0, s>>>(Xhi, Xlo, so, sr, outer, red, opad, L.Q, L.S, L.w, maxbits,
+                                               (u32x4*)pack);
+  }
+  return hipGetLastError();
+}
+
+namespace {
+
+// Diagnostic copy of packed slices into plain column-major 16-bit planes:
+// element (o, r) of slice t goes to out[t*plane + o*oo + r*ro].
+__global__ void __launch_bounds__(256)
+slices_unpack(const uint16_t* __restrict__ pack, int64_t outer, int64_t red, int64_t Q, int S,
+              int64_t oo, int64_t ro, uint16_t* __restrict__ out) {
+  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t plane = outer * red;
+  if (u >= plane * S) return;
+  const int t = (int)(u / plane);
+  const int64_t rest = u - (int64_t)t * plane;
+  const int64_t o = rest % outer, r = rest / outer;
+  const int64_t rb = o / 32, q = r / 16;
+  const int lane = (int)(o % 32) + 32 * (int)((r % 16) / 8);
+  out[t * plane + o * oo + r * ro] = pack[(((rb * Q + q) * S + t) * 64 + lane) * 8 + (r % 8)];
+}
+
+}  // namespace
+
+hipError_t launch_slices_unpack(const void* pack, int64_t outer, int64_t red, const SlicesLayout& L,
+                                int64_t oo, int64_t ro, uint16_t* out, hipStream_t s) {
+  const int64_t units = outer * red * L.S;
+  slices_unpack<<<(unsigned)((units + 255) / 256), 256, 0, s>>>((const uint16_t*)pack, outer, red, L.Q, L.S,
+                                                                oo, ro, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_slices_product(const SlicesLayout& L, const void* Apack, const void* Bpack,
+                                 const uint64_t* amax, const uint64_t* bmax, double* planes, double* Chi,
+                                 double* Clo, int64_t ldc, int64_t q0, int64_t q1, hipStream_t s) {
+  ProductArgs a{};
+  a.Apack = (const u32x4*)Apack;
+  a.Bpack = (const u32x4*)Bpack;
+  a.amax = amax;
+  a.bmax = bmax;
+  a.Chi = Chi;
+  a.Clo = Clo;
+  a.planes = planes;
+  a.ldc = ldc;
+  a.m = L.m;
+  a.n = L.n;
+  a.tiles_m = L.mpad / 64;
+  a.tiles_n = L.npad / 64;
+  a.Q = L.Q;
+  a.S = L.S;
+  a.NG = (L.S + kGroup - 1) / kGroup;
+  a.NGU = L.S > kSplit ? a.NG - kSplit / kGroup : 0;
+  a.q0 = (int32_t)q0;
+  a.q1 = (int32_t)q1;
+  a.w = L.w;
+  for (int i = 0; i < 16; ++i) a.flush_mask[i] = L.flush_mask[i];
+  const int64_t blocks = a.tiles_m * a.tiles_n;
+  if (L.S > kSplit) {
+    const hipError_t e = L.f16 ? launch_upper<true>(L.S, a, blocks, s) : launch_upper<false>(L.S, a, blocks, s);
+    if (e != hipSuccess) return e;
+  }
+  return L.f16 ? launch_lower<true>(L.S, a, blocks, s) : launch_lower<false>(L.S, a, blocks, s);
+}
+
+}  // namespace ddk

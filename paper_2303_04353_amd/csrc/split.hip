@@ -1,9 +1,10 @@
 // Phase one of the cascade (Sec. 4): Sigma and T, then the split of
 // Appendix A into pre-weighted, MFMA-fragment-packed digit planes.
 //
-//  * max_abs_bits_*: per row of op(A) / column of op(B), the largest |hi| as a
-//    bit pattern (non-negative doubles order like their bits), reduced with
-//    atomicMax; the exponent e = frexp_exp(max) is taken where it is used.
+//  * max_abs_bits_*: per row of op(A) / column of op(B), the largest |hi| (or
+//    |fl(hi + lo)| when the lo plane is given) as a bit pattern (non-negative
+//    doubles order like their bits), reduced with atomicMax; the exponent
+//    e = frexp_exp(max) is taken where it is used.
 //  * pack_a / pack_b: one wave per 64-lane fragment, each lane splits one
 //    entry and writes its 4 (A) or 7 (B) planes; zero padding outside m, n, k.
 //  * unpack_*: diagnostic copy of the packed planes into plain column-major
@@ -24,15 +25,16 @@ __global__ void fill_u64(uint64_t* p, int64_t n, uint64_t v) {
 
 // Element (o, r) at X[o + r*ld]: consecutive threads take consecutive o.
 __global__ void __launch_bounds__(256)
-max_abs_bits_outer_contig(const double* __restrict__ X, int64_t outer, int64_t red, int64_t ld,
-                          int64_t chunk, uint64_t* __restrict__ out) {
+max_abs_bits_outer_contig(const double* __restrict__ X, const double* __restrict__ Xlo, int64_t outer,
+                          int64_t red, int64_t ld, int64_t chunk, uint64_t* __restrict__ out) {
   int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (o >= outer) return;
   int64_t r0 = (int64_t)blockIdx.y * chunk;
   int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
   uint64_t mx = 0;
   for (int64_t r = r0; r < r1; ++r) {
-    uint64_t b = __builtin_bit_cast(uint64_t, X[o + r * ld]) & 0x7fffffffffffffffull;
+    const double v = Xlo ? X[o + r * ld] + Xlo[o + r * ld] : X[o + r * ld];
+    uint64_t b = __builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull;
     mx = b > mx ? b : mx;
   }
   if (r1 > r0) atomicMax((unsigned long long*)&out[o], (unsigned long long)mx);
@@ -40,8 +42,8 @@ max_abs_bits_outer_contig(const double* __restrict__ X, int64_t outer, int64_t r
 
 // Element (o, r) at X[r + o*ld]: one wave per o, lanes stride over r.
 __global__ void __launch_bounds__(256)
-max_abs_bits_red_contig(const double* __restrict__ X, int64_t outer, int64_t red, int64_t ld,
-                        int64_t chunk, uint64_t* __restrict__ out) {
+max_abs_bits_red_contig(const double* __restrict__ X, const double* __restrict__ Xlo, int64_t outer,
+                        int64_t red, int64_t ld, int64_t chunk, uint64_t* __restrict__ out) {
   int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (o >= outer) return;
@@ -49,8 +51,10 @@ max_abs_bits_red_contig(const double* __restrict__ X, int64_t outer, int64_t red
   int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
   uint64_t mx = 0;
   const double* col = X + o * ld;
+  const double* col_lo = Xlo ? Xlo + o * ld : nullptr;
   for (int64_t r = r0 + lane; r < r1; r += 64) {
-    uint64_t b = __builtin_bit_cast(uint64_t, col[r]) & 0x7fffffffffffffffull;
+    const double v = col_lo ? col[r] + col_lo[r] : col[r];
+    uint64_t b = __builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull;
     mx = b > mx ? b : mx;
   }
 #pragma unroll
@@ -275,20 +279,20 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
 // max |X(o, r)| bits over r for o < outer, X(o, r) = X[o*so + r*sr]; one of
 // so, sr is 1.  out must be zero on entry.
 hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int64_t so, int64_t sr,
-                               uint64_t* out, hipStream_t s) {
+                               uint64_t* out, hipStream_t s, const double* Xlo) {
   if (outer <= 0 || red <= 0) return hipSuccess;
   if (so == 1) {
     int64_t chunk = 256;
     int64_t gy = (red + chunk - 1) / chunk;
     while (gy > 65535) { chunk *= 2; gy = (red + chunk - 1) / chunk; }
     dim3 grid(blocks_for(outer, 256), (unsigned)gy);
-    max_abs_bits_outer_contig<<<grid, 256, 0, s>>>(X, outer, red, sr, chunk, out);
+    max_abs_bits_outer_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, sr, chunk, out);
   } else {
     int64_t chunk = 4096;
     int64_t gy = (red + chunk - 1) / chunk;
     while (gy > 65535) { chunk *= 2; gy = (red + chunk - 1) / chunk; }
     dim3 grid(blocks_for(outer, 4), (unsigned)gy);
-    max_abs_bits_red_contig<<<grid, 256, 0, s>>>(X, outer, red, so, chunk, out);
+    max_abs_bits_red_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, so, chunk, out);
   }
   return hipGetLastError();
 }

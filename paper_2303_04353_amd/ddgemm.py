@@ -26,8 +26,10 @@ DD_OP_N = 0
 DD_OP_T = 1
 DD_ALGO_CASCADE_F64 = 0
 DD_ALGO_DD_VALU = 1
+DD_ALGO_SLICES_BF16 = 2
+DD_ALGO_SLICES_F16 = 3
 
-EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_dot",
+EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_slices_split", "dd_dot",
             "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",
             "dd_batched_plan_schedule", "dd_batched_plan_info", "dd_batched_plan_destroy",
             "dd_gemm_batched", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version")
@@ -35,6 +37,7 @@ EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split
 
 class dd_gemm_opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("kc", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("slices", ctypes.c_int32), ("slice_bits", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int64)]
 
 
@@ -65,6 +68,8 @@ def lib():
         L.dd_gemm_ex.restype = i32
         L.dd_cascade_split.argtypes = [i32, i32, i64, i64, vp, vp, i64, i32, vp, vp, vp]
         L.dd_cascade_split.restype = i32
+        L.dd_slices_split.argtypes = [i32, i32, i64, i64, vp, vp, i64, i32, i32, i32, vp, vp, vp]
+        L.dd_slices_split.restype = i32
         L.dd_dot.argtypes = [i64, vp, vp, i64, vp, vp, i64, vp, vp]
         L.dd_dot.restype = i32
         L.dd_scal.argtypes = [i64, ctypes.c_double, ctypes.c_double, vp, vp, i64, vp, vp, i64, vp]
@@ -156,6 +161,12 @@ def dd_gemm_ex(transa, transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, 
 def dd_cascade_split(side, trans, rows, cols, X_hi, X_lo, ldx, kc, exps, planes, stream=None) -> int:
     return int(lib().dd_cascade_split(int(side), int(trans), rows, cols, _ptr(X_hi), _ptr(X_lo), ldx,
                                       int(kc), _ptr(exps), _ptr(planes), _stream(stream)))
+
+
+def dd_slices_split(side, trans, rows, cols, X_hi, X_lo, ldx, f16, slices, slice_bits, exps, out,
+                    stream=None) -> int:
+    return int(lib().dd_slices_split(int(side), int(trans), rows, cols, _ptr(X_hi), _ptr(X_lo), ldx, int(f16),
+                                     int(slices), int(slice_bits), _ptr(exps), _ptr(out), _stream(stream)))
 
 
 def dd_dot(n, x_hi, x_lo, incx, y_hi, y_lo, incy, result, stream=None) -> int:

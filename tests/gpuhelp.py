@@ -23,7 +23,7 @@ def down(t):
 
 
 def run_gemm(A, B, C, *, transa=False, transb=False, algo=dg.DD_ALGO_CASCADE_F64, kc=0,
-             plain=False):
+             plain=False, slices=0, slice_bits=0):
     """op(A) op(B) + C on the GPU through the C ABI; A, B, C are numpy (hi, lo)
     pairs as stored.  Returns numpy (hi, lo)."""
     import torch
@@ -39,7 +39,7 @@ def run_gemm(A, B, C, *, transa=False, transb=False, algo=dg.DD_ALGO_CASCADE_F64
         st = dg.dd_gemm(m, n, k, Ah, Al, lda, Bh, Bl, ldb, Ch, Cl, ldc)
     else:
         st = dg.dd_gemm_ex(int(transa), int(transb), m, n, k, Ah, Al, lda, Bh, Bl, ldb, Ch, Cl, ldc,
-                           opts={"algo": algo, "kc": kc})
+                           opts={"algo": algo, "kc": kc, "slices": slices, "slice_bits": slice_bits})
     dg.check(st, "dd_gemm_ex")
     torch.cuda.synchronize()
     return down(Ch), down(Cl)

@@ -78,3 +78,36 @@ def test_workspace_size_formula():
     assert dg.dd_gemm_workspace_size(0, 0, 100, 70, 300, {"algo": dg.DD_ALGO_DD_VALU}) == 0
     assert dg.dd_gemm_workspace_size(3, 0, 100, 70, 300) == 0
     assert dg.dd_gemm_workspace_size(0, 0, 0, 70, 300) == 0
+
+
+def test_slices_options_and_workspace():
+    bf, f16 = dg.DD_ALGO_SLICES_BF16, dg.DD_ALGO_SLICES_F16
+    m, n, k = 100, 70, 300
+    mpad, npad, kpad = 128, 128, 304
+    # default BF16: 14 slices of 8 bits, plus the upper pass's groups 3 and 4
+    ws = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": bf})
+    need = 8 * (mpad + npad) + 2 * 14 * (mpad + npad) * kpad + 8 * 2 * mpad * npad
+    assert need <= ws <= need + 6 * 256
+    # nine slices or fewer run in one pass: no group planes
+    ws9 = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": bf, "slices": 9})
+    need9 = 8 * (mpad + npad) + 2 * 9 * (mpad + npad) * kpad
+    assert need9 <= ws9 <= need9 + 6 * 256
+    assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": f16}) > 0
+    for bad in ({"algo": bf, "slice_bits": 10}, {"algo": bf, "slices": 17}, {"algo": f16, "slice_bits": 10},
+                {"algo": bf, "kc": 256}, {"algo": 0, "slices": 4}, {"algo": 1, "slice_bits": 8},
+                {"algo": f16, "slice_bits": 12, "slices": 1}, {"algo": 4}):
+        assert dg.dd_gemm_workspace_size(0, 0, m, n, k, bad) == 0, bad
+    assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": f16, "slice_bits": 11, "slices": 1}) > 0
+    base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"algo": bf, "slices": 20}, stream=0) == -17
+
+
+def test_slices_split_rejects_bad_arguments():
+    assert dg.dd_slices_split(2, 0, 4, 4, 8, 16, 4, 0, 0, 0, 32, 64, stream=0) == -1
+    assert dg.dd_slices_split(0, 2, 4, 4, 8, 16, 4, 0, 0, 0, 32, 64, stream=0) == -2
+    assert dg.dd_slices_split(0, 0, -4, 4, 8, 16, 4, 0, 0, 0, 32, 64, stream=0) == -3
+    assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 3, 0, 0, 0, 32, 64, stream=0) == -7
+    assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 2, 0, 0, 32, 64, stream=0) == -8
+    assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 0, 0, 10, 32, 64, stream=0) == -9
+    assert dg.dd_slices_split(0, 0, 4, 4, 0, 16, 4, 0, 0, 0, 32, 64, stream=0) == -5
+    assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 0, 0, 0, 0, 64, stream=0) == -11
