@@ -33,7 +33,7 @@ the number of slices:
    S_L 2^(w(3g+2-L)) -- exact while
    k * s * 2^(2w-2) * (2^(2w) + 2^w + 1) <= 2^53; the inner dimension is cut
    into consecutive chunks of at most ``chunk_limit`` indices (a multiple of
-   16) otherwise, each chunk computed and added to C in turn.
+   64) otherwise, each chunk computed and added to C in turn.
 5. Combine: V = sum_g G_g W_g with W_g = 2^(2 - (3g+4)w), accumulated in
    FP64x2 from the last (least significant) group to group 0 with the
    FP64x2 + FP64 addition; both words scaled by 2^(e_i + f_j); C added last
@@ -85,10 +85,10 @@ def flush_depths(w: int, s: int):
 
 
 def chunk_limit(w: int, s: int):
-    """Largest inner-dimension chunk (a multiple of 16) for which every level
+    """Largest inner-dimension chunk (a multiple of 64) for which every level
     group sum stays an exact FP64 integer."""
     per = s * 2 ** (2 * w - 2) * (2 ** (2 * w) + 2 ** w + 1)
-    return (2 ** 53 // per) // 16 * 16
+    return (2 ** 53 // per) // 64 * 64
 
 
 def n_products(s: int) -> int:

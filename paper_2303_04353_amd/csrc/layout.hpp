@@ -100,12 +100,12 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
 // holds row (column) rb*32 + l%32 and inner indices q*16 + 8*(l/32) + 0..7:
 //   pack[((rb*Q + q)*S + t)*64 + l]   (in 16-byte units)
 // Rows/columns are padded with zeros to the 64 x 64 workgroup tile and the
-// inner dimension to a multiple of 16.
+// inner dimension to a multiple of 64 (whole blocks of four steps).
 struct SlicesLayout {
   int64_t m, n, k;
   int64_t mpad, npad, kpad, Q;  // Q = kpad / 16 steps
   int32_t S, w, f16;            // slice count, width, format (1 = FP16)
-  int32_t chunk_q;              // steps per inner-dimension chunk (group sums exact)
+  int32_t chunk_q;              // steps per inner-dimension chunk (group sums exact), a multiple of 4
   int32_t flush_mask[16];       // level L is flushed to FP64 every flush_mask[L] + 1 steps
   size_t off_amax, off_bmax, off_apack, off_bpack, off_planes, bytes;
 };
@@ -114,13 +114,13 @@ struct SlicesLayout {
 // own, whose FP64 group sums go through the workspace.
 constexpr int kSlicesSplit = 9;
 
-// Largest chunk of the inner dimension (a multiple of 16) keeping every FP64
+// Largest chunk of the inner dimension (a multiple of 64) keeping every FP64
 // level-group sum an exact integer: k s 2^(2w-2) (2^2w + 2^w + 1) <= 2^53.
 inline int64_t slices_chunk_limit(int w, int S) {
   const double per = (double)S * __builtin_ldexp(1.0, 2 * w - 2) *
                      (__builtin_ldexp(1.0, 2 * w) + __builtin_ldexp(1.0, w) + 1.0);
   const int64_t lim = (int64_t)(__builtin_ldexp(1.0, 53) / per);
-  return lim / 16 * 16;
+  return lim / 64 * 64;
 }
 
 // (w, S) usable in the format: slices (|a| <= 2^(w-1)) exact in it, and the
@@ -137,7 +137,7 @@ inline SlicesLayout make_slices_layout(int64_t m, int64_t n, int64_t k, int S, i
   L.S = S; L.w = w; L.f16 = f16 ? 1 : 0;
   L.mpad = round_up(m > 0 ? m : 1, 64);
   L.npad = round_up(n > 0 ? n : 1, 64);
-  L.kpad = round_up(k > 0 ? k : 1, 16);
+  L.kpad = round_up(k > 0 ? k : 1, 64);
   L.Q = L.kpad / 16;
   L.chunk_q = (int32_t)(slices_chunk_limit(w, S) / 16);
   for (int lv = 0; lv < 16; ++lv) {

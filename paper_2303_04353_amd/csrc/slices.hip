@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dd_device.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
@@ -123,6 +125,43 @@ __device__ __forceinline__ f32x16 mma(u32x4 a, u32x4 b, f32x16 c) {
   }
 }
 
+// A scheduling group of n MFMAs (n is a constant once the loops are unrolled).
+template <int N>
+__device__ __forceinline__ void mfma_group_n() {
+  __builtin_amdgcn_sched_group_barrier(0x008, N, 0);
+}
+__device__ __forceinline__ void mfma_group(int n) {
+  switch (n) {
+    case 1: mfma_group_n<1>(); break;
+    case 2: mfma_group_n<2>(); break;
+    case 3: mfma_group_n<3>(); break;
+    case 4: mfma_group_n<4>(); break;
+    case 5: mfma_group_n<5>(); break;
+    case 6: mfma_group_n<6>(); break;
+    case 7: mfma_group_n<7>(); break;
+    case 8: mfma_group_n<8>(); break;
+    case 9: mfma_group_n<9>(); break;
+    case 10: mfma_group_n<10>(); break;
+    case 11: mfma_group_n<11>(); break;
+    case 12: mfma_group_n<12>(); break;
+    case 13: mfma_group_n<13>(); break;
+    case 14: mfma_group_n<14>(); break;
+    case 15: mfma_group_n<15>(); break;
+    case 16: mfma_group_n<16>(); break;
+    default: break;
+  }
+}
+
+// A scheduling group of n vector-memory reads (n in 1..3).
+__device__ __forceinline__ void vmem_group(int n) {
+  switch (n) {
+    case 1: __builtin_amdgcn_sched_group_barrier(0x020, 1, 0); break;
+    case 2: __builtin_amdgcn_sched_group_barrier(0x020, 2, 0); break;
+    case 3: __builtin_amdgcn_sched_group_barrier(0x020, 3, 0); break;
+    default: break;
+  }
+}
+
 struct ProductArgs {
   const u32x4* Apack;
   const u32x4* Bpack;
@@ -134,74 +173,119 @@ struct ProductArgs {
   int64_t ldc, m, n, tiles_m, tiles_n, Q;
   int32_t S, NG, NGU;  // slices (operand stride), groups in total, groups of the upper pass
   int32_t q0, q1, w;
-  int32_t flush_mask[16];
 };
 
 // Levels [LB, LE) of the product triangle for one 64 x 64 tile.  With LB == 0
 // the epilogue combines every group (groups at or above LE/3 are read from
 // `planes`) and updates C; otherwise it writes its groups to `planes`.
-template <int LB, int LE, bool F16>
+//
+// Flush schedule: level L goes to its FP64 group after the steps whose index
+// (counted from q0) is congruent to L modulo P, and at the end.  P divides 4
+// and every level's exact depth, so no FP32 sum passes 2^24; staggering the
+// levels spreads the conversions over the steps.  A flushed accumulator is
+// not cleared: the level's first product of the next step takes C = 0.  The
+// step loop is unrolled by 4 so that this schedule is fixed at compile time.
+template <int LB, int LE, int P, bool F16>
 __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
   static_assert(LB % kGroup == 0, "a pass owns whole level groups");
+  static_assert(P == 1 || P == 4, "the flush period divides the unroll");
   constexpr int NL = LE - LB;
   constexpr int G0 = LB / kGroup, NGP = (LE + kGroup - 1) / kGroup - G0;   // groups of this pass
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wave index is uniform: operand addresses are formed on the scalar unit
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int64_t tm, tn;
   tile_order(blockIdx.x, a.tiles_m, a.tiles_n, tm, tn);
   const int64_t rb = tm * 2 + (wv >> 1), cb = tn * 2 + (wv & 1);
   const int64_t step = (int64_t)a.S * 64;
-  const u32x4* __restrict__ Ap = a.Apack + rb * a.Q * step + lane;
-  const u32x4* __restrict__ Bp = a.Bpack + cb * a.Q * step + lane;
+  const u32x4* Ap = a.Apack + rb * a.Q * step + lane;   // not restrict: the loads stay where written
+  const u32x4* Bp = a.Bpack + cb * a.Q * step + lane;
 
   f32x16 acc[NL];
   double grp[NGP][16];
+  const f32x16 zero = {};
 #pragma unroll
-  for (int L = 0; L < NL; ++L)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[L][v] = 0.0f;
+  for (int L = 0; L < NL; ++L) acc[L] = zero;
 #pragma unroll
   for (int g = 0; g < NGP; ++g)
 #pragma unroll
     for (int v = 0; v < 16; ++v) grp[g][v] = 0.0;
   const double up1 = __builtin_ldexp(1.0, a.w), up2 = __builtin_ldexp(1.0, 2 * a.w);
 
-  // slices 0 .. LE-1 of both operands take part (every one reaches level LE-1)
-  u32x4 fa[LE], fb[LE];
+  // slices 0 .. LE-1 of both operands take part (every one reaches level LE-1).
+  // A_i is reloaded for the next step right after its products; B_0 is
+  // needed until the end of a step, so B has two buffers: the next step's B
+  // loads early in the current step.
+  u32x4 fa[LE], fb0[LE], fb1[LE];
   {
+    // same order as the loads inside the loop, so the waits there can count
     const int64_t base = (int64_t)a.q0 * step;
 #pragma unroll
-    for (int t = 0; t < LE; ++t) {
-      fa[t] = Ap[base + t * 64];
-      fb[t] = Bp[base + t * 64];
+    for (int i = 0; i < LE; ++i) {
+      fa[i] = Ap[base + i * 64];
+      if (2 * i < LE) fb0[2 * i] = Bp[base + 2 * i * 64];
+      if (2 * i + 1 < LE) fb0[2 * i + 1] = Bp[base + (2 * i + 1) * 64];
+      asm volatile("" ::: "memory");
     }
   }
-  for (int q = a.q0; q < a.q1; ++q) {
-    const bool more = q + 1 < a.q1;
-    // next step's operands (the current step's again on the last step)
-    const int64_t nxt = (int64_t)(more ? q + 1 : q) * step;
+
+  // level L's FP32 sum into its group (exact: an integer times a power of two)
+  auto flush = [&](int L) {
+    const int g = L / kGroup - G0, shift = kGroup - 1 - L % kGroup;
+    const double sc = shift == 2 ? up2 : (shift == 1 ? up1 : 1.0);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) grp[g][v] = __builtin_fma((double)acc[L - LB][v], sc, grp[g][v]);
+  };
+
+  // One 16-deep step of phase PH (its index from q0, mod 4): the products
+  // with B from `fb`, next step's A into fa and B into `fbn`, then the
+  // flushes of this phase.
+  auto run_step = [&](auto phase, const u32x4 (&fb)[LE], u32x4 (&fbn)[LE], int q) {
+    constexpr int PH = decltype(phase)::value;
+    const int64_t nxt = (int64_t)(q + 1 < a.q1 ? q + 1 : q) * step;   // in bounds on the last step
+    bool started[NL];
+#pragma unroll
+    for (int L = 0; L < NL; ++L) started[L] = false;
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
       // j descending: the low B slices, used by most i, come last
+      int nm = 0;
 #pragma unroll
-      for (int j = LE - 1 - i; j >= 0 && i + j >= LB; --j) acc[i + j - LB] = mma<F16>(fa[i], fb[j], acc[i + j - LB]);
-      // A_i and B_{LE-1-i} are not needed again in this step
-      fa[i] = Ap[nxt + i * 64];
-      fb[LE - 1 - i] = Bp[nxt + (LE - 1 - i) * 64];
-    }
-    const uint32_t done = (uint32_t)(q - a.q0 + 1);
-#pragma unroll
-    for (int L = LB; L < LE; ++L) {
-      if ((done & (uint32_t)a.flush_mask[L]) == 0 || !more) {
-        const int g = L / kGroup - G0, shift = kGroup - 1 - L % kGroup;
-        const double sc = shift == 2 ? up2 : (shift == 1 ? up1 : 1.0);
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          grp[g][v] = __builtin_fma((double)acc[L - LB][v], sc, grp[g][v]);
-          acc[L - LB][v] = 0.0f;
-        }
+      for (int j = LE - 1 - i; j >= 0 && i + j >= LB; --j, ++nm) {
+        const int L = i + j - LB;
+        // flushed after the previous step (phase PH-1): start from zero
+        const bool fresh = !started[L] && ((i + j) % P == (PH + P - 1) % P);
+        acc[L] = mma<F16>(fa[i], fb[j], fresh ? zero : acc[L]);
+        started[L] = true;
       }
+      // A_i is not needed again in this step; two of next step's B slices
+      fa[i] = Ap[nxt + i * 64];
+      int nl = 1;
+      if (2 * i < LE) { fbn[2 * i] = Bp[nxt + 2 * i * 64]; ++nl; }
+      if (2 * i + 1 < LE) { fbn[2 * i + 1] = Bp[nxt + (2 * i + 1) * 64]; ++nl; }
+      // keep the loads here (not sunk below the flushes)
+      asm volatile("" ::: "memory");
+      mfma_group(nm);                                      // this iteration's MFMAs,
+      vmem_group(nl);                                      // then its loads
     }
+#pragma unroll
+    for (int L = LB; L < LE; ++L)
+      if (L % P == PH % P) flush(L);
+  };
+  using Ph0 = std::integral_constant<int, 0>;
+  using Ph1 = std::integral_constant<int, 1>;
+  using Ph2 = std::integral_constant<int, 2>;
+  using Ph3 = std::integral_constant<int, 3>;
+  // q1 - q0 is a multiple of 4 (the inner dimension is padded to 64)
+  for (int q = a.q0; q < a.q1; q += 4) {
+    run_step(Ph0{}, fb0, fb1, q);
+    run_step(Ph1{}, fb1, fb0, q + 1);
+    run_step(Ph2{}, fb0, fb1, q + 2);
+    run_step(Ph3{}, fb1, fb0, q + 3);
   }
+  // levels not flushed after the last step (phase 3)
+#pragma unroll
+  for (int L = LB; L < LE; ++L)
+    if (L % P != 3 % P) flush(L);
 
   // group sums of the upper pass: per tile, wave, group and register, 64 lanes
   const int64_t tile = tm * a.tiles_n + tn;
@@ -245,9 +329,9 @@ __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
   }
 }
 
-template <int LB, int LE, bool F16>
+template <int LB, int LE, int P, bool F16>
 hipError_t launch_pass(const ProductArgs& a, int64_t blocks, hipStream_t s) {
-  slices_product<LB, LE, F16><<<(unsigned)blocks, 256, 0, s>>>(a);
+  slices_product<LB, LE, P, F16><<<(unsigned)blocks, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -256,34 +340,51 @@ hipError_t launch_pass(const ProductArgs& a, int64_t blocks, hipStream_t s) {
 constexpr int kSplit = kSlicesSplit;
 static_assert(kSplit % kGroup == 0, "the passes split between level groups");
 
-template <bool F16>
+template <int P, bool F16>
 hipError_t launch_lower(int S, const ProductArgs& a, int64_t blocks, hipStream_t s) {
   switch (S < kSplit ? S : kSplit) {
-    case 1: return launch_pass<0, 1, F16>(a, blocks, s);
-    case 2: return launch_pass<0, 2, F16>(a, blocks, s);
-    case 3: return launch_pass<0, 3, F16>(a, blocks, s);
-    case 4: return launch_pass<0, 4, F16>(a, blocks, s);
-    case 5: return launch_pass<0, 5, F16>(a, blocks, s);
-    case 6: return launch_pass<0, 6, F16>(a, blocks, s);
-    case 7: return launch_pass<0, 7, F16>(a, blocks, s);
-    case 8: return launch_pass<0, 8, F16>(a, blocks, s);
-    case 9: return launch_pass<0, 9, F16>(a, blocks, s);
+    case 1: return launch_pass<0, 1, P, F16>(a, blocks, s);
+    case 2: return launch_pass<0, 2, P, F16>(a, blocks, s);
+    case 3: return launch_pass<0, 3, P, F16>(a, blocks, s);
+    case 4: return launch_pass<0, 4, P, F16>(a, blocks, s);
+    case 5: return launch_pass<0, 5, P, F16>(a, blocks, s);
+    case 6: return launch_pass<0, 6, P, F16>(a, blocks, s);
+    case 7: return launch_pass<0, 7, P, F16>(a, blocks, s);
+    case 8: return launch_pass<0, 8, P, F16>(a, blocks, s);
+    case 9: return launch_pass<0, 9, P, F16>(a, blocks, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <bool F16>
+template <int P, bool F16>
 hipError_t launch_upper(int S, const ProductArgs& a, int64_t blocks, hipStream_t s) {
   switch (S) {
-    case 10: return launch_pass<kSplit, 10, F16>(a, blocks, s);
-    case 11: return launch_pass<kSplit, 11, F16>(a, blocks, s);
-    case 12: return launch_pass<kSplit, 12, F16>(a, blocks, s);
-    case 13: return launch_pass<kSplit, 13, F16>(a, blocks, s);
-    case 14: return launch_pass<kSplit, 14, F16>(a, blocks, s);
-    case 15: return launch_pass<kSplit, 15, F16>(a, blocks, s);
-    case 16: return launch_pass<kSplit, 16, F16>(a, blocks, s);
+    case 10: return launch_pass<kSplit, 10, P, F16>(a, blocks, s);
+    case 11: return launch_pass<kSplit, 11, P, F16>(a, blocks, s);
+    case 12: return launch_pass<kSplit, 12, P, F16>(a, blocks, s);
+    case 13: return launch_pass<kSplit, 13, P, F16>(a, blocks, s);
+    case 14: return launch_pass<kSplit, 14, P, F16>(a, blocks, s);
+    case 15: return launch_pass<kSplit, 15, P, F16>(a, blocks, s);
+    case 16: return launch_pass<kSplit, 16, P, F16>(a, blocks, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// The flush period of a pass: 4 steps if its top level (the one with the
+// smallest exact depth) allows it, else every step (always exact).
+inline int flush_period(const SlicesLayout& L, int top_level) {
+  return L.flush_mask[top_level] + 1 >= 4 ? 4 : 1;
+}
+
+template <bool F16>
+hipError_t launch_passes(const SlicesLayout& L, const ProductArgs& a, int64_t blocks, hipStream_t s) {
+  if (L.S > kSplit) {
+    const hipError_t e = flush_period(L, L.S - 1) == 4 ? launch_upper<4, F16>(L.S, a, blocks, s)
+                                                       : launch_upper<1, F16>(L.S, a, blocks, s);
+    if (e != hipSuccess) return e;
+  }
+  return flush_period(L, (L.S < kSplit ? L.S : kSplit) - 1) == 4 ? launch_lower<4, F16>(L.S, a, blocks, s)
+                                                                 : launch_lower<1, F16>(L.S, a, blocks, s);
 }
 
 }  // namespace
@@ -354,13 +455,8 @@ hipError_t launch_slices_product(const SlicesLayout& L, const void* Apack, const
   a.q0 = (int32_t)q0;
   a.q1 = (int32_t)q1;
   a.w = L.w;
-  for (int i = 0; i < 16; ++i) a.flush_mask[i] = L.flush_mask[i];
   const int64_t blocks = a.tiles_m * a.tiles_n;
-  if (L.S > kSplit) {
-    const hipError_t e = L.f16 ? launch_upper<true>(L.S, a, blocks, s) : launch_upper<false>(L.S, a, blocks, s);
-    if (e != hipSuccess) return e;
-  }
-  return L.f16 ? launch_lower<true>(L.S, a, blocks, s) : launch_lower<false>(L.S, a, blocks, s);
+  return L.f16 ? launch_passes<true>(L, a, blocks, s) : launch_passes<false>(L, a, blocks, s);
 }
 
 }  // namespace ddk

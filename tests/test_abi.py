@@ -83,7 +83,7 @@ def test_workspace_size_formula():
 def test_slices_options_and_workspace():
     bf, f16 = dg.DD_ALGO_SLICES_BF16, dg.DD_ALGO_SLICES_F16
     m, n, k = 100, 70, 300
-    mpad, npad, kpad = 128, 128, 304
+    mpad, npad, kpad = 128, 128, 320
     # default BF16: 14 slices of 8 bits, plus the upper pass's groups 3 and 4
     ws = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": bf})
     need = 8 * (mpad + npad) + 2 * 14 * (mpad + npad) * kpad + 8 * 2 * mpad * npad

@@ -50,10 +50,10 @@ def test_flush_depths_are_the_largest_exact_blocks(w, s):
 def test_chunk_limit_keeps_group_sums_below_2_53():
     for w, s in CONFIGS:
         c = sl.chunk_limit(w, s)
-        assert c % 16 == 0 and c > 0
+        assert c % 64 == 0 and c > 0
         worst = c * s * 2 ** (2 * w - 2) * (2 ** (2 * w) + 2 ** w + 1)
         assert worst <= 2 ** 53
-        assert (c + 16) * s * 2 ** (2 * w - 2) * (2 ** (2 * w) + 2 ** w + 1) > 2 ** 53
+        assert (c + 64) * s * 2 ** (2 * w - 2) * (2 ** (2 * w) + 2 ** w + 1) > 2 ** 53
     assert sl.chunk_limit(8, 14) > 8192 and sl.chunk_limit(9, 12) > 8192
 
 
