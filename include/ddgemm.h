@@ -85,10 +85,12 @@ typedef struct {
                           split widths follow from min(kc, k) by the constraints
                           of Sec. 3.3.  Must be 0 for the slices variants.      */
   int32_t tile;        /* must be 0 (tile configuration chosen by the library)    */
-  int32_t slices;      /* slices variants: s in [1, 16]; 0 = 14 (BF16), 12 (FP16) */
-  int32_t slice_bits;  /* slices variants: w; 0 = 8 (BF16), 9 (FP16).  Needs
-                          w - 1 <= 8 (BF16) or 11 (FP16) significant bits and
-                          16 s 2^(2w-2) <= 2^24.  Both must be 0 otherwise.      */
+  int32_t slices;      /* slices variants: s in [1, 16]; 0 = 14                   */
+  int32_t slice_bits;  /* slices variants: w; 0 = 8.  Needs w - 1 <= 8 (BF16) or
+                          11 (FP16) significant bits and 16 s 2^(2w-2) <= 2^24.
+                          With w <= 8 every level is flushed every 4 steps (the
+                          fast schedule); wider slices flush every step.  Both
+                          must be 0 for the other algorithms.                    */
   int32_t reserved0;   /* must be 0                                                */
   int64_t reserved1;   /* must be 0                                                */
 } dd_gemm_opts;

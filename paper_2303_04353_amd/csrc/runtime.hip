@@ -183,8 +183,8 @@ struct Opts {
 
 // Slice count and width with the format's defaults filled in; false if unusable.
 bool slice_params(bool f16, int32_t slices, int32_t bits, int32_t* S, int32_t* w) {
-  *S = slices ? slices : (f16 ? 12 : 14);
-  *w = bits ? bits : (f16 ? 9 : 8);
+  *S = slices ? slices : 14;
+  *w = bits ? bits : 8;
   return ddk::slices_params_ok(*w, *S, f16);
 }
 

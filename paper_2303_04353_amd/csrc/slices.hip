@@ -185,6 +185,7 @@ struct ProductArgs {
 // levels spreads the conversions over the steps.  A flushed accumulator is
 // not cleared: the level's first product of the next step takes C = 0.  The
 // step loop is unrolled by 4 so that this schedule is fixed at compile time.
+// The first step's "previous" flushes take the zero accumulators: harmless.
 template <int LB, int LE, int P, bool F16>
 __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
   static_assert(LB % kGroup == 0, "a pass owns whole level groups");
@@ -228,32 +229,48 @@ __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
     }
   }
 
-  // level L's FP32 sum into its group (exact: an integer times a power of two)
-  auto flush = [&](int L) {
+  // level L's FP32 sum `x` (values [v0, v1)) into its group (exact: an
+  // integer times a power of two)
+  auto flush_vals = [&](int L, const f32x16& x, int v0, int v1) {
     const int g = L / kGroup - G0, shift = kGroup - 1 - L % kGroup;
     const double sc = shift == 2 ? up2 : (shift == 1 ? up1 : 1.0);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) grp[g][v] = __builtin_fma((double)acc[L - LB][v], sc, grp[g][v]);
+    for (int v = v0; v < v1; ++v) grp[g][v] = __builtin_fma((double)x[v], sc, grp[g][v]);
   };
 
+  // With P = 4 a level's flush is deferred: at the start of the step after
+  // its flush point its sum is copied to `held` (before the level restarts
+  // from zero) and converted a few values per iteration, among the step's
+  // products.  With P = 1 every level flushes at the end of every step.
+  constexpr int NH = P == 4 ? (NL + 3) / 4 : 1;
+  constexpr int kSpread = LE < 8 ? LE : 8;            // iterations that take a share
+  constexpr int kShare = (16 + kSpread - 1) / kSpread;  // values per iteration
+  f32x16 held[NH];
+
   // One 16-deep step of phase PH (its index from q0, mod 4): the products
-  // with B from `fb`, next step's A into fa and B into `fbn`, then the
-  // flushes of this phase.
+  // with B from `fb`, next step's A into fa and B into `fbn`, the flushes.
   auto run_step = [&](auto phase, const u32x4 (&fb)[LE], u32x4 (&fbn)[LE], int q) {
     constexpr int PH = decltype(phase)::value;
+    constexpr int PREV = (PH + P - 1) % P;   // levels flushed after the previous step
     const int64_t nxt = (int64_t)(q + 1 < a.q1 ? q + 1 : q) * step;   // in bounds on the last step
+    if constexpr (P == 4) {
+      int h = 0;
+#pragma unroll
+      for (int L = LB; L < LE; ++L)
+        if (L % 4 == PREV) held[h++] = acc[L - LB];
+    }
     bool started[NL];
 #pragma unroll
     for (int L = 0; L < NL; ++L) started[L] = false;
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
-      // j descending: the low B slices, used by most i, come last
+      // levels ascending: the one restarted last in iteration 0 is the top one
       int nm = 0;
 #pragma unroll
-      for (int j = LE - 1 - i; j >= 0 && i + j >= LB; --j, ++nm) {
+      for (int j = (LB - i > 0 ? LB - i : 0); j <= LE - 1 - i; ++j, ++nm) {
         const int L = i + j - LB;
-        // flushed after the previous step (phase PH-1): start from zero
-        const bool fresh = !started[L] && ((i + j) % P == (PH + P - 1) % P);
+        // flushed after the previous step: start from zero
+        const bool fresh = !started[L] && ((i + j) % P == PREV);
         acc[L] = mma<F16>(fa[i], fb[j], fresh ? zero : acc[L]);
         started[L] = true;
       }
@@ -266,10 +283,20 @@ __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
       asm volatile("" ::: "memory");
       mfma_group(nm);                                      // this iteration's MFMAs,
       vmem_group(nl);                                      // then its loads
-    }
+      if constexpr (P == 4) {
+        if (i < kSpread) {
+          const int v0 = i * kShare, v1 = v0 + kShare < 16 ? v0 + kShare : 16;
+          int h = 0;
 #pragma unroll
-    for (int L = LB; L < LE; ++L)
-      if (L % P == PH % P) flush(L);
+          for (int L = LB; L < LE; ++L)
+            if (L % 4 == PREV) flush_vals(L, held[h++], v0, v1);
+        }
+      }
+    }
+    if constexpr (P == 1) {
+#pragma unroll
+      for (int L = LB; L < LE; ++L) flush_vals(L, acc[L - LB], 0, 16);
+    }
   };
   using Ph0 = std::integral_constant<int, 0>;
   using Ph1 = std::integral_constant<int, 1>;
@@ -282,10 +309,11 @@ __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
     run_step(Ph2{}, fb0, fb1, q + 2);
     run_step(Ph3{}, fb1, fb0, q + 3);
   }
-  // levels not flushed after the last step (phase 3)
+  // what every level has gathered since its last flush
+  if constexpr (P == 4) {
 #pragma unroll
-  for (int L = LB; L < LE; ++L)
-    if (L % P != 3 % P) flush(L);
+    for (int L = LB; L < LE; ++L) flush_vals(L, acc[L - LB], 0, 16);
+  }
 
   // group sums of the upper pass: per tile, wave, group and register, 64 lanes
   const int64_t tile = tm * a.tiles_n + tn;

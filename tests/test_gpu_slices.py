@@ -87,8 +87,7 @@ def test_defaults_meet_the_fp64x2_tolerance(variant, algo):
     got = run_gemm(P["A"], P["B"], P["C"], algo=algo)
     ref = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
     assert np.all(dd_diff(got, ref) <= north_star_bound(P["A"], P["B"], k))
-    w, s = (9, 12) if algo == F16 else (8, 14)
-    want = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s)
+    want = sl.slices_gemm(P["A"], P["B"], P["C"], w=8, s=14)
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
 
 
