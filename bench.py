@@ -47,6 +47,9 @@ def parse():
                          "(used only while the kernel source is unchanged since the measurement)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (512 uneven problems) and differentiation timings")
+    ap.add_argument("--slices-only", action="store_true",
+                    help="time only the narrow-slice variant at 4096^3 (for profiling it); "
+                         "not the headline workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy of MIB MiB (reads and writes that many "
                          "bytes once), the reference for scaling HBM byte counters")
@@ -117,6 +120,82 @@ def bench_batched(torch, dg, stream):
             "speedup": round(lms / gms, 2), "plan_device_bytes": nbytes}
 
 
+PEAK_BF16_MFMA_TFLOPS = 2500.0   # MI355X, dense BF16 / FP16 matrix
+
+
+def bench_slices(torch, dg, stream, n=4096, reps=3):
+    """The narrow-slice precision variant at m = n = k = 4096: BF16 and FP16
+    slices (w = 8 bits, s = 14 slices, 105 products), uniform and ill-scaled
+    inputs.  Returns the timings and, per case, the device result's sampled
+    entries for the accuracy check of the CPU-baseline leg."""
+    from paper_2303_04353_amd.inputs import make_problem, sample_entries
+    w, s = 8, 14
+    prods = s * (s + 1) // 2
+    out = {"workload": f"FP64x2 GEMM C := A*B + C, m=n=k={n}, slices of {w} bits, {s} slices, "
+                       f"{prods} products on 32x32x16 BF16/FP16 MFMA with exact FP32 level sums",
+           "slices": s, "slice_bits": w, "products": prods,
+           "flush_every_steps_of_16": 4, "cases": {}}
+    samples = {}
+    I, J = sample_entries(n, n, 4096, seed=13)
+    for variant in ("uniform", "ill"):
+        P = make_problem(n, n, n, cfg=2, variant=variant)
+        Ah, Al, Bh, Bl, C0h, C0l = (dg.colmajor_to_device(x) for x in (*P["A"], *P["B"], *P["C"]))
+        for fmt, algo in (("bf16", dg.DD_ALGO_SLICES_BF16), ("f16", dg.DD_ALGO_SLICES_F16)):
+            opts = {"algo": algo, "slices": s, "slice_bits": w}
+            Ch, Cl = C0h.clone(), C0l.clone()
+            dg.check(dg.dd_gemm_ex(0, 0, n, n, n, Ah, Al, n, Bh, Bl, n, Ch, Cl, n, opts=opts, stream=stream))
+            torch.cuda.synchronize()
+            Gh = Ch.T[torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()].cpu().numpy()
+            Gl = Cl.T[torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()].cpu().numpy()
+            dg.dd_profile_enable(1)
+            dg.dd_phase_times()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                dg.check(dg.dd_gemm_ex(0, 0, n, n, n, Ah, Al, n, Bh, Bl, n, Ch, Cl, n, opts=opts, stream=stream))
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            st, sp, pr, calls = dg.dd_phase_times()
+            dg.dd_profile_enable(0)
+            pr /= max(calls, 1)
+            sp /= max(calls, 1)
+            mfma = prods * 2.0 * n ** 3 / (pr * 1e-3) / 1e12
+            out["cases"][f"{fmt}_{variant}"] = {
+                "ms": round(ms, 3), "gflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 1),
+                "split_ms": round(sp, 3), "product_ms": round(pr, 3),
+                "mfma_tflops": round(mfma, 1), "pct_of_bf16_f16_peak": round(100 * mfma / PEAK_BF16_MFMA_TFLOPS, 1)}
+            samples[(fmt, variant)] = (Gh, Gl)
+            del Ch, Cl
+        samples[("problem", variant)] = P
+        del Ah, Al, Bh, Bl, C0h, C0l
+    return out, samples, (I, J)
+
+
+def slices_accuracy(out, samples, IJ, n=4096):
+    """Sampled entries of the slices results against the FP64x2 oracle, and
+    bit for bit against the slices oracle (CPU-baseline leg)."""
+    from oracle.ref import dd_gemm_ref_entries
+    from oracle.slices import slices_gemm_entries
+    I, J = IJ
+    for variant in ("uniform", "ill"):
+        P = samples[("problem", variant)]
+        Rh, Rl, _ = dd_gemm_ref_entries(P["A"], P["B"], P["C"], I, J)
+        k = 96   # exact slices-oracle entries (each a full split of one row and one column)
+        Sh, Sl = slices_gemm_entries(P["A"], P["B"], P["C"], I[:k], J[:k], w=out["slice_bits"], s=out["slices"])
+        AB = np.array([np.abs(P["A"][0][i]) @ np.abs(P["B"][0][:, j]) for i, j in zip(I[:1024], J[:1024])])
+        for fmt in ("bf16", "f16"):
+            Gh, Gl = samples[(fmt, variant)]
+            diff = np.abs((Gh - Rh) + (Gl - Rl))
+            nz = np.abs(Rh) > 0
+            rel = diff[nz] / np.abs(Rh[nz])
+            normed = diff[:1024] / AB
+            out["cases"][f"{fmt}_{variant}"].update({
+                "sampled_entries": int(len(I)), "max_rel_err": float(np.max(rel)),
+                "median_rel_err": float(np.median(rel)),
+                "max_err_over_absAabsB": float(np.max(normed)),
+                "within_tolerance": bool(np.all(normed <= 64 * n * 2.0 ** -104)),
+                "bitwise_equal_to_slices_oracle": bool(np.array_equal(Gh[:k], Sh) and np.array_equal(Gl[:k], Sl))})
+
+
 def bench_autograd(torch):
     """Forward and cascaded backward of L = sum((W2 (W1 X)) o G), W 2048^2, X, G 2048x512."""
     from paper_2303_04353_amd import autograd as ag
@@ -157,6 +236,12 @@ def main():
 
     torch.cuda.set_device(0)
     dg.lib()  # fails loudly if the HIP library is missing
+    if args.slices_only:
+        sres, samples, IJ = bench_slices(torch, dg, torch.cuda.current_stream(), reps=max(1, args.steps))
+        if not args.no_cpu_baseline:
+            slices_accuracy(sres, samples, IJ)
+        print(json.dumps({"slices": sres}), flush=True)
+        return
     N = args.size
     m = n = k = N
     if args.shape:
@@ -309,6 +394,14 @@ def main():
         result["batched"] = bench_batched(torch, dg, stream)
         log("differentiation chain")
         result["autograd"] = bench_autograd(torch)
+        log("slices variant at 4096^3")
+        del Ah, Al, Bh, Bl, Ch, Cl, C0h, C0l, dev
+        torch.cuda.empty_cache()
+        sres, samples, IJ = bench_slices(torch, dg, stream)
+        if not args.no_cpu_baseline:
+            log("slices accuracy against the oracles (sampled entries)")
+            slices_accuracy(sres, samples, IJ)
+        result["slices"] = sres
     print(json.dumps(result), flush=True)
 
 

@@ -34,7 +34,9 @@ def source_hash(path: str = PRODUCT_SOURCE) -> str:
 
 
 def _short(name: str) -> str:
-    name = name.strip('"')
+    name = name.strip('"').replace("(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
     cut = name.find("(")
     return name[:cut] if cut > 0 else name[:80]
 
