@@ -92,7 +92,14 @@ typedef struct {
                           fast schedule); wider slices flush every step.  Both
                           must be 0 for the other algorithms.                    */
   int32_t reserved0;   /* must be 0                                                */
-  int64_t reserved1;   /* must be 0                                                */
+  uint32_t* flags_out; /* cascade only, may be NULL: device bitmap of ceil(m n / 32)
+                          words, bit (i + j m) for entry (i, j) of C.  The call
+                          zeroes it, then sets the bit of every entry at risk of
+                          cancellation: in some rank-kc block the exact bin 0
+                          (the leading digits' product, Sec. 3.7 and Sec. 4.4)
+                          is zero while a lower bin of that block is not.  No
+                          correction is applied.  Must be NULL for the other
+                          algorithms and for the batched calls.                  */
 } dd_gemm_opts;
 
 /*

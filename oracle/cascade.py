@@ -30,6 +30,8 @@ Steps, in the paper's order and notation:
    expression for fl_casc): bin0 + (bin1 + (bin2 + fl(bin 3-6))); the
    rank-kc results are accumulated in FP64x2 (Sec. 4.2, Fig. gemmrankk).
 6. Apply Sigma and T (Sec. 4.2) and add C last.
+7. Cancellation flags (Sec. 3.7, Sec. 4.4): an entry is flagged when bin 0
+   of a rank-kc block is zero while a lower bin of that block is not.
 
 Readings where the paper is silent (each also listed in the design notes):
 B4', B5' and B6' are each rounded once to FP64 (B6' = RN(hi*2^-f + lo*2^-f));
@@ -166,6 +168,21 @@ def combine_bins(bin0, bin1, bin2, bin36):
     s, e = dd_add_d(s, e, bin1)
     s, e = dd_add_d(s, e, bin0)
     return s, e
+
+
+def cancellation_flags(blocks):
+    """Sec. 3.7 / Sec. 4.4: an entry is at risk of cancellation when a rank-kc
+    block's bin 0 (the leading digits' product, exact) is zero while one of
+    its lower bins is not.  ``blocks`` is the list of (bin0, bin1, bin2,
+    bin36) of every block (``cascade_gemm(..., return_parts=True)["bins"]``).
+    For k <= kc this is the paper's check on bin 0; a block whose bins are
+    all zero (zero row or column segment) carries no risk and is not
+    flagged."""
+    flag = None
+    for b0, b1, b2, b36 in blocks:
+        f = (b0 == 0) & ((b1 != 0) | (b2 != 0) | (b36 != 0))
+        flag = f if flag is None else (flag | f)
+    return flag
 
 
 def cascade_gemm(A, B, C=None, *, kc=256, c=None, return_parts=False):

@@ -132,12 +132,19 @@ __device__ __forceinline__ void ten_products(Bins& B, const Ops& o) {
 }
 
 // bin0 + (bin1 + (bin2 + bin36)) in FP64x2, added to the accumulator; bins reset.
+// With kFlags, bit (i * kWaveCB + g) of `flg` is set when this block's bin 0
+// is zero while a lower bin is not (cancellation, Sec. 3.7 and Sec. 4.4).
+template <bool kFlags>
 __device__ __forceinline__ void combine(Bins& B, double (&acc_h)[kSub][kWaveCB],
-                                        double (&acc_l)[kSub][kWaveCB]) {
+                                        double (&acc_l)[kSub][kWaveCB], uint32_t& flg) {
 #pragma unroll
   for (int i = 0; i < kSub; ++i)
 #pragma unroll
     for (int g = 0; g < kWaveCB; ++g) {
+      if constexpr (kFlags) {
+        const bool lower = B.b1[i][g] != 0.0 || B.b2[i][g] != 0.0 || B.b36[i][g] != 0.0;
+        if (B.b0[i][g] == 0.0 && lower) flg |= 1u << (i * kWaveCB + g);
+      }
       double s, e;
       two_sum(B.b2[i][g], B.b36[i][g], s, e);
       dd_add_d(s, e, B.b1[i][g], s, e);
@@ -173,14 +180,18 @@ __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? 
 }  // namespace
 
 // One 64x64 output tile (tile row tm, tile column tn) of one GEMM, computed
-// by the whole workgroup.  `lds` is the workgroup's staging memory.
+// by the whole workgroup.  `lds` is the workgroup's staging memory.  With
+// kFlags, entries at risk of cancellation get their bit set in the m x n
+// column-major bitmap `flags` (bit i + j*m).
+template <bool kFlags>
 __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const double* __restrict__ Apack,
                                              const double* __restrict__ Bpack,
                                              const uint64_t* __restrict__ amax,
                                              const uint64_t* __restrict__ bmax, int64_t K4, int32_t kcq,
                                              int64_t m, int64_t n, int64_t tm, int64_t tn,
                                              double* __restrict__ Chi, double* __restrict__ Clo,
-                                             int64_t ldc) {
+                                             int64_t ldc, uint32_t* __restrict__ flags) {
+  uint32_t flg = 0;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 1, wn = wave & 1;     // 16-row block wm, 32-column half wn
@@ -265,7 +276,7 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
     derive_b(ox);
     ten_products(bins, ox);
     interleave_reads();
-    if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
+    if (++inblk == kcq) { inblk = 0; combine<kFlags>(bins, acc_h, acc_l, flg); }
     derive_b(oy);
     if (st < last) {
       store_stage(st + 1);
@@ -276,9 +287,9 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
     }
     ten_products(bins, oy);
     interleave_reads();
-    if (++inblk == kcq) { inblk = 0; combine(bins, acc_h, acc_l); }
+    if (++inblk == kcq) { inblk = 0; combine<kFlags>(bins, acc_h, acc_l, flg); }
   }
-  if (inblk != 0) combine(bins, acc_h, acc_l);
+  if (inblk != 0) combine<kFlags>(bins, acc_h, acc_l, flg);
 
   // Epilogue: D lane 16i + 4b + j of (sub-block, group) holds row 4*sub + i,
   // column 16*group + 4b + j, i.e. row lane/16 and column lane%16.
@@ -299,19 +310,26 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
       dd_add(Chi[idx], Clo[idx], h, l, rh, rl);
       Chi[idx] = rh;
       Clo[idx] = rl;
+      if constexpr (kFlags) {
+        if (flg & (1u << (i * kWaveCB + g))) {
+          const int64_t bit = row + col * m;
+          atomicOr(&flags[bit >> 5], 1u << (bit & 31));
+        }
+      }
     }
   }
 }
 
+template <bool kFlags>
 __global__ void __launch_bounds__(kWaves * 64)
 cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpack,
                const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax,
                int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_m, int64_t tiles_n,
-               double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc) {
+               double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc, uint32_t* __restrict__ flags) {
   __shared__ __attribute__((aligned(16))) double lds[kNBuf * kStage];
   int64_t tm, tn;
   tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  cascade_tile(lds, Apack, Bpack, amax, bmax, K4, kcq, m, n, tm, tn, Chi, Clo, ldc);
+  cascade_tile<kFlags>(lds, Apack, Bpack, amax, bmax, K4, kcq, m, n, tm, tn, Chi, Clo, ldc, flags);
 }
 
 // Persistent form for a batch of GEMMs: every workgroup takes tiles from the
@@ -334,9 +352,9 @@ cascade_batched_kernel(const BatchDesc* __restrict__ desc, const BatchTile* __re
     if (w >= ntiles) break;
     const BatchTile t = tiles[w];
     const BatchDesc d = desc[t.p];
-    cascade_tile(lds, (const double*)(ws + d.off_apack), (const double*)(ws + d.off_bpack),
-                 (const uint64_t*)(ws + d.off_amax), (const uint64_t*)(ws + d.off_bmax), d.K4, d.kcq,
-                 d.m, d.n, t.tm, t.tn, Chi[t.p], Clo[t.p], d.ldc);
+    cascade_tile<false>(lds, (const double*)(ws + d.off_apack), (const double*)(ws + d.off_bpack),
+                        (const uint64_t*)(ws + d.off_amax), (const uint64_t*)(ws + d.off_bmax), d.K4, d.kcq,
+                        d.m, d.n, t.tm, t.tn, Chi[t.p], Clo[t.p], d.ldc, nullptr);
     __syncthreads();  // the next tile reuses the staging buffers
     if (!dynamic) w += gridDim.x;
   }
@@ -358,13 +376,18 @@ hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles,
 
 hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,
                           const uint64_t* amax, const uint64_t* bmax,
-                          double* Chi, double* Clo, int64_t ldc, hipStream_t s) {
+                          double* Chi, double* Clo, int64_t ldc, uint32_t* flags, hipStream_t s) {
   if (L.tile_m != kTile || L.tile_n != kTile || L.K4 % kStageQ != 0) return hipErrorInvalidValue;
   const int64_t tiles_m = L.mpad / kTile, tiles_n = L.npad / kTile;
   const int64_t tiles = tiles_m * tiles_n;
   if (tiles <= 0 || tiles > 0x7fffffff) return hipErrorInvalidValue;
-  cascade_kernel<<<(unsigned)tiles, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
-                                                 tiles_m, tiles_n, Chi, Clo, ldc);
+  if (flags) {
+    cascade_kernel<true><<<(unsigned)tiles, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m,
+                                                                 L.n, tiles_m, tiles_n, Chi, Clo, ldc, flags);
+  } else {
+    cascade_kernel<false><<<(unsigned)tiles, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m,
+                                                                  L.n, tiles_m, tiles_n, Chi, Clo, ldc, nullptr);
+  }
   return hipGetLastError();
 }
 

@@ -40,10 +40,13 @@ hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles,
                                   uint32_t* counter, int grid, bool dynamic, hipStream_t s);
 
 // The fused product kernel: ten FP64 MFMA products per rank-kc block, bins
-// combined in FP64x2, Sigma/T applied, C := C + result.
+// combined in FP64x2, Sigma/T applied, C := C + result.  `flags` (may be
+// null): m x n bitmap, zeroed by the caller, of entries at risk of
+// cancellation (a block's bin 0 zero while a lower bin is not).
 hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,
                           const uint64_t* amax, const uint64_t* bmax,
-                          double* Chi, double* Clo, int64_t ldc, hipStream_t s);
+                          double* Chi, double* Clo, int64_t ldc, uint32_t* flags, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
 // Plain software double-double GEMM on the vector units.
 hipError_t launch_dd_valu(int64_t m, int64_t n, int64_t k,

@@ -177,6 +177,7 @@ struct Opts {
   int32_t algo = DD_ALGO_CASCADE_F64;
   int32_t kc = kDefaultKc;
   int32_t S = 0, w = 0;   // slices variants
+  uint32_t* flags = nullptr;   // cascade: cancellation bitmap (may be null)
   bool slices() const { return algo == DD_ALGO_SLICES_BF16 || algo == DD_ALGO_SLICES_F16; }
   bool f16() const { return algo == DD_ALGO_SLICES_F16; }
 };
@@ -268,10 +269,14 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
   st = run_split(p, L, ws, s);
   if (st != DD_OK) return st;
   if (pe.e1) (void)hipEventRecord(pe.e1, s);
+  if (o.flags) {
+    st = hip_status(ddk::launch_fill_u32(o.flags, (p.m * p.n + 31) / 32, 0u, s));
+    if (st != DD_OK) return st;
+  }
   st = hip_status(ddk::launch_cascade(L, (const double*)(ws + L.off_apack),
                                       (const double*)(ws + L.off_bpack),
                                       (const uint64_t*)(ws + L.off_amax),
-                                      (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, s));
+                                      (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, o.flags, s));
   if (pe.e2) {
     (void)hipEventRecord(pe.e2, s);
     std::lock_guard<std::mutex> lk(g_mu);
@@ -299,8 +304,10 @@ static bool read_opts(const dd_gemm_opts* o, Opts* out) {
   *out = Opts{};
   if (!o) return true;
   if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_SLICES_F16) return false;
-  if (o->tile != 0 || o->reserved0 != 0 || o->reserved1 != 0) return false;
+  if (o->tile != 0 || o->reserved0 != 0) return false;
   out->algo = o->algo;
+  if (o->flags_out && o->algo != DD_ALGO_CASCADE_F64) return false;
+  out->flags = o->flags_out;
   if (out->slices()) {
     if (o->kc != 0) return false;
     return slice_params(out->f16(), o->slices, o->slice_bits, &out->S, &out->w);

@@ -23,6 +23,11 @@ __global__ void fill_u64(uint64_t* p, int64_t n, uint64_t v) {
   if (i < n) p[i] = v;
 }
 
+__global__ void fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // Element (o, r) at X[o + r*ld]: consecutive threads take consecutive o.
 __global__ void __launch_bounds__(256)
 max_abs_bits_outer_contig(const double* __restrict__ X, const double* __restrict__ Xlo, int64_t outer,
@@ -273,6 +278,12 @@ static inline unsigned blocks_for(int64_t n, int64_t per) { return (unsigned)((n
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   fill_u64<<<blocks_for(n, 256), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_u32<<<blocks_for(n, 256), 256, 0, s>>>(p, n, v);
   return hipGetLastError();
 }
 

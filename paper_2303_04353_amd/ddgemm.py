@@ -38,7 +38,7 @@ EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split
 class dd_gemm_opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("kc", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("slices", ctypes.c_int32), ("slice_bits", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int64)]
+                ("reserved0", ctypes.c_int32), ("flags_out", ctypes.c_void_p)]
 
 
 class DDError(RuntimeError):
@@ -129,7 +129,7 @@ def _opts(opts):
         return ctypes.byref(opts)
     o = dd_gemm_opts()
     for key, val in dict(opts).items():
-        setattr(o, key, int(val))
+        setattr(o, key, _ptr(val) if key == "flags_out" else int(val))
     return ctypes.byref(o)
 
 

@@ -220,3 +220,68 @@ def test_full_size_sampled_parity_8192():
     diff = torch.abs((Cc[0] - Cv[0]) + (Cc[1] - Cv[1]))
     assert bool(torch.all(diff <= 64 * N * 2.0 ** -104 * ABfull))
     log("full size 8192: done")
+
+
+def _flags_gpu(A, B, C, kc=0):
+    """op(A) op(B) + C with the cancellation bitmap; returns (hi, lo, flags m x n)."""
+    import torch
+    m, k = A[0].shape
+    n = B[0].shape[1]
+    Ch, Cl = up(C[0]), up(C[1])
+    words = torch.full(((m * n + 31) // 32,), -1, dtype=torch.int32, device="cuda")   # the call zeroes it
+    st = dg.dd_gemm_ex(0, 0, m, n, k, up(A[0]), up(A[1]), m, up(B[0]), up(B[1]), k, Ch, Cl, m,
+                       opts={"kc": kc, "flags_out": words})
+    dg.check(st, "dd_gemm_ex flags")
+    torch.cuda.synchronize()
+    bits = np.unpackbits(words.cpu().numpy().view(np.uint8), bitorder="little")[:m * n]
+    return down(Ch), down(Cl), bits.reshape(n, m).T.astype(bool)
+
+
+@pytest.mark.parametrize("kc", [0, 64])
+def test_cancellation_flags_match_the_oracle(kc):
+    rng = np.random.default_rng(8)
+    m, n, k = 70, 66, 300
+    P = make_problem(m, n, k, cfg=17)
+    Ahi, Alo = P["A"][0].copy(), P["A"][1].copy()
+    Bhi, Blo = P["B"][0].copy(), P["B"][1].copy()
+    # rows 3 and 40 against columns 5 and 60: leading digits cancel exactly in every block
+    for r in (3, 40):
+        Ahi[r, :] = 0.75
+        Ahi[r, 1::2] = 0.75 + 2.0 ** -30
+        Alo[r, :] = 0.0
+    for c in (5, 60):
+        Bhi[:, c] = 0.5
+        Bhi[1::2, c] = -0.5
+        Blo[:, c] = 0.0
+    Ahi[10, :] = 0.0   # a zero row: exact zeros, no flag
+    Alo[10, :] = 0.0
+    A, B = (Ahi, Alo), (Bhi, Blo)
+    log(f"cancellation flags kc={kc}")
+    gh, gl, flags = _flags_gpu(A, B, P["C"], kc=kc)
+    wh, wl, parts = cz.cascade_gemm(A, B, P["C"], kc=kc or 256, return_parts=True)
+    want = cz.cancellation_flags(parts["bins"])
+    assert np.array_equal(flags, want)
+    assert flags[3, 5] and flags[40, 60] and flags.sum() == 4
+    # the flags do not change the result
+    base = run_gemm(A, B, P["C"], kc=kc)
+    assert np.array_equal(gh, base[0]) and np.array_equal(gl, base[1])
+
+
+def test_cancellation_flag_of_the_worked_example():
+    case = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "worked_example_sec3_6.json")))["cases"][1]
+    h = lambda v: np.asfortranarray(np.array([[float.fromhex(x) for x in row] for row in v]))
+    A = (h(case["A"]["hi"]), h(case["A"]["lo"]))
+    B = (h(case["B"]["hi"]), h(case["B"]["lo"]))
+    C = (np.zeros((1, 1), order="F"), np.zeros((1, 1), order="F"))
+    gh, gl, flags = _flags_gpu(A, B, C)
+    assert flags[0, 0]
+    assert gh[0, 0] == float.fromhex(case["cascade_result"]["hi"])
+
+
+def test_flags_rejected_for_other_algorithms():
+    import torch
+    words = torch.zeros(4, dtype=torch.int32, device="cuda")
+    base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
+    for algo in (dg.DD_ALGO_DD_VALU, dg.DD_ALGO_SLICES_BF16):
+        assert dg.dd_gemm_ex(0, 0, *base, opts={"algo": algo, "flags_out": words}) == -17

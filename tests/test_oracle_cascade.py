@@ -272,3 +272,41 @@ def test_derived_B_planes_are_single_roundings():
             assert q[6] == Fraction(float(y))
             nb6 += q[6] != Fraction(float(hi[p, j])) * Fraction(2) ** -int(f[j])
     assert nb6 > 0  # the low word changes B6' for some entries
+
+
+def test_cancellation_flag_on_the_worked_example():
+    # Sec. 3.6: x = (1, eps), y = (0, 1): the leading digits' product is zero
+    # while the last bin carries eps, and the cascade loses eps's low word
+    # (Sec. 3.7: zeros in bin 0 flag results subject to cancellation error).
+    case = json.load(open(os.path.join(GOLDEN, "worked_example_sec3_6.json")))["cases"][0]
+    h = lambda v: np.array([[float.fromhex(x) for x in row] for row in v])
+    A = (h(case["A"]["hi"]), h(case["A"]["lo"]))
+    B = (h(case["B"]["hi"]), h(case["B"]["lo"]))
+    hi, lo, parts = cz.cascade_gemm(A, B, c=tuple(case["c"]), return_parts=True)
+    assert cz.cancellation_flags(parts["bins"])[0, 0]
+    assert hi[0, 0] == float.fromhex(case["cascade_result"]["hi"])
+
+
+def test_cancellation_flags_constructed_and_random():
+    rng = np.random.default_rng(4)
+    m, n, k = 6, 5, 40
+    Ahi = rng.uniform(-1, 1, (m, k))
+    Bhi = rng.uniform(-1, 1, (k, n))
+    z = np.zeros
+    # row 2 of A and column 3 of B agree in their leading digits up to a sign
+    # flip in half the terms: the leading products cancel exactly, the rest not
+    Ahi[2, :] = 0.75
+    Ahi[2, 1::2] = 0.75 + 2.0 ** -30
+    Bhi[:, 3] = 0.5
+    Bhi[1::2, 3] = -0.5
+    # row 4 of A is zero: its products are exactly zero, no risk
+    Ahi[4, :] = 0.0
+    hi, lo, parts = cz.cascade_gemm((Ahi, z((m, k))), (Bhi, z((k, n))), kc=16, return_parts=True)
+    flags = cz.cancellation_flags(parts["bins"])
+    assert flags[2, 3]
+    # the result itself is the small difference: 20 * 2^-30 * 0.5 with the sign of the odd terms
+    assert hi[2, 3] == -20 * 2.0 ** -31
+    assert not flags[4].any()
+    others = np.ones_like(flags)
+    others[2, 3] = False
+    assert not flags[others].any()
