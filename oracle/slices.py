@@ -9,8 +9,11 @@ The method carries the bfloat16 cascade of Sec. 6.2 ("FP32 in terms of
 bfloat16": a few bfloat16 splits, products accumulated in FP32 so the bins
 need no separate accumulation) to FP64x2, with every split of the same width
 and the product set of Sec. 6.1 (equal-width splits: only the t(t+1)/2
-leading products are formed).  Steps, with w the slice width in bits and s
-the number of slices:
+leading products are formed).  The INT8 form (Sec. 6.2, "FP64x2 in terms of
+INT8": 14-15 splits, 105-120 products, 32-bit integer accumulation) is the
+same computation with slices held in int8 and level sums in INT32; only the
+chunk of the inner dimension can differ.  Steps, with w the slice width in
+bits and s the number of slices:
 
 1. Sigma and T (Sec. 3.4, Appendix A, as in the cascade): one power of two
    per row of A and per column of B, 2^e with e the frexp exponent of the
@@ -20,7 +23,8 @@ the number of slices:
    remainder rounded to a multiple of u_t by (r + K_t) - K_t,
    K_t = 3 * 2^(52 - (t+1)w); the remainder is carried as an unevaluated
    FP64 pair renormalised by TwoSum after each slice.  a_t = d_t / u_t is an
-   integer with |a_t| <= 2^(w-1), exact in BF16 (w <= 9) or FP16 (w <= 12).
+   integer with |a_t| <= 2^(w-1), exact in BF16 (w <= 9), FP16 (w <= 12) or
+   INT8 (w <= 7).
    Slices after s are dropped.
 3. Level sums: S_L = sum over i + j = L of A_i B_j (integer matrices), for
    L = 0 .. s-1 only (the triangle of Sec. 6.1).  They are exact integers;
@@ -31,9 +35,10 @@ the number of slices:
    integers, so the oracle does not model it.)
 4. Level groups: G_g = sum over L in {3g, 3g+1, 3g+2}, L < s, of
    S_L 2^(w(3g+2-L)) -- exact while
-   k * s * 2^(2w-2) * (2^(2w) + 2^w + 1) <= 2^53; the inner dimension is cut
-   into consecutive chunks of at most ``chunk_limit`` indices (a multiple of
-   64) otherwise, each chunk computed and added to C in turn.
+   k * s * 2^(2w-2) * (2^(2w) + 2^w + 1) <= 2^53 (for INT8 also
+   k * s * 2^(2w-2) <= 2^31 - 1); the inner dimension is cut into
+   consecutive chunks of at most ``chunk_limit`` indices otherwise, each
+   chunk computed and added to C in turn.
 5. Combine: V = sum_g G_g W_g with W_g = 2^(2 - (3g+4)w), accumulated in
    FP64x2 from the last (least significant) group to group 0 with the
    FP64x2 + FP64 addition; both words scaled by 2^(e_i + f_j); C added last
@@ -52,22 +57,26 @@ import numpy as np
 
 from .cascade import dd_add, dd_add_d, two_sum
 
-FORMAT_BITS = {"bf16": 8, "f16": 11}  # significant bits of the slice format
+# largest slice magnitude each format holds exactly: every integer up to
+# 2^8 (BF16, 8 significant bits), 2^11 (FP16), 127 (INT8)
+FORMAT_MAX = {"bf16": 2 ** 8, "f16": 2 ** 11, "i8": 127}
+FORMAT_BITS = {"bf16": 8, "f16": 11}  # significant bits of the floating-point formats
 GROUP = 3                              # levels per FP64 group
 
 
 # ---------------------------------------------------------------- parameters
 def check_params(w: int, s: int, fmt: str = "bf16"):
-    """Raise ValueError unless (w, s) can run on the device: slices exact in
-    ``fmt``, and every level's FP32 partial sums exact over at least one
-    16-deep matrix-core step (16 * s * 2^(2w-2) <= 2^24)."""
-    if fmt not in FORMAT_BITS:
-        raise ValueError("fmt must be 'bf16' or 'f16'")
-    if not (2 <= w <= FORMAT_BITS[fmt] + 1):
+    """Raise ValueError unless (w, s) can run on the device: slices
+    (|a| <= 2^(w-1)) exact in ``fmt``; for BF16/FP16 every level's FP32
+    partial sums exact over at least one 16-deep matrix-core step
+    (16 * s * 2^(2w-2) <= 2^24).  INT8 sums in INT32 over a whole chunk."""
+    if fmt not in FORMAT_MAX:
+        raise ValueError("fmt must be 'bf16', 'f16' or 'i8'")
+    if not (2 <= w and 2 ** (w - 1) <= FORMAT_MAX[fmt]):
         raise ValueError("slice width out of range for the format")
     if not (1 <= s <= 16):
         raise ValueError("slice count must be in [1, 16]")
-    if 16 * s * 2 ** (2 * w - 2) > 2 ** 24:
+    if fmt != "i8" and 16 * s * 2 ** (2 * w - 2) > 2 ** 24:
         raise ValueError("FP32 level sums would not be exact for one 16-deep step")
 
 
@@ -84,11 +93,16 @@ def flush_depths(w: int, s: int):
     return out
 
 
-def chunk_limit(w: int, s: int):
-    """Largest inner-dimension chunk (a multiple of 64) for which every level
-    group sum stays an exact FP64 integer."""
+def chunk_limit(w: int, s: int, fmt: str = "bf16"):
+    """Largest inner-dimension chunk for which every level group sum stays an
+    exact FP64 integer (a multiple of 64); for INT8 also every level sum an
+    INT32 (|sum| <= 2^31 - 1; a multiple of 128)."""
     per = s * 2 ** (2 * w - 2) * (2 ** (2 * w) + 2 ** w + 1)
-    return (2 ** 53 // per) // 64 * 64
+    lim = 2 ** 53 // per
+    if fmt == "i8":
+        lim = min(lim, (2 ** 31 - 1) // (s * 2 ** (2 * w - 2)))
+        return lim // 128 * 128
+    return lim // 64 * 64
 
 
 def n_products(s: int) -> int:
@@ -189,7 +203,7 @@ def slices_gemm(A, B, C=None, *, w=8, s=14, fmt="bf16", return_parts=False):
     As, _ = split_slices(Ahi, Alo, e, 1, w, s)
     Bs, _ = split_slices(Bhi, Blo, f, 0, w, s)
     shift = e.astype(np.int64)[:, None] + f.astype(np.int64)[None, :]
-    step = chunk_limit(w, s)
+    step = chunk_limit(w, s, fmt)
     parts = {"e": e, "f": f, "A": As, "B": Bs}
     with np.errstate(invalid="ignore", over="ignore"):
         for p0 in range(0, k, step):
@@ -223,7 +237,7 @@ def slices_gemm_entries(A, B, C, I, J, *, w=8, s=14, fmt="bf16"):
         return Rh, Rl
     As, _ = split_slices(*rows, e, 1, w, s)     # len(I) x k
     Bs, _ = split_slices(*cols, f, 0, w, s)     # k x len(J)
-    step = chunk_limit(w, s)
+    step = chunk_limit(w, s, fmt)
     shift = e.astype(np.int64) + f.astype(np.int64)
     with np.errstate(invalid="ignore", over="ignore"):
         for p0 in range(0, k, step):

@@ -29,8 +29,10 @@ def test_params_rules():
     sl.check_params(9, 12, "f16")
     sl.check_params(10, 4, "f16")
     sl.check_params(11, 1, "f16")
+    sl.check_params(7, 16, "i8")
+    sl.check_params(7, 1, "i8")
     for bad in [(10, 4, "bf16"), (9, 17, "bf16"), (10, 5, "f16"), (12, 1, "f16"), (1, 4, "bf16"),
-                (8, 0, "bf16"), (8, 4, "f32")]:
+                (8, 0, "bf16"), (8, 4, "f32"), (8, 16, "i8"), (7, 17, "i8")]:
         with pytest.raises(ValueError):
             sl.check_params(*bad)
     assert [sl.n_products(s) for s in (12, 13, 14)] == [78, 91, 105]
@@ -247,3 +249,38 @@ def test_empty_and_zero_inner_dimension():
     P = make_problem(3, 4, 0, cfg=108)
     hi, lo = sl.slices_gemm(P["A"], P["B"], P["C"], w=8, s=14)
     assert np.array_equal(hi, P["C"][0]) and np.array_equal(lo, P["C"][1])
+
+
+def test_int8_chunk_limit_keeps_level_sums_in_int32():
+    for w, s in ((7, 16), (7, 15), (6, 16), (4, 9)):
+        c = sl.chunk_limit(w, s, "i8")
+        assert c % 128 == 0 and c > 0
+        assert c * s * 2 ** (2 * w - 2) <= 2 ** 31 - 1
+        assert c <= sl.chunk_limit(w, s)
+    assert sl.chunk_limit(7, 16, "i8") >= 8192
+
+
+def test_int8_slices_fit_and_results_equal_the_bf16_form():
+    # INT8 is the same computation as BF16 at the same (w, s) while one chunk
+    # covers the inner dimension
+    w, s = 7, 16
+    hi, lo = _values()
+    e = sl.slice_exponents(hi.reshape(1, -1), lo.reshape(1, -1), axis=1)
+    slices, _ = sl.split_slices(hi.reshape(1, -1), lo.reshape(1, -1), e, 1, w, s)
+    for a in slices:
+        assert np.array_equal(a.astype(np.int8).astype(np.float64), a)
+    P = make_problem(20, 17, 300, cfg=109, variant="ill")
+    x = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s, fmt="i8")
+    y = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s, fmt="bf16")
+    assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
+def test_int8_chunked_inner_dimension_stays_accurate():
+    w, s = 5, 12
+    k = sl.chunk_limit(w, s, "i8") + 100
+    P = make_problem(2, 2, k, cfg=110)
+    hi, lo = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s, fmt="i8")
+    exact_bound = k * (s + 1) * 1.01 * 2.0 ** (-s * w)
+    rh, rl, _ = dd_gemm_ref(P["A"], P["B"], P["C"])
+    scale = np.max(np.abs(P["A"][0]), axis=1)[:, None] * np.max(np.abs(P["B"][0]), axis=0)[None, :]
+    assert np.all(np.abs((hi - rh) + (lo - rl)) <= (exact_bound + 2.0 ** -98 * k) * 2 * scale)
