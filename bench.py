@@ -123,24 +123,33 @@ def bench_batched(torch, dg, stream):
 PEAK_BF16_MFMA_TFLOPS = 2500.0   # MI355X, dense BF16 / FP16 matrix
 
 
+SLICES_FORMATS = (("bf16", 8, 14), ("f16", 8, 14), ("i8", 7, 16))   # (format, w, s)
+PEAK_I8_MFMA_TOPS = 5000.0       # MI355X, dense INT8 matrix
+
+
 def bench_slices(torch, dg, stream, n=4096, reps=3):
     """The narrow-slice precision variant at m = n = k = 4096: BF16 and FP16
-    slices (w = 8 bits, s = 14 slices, 105 products), uniform and ill-scaled
-    inputs.  Returns the timings and, per case, the device result's sampled
-    entries for the accuracy check of the CPU-baseline leg."""
+    slices (w = 8 bits, s = 14 slices, 105 products, FP32 level sums flushed
+    to FP64) and INT8 slices (w = 7, s = 16, 136 products, INT32 level sums),
+    uniform and ill-scaled inputs.  Returns the timings and, per case, the
+    device result's sampled entries for the accuracy check of the
+    CPU-baseline leg."""
     from paper_2303_04353_amd.inputs import make_problem, sample_entries
-    w, s = 8, 14
-    prods = s * (s + 1) // 2
-    out = {"workload": f"FP64x2 GEMM C := A*B + C, m=n=k={n}, slices of {w} bits, {s} slices, "
-                       f"{prods} products on 32x32x16 BF16/FP16 MFMA with exact FP32 level sums",
-           "slices": s, "slice_bits": w, "products": prods,
-           "flush_every_steps_of_16": 4, "cases": {}}
+    algos = {"bf16": dg.DD_ALGO_SLICES_BF16, "f16": dg.DD_ALGO_SLICES_F16, "i8": dg.DD_ALGO_SLICES_I8}
+    out = {"workload": f"FP64x2 GEMM C := A*B + C, m=n=k={n}, slices s(s+1)/2 products on 32x32x16 "
+                       "BF16/FP16 MFMA (exact FP32 level sums, flushed every 4 steps) or 32x32x32 INT8 "
+                       "MFMA (exact INT32 level sums)",
+           "formats": {f: {"slice_bits": w, "slices": s, "products": s * (s + 1) // 2}
+                       for f, w, s in SLICES_FORMATS},
+           "cases": {}}
     samples = {}
     I, J = sample_entries(n, n, 4096, seed=13)
     for variant in ("uniform", "ill"):
         P = make_problem(n, n, n, cfg=2, variant=variant)
         Ah, Al, Bh, Bl, C0h, C0l = (dg.colmajor_to_device(x) for x in (*P["A"], *P["B"], *P["C"]))
-        for fmt, algo in (("bf16", dg.DD_ALGO_SLICES_BF16), ("f16", dg.DD_ALGO_SLICES_F16)):
+        for fmt, w, s in SLICES_FORMATS:
+            algo = algos[fmt]
+            prods = s * (s + 1) // 2
             opts = {"algo": algo, "slices": s, "slice_bits": w}
             Ch, Cl = C0h.clone(), C0l.clone()
             dg.check(dg.dd_gemm_ex(0, 0, n, n, n, Ah, Al, n, Bh, Bl, n, Ch, Cl, n, opts=opts, stream=stream))
@@ -159,10 +168,12 @@ def bench_slices(torch, dg, stream, n=4096, reps=3):
             pr /= max(calls, 1)
             sp /= max(calls, 1)
             mfma = prods * 2.0 * n ** 3 / (pr * 1e-3) / 1e12
+            peak = PEAK_I8_MFMA_TOPS if fmt == "i8" else PEAK_BF16_MFMA_TFLOPS
             out["cases"][f"{fmt}_{variant}"] = {
                 "ms": round(ms, 3), "gflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 1),
                 "split_ms": round(sp, 3), "product_ms": round(pr, 3),
-                "mfma_tflops": round(mfma, 1), "pct_of_bf16_f16_peak": round(100 * mfma / PEAK_BF16_MFMA_TFLOPS, 1)}
+                "matrix_tops": round(mfma, 1), "matrix_peak_tops": peak,
+                "pct_of_matrix_peak": round(100 * mfma / peak, 1)}
             samples[(fmt, variant)] = (Gh, Gl)
             del Ch, Cl
         samples[("problem", variant)] = P
@@ -180,9 +191,9 @@ def slices_accuracy(out, samples, IJ, n=4096):
         P = samples[("problem", variant)]
         Rh, Rl, _ = dd_gemm_ref_entries(P["A"], P["B"], P["C"], I, J)
         k = 96   # exact slices-oracle entries (each a full split of one row and one column)
-        Sh, Sl = slices_gemm_entries(P["A"], P["B"], P["C"], I[:k], J[:k], w=out["slice_bits"], s=out["slices"])
         AB = np.array([np.abs(P["A"][0][i]) @ np.abs(P["B"][0][:, j]) for i, j in zip(I[:1024], J[:1024])])
-        for fmt in ("bf16", "f16"):
+        for fmt, w, s in SLICES_FORMATS:
+            Sh, Sl = slices_gemm_entries(P["A"], P["B"], P["C"], I[:k], J[:k], w=w, s=s, fmt=fmt)
             Gh, Gl = samples[(fmt, variant)]
             diff = np.abs((Gh - Rh) + (Gl - Rl))
             nz = np.abs(Rh) > 0

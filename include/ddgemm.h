@@ -74,7 +74,14 @@ typedef enum {
    * remainders are below (s+1) 2^-(s w) per inner index relative to the row
    * and column scales. */
   DD_ALGO_SLICES_BF16 = 2,
-  DD_ALGO_SLICES_F16 = 3
+  DD_ALGO_SLICES_F16 = 3,
+  /* The same computation with INT8 slices on v_mfma_i32_32x32x32_i8 (the
+   * "FP64x2 in terms of INT8" case of Sec. 6.2): level sums in INT32 are exact
+   * over a whole chunk of the inner dimension, so no flushes; the chunk is
+   * bounded by k s 2^(2w-2) <= 2^31 - 1 as well.  Slices need |a| <= 127,
+   * i.e. w <= 7; defaults w = 7, s = 16 (111 bits, 136 products).  Results
+   * equal DD_ALGO_SLICES_BF16 at the same (w, s) while k fits one chunk. */
+  DD_ALGO_SLICES_I8 = 4
 } dd_algo;
 
 /* Options of dd_gemm_ex / dd_gemm_batched.  A NULL pointer means all zero. */
@@ -85,12 +92,14 @@ typedef struct {
                           split widths follow from min(kc, k) by the constraints
                           of Sec. 3.3.  Must be 0 for the slices variants.      */
   int32_t tile;        /* must be 0 (tile configuration chosen by the library)    */
-  int32_t slices;      /* slices variants: s in [1, 16]; 0 = 14                   */
-  int32_t slice_bits;  /* slices variants: w; 0 = 8.  Needs w - 1 <= 8 (BF16) or
-                          11 (FP16) significant bits and 16 s 2^(2w-2) <= 2^24.
-                          With w <= 8 every level is flushed every 4 steps (the
-                          fast schedule); wider slices flush every step.  Both
-                          must be 0 for the other algorithms.                    */
+  int32_t slices;      /* slices variants: s in [1, 16]; 0 = 14 (BF16, FP16) or
+                          16 (INT8)                                              */
+  int32_t slice_bits;  /* slices variants: w; 0 = 8 (BF16, FP16) or 7 (INT8).
+                          Needs 2^(w-1) <= 256 (BF16), 2048 (FP16) or 127 (INT8),
+                          and for BF16/FP16 16 s 2^(2w-2) <= 2^24.  With w <= 8
+                          every level is flushed every 4 steps (the fast
+                          schedule); wider slices flush every step.  Both must
+                          be 0 for the other algorithms.                         */
   int32_t reserved0;   /* must be 0                                                */
   uint32_t* flags_out; /* cascade only, may be NULL: device bitmap of ceil(m n / 32)
                           words, bit (i + j m) for entry (i, j) of C.  The call
@@ -118,8 +127,9 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
 
 /* Bytes of device workspace dd_gemm_ex needs for this problem and options
  * (0 for DD_ALGO_DD_VALU).  Returns 0 as well for invalid arguments.
- * The slices variants need 2 s (mpad + npad) kpad bytes of packed slices
- * (mpad, npad rounded up to 64, kpad to 16) plus, for s > 9, 8 mpad npad
+ * The slices variants need b s (mpad + npad) kpad bytes of packed slices
+ * (b = 2 for BF16/FP16, 1 for INT8; mpad, npad rounded up to 64, kpad to 64
+ * for BF16/FP16 and to 128 for INT8) plus, for s > 9, 8 mpad npad
  * (ceil(s/3) - 3) bytes of FP64 group sums. */
 size_t dd_gemm_workspace_size(dd_op transa, dd_op transb,
                               int64_t m, int64_t n, int64_t k,
@@ -211,19 +221,20 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
                            hipStream_t stream);
 
 /*
- * The slice split of DD_ALGO_SLICES_BF16 / _F16 on its own, for inspection
- * and testing.  `side` = 0: X is op(A), rows x cols = m x k, one exponent
- * per row; `side` = 1: X is op(B), rows x cols = k x n, one per column.
- * exps receives e (int32) with max |fl(hi + lo)| of the row/column in
+ * The slice split of the slices variants on its own, for inspection and
+ * testing.  `side` = 0: X is op(A), rows x cols = m x k, one exponent per
+ * row; `side` = 1: X is op(B), rows x cols = k x n, one per column.  exps
+ * receives e (int32) with max |fl(hi + lo)| of the row/column in
  * [2^(e-1), 2^e) (0 for an all-zero or non-finite one); `out` receives the
- * 16-bit BF16 (f16 = 0) or FP16 (f16 = 1) patterns of the integer slices,
- * slice t at out + t*rows*cols, column-major with leading dimension rows.
- * slices / slice_bits as in dd_gemm_opts (0 = the format's default).
- * exps and out are device pointers.
+ * slices as 16-bit values: BF16 (fmt = 0) or FP16 (fmt = 1) patterns, or
+ * INT8 integers sign-extended to 16 bits (fmt = 2), slice t at
+ * out + t*rows*cols, column-major with leading dimension rows.  slices /
+ * slice_bits as in dd_gemm_opts (0 = the format's default).  exps and out
+ * are device pointers.
  */
 dd_status dd_slices_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
                           const double* X_hi, const double* X_lo, int64_t ldx,
-                          int32_t f16, int32_t slices, int32_t slice_bits,
+                          int32_t fmt, int32_t slices, int32_t slice_bits,
                           int32_t* exps, uint16_t* out, hipStream_t stream);
 
 /*

@@ -93,20 +93,25 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
   return L;
 }
 
-// Workspace of the narrow-slice variant.  Slices are 16-bit integers-valued
-// BF16 or FP16 numbers packed for v_mfma_f32_32x32x16_{bf16,f16}: for each
-// 32-row block rb of op(A) (32-column block of op(B)), each step q of 16 inner
-// indices and each slice t, one 64-lane operand of 16 bytes per lane; lane l
-// holds row (column) rb*32 + l%32 and inner indices q*16 + 8*(l/32) + 0..7:
+// Slice formats of the narrow-slice variants.
+constexpr int kSliceBF16 = 0, kSliceF16 = 1, kSliceI8 = 2;
+
+// Workspace of the narrow-slice variants.  Slices are integer-valued BF16 /
+// FP16 numbers or INT8 integers packed for v_mfma_f32_32x32x16_{bf16,f16} /
+// v_mfma_i32_32x32x32_i8: for each 32-row block rb of op(A) (32-column block
+// of op(B)), each step q of the inner dimension (16 indices for BF16/FP16, 32
+// for INT8) and each slice t, one 64-lane operand of 16 bytes per lane; lane
+// l holds row (column) rb*32 + l%32 and the step's inner indices
+// (l/32)*E .. (l/32)*E + E-1 (E = 8 two-byte or 16 one-byte values):
 //   pack[((rb*Q + q)*S + t)*64 + l]   (in 16-byte units)
 // Rows/columns are padded with zeros to the 64 x 64 workgroup tile and the
-// inner dimension to a multiple of 64 (whole blocks of four steps).
+// inner dimension to whole blocks of four steps (64 or 128 indices).
 struct SlicesLayout {
   int64_t m, n, k;
-  int64_t mpad, npad, kpad, Q;  // Q = kpad / 16 steps
-  int32_t S, w, f16;            // slice count, width, format (1 = FP16)
-  int32_t chunk_q;              // steps per inner-dimension chunk (group sums exact), a multiple of 4
-  int32_t flush_mask[16];       // level L is flushed to FP64 every flush_mask[L] + 1 steps
+  int64_t mpad, npad, kpad, Q;  // Q = kpad / kstep steps
+  int32_t S, w, fmt, kstep;     // slice count, width, format, inner indices per step
+  int32_t chunk_q;              // steps per inner-dimension chunk (sums exact), a multiple of 4
+  int32_t flush_mask[16];       // BF16/FP16: level L may go flush_mask[L] + 1 steps between flushes
   size_t off_amax, off_bmax, off_apack, off_bpack, off_planes, bytes;
 };
 
@@ -114,32 +119,41 @@ struct SlicesLayout {
 // own, whose FP64 group sums go through the workspace.
 constexpr int kSlicesSplit = 9;
 
-// Largest chunk of the inner dimension (a multiple of 64) keeping every FP64
-// level-group sum an exact integer: k s 2^(2w-2) (2^2w + 2^w + 1) <= 2^53.
-inline int64_t slices_chunk_limit(int w, int S) {
+// Largest chunk of the inner dimension keeping every FP64 level-group sum an
+// exact integer, k s 2^(2w-2) (2^2w + 2^w + 1) <= 2^53, and for INT8 every
+// level sum an INT32, k s 2^(2w-2) <= 2^31 - 1; a multiple of four steps.
+inline int64_t slices_chunk_limit(int w, int S, int fmt) {
   const double per = (double)S * __builtin_ldexp(1.0, 2 * w - 2) *
                      (__builtin_ldexp(1.0, 2 * w) + __builtin_ldexp(1.0, w) + 1.0);
-  const int64_t lim = (int64_t)(__builtin_ldexp(1.0, 53) / per);
+  int64_t lim = (int64_t)(__builtin_ldexp(1.0, 53) / per);
+  if (fmt == kSliceI8) {
+    const int64_t l32 = ((int64_t(1) << 31) - 1) / ((int64_t)S << (2 * w - 2));
+    lim = lim < l32 ? lim : l32;
+    return lim / 128 * 128;
+  }
   return lim / 64 * 64;
 }
 
-// (w, S) usable in the format: slices (|a| <= 2^(w-1)) exact in it, and the
-// FP32 sums of the top level exact over one 16-deep step.
-inline bool slices_params_ok(int w, int S, bool f16) {
-  const int bits = f16 ? 11 : 8;
-  if (w < 2 || w > bits + 1 || S < 1 || S > 16) return false;
+// (w, S) usable in the format: slices (|a| <= 2^(w-1)) exact in it, and for
+// BF16/FP16 the FP32 sums of the top level exact over one 16-deep step.
+inline bool slices_params_ok(int w, int S, int fmt) {
+  if (w < 2 || S < 1 || S > 16) return false;
+  const double maxmag = fmt == kSliceI8 ? 127.0 : (fmt == kSliceF16 ? 2048.0 : 256.0);
+  if (__builtin_ldexp(1.0, w - 1) > maxmag) return false;
+  if (fmt == kSliceI8) return true;
   return 16.0 * S * __builtin_ldexp(1.0, 2 * w - 2) <= __builtin_ldexp(1.0, 24);
 }
 
-inline SlicesLayout make_slices_layout(int64_t m, int64_t n, int64_t k, int S, int w, bool f16) {
+inline SlicesLayout make_slices_layout(int64_t m, int64_t n, int64_t k, int S, int w, int fmt) {
   SlicesLayout L{};
   L.m = m; L.n = n; L.k = k;
-  L.S = S; L.w = w; L.f16 = f16 ? 1 : 0;
+  L.S = S; L.w = w; L.fmt = fmt;
+  L.kstep = fmt == kSliceI8 ? 32 : 16;
   L.mpad = round_up(m > 0 ? m : 1, 64);
   L.npad = round_up(n > 0 ? n : 1, 64);
-  L.kpad = round_up(k > 0 ? k : 1, 64);
-  L.Q = L.kpad / 16;
-  L.chunk_q = (int32_t)(slices_chunk_limit(w, S) / 16);
+  L.kpad = round_up(k > 0 ? k : 1, 4 * L.kstep);
+  L.Q = L.kpad / L.kstep;
+  L.chunk_q = (int32_t)(slices_chunk_limit(w, S, fmt) / L.kstep);
   for (int lv = 0; lv < 16; ++lv) {
     // largest power-of-two number of steps with 16 * steps * (lv+1) * 2^(2w-2) <= 2^24
     int64_t steps = 1;
@@ -148,10 +162,11 @@ inline SlicesLayout make_slices_layout(int64_t m, int64_t n, int64_t k, int S, i
   }
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up((int64_t)(off + bytes), 256); return o; };
+  const size_t esize = fmt == kSliceI8 ? 1 : 2;
   L.off_amax = take(sizeof(uint64_t) * (size_t)L.mpad);
   L.off_bmax = take(sizeof(uint64_t) * (size_t)L.npad);
-  L.off_apack = take(2 * (size_t)S * (size_t)L.mpad * (size_t)L.kpad);
-  L.off_bpack = take(2 * (size_t)S * (size_t)L.npad * (size_t)L.kpad);
+  L.off_apack = take(esize * (size_t)S * (size_t)L.mpad * (size_t)L.kpad);
+  L.off_bpack = take(esize * (size_t)S * (size_t)L.npad * (size_t)L.kpad);
   const int upper_groups = S > kSlicesSplit ? (S + 2) / 3 - kSlicesSplit / 3 : 0;
   L.off_planes = take(sizeof(double) * (size_t)upper_groups * (size_t)L.mpad * (size_t)L.npad);
   L.bytes = off;

@@ -178,19 +178,24 @@ struct Opts {
   int32_t kc = kDefaultKc;
   int32_t S = 0, w = 0;   // slices variants
   uint32_t* flags = nullptr;   // cascade: cancellation bitmap (may be null)
-  bool slices() const { return algo == DD_ALGO_SLICES_BF16 || algo == DD_ALGO_SLICES_F16; }
-  bool f16() const { return algo == DD_ALGO_SLICES_F16; }
+  bool slices() const {
+    return algo == DD_ALGO_SLICES_BF16 || algo == DD_ALGO_SLICES_F16 || algo == DD_ALGO_SLICES_I8;
+  }
+  int fmt() const {
+    return algo == DD_ALGO_SLICES_I8 ? ddk::kSliceI8 : (algo == DD_ALGO_SLICES_F16 ? ddk::kSliceF16 : ddk::kSliceBF16);
+  }
 };
 
-// Slice count and width with the format's defaults filled in; false if unusable.
-bool slice_params(bool f16, int32_t slices, int32_t bits, int32_t* S, int32_t* w) {
-  *S = slices ? slices : 14;
-  *w = bits ? bits : 8;
-  return ddk::slices_params_ok(*w, *S, f16);
+// Slice count and width with the format's defaults filled in (BF16/FP16:
+// 14 slices of 8 bits; INT8: 16 slices of 7 bits); false if unusable.
+bool slice_params(int fmt, int32_t slices, int32_t bits, int32_t* S, int32_t* w) {
+  *S = slices ? slices : (fmt == ddk::kSliceI8 ? 16 : 14);
+  *w = bits ? bits : (fmt == ddk::kSliceI8 ? 7 : 8);
+  return ddk::slices_params_ok(*w, *S, fmt);
 }
 
 ddk::SlicesLayout slices_layout(const Problem& p, const Opts& o) {
-  return ddk::make_slices_layout(p.m, p.n, p.k, o.S, o.w, o.f16());
+  return ddk::make_slices_layout(p.m, p.n, p.k, o.S, o.w, o.fmt());
 }
 
 // Phase one of the slices variant: exponents from max |fl(hi + lo)|, then the split.
@@ -303,14 +308,14 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
 static bool read_opts(const dd_gemm_opts* o, Opts* out) {
   *out = Opts{};
   if (!o) return true;
-  if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_SLICES_F16) return false;
+  if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_SLICES_I8) return false;
   if (o->tile != 0 || o->reserved0 != 0) return false;
   out->algo = o->algo;
   if (o->flags_out && o->algo != DD_ALGO_CASCADE_F64) return false;
   out->flags = o->flags_out;
   if (out->slices()) {
     if (o->kc != 0) return false;
-    return slice_params(out->f16(), o->slices, o->slice_bits, &out->S, &out->w);
+    return slice_params(out->fmt(), o->slices, o->slice_bits, &out->S, &out->w);
   }
   if (o->slices != 0 || o->slice_bits != 0) return false;
   if (o->kc != 0 && !valid_kc(o->kc)) return false;
@@ -324,7 +329,7 @@ size_t dd_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, 
   if (!read_opts(opts, &o)) return 0;
   if ((transa != DD_OP_N && transa != DD_OP_T) || (transb != DD_OP_N && transb != DD_OP_T)) return 0;
   if (m <= 0 || n <= 0 || k <= 0 || o.algo == DD_ALGO_DD_VALU) return 0;
-  if (o.slices()) return ddk::make_slices_layout(m, n, k, o.S, o.w, o.f16()).bytes;
+  if (o.slices()) return ddk::make_slices_layout(m, n, k, o.S, o.w, o.fmt()).bytes;
   return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN).bytes;
 }
 
@@ -397,7 +402,7 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
 
 dd_status dd_slices_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
                           const double* X_hi, const double* X_lo, int64_t ldx,
-                          int32_t f16, int32_t slices, int32_t slice_bits,
+                          int32_t fmt, int32_t slices, int32_t slice_bits,
                           int32_t* exps, uint16_t* out, hipStream_t stream) {
   if (side != 0 && side != 1) return -1;
   if (trans != DD_OP_N && trans != DD_OP_T) return -2;
@@ -405,10 +410,10 @@ dd_status dd_slices_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
   if (cols < 0) return -4;
   const int64_t srows = trans ? cols : rows;
   if (ldx < (srows > 1 ? srows : 1)) return -7;
-  if (f16 != 0 && f16 != 1) return -8;
+  if (fmt < 0 || fmt > 2) return -8;
   Opts o;
-  o.algo = f16 ? DD_ALGO_SLICES_F16 : DD_ALGO_SLICES_BF16;
-  if (!slice_params(f16 != 0, slices, slice_bits, &o.S, &o.w)) return -9;
+  o.algo = fmt == 2 ? DD_ALGO_SLICES_I8 : (fmt == 1 ? DD_ALGO_SLICES_F16 : DD_ALGO_SLICES_BF16);
+  if (!slice_params(o.fmt(), slices, slice_bits, &o.S, &o.w)) return -9;
   if (rows == 0 || cols == 0) return DD_OK;
   if (!X_hi) return -5;
   if (!X_lo) return -6;

@@ -28,6 +28,7 @@ DD_ALGO_CASCADE_F64 = 0
 DD_ALGO_DD_VALU = 1
 DD_ALGO_SLICES_BF16 = 2
 DD_ALGO_SLICES_F16 = 3
+DD_ALGO_SLICES_I8 = 4
 
 EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_slices_split", "dd_dot",
             "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",
@@ -163,9 +164,9 @@ def dd_cascade_split(side, trans, rows, cols, X_hi, X_lo, ldx, kc, exps, planes,
                                       int(kc), _ptr(exps), _ptr(planes), _stream(stream)))
 
 
-def dd_slices_split(side, trans, rows, cols, X_hi, X_lo, ldx, f16, slices, slice_bits, exps, out,
+def dd_slices_split(side, trans, rows, cols, X_hi, X_lo, ldx, fmt, slices, slice_bits, exps, out,
                     stream=None) -> int:
-    return int(lib().dd_slices_split(int(side), int(trans), rows, cols, _ptr(X_hi), _ptr(X_lo), ldx, int(f16),
+    return int(lib().dd_slices_split(int(side), int(trans), rows, cols, _ptr(X_hi), _ptr(X_lo), ldx, int(fmt),
                                      int(slices), int(slice_bits), _ptr(exps), _ptr(out), _stream(stream)))
 
 

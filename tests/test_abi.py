@@ -95,9 +95,16 @@ def test_slices_options_and_workspace():
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": f16}) > 0
     for bad in ({"algo": bf, "slice_bits": 10}, {"algo": bf, "slices": 17}, {"algo": f16, "slice_bits": 10},
                 {"algo": bf, "kc": 256}, {"algo": 0, "slices": 4}, {"algo": 1, "slice_bits": 8},
-                {"algo": f16, "slice_bits": 12, "slices": 1}, {"algo": 4}):
+                {"algo": f16, "slice_bits": 12, "slices": 1}, {"algo": 5}):
         assert dg.dd_gemm_workspace_size(0, 0, m, n, k, bad) == 0, bad
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": f16, "slice_bits": 11, "slices": 1}) > 0
+    # INT8: 16 slices of 7 bits, one byte each, k padded to 128, groups 3..5 of the upper pass
+    i8 = dg.DD_ALGO_SLICES_I8
+    ws8 = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": i8})
+    need8 = 8 * (mpad + npad) + 16 * (mpad + npad) * 384 + 8 * 3 * mpad * npad
+    assert need8 <= ws8 <= need8 + 6 * 256
+    assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": i8, "slice_bits": 8}) == 0
+    assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": 5}) == 0
     base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
     assert dg.dd_gemm_ex(0, 0, *base, opts={"algo": bf, "slices": 20}, stream=0) == -17
 
@@ -107,7 +114,8 @@ def test_slices_split_rejects_bad_arguments():
     assert dg.dd_slices_split(0, 2, 4, 4, 8, 16, 4, 0, 0, 0, 32, 64, stream=0) == -2
     assert dg.dd_slices_split(0, 0, -4, 4, 8, 16, 4, 0, 0, 0, 32, 64, stream=0) == -3
     assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 3, 0, 0, 0, 32, 64, stream=0) == -7
-    assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 2, 0, 0, 32, 64, stream=0) == -8
+    assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 3, 0, 0, 32, 64, stream=0) == -8
+    assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 2, 0, 8, 32, 64, stream=0) == -9   # w = 8 overflows int8
     assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 0, 0, 10, 32, 64, stream=0) == -9
     assert dg.dd_slices_split(0, 0, 4, 4, 0, 16, 4, 0, 0, 0, 32, 64, stream=0) == -5
     assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 0, 0, 0, 0, 64, stream=0) == -11

@@ -23,20 +23,24 @@ from tests.gpuhelp import dd_diff, log, north_star_bound, run_gemm, up
 
 pytestmark = pytest.mark.gpu
 
-BF, F16 = dg.DD_ALGO_SLICES_BF16, dg.DD_ALGO_SLICES_F16
+BF, F16, I8 = dg.DD_ALGO_SLICES_BF16, dg.DD_ALGO_SLICES_F16, dg.DD_ALGO_SLICES_I8
+FMT = {BF: "bf16", F16: "f16", I8: "i8"}
 
 
-def _bits(a, f16):
-    """16-bit pattern of integer-valued float64 slices in BF16 or FP16."""
-    if f16:
+def _bits(a, fmt):
+    """16-bit form of integer-valued float64 slices: the BF16 (0) or FP16 (1)
+    pattern, or the INT8 value sign-extended (2)."""
+    if fmt == 1:
         return a.astype(np.float16).view(np.uint16)
+    if fmt == 2:
+        return a.astype(np.int16).view(np.uint16)
     return (a.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
 
 
 @pytest.mark.parametrize("shape", [(37, 50), (64, 256), (129, 300), (1, 1), (70, 33)])
 @pytest.mark.parametrize("variant", ["uniform", "ill"])
 @pytest.mark.parametrize("trans", [False, True])
-@pytest.mark.parametrize("f16,w,s", [(0, 8, 14), (1, 9, 12), (0, 9, 16), (1, 11, 1)])
+@pytest.mark.parametrize("f16,w,s", [(0, 8, 14), (1, 9, 12), (0, 9, 16), (1, 11, 1), (2, 7, 16), (2, 5, 3)])
 def test_split_bitwise(shape, variant, trans, f16, w, s):
     import torch
     rows, cols = shape
@@ -68,18 +72,26 @@ CASES = [((37, 50, 300), "uniform"), ((130, 70, 1000), "ill"), ((1, 1, 1), "unif
 
 @pytest.mark.parametrize("shape,variant", CASES)
 @pytest.mark.parametrize("algo,w,s", [(BF, 8, 14), (BF, 9, 12), (F16, 9, 12), (BF, 7, 16), (BF, 8, 9),
-                                      (BF, 6, 4), (F16, 11, 1)])
+                                      (BF, 6, 4), (F16, 11, 1), (I8, 7, 16), (I8, 7, 12), (I8, 6, 9), (I8, 4, 2)])
 def test_gemm_bitwise_against_oracle(shape, variant, algo, w, s):
     m, n, k = shape
     log(f"slices gemm {shape} {variant} algo={algo} w={w} s={s}")
     P = make_problem(m, n, k, cfg=41, variant=variant)
     got = run_gemm(P["A"], P["B"], P["C"], algo=algo, slices=s, slice_bits=w)
-    want = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s, fmt="f16" if algo == F16 else "bf16")
+    want = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s, fmt=FMT[algo])
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
 
 
+def test_int8_equals_bf16_at_the_same_widths():
+    m, n, k = 150, 90, 700
+    P = make_problem(m, n, k, cfg=48, variant="ill")
+    a = run_gemm(P["A"], P["B"], P["C"], algo=I8, slices=16, slice_bits=7)
+    b = run_gemm(P["A"], P["B"], P["C"], algo=BF, slices=16, slice_bits=7)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 @pytest.mark.parametrize("variant", ["uniform", "ill"])
-@pytest.mark.parametrize("algo", [BF, F16])
+@pytest.mark.parametrize("algo", [BF, F16, I8])
 def test_defaults_meet_the_fp64x2_tolerance(variant, algo):
     m, n, k = 150, 120, 700
     log(f"slices default accuracy algo={algo} {variant}")
@@ -87,7 +99,8 @@ def test_defaults_meet_the_fp64x2_tolerance(variant, algo):
     got = run_gemm(P["A"], P["B"], P["C"], algo=algo)
     ref = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
     assert np.all(dd_diff(got, ref) <= north_star_bound(P["A"], P["B"], k))
-    want = sl.slices_gemm(P["A"], P["B"], P["C"], w=8, s=14)
+    w, s = (7, 16) if algo == I8 else (8, 14)
+    want = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s, fmt=FMT[algo])
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
 
 
@@ -102,13 +115,13 @@ def test_transposes_are_bit_identical(ta, tb):
     assert np.array_equal(got[0], base[0]) and np.array_equal(got[1], base[1])
 
 
-def test_chunked_inner_dimension():
-    w, s = 9, 12
-    k = sl.chunk_limit(w, s) + 40
-    log(f"slices chunked k={k}")
+@pytest.mark.parametrize("algo,w,s", [(BF, 9, 12), (I8, 7, 16)])
+def test_chunked_inner_dimension(algo, w, s):
+    k = sl.chunk_limit(w, s, FMT[algo]) + 40
+    log(f"slices chunked algo={algo} k={k}")
     P = make_problem(5, 66, k, cfg=44)
-    got = run_gemm(P["A"], P["B"], P["C"], algo=BF, slices=s, slice_bits=w)
-    want = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s)
+    got = run_gemm(P["A"], P["B"], P["C"], algo=algo, slices=s, slice_bits=w)
+    want = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s, fmt=FMT[algo])
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
 
 
@@ -120,18 +133,20 @@ def test_zero_inner_dimension_and_empty():
     assert st == dg.DD_OK
 
 
-def test_non_finite_rows_and_columns_give_nan():
+@pytest.mark.parametrize("algo", [BF, I8])
+def test_non_finite_rows_and_columns_give_nan(algo):
     P = make_problem(40, 30, 50, cfg=46)
     A = (P["A"][0].copy(), P["A"][1].copy())
     B = (P["B"][0].copy(), P["B"][1].copy())
     A[0][7, 3] = np.inf
     B[0][11, 4] = np.nan
-    got = run_gemm(A, B, P["C"], algo=BF)
+    got = run_gemm(A, B, P["C"], algo=algo)
     assert np.all(np.isnan(got[0][7, :])) and np.all(np.isnan(got[0][:, 4]))
     ok = np.ones_like(got[0], dtype=bool)
     ok[7, :] = False
     ok[:, 4] = False
-    want = sl.slices_gemm(A, B, P["C"], w=8, s=14)
+    w, s = (7, 16) if algo == I8 else (8, 14)
+    want = sl.slices_gemm(A, B, P["C"], w=w, s=s, fmt=FMT[algo])
     assert np.array_equal(got[0][ok], want[0][ok]) and np.array_equal(got[1][ok], want[1][ok])
 
 
@@ -154,8 +169,9 @@ def test_caller_workspace_equals_internal():
                          Ch, Cl, m, workspace=ws, ws_bytes=nbytes - 1, opts=opts) == dg.DD_ERR_WORKSPACE
 
 
+@pytest.mark.parametrize("algo", [BF, I8])
 @pytest.mark.parametrize("variant", ["uniform", "ill"])
-def test_full_size_sampled_parity_4096(variant):
+def test_full_size_sampled_parity_4096(variant, algo):
     import torch
     n = 4096
     log(f"slices 4096^3 {variant}: generating")
@@ -163,13 +179,14 @@ def test_full_size_sampled_parity_4096(variant):
     Ah, Al, Bh, Bl = (up(x) for x in (*P["A"], *P["B"]))
     Ch, Cl = up(P["C"][0]), up(P["C"][1])
     log("slices 4096^3: running")
-    dg.check(dg.dd_gemm_ex(0, 0, n, n, n, Ah, Al, n, Bh, Bl, n, Ch, Cl, n, opts={"algo": BF}))
+    dg.check(dg.dd_gemm_ex(0, 0, n, n, n, Ah, Al, n, Bh, Bl, n, Ch, Cl, n, opts={"algo": algo}))
     torch.cuda.synchronize()
     I, J = sample_entries(n, n, 48, seed=11)
     gh = Ch.T.cpu().numpy()[I, J]
     gl = Cl.T.cpu().numpy()[I, J]
     log("slices 4096^3: oracle entries")
-    wh, wl = sl.slices_gemm_entries(P["A"], P["B"], P["C"], I, J, w=8, s=14)
+    w, s = (7, 16) if algo == I8 else (8, 14)
+    wh, wl = sl.slices_gemm_entries(P["A"], P["B"], P["C"], I, J, w=w, s=s, fmt=FMT[algo])
     assert np.array_equal(gh, wh) and np.array_equal(gl, wl)
     rh, rl, _ = dd_gemm_ref_entries(P["A"], P["B"], P["C"], I, J)
     AB = np.array([np.abs(P["A"][0][i]) @ np.abs(P["B"][0][:, j]) for i, j in zip(I, J)])
