@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--size", type=int, default=8192, help="m = n = k")
     ap.add_argument("--shape", default=None, metavar="M,N,K",
                     help="time another shape instead (exploration; not the headline workload)")
-    ap.add_argument("--variant", default="uniform", choices=["uniform", "ill"])
+    ap.add_argument("--variant", default="uniform", choices=["uniform", "scaled"])
     ap.add_argument("--oracle-seconds", type=float, default=15.0,
                     help="CPU time budget of the sampled oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -144,7 +144,7 @@ def bench_slices(torch, dg, stream, n=4096, reps=3):
            "cases": {}}
     samples = {}
     I, J = sample_entries(n, n, 4096, seed=13)
-    for variant in ("uniform", "ill"):
+    for variant in ("uniform", "scaled"):
         P = make_problem(n, n, n, cfg=2, variant=variant)
         Ah, Al, Bh, Bl, C0h, C0l = (dg.colmajor_to_device(x) for x in (*P["A"], *P["B"], *P["C"]))
         for fmt, w, s in SLICES_FORMATS:
@@ -187,7 +187,7 @@ def slices_accuracy(out, samples, IJ, n=4096):
     from oracle.ref import dd_gemm_ref_entries
     from oracle.slices import slices_gemm_entries
     I, J = IJ
-    for variant in ("uniform", "ill"):
+    for variant in ("uniform", "scaled"):
         P = samples[("problem", variant)]
         Rh, Rl, _ = dd_gemm_ref_entries(P["A"], P["B"], P["C"], I, J)
         k = 96   # exact slices-oracle entries (each a full split of one row and one column)

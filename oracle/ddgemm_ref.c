@@ -139,3 +139,78 @@ int oracle_dd_gemm_entries(int64_t count, const int64_t *I, const int64_t *J, in
     }
     return used;
 }
+
+/*
+ * Exact reference for accuracy workloads (the role the paper's FP128x2
+ * results play in Sec. 5.2): for each requested entry (i, j), the exact value
+ * V = sum_p (A_hi + A_lo)_ip (B_hi + B_lo)_pj + (C_hi + C_lo)_ij is kept as a
+ * nonoverlapping expansion of doubles (Shewchuk's GROW-EXPANSION with zero
+ * elimination, fed every product as the exact pair TwoProd gives); then the
+ * computed (R_hi, R_lo) is subtracted inside the same expansion, so the
+ * difference R - V is exact before its final rounding.  Outputs: V and R - V
+ * rounded to double (sum of the expansion from its small end).  Exact as long
+ * as no TwoProd error term falls below the normal range (each such product
+ * then loses at most 2^-1074).  Returns the threads used, or -1 when an
+ * expansion would outgrow EXP_MAX terms (inputs spanning too many binades).
+ */
+#define EXP_MAX 600
+
+static int grow_expansion(double *e, int n, double b) {
+    double q = b;
+    int h = 0;
+    for (int i = 0; i < n; ++i) {
+        dd_t s = two_sum(q, e[i]);
+        q = s.hi;
+        if (s.lo != 0.0) e[h++] = s.lo;
+    }
+    if (q != 0.0 || h == 0) e[h++] = q;
+    return h;
+}
+
+static double expansion_value(const double *e, int n) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += e[i];
+    return s;
+}
+
+int oracle_exact_entries(int64_t count, const int64_t *I, const int64_t *J, int64_t k,
+                         const double *Ahi, const double *Alo, int64_t lda,
+                         const double *Bhi, const double *Blo, int64_t ldb,
+                         const double *Chi, const double *Clo, int64_t ldc,
+                         const double *Rhi, const double *Rlo,
+                         double *exact, double *err, int nthreads) {
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    int used = 1;
+    int bad = 0;
+#pragma omp parallel reduction(|:bad)
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+        double e[EXP_MAX];
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < count; ++t) {
+            const int64_t i = I[t], j = J[t];
+            int n = 0;
+            for (int64_t p = 0; p < k && !bad; ++p) {
+                const double a[2] = {Ahi[i + p * lda], Alo[i + p * lda]};
+                const double b[2] = {Bhi[p + j * ldb], Blo[p + j * ldb]};
+                for (int x = 0; x < 2; ++x)
+                    for (int y = 0; y < 2; ++y) {
+                        dd_t pr = two_prod(a[x], b[y]);
+                        if (n + 2 >= EXP_MAX) { bad = 1; break; }
+                        n = grow_expansion(e, n, pr.lo);
+                        n = grow_expansion(e, n, pr.hi);
+                    }
+            }
+            if (n + 4 >= EXP_MAX) bad = 1;
+            if (bad) continue;
+            n = grow_expansion(e, n, Clo[i + j * ldc]);
+            n = grow_expansion(e, n, Chi[i + j * ldc]);
+            exact[t] = expansion_value(e, n);
+            n = grow_expansion(e, n, -Rlo[t]);
+            n = grow_expansion(e, n, -Rhi[t]);
+            err[t] = -expansion_value(e, n);   /* R - V */
+        }
+    }
+    return bad ? -1 : used;
+}

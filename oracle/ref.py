@@ -31,6 +31,9 @@ def _load():
                                                vp, vp, i64, vp, vp, i64, vp, vp, ci]
         lib.oracle_dd_gemm_entries.restype = ci
         lib.oracle_max_threads.restype = ci
+        lib.oracle_exact_entries.argtypes = [i64, vp, vp, i64, vp, vp, i64, vp, vp, i64, vp, vp, i64,
+                                             vp, vp, vp, vp, ci]
+        lib.oracle_exact_entries.restype = ci
         _lib = lib
     return _lib
 
@@ -87,3 +90,26 @@ def dd_gemm_ref_entries(A, B, C, I, J, *, transa=False, transb=False, threads=0)
         _ptr(Ahi), _ptr(Alo), max(1, Ahi.shape[0]), _ptr(Bhi), _ptr(Blo), max(1, Bhi.shape[0]),
         _ptr(Chi), _ptr(Clo), max(1, Chi.shape[0]), _ptr(out_hi), _ptr(out_lo), int(threads))
     return out_hi, out_lo, int(used)
+
+
+def exact_entries(A, B, C, I, J, R, *, threads=0):
+    """Exact value of entries (I[t], J[t]) of A B + C (FP64x2 operands as
+    stored, no transposes) and the exact difference R - exact for computed
+    results ``R = (hi, lo)`` at those entries, both rounded to double.
+    Returns ``(exact, err)``."""
+    Ahi, Alo = _as_f(A[0]), _as_f(A[1])
+    Bhi, Blo = _as_f(B[0]), _as_f(B[1])
+    Chi, Clo = _as_f(C[0]), _as_f(C[1])
+    I = np.ascontiguousarray(I, dtype=np.int64)
+    J = np.ascontiguousarray(J, dtype=np.int64)
+    Rh = np.ascontiguousarray(R[0], dtype=np.float64)
+    Rl = np.ascontiguousarray(R[1], dtype=np.float64)
+    exact = np.empty(I.shape[0])
+    err = np.empty(I.shape[0])
+    st = _load().oracle_exact_entries(
+        I.shape[0], _ptr(I), _ptr(J), Ahi.shape[1], _ptr(Ahi), _ptr(Alo), max(1, Ahi.shape[0]),
+        _ptr(Bhi), _ptr(Blo), max(1, Bhi.shape[0]), _ptr(Chi), _ptr(Clo), max(1, Chi.shape[0]),
+        _ptr(Rh), _ptr(Rl), _ptr(exact), _ptr(err), int(threads))
+    if st < 0:
+        raise RuntimeError("expansion too long (exponent range of the inputs too wide)")
+    return exact, err

@@ -4,14 +4,21 @@ This module only draws random numbers and lays them out; it holds none of the
 cascade's arithmetic, so both the HIP path's tests and the CPU oracle can take
 their inputs from here.
 
-Workload recipe (Sec. 5.2, "uniformly random data" and "wide-range data"):
+Workload recipes (Sec. 5.2, "uniformly random data" and "wide-range data"):
 
 * ``uniform``: ``hi ~ U[-1, 1)`` and ``lo = (hi * 2**-53) * U[-1, 1)``, so the
   pair carries about 106 significant bits and ``|lo| < ulp(hi)``.
-* ``ill``: as ``uniform``, but every row of A and every column of B is first
-  multiplied by ``2**e`` with ``e`` a uniform integer in ``[-30, 30]``; C is
-  multiplied by ``2**(e_i + f_j)`` so that it lives on the same scale as the
-  product.
+* ``scaled``: as ``uniform``, but every row of A and every column of B is
+  first multiplied by ``2**e`` with ``e`` a uniform integer in ``[-30, 30]``;
+  C is multiplied by ``2**(e_i + f_j)`` so that it lives on the same scale as
+  the product.  Exercises the per-row and per-column exponents.
+* ``wide``: the paper's wide-range data.  For every row of A and every
+  column of B two decimal exponents are drawn uniformly from ``[-60, 20]``
+  and each gets a random sign, giving the end points ``x = s1 10**e1`` and
+  ``y = s2 10**e2``; the row (column) is then filled with ``U[min, max]``
+  draws, and ``lo = (hi * 2**-53) * U[-1, 1)`` as above.  C is zero (the
+  experiment forms A B alone).  Rows whose range straddles zero hold values
+  of every magnitude below the larger end point.
 
 All arrays are float64 in Fortran (column-major) order, matching the BLAS
 layout of the C ABI.
@@ -21,7 +28,7 @@ from __future__ import annotations
 import numpy as np
 
 SEED_ROOT = 230304353
-VARIANTS = {"uniform": 0, "ill": 1}
+VARIANTS = {"uniform": 0, "scaled": 1, "wide": 2}
 
 
 def _rng(cfg: int, variant: str, m: int, n: int, k: int, salt: int = 0):
@@ -41,13 +48,15 @@ def make_problem(m: int, n: int, k: int, *, cfg: int = 0, variant: str = "unifor
                  salt: int = 0):
     """Return ``dict(A=(hi, lo), B=(hi, lo), C=(hi, lo))`` with A m×k, B k×n, C m×n."""
     rng = _rng(cfg, variant, m, n, k, salt)
+    if variant == "wide":
+        return _wide(rng, m, n, k)
     Ahi = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(m, k)))
     Au = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(m, k)))
     Bhi = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(k, n)))
     Bu = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(k, n)))
     Chi = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(m, n)))
     Cu = np.asfortranarray(rng.uniform(-1.0, 1.0, size=(m, n)))
-    if variant == "ill":
+    if variant == "scaled":
         eA = rng.integers(-30, 31, size=m)
         fB = rng.integers(-30, 31, size=n)
         Ahi *= np.ldexp(1.0, eA)[:, None]
@@ -57,6 +66,26 @@ def make_problem(m: int, n: int, k: int, *, cfg: int = 0, variant: str = "unifor
     Blo = np.asfortranarray((Bhi * 2.0 ** -53) * Bu)
     Clo = np.asfortranarray((Chi * 2.0 ** -53) * Cu)
     return {"A": (Ahi, Alo), "B": (Bhi, Blo), "C": (Chi, Clo)}
+
+
+def _ranges(rng, count):
+    """Per-vector end points ``(lo, hi)`` of the wide-range recipe."""
+    e = rng.uniform(-60.0, 20.0, size=(count, 2))
+    sgn = np.where(rng.uniform(size=(count, 2)) < 0.5, -1.0, 1.0)
+    ends = sgn * 10.0 ** e
+    return ends.min(axis=1), ends.max(axis=1)
+
+
+def _wide(rng, m, n, k):
+    a0, a1 = _ranges(rng, m)
+    b0, b1 = _ranges(rng, n)
+    Ahi = np.asfortranarray(a0[:, None] + (a1 - a0)[:, None] * rng.uniform(size=(m, k)))
+    Bhi = np.asfortranarray(b0[None, :] + (b1 - b0)[None, :] * rng.uniform(size=(k, n)))
+    Alo = np.asfortranarray((Ahi * 2.0 ** -53) * rng.uniform(-1.0, 1.0, size=(m, k)))
+    Blo = np.asfortranarray((Bhi * 2.0 ** -53) * rng.uniform(-1.0, 1.0, size=(k, n)))
+    Z = np.zeros((m, n), order="F")
+    return {"A": (Ahi, Alo), "B": (Bhi, Blo), "C": (Z, Z.copy()),
+            "ranges": {"A": (a0, a1), "B": (b0, b1)}}
 
 
 def make_pair(shape, *, seed: int):

@@ -40,7 +40,7 @@ def _split_gpu(side, X, trans, kc):
 
 
 @pytest.mark.parametrize("shape", [(37, 50), (64, 256), (129, 300), (1, 1), (16, 5)])
-@pytest.mark.parametrize("variant", ["uniform", "ill"])
+@pytest.mark.parametrize("variant", ["uniform", "scaled"])
 @pytest.mark.parametrize("trans", [False, True])
 def test_split_planes_bitwise(shape, variant, trans):
     rows, cols = shape
@@ -63,8 +63,8 @@ def test_split_planes_bitwise(shape, variant, trans):
             assert np.array_equal(got[t].view(np.int64), np.asarray(want[t]).view(np.int64)), (side, t)
 
 
-CASES = [(128, 128, 128, "uniform", 256), (100, 70, 300, "uniform", 256), (65, 33, 17, "ill", 256),
-         (1, 1, 1, "uniform", 256), (200, 96, 520, "ill", 128), (64, 64, 1000, "uniform", 64),
+CASES = [(128, 128, 128, "uniform", 256), (100, 70, 300, "uniform", 256), (65, 33, 17, "scaled", 256),
+         (1, 1, 1, "uniform", 256), (200, 96, 520, "scaled", 128), (64, 64, 1000, "uniform", 64),
          (3, 130, 257, "uniform", 256)]
 
 

@@ -38,7 +38,7 @@ def _bits(a, fmt):
 
 
 @pytest.mark.parametrize("shape", [(37, 50), (64, 256), (129, 300), (1, 1), (70, 33)])
-@pytest.mark.parametrize("variant", ["uniform", "ill"])
+@pytest.mark.parametrize("variant", ["uniform", "scaled"])
 @pytest.mark.parametrize("trans", [False, True])
 @pytest.mark.parametrize("f16,w,s", [(0, 8, 14), (1, 9, 12), (0, 9, 16), (1, 11, 1), (2, 7, 16), (2, 5, 3)])
 def test_split_bitwise(shape, variant, trans, f16, w, s):
@@ -65,9 +65,9 @@ def test_split_bitwise(shape, variant, trans, f16, w, s):
             assert np.array_equal(got[t].T, _bits(want[t], f16)), (side, t)
 
 
-CASES = [((37, 50, 300), "uniform"), ((130, 70, 1000), "ill"), ((1, 1, 1), "uniform"),
-         ((64, 64, 64), "ill"), ((65, 65, 65), "uniform"), ((200, 128, 520), "uniform"),
-         ((3, 200, 17), "ill"), ((128, 3, 257), "uniform")]
+CASES = [((37, 50, 300), "uniform"), ((130, 70, 1000), "scaled"), ((1, 1, 1), "uniform"),
+         ((64, 64, 64), "scaled"), ((65, 65, 65), "uniform"), ((200, 128, 520), "uniform"),
+         ((3, 200, 17), "scaled"), ((128, 3, 257), "uniform")]
 
 
 @pytest.mark.parametrize("shape,variant", CASES)
@@ -84,13 +84,13 @@ def test_gemm_bitwise_against_oracle(shape, variant, algo, w, s):
 
 def test_int8_equals_bf16_at_the_same_widths():
     m, n, k = 150, 90, 700
-    P = make_problem(m, n, k, cfg=48, variant="ill")
+    P = make_problem(m, n, k, cfg=48, variant="scaled")
     a = run_gemm(P["A"], P["B"], P["C"], algo=I8, slices=16, slice_bits=7)
     b = run_gemm(P["A"], P["B"], P["C"], algo=BF, slices=16, slice_bits=7)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("variant", ["uniform", "ill"])
+@pytest.mark.parametrize("variant", ["uniform", "scaled"])
 @pytest.mark.parametrize("algo", [BF, F16, I8])
 def test_defaults_meet_the_fp64x2_tolerance(variant, algo):
     m, n, k = 150, 120, 700
@@ -107,7 +107,7 @@ def test_defaults_meet_the_fp64x2_tolerance(variant, algo):
 @pytest.mark.parametrize("ta,tb", [(True, False), (False, True), (True, True)])
 def test_transposes_are_bit_identical(ta, tb):
     m, n, k = 70, 90, 130
-    P = make_problem(m, n, k, cfg=43, variant="ill")
+    P = make_problem(m, n, k, cfg=43, variant="scaled")
     base = run_gemm(P["A"], P["B"], P["C"], algo=BF)
     A = (np.asfortranarray(P["A"][0].T), np.asfortranarray(P["A"][1].T)) if ta else P["A"]
     B = (np.asfortranarray(P["B"][0].T), np.asfortranarray(P["B"][1].T)) if tb else P["B"]
@@ -170,7 +170,7 @@ def test_caller_workspace_equals_internal():
 
 
 @pytest.mark.parametrize("algo", [BF, I8])
-@pytest.mark.parametrize("variant", ["uniform", "ill"])
+@pytest.mark.parametrize("variant", ["uniform", "scaled"])
 def test_full_size_sampled_parity_4096(variant, algo):
     import torch
     n = 4096

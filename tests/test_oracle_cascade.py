@@ -113,7 +113,7 @@ def test_fp64x2_conversion_error_bound(kc):
 
 
 def test_exponents_bracket_the_row_max():
-    P = make_problem(9, 7, 13, cfg=81, variant="ill")
+    P = make_problem(9, 7, 13, cfg=81, variant="scaled")
     e = cz.exponents(P["A"][0], axis=1)
     f = cz.exponents(P["B"][0], axis=0)
     for i in range(9):
@@ -190,7 +190,7 @@ def test_integer_matrices_exact_over_several_blocks():
     assert np.all(hi.astype(object) == want) and np.all(lo == 0)
 
 
-@pytest.mark.parametrize("m,n,k,variant", [(4, 3, 9, "uniform"), (5, 4, 40, "ill"), (3, 3, 70, "uniform")])
+@pytest.mark.parametrize("m,n,k,variant", [(4, 3, 9, "uniform"), (5, 4, 40, "scaled"), (3, 3, 70, "uniform")])
 def test_forward_bound_vs_exact(m, n, k, variant):
     # eq. (cascerr) per entry, with the rank-kc blocks accumulated in FP64x2:
     # |G - X| <= (1 + 2 nb) 2^-106 (|A||B|)_ij + 40 kc k eps~ ||a_i|| ||b_j|| (+ C rounding)

@@ -150,7 +150,7 @@ def _bound(P, w, s, k, e, f, C):
 
 
 @pytest.mark.parametrize("w,s", CONFIGS)
-@pytest.mark.parametrize("variant", ["uniform", "ill"])
+@pytest.mark.parametrize("variant", ["uniform", "scaled"])
 def test_against_exact_rationals(w, s, variant):
     m, n, k = 4, 5, 23
     P = make_problem(m, n, k, cfg=102, variant=variant)
@@ -195,7 +195,7 @@ def test_power_of_two_row_and_column_scaling():
     assert np.array_equal(got[0], np.ldexp(base[0], sh)) and np.array_equal(got[1], np.ldexp(base[1], sh))
 
 
-@pytest.mark.parametrize("variant", ["uniform", "ill"])
+@pytest.mark.parametrize("variant", ["uniform", "scaled"])
 @pytest.mark.parametrize("w,s", [(8, 14), (9, 12)])
 def test_meets_the_fp64x2_tolerance_of_the_dd_oracle(variant, w, s):
     m, n, k = 48, 40, 300
@@ -211,7 +211,7 @@ def test_meets_the_fp64x2_tolerance_of_the_dd_oracle(variant, w, s):
 
 
 def test_entries_equal_full_result():
-    P = make_problem(30, 20, 70, cfg=105, variant="ill")
+    P = make_problem(30, 20, 70, cfg=105, variant="scaled")
     hi, lo = sl.slices_gemm(P["A"], P["B"], P["C"], w=9, s=12)
     I = np.array([0, 3, 29, 17, 8])
     J = np.array([19, 0, 7, 7, 12])
@@ -269,7 +269,7 @@ def test_int8_slices_fit_and_results_equal_the_bf16_form():
     slices, _ = sl.split_slices(hi.reshape(1, -1), lo.reshape(1, -1), e, 1, w, s)
     for a in slices:
         assert np.array_equal(a.astype(np.int8).astype(np.float64), a)
-    P = make_problem(20, 17, 300, cfg=109, variant="ill")
+    P = make_problem(20, 17, 300, cfg=109, variant="scaled")
     x = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s, fmt="i8")
     y = sl.slices_gemm(P["A"], P["B"], P["C"], w=w, s=s, fmt="bf16")
     assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
