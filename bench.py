@@ -208,47 +208,60 @@ def slices_accuracy(out, samples, IJ, n=4096):
 
 
 ACCURACY_WORKLOADS = ("uniform", "wide", "ill-1e-9", "ill-1e-14", "ill-1e-19")
+ACCURACY_SIZES = (128, 256, 257, 384)   # ill-conditioned, t = 1e-14, kc = 256
+
+
+def _accuracy_case(torch, dg, name, n):
+    """Cascade and FP64x2 comparator on the GPU for one accuracy workload,
+    every entry's relative error against the exact product."""
+    from oracle.illcond import ill_conditioned
+    from oracle.ref import exact_entries
+    from paper_2303_04353_amd.inputs import make_problem
+    P = (ill_conditioned(n, float(name[4:]), seed=0) if name.startswith("ill")
+         else make_problem(n, n, n, cfg=0, variant=name))
+    I, J = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    dev = [dg.colmajor_to_device(x) for x in (*P["A"], *P["B"])]
+    rel, case = {}, {}
+    for label, algo in (("cascade", dg.DD_ALGO_CASCADE_F64), ("fp64x2", dg.DD_ALGO_DD_VALU)):
+        Ch, Cl = dg.colmajor_to_device(P["C"][0]), dg.colmajor_to_device(P["C"][1])
+        opts = {"algo": algo}
+        flags = None
+        if algo == dg.DD_ALGO_CASCADE_F64:
+            flags = torch.zeros(((n * n + 31) // 32,), dtype=torch.int32, device="cuda")
+            opts["flags_out"] = flags
+        dg.check(dg.dd_gemm_ex(0, 0, n, n, n, dev[0], dev[1], n, dev[2], dev[3], n, Ch, Cl, n, opts=opts))
+        torch.cuda.synchronize()
+        R = dg.colmajor_from_device(Ch), dg.colmajor_from_device(Cl)
+        ex, err = exact_entries(P["A"], P["B"], P["C"], I, J, (R[0][I, J], R[1][I, J]))
+        rel[label] = np.abs(err) / np.abs(ex)
+        case[f"{label}_max_rel_err"] = float(rel[label].max())
+        if flags is not None:
+            bits = np.unpackbits(flags.cpu().numpy().view(np.uint8), bitorder="little")
+            case["cascade_entries_flagged"] = int(bits[:n * n].sum())
+    return rel, case
 
 
 def accuracy_workloads(torch, dg, n=240):
     """The paper's element-wise accuracy study (Sec. 5.2) at n = 240: uniform,
     wide-range and ill-conditioned (t = 1e-9, 1e-14, 1e-19) inputs, the
     cascade and the FP64x2 comparator kernel on the GPU, every entry's
-    relative error against the exact product (CPU-baseline leg: the exact
-    reference and the generators are test infrastructure)."""
-    from oracle.illcond import ill_conditioned
-    from oracle.ref import exact_entries
-    from paper_2303_04353_amd.inputs import make_problem
-    out = {"n": n, "reference": "exact (expansion arithmetic)", "cases": {}}
-    I, J = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
-    I, J = I.ravel(), J.ravel()
+    relative error against the exact product; then the largest error by
+    problem size around kc = 256, where the cascade starts to accumulate
+    several rank-kc blocks in FP64x2 (CPU-baseline leg: the exact reference
+    and the generators are test infrastructure)."""
+    out = {"n": n, "reference": "exact (expansion arithmetic)", "cases": {}, "by_size_ill_1e-14": {}}
     for name in ACCURACY_WORKLOADS:
-        P = (ill_conditioned(n, float(name[4:]), seed=0) if name.startswith("ill")
-             else make_problem(n, n, n, cfg=0, variant=name))
-        dev = [dg.colmajor_to_device(x) for x in (*P["A"], *P["B"])]
-        rel, case = {}, {}
-        for label, algo in (("cascade", dg.DD_ALGO_CASCADE_F64), ("fp64x2", dg.DD_ALGO_DD_VALU)):
-            Ch, Cl = dg.colmajor_to_device(P["C"][0]), dg.colmajor_to_device(P["C"][1])
-            opts = {"algo": algo}
-            flags = None
-            if algo == dg.DD_ALGO_CASCADE_F64:
-                flags = torch.zeros(((n * n + 31) // 32,), dtype=torch.int32, device="cuda")
-                opts["flags_out"] = flags
-            dg.check(dg.dd_gemm_ex(0, 0, n, n, n, dev[0], dev[1], n, dev[2], dev[3], n, Ch, Cl, n,
-                                   opts=opts))
-            torch.cuda.synchronize()
-            R = dg.colmajor_from_device(Ch), dg.colmajor_from_device(Cl)
-            ex, err = exact_entries(P["A"], P["B"], P["C"], I, J, (R[0][I, J], R[1][I, J]))
-            rel[label] = np.abs(err) / np.abs(ex)
-            case[f"{label}_max_rel_err"] = float(rel[label].max())
-            if flags is not None:
-                bits = np.unpackbits(flags.cpu().numpy().view(np.uint8), bitorder="little")
-                case["cascade_entries_flagged"] = int(bits[:n * n].sum())
+        rel, case = _accuracy_case(torch, dg, name, n)
         ratio = np.sort(rel["fp64x2"] / np.maximum(rel["cascade"], 1e-300))
         case["frac_cascade_at_least_as_accurate"] = round(float(np.mean(rel["cascade"] <= rel["fp64x2"])), 4)
         case["ratio_fp64x2_over_cascade_quantiles"] = {
             q: float(ratio[min(len(ratio) - 1, int(float(q) * len(ratio)))]) for q in ("0.01", "0.1", "0.5", "0.9")}
         out["cases"][name] = case
+    for size in ACCURACY_SIZES:
+        _, case = _accuracy_case(torch, dg, "ill-1e-14", size)
+        case["ratio_of_max_errors"] = case["fp64x2_max_rel_err"] / max(case["cascade_max_rel_err"], 1e-300)
+        out["by_size_ill_1e-14"][str(size)] = case
     return out
 
 

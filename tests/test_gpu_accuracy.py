@@ -3,10 +3,11 @@ measured against the exact product.
 
 For 240 x 240 x 240 problems (the size of the paper's element-wise study):
 uniform data, wide-range data, and the ill-conditioned construction for
-t = 1e-9, 1e-14, 1e-19.  Every entry's error is taken exactly (expansion
-arithmetic) and held to the FP64x2 tolerance 64 k 2^-104 (|A||B|)_ij; on the
-ill-conditioned problems the cascade must also be the more accurate of the
-two methods on most entries, against the FP64x2 comparator kernel.
+t = 1e-9, 1e-14, 1e-19; and 384^3 ill-conditioned data (two rank-256
+blocks).  Every entry's error is taken exactly (expansion arithmetic) and
+held to the FP64x2 tolerance 64 k 2^-104 (|A||B|)_ij; the cascade must also
+be the more accurate of the two methods on most entries, against the FP64x2
+comparator kernel.
 """
 import numpy as np
 import pytest
@@ -24,28 +25,29 @@ ALGOS = {"cascade": dict(algo=dg.DD_ALGO_CASCADE_F64), "fp64x2": dict(algo=dg.DD
          "bf16": dict(algo=dg.DD_ALGO_SLICES_BF16), "i8": dict(algo=dg.DD_ALGO_SLICES_I8)}
 
 
-def _workload(name):
+def _workload(name, n):
     if name.startswith("ill"):
-        return ill_conditioned(N, float(name[4:]), seed=0)
-    return make_problem(N, N, N, cfg=0, variant=name)
+        return ill_conditioned(n, float(name[4:]), seed=0)
+    return make_problem(n, n, n, cfg=0, variant=name)
 
 
-def _rel_errors(P, R):
-    I, J = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+def _rel_errors(P, R, n):
+    I, J = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     I, J = I.ravel(), J.ravel()
     ex, err = exact_entries(P["A"], P["B"], P["C"], I, J, (R[0][I, J], R[1][I, J]))
     return np.abs(err), np.abs(ex), I, J
 
 
-@pytest.mark.parametrize("name", ["uniform", "wide", "ill-1e-9", "ill-1e-14", "ill-1e-19"])
-def test_errors_against_the_exact_product(name):
-    log(f"accuracy workload {name} n={N}")
-    P = _workload(name)
-    tol = north_star_bound(P["A"], P["B"], N)
+@pytest.mark.parametrize("name,n", [("uniform", N), ("wide", N), ("ill-1e-9", N), ("ill-1e-14", N),
+                                    ("ill-1e-19", N), ("ill-1e-14", 384)])
+def test_errors_against_the_exact_product(name, n):
+    log(f"accuracy workload {name} n={n}")
+    P = _workload(name, n)
+    tol = north_star_bound(P["A"], P["B"], n)
     rel = {}
     for algo, kw in ALGOS.items():
         R = run_gemm(P["A"], P["B"], P["C"], **kw)
-        err, ex, I, J = _rel_errors(P, R)
+        err, ex, I, J = _rel_errors(P, R, n)
         assert np.all(err <= tol[I, J]), (name, algo, float(np.max(err / tol[I, J])))
         rel[algo] = err / ex
     ratio = rel["fp64x2"] / np.maximum(rel["cascade"], 1e-300)
