@@ -423,6 +423,28 @@ def main():
               Vl.T[torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()].cpu().numpy())
         del Vh, Vl
 
+    if not args.no_comparator:
+        # the paper states the cascade's cost as a multiple of DGEMM time on
+        # the same machine (Sec. 5.1): time the vendor FP64 GEMM at this shape
+        log("vendor DGEMM (torch.matmul, float64) at the same shape")
+        X, Y = Ah.T, Bh.T                       # row-major views: Y @ X = (A B)^T
+        Z = torch.empty((n, m), dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            torch.matmul(Y, X, out=Z)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        ev0.record(stream)
+        for _ in range(reps):
+            torch.matmul(Y, X, out=Z)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        gms = ev0.elapsed_time(ev1) / reps
+        result["dgemm"] = {"library": "torch.matmul float64 (vendor BLAS)", "ms": round(gms, 3),
+                           "tflops": round(2.0 * m * n * k / (gms * 1e-3) / 1e12, 2),
+                           "cascade_time_over_dgemm": round(ms_per_step / gms, 2)}
+        del Z
+
     if not args.no_cpu_baseline:
         from oracle.ref import dd_gemm_ref_entries  # CPU baseline leg only
         A, B, C = P["A"], P["B"], P["C"]
