@@ -29,7 +29,9 @@ Steps, in the paper's order and notation:
 5. Across bins in FP64x2, least significant first (Sec. 3.3; Sec. 3.6, the
    expression for fl_casc): bin0 + (bin1 + (bin2 + fl(bin 3-6))); the
    rank-kc results are accumulated in FP64x2 (Sec. 4.2, Fig. gemmrankk).
-6. Apply Sigma and T (Sec. 4.2) and add C last.
+6. Apply Sigma and T (Sec. 4.2) and add C last.  (Option: Sigma and T per
+   rank-kc panel, each panel's result scaled before it is accumulated; the
+   paper packs and splits one kc panel at a time, Sec. 4.3.)
 7. Cancellation flags (Sec. 3.7, Sec. 4.4): an entry is flagged when bin 0
    of a rank-kc block is zero while a lower bin of that block is not.
 
@@ -185,14 +187,20 @@ def cancellation_flags(blocks):
     return flag
 
 
-def cascade_gemm(A, B, C=None, *, kc=256, c=None, return_parts=False):
+def cascade_gemm(A, B, C=None, *, kc=256, c=None, scaling="global", return_parts=False):
     """C + A B by the cascade; A (m×k), B (k×n), C (m×n) as (hi, lo) pairs.
 
     The rank-kc block is ``min(kc, k)`` and the split widths follow from it,
     unless ``c`` fixes them (the paper's k_C = 256 setting is c = (22, 21, 21)).
+    ``scaling="panel"`` takes Sigma and T per rank-kc panel instead (step 2
+    applied to each panel A[:, p0:p1], B[p0:p1, :] on its own; the panel's
+    FP64x2 result is scaled by its own powers of two before it joins the
+    accumulator, and no scaling is left for the end).
     Returns ``(hi, lo)``; with ``return_parts`` also a dict holding the planes,
     exponents and the bins of every rank-kc block.
     """
+    if scaling not in ("global", "panel"):
+        raise ValueError("scaling must be 'global' or 'panel'")
     Ahi, Alo = (np.asarray(x, dtype=np.float64) for x in A)
     Bhi, Blo = (np.asarray(x, dtype=np.float64) for x in B)
     m, k = Ahi.shape
@@ -205,6 +213,8 @@ def cascade_gemm(A, B, C=None, *, kc=256, c=None, return_parts=False):
         return (Chi, Clo, {}) if return_parts else (Chi, Clo)
     kc_eff = min(int(kc), k)
     c = split_widths(kc_eff) if c is None else tuple(int(v) for v in c)
+    if scaling == "panel":
+        return _cascade_panels(Ahi, Alo, Bhi, Blo, Chi, Clo, kc_eff, c, return_parts)
     Ap, e = cascade_A(Ahi, Alo, c)
     Bp, f = cascade_B(Bhi, Blo, c)
     acc_h = np.zeros((m, n))
@@ -223,4 +233,29 @@ def cascade_gemm(A, B, C=None, *, kc=256, c=None, return_parts=False):
     Rh, Rl = dd_add(Chi, Clo, acc_h, acc_l)
     if return_parts:
         return Rh, Rl, {"c": c, "kc": kc_eff, "A": Ap, "B": Bp, "e": e, "f": f, "bins": blocks}
+    return Rh, Rl
+
+
+def _cascade_panels(Ahi, Alo, Bhi, Blo, Chi, Clo, kc, c, return_parts):
+    """The cascade with Sigma and T of each rank-kc panel (``scaling="panel"``)."""
+    m, k = Ahi.shape
+    n = Bhi.shape[1]
+    acc_h = np.zeros((m, n))
+    acc_l = np.zeros((m, n))
+    blocks, es, fs = [], [], []
+    for p0 in range(0, k, kc):
+        p1 = min(k, p0 + kc)
+        Ap, e = cascade_A(Ahi[:, p0:p1], Alo[:, p0:p1], c)
+        Bp, f = cascade_B(Bhi[p0:p1, :], Blo[p0:p1, :], c)
+        b = bins_block(Ap, Bp, 0, p1 - p0)
+        th, tl = combine_bins(*b)
+        shift = e.astype(np.int64)[:, None] + f.astype(np.int64)[None, :]
+        acc_h, acc_l = dd_add(acc_h, acc_l, np.ldexp(th, shift), np.ldexp(tl, shift))
+        if return_parts:
+            blocks.append(b)
+            es.append(e)
+            fs.append(f)
+    Rh, Rl = dd_add(Chi, Clo, acc_h, acc_l)
+    if return_parts:
+        return Rh, Rl, {"c": c, "kc": kc, "e": np.array(es), "f": np.array(fs), "bins": blocks}
     return Rh, Rl

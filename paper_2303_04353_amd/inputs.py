@@ -19,6 +19,12 @@ Workload recipes (Sec. 5.2, "uniformly random data" and "wide-range data"):
   draws, and ``lo = (hi * 2**-53) * U[-1, 1)`` as above.  C is zero (the
   experiment forms A B alone).  Rows whose range straddles zero hold values
   of every magnitude below the larger end point.
+* ``panels``: as ``uniform``, but the scale changes along the inner
+  dimension: every run of ``panel`` inner indices of every row of A is
+  multiplied by ``2**e`` and of every column of B by ``2**f``, e and f
+  uniform integers in ``[-40, 40]`` drawn independently per (row, panel)
+  and (panel, column); C is scaled by ``2**max_b(e_ib + f_bj)``.  One
+  exponent per whole row or column then fits only the largest panel.
 
 All arrays are float64 in Fortran (column-major) order, matching the BLAS
 layout of the C ABI.
@@ -28,7 +34,7 @@ from __future__ import annotations
 import numpy as np
 
 SEED_ROOT = 230304353
-VARIANTS = {"uniform": 0, "scaled": 1, "wide": 2}
+VARIANTS = {"uniform": 0, "scaled": 1, "wide": 2, "panels": 3}
 
 
 def _rng(cfg: int, variant: str, m: int, n: int, k: int, salt: int = 0):
@@ -45,7 +51,7 @@ def _pair(rng, shape):
 
 
 def make_problem(m: int, n: int, k: int, *, cfg: int = 0, variant: str = "uniform",
-                 salt: int = 0):
+                 salt: int = 0, panel: int = 256):
     """Return ``dict(A=(hi, lo), B=(hi, lo), C=(hi, lo))`` with A m×k, B k×n, C m×n."""
     rng = _rng(cfg, variant, m, n, k, salt)
     if variant == "wide":
@@ -62,6 +68,15 @@ def make_problem(m: int, n: int, k: int, *, cfg: int = 0, variant: str = "unifor
         Ahi *= np.ldexp(1.0, eA)[:, None]
         Bhi *= np.ldexp(1.0, fB)[None, :]
         Chi *= np.ldexp(1.0, eA[:, None] + fB[None, :])
+    elif variant == "panels":
+        nb = max(1, -(-k // panel))
+        eA = rng.integers(-40, 41, size=(m, nb))
+        fB = rng.integers(-40, 41, size=(nb, n))
+        pan = np.arange(k) // panel
+        Ahi *= np.ldexp(1.0, eA[:, pan])
+        Bhi *= np.ldexp(1.0, fB[pan, :])
+        top = np.max(eA[:, :, None] + fB[None, :, :], axis=1) if m and n else np.zeros((m, n), dtype=np.int64)
+        Chi *= np.ldexp(1.0, top)
     Alo = np.asfortranarray((Ahi * 2.0 ** -53) * Au)
     Blo = np.asfortranarray((Bhi * 2.0 ** -53) * Bu)
     Clo = np.asfortranarray((Chi * 2.0 ** -53) * Cu)

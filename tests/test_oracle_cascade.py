@@ -310,3 +310,115 @@ def test_cancellation_flags_constructed_and_random():
     others = np.ones_like(flags)
     others[2, 3] = False
     assert not flags[others].any()
+
+
+# --- Sigma and T per rank-kc panel (scaling="panel") ------------------------------
+
+def test_panel_scaling_equals_global_for_one_block():
+    P = make_problem(9, 7, 50, cfg=86, variant="scaled")
+    for kc in (50, 64, 256):
+        a = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc)
+        b = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc, scaling="panel")
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_panel_scaling_equals_global_when_panel_maxima_share_the_exponent():
+    # every panel of every row (column) holds an entry in the row's (column's)
+    # top binade, so the panel exponents equal the global ones: scaling each
+    # block exactly by the same powers of two before or after the FP64x2
+    # accumulation gives the same bits
+    m, n, k, kc = 10, 8, 100, 16
+    P = make_problem(m, n, k, cfg=87, variant="scaled")
+    A, B = [x.copy() for x in P["A"]], [x.copy() for x in P["B"]]
+    for p0 in range(0, k, kc):
+        A[0][:, p0] = 0.99 * np.ldexp(1.0, cz.exponents(P["A"][0], axis=1)) * 0.75
+        B[0][p0, :] = -0.99 * np.ldexp(1.0, cz.exponents(P["B"][0], axis=0)) * 0.75
+    A[1][:, ::kc] = 0.0
+    B[1][::kc, :] = 0.0
+    _, _, parts = cz.cascade_gemm(A, B, P["C"], kc=kc, scaling="panel", return_parts=True)
+    eg, fg = cz.exponents(A[0], axis=1), cz.exponents(B[0], axis=0)
+    assert np.all(parts["e"] == eg[None, :]) and np.all(parts["f"] == fg[None, :])
+    a = cz.cascade_gemm(A, B, P["C"], kc=kc)
+    b = cz.cascade_gemm(A, B, P["C"], kc=kc, scaling="panel")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_panel_scaling_is_invariant_to_power_of_two_balancing():
+    # A F F^-1 B with F a power of two constant over each panel (Sec. 6,
+    # scaling/balancing): per-panel exponents absorb F exactly, bit for bit
+    m, n, k, kc = 11, 9, 90, 32
+    P = make_problem(m, n, k, cfg=88)
+    pan = np.arange(k) // kc
+    t = np.array([7, -12, 30])[pan]
+    Af = (np.ldexp(P["A"][0], t[None, :]), np.ldexp(P["A"][1], t[None, :]))
+    Bf = (np.ldexp(P["B"][0], -t[:, None]), np.ldexp(P["B"][1], -t[:, None]))
+    a = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc, scaling="panel")
+    b = cz.cascade_gemm(Af, Bf, P["C"], kc=kc, scaling="panel")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # with one exponent per row the balancing changes the result
+    g = cz.cascade_gemm(Af, Bf, P["C"], kc=kc)
+    h = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc)
+    assert not (np.array_equal(g[0], h[0]) and np.array_equal(g[1], h[1]))
+
+
+@pytest.mark.parametrize("m,n,k,kc", [(4, 3, 24, 8), (5, 4, 40, 16), (3, 5, 33, 8)])
+def test_panel_scaling_forward_bound_vs_exact(m, n, k, kc):
+    # eq. (cascerr) per panel: each block's bound uses that panel's row and
+    # column maxima, so on data whose scale changes along k the sum of panel
+    # bounds stays near (|A||B|)_ij, where one exponent per row does not
+    P = make_problem(m, n, k, cfg=89, variant="panels", panel=kc)
+    hi, lo = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc, scaling="panel")
+    X = exact_gemm(P["A"], P["B"], P["C"])
+    S = abs_gemm(P["A"], P["B"])
+    Cabs = np.abs(dd_value(*P["C"]))
+    c = cz.split_widths(kc)
+    eps_t = Fraction(2) ** -(sum(c) + 53)
+    nb = -(-k // kc)
+    a = dd_value(*P["A"])
+    b = dd_value(*P["B"])
+    G = dd_value(hi, lo)
+    for i in range(m):
+        for j in range(n):
+            panel_term = Fraction(0)
+            for p0 in range(0, k, kc):
+                ai = max(abs(v) for v in a[i, p0:p0 + kc])
+                bj = max(abs(v) for v in b[p0:p0 + kc, j])
+                panel_term += 40 * kc * kc * eps_t * ai * bj
+            bound = ((1 + 2 * nb) * Fraction(U2) * S[i, j] + panel_term
+                     + 4 * Fraction(U2) * (Cabs[i, j] + S[i, j]))
+            assert abs(G[i, j] - X[i, j]) <= bound
+
+
+def test_panel_scaling_meets_the_tolerance_where_global_scaling_does_not():
+    # rows large in the first panel and small in the second, columns the other
+    # way round: every product is small, and one exponent per row or column
+    # leaves the small halves with FP64 digits only
+    m = n = 6
+    kc, k = 16, 32
+    rng = np.random.default_rng(9)
+    Ahi = rng.uniform(-1, 1, (m, k))
+    Bhi = rng.uniform(-1, 1, (k, n))
+    Ahi[:, kc:] *= 2.0 ** -90
+    Bhi[:kc, :] *= 2.0 ** -90
+    A = (Ahi, Ahi * 2.0 ** -53 * rng.uniform(-1, 1, (m, k)))
+    B = (Bhi, Bhi * 2.0 ** -53 * rng.uniform(-1, 1, (k, n)))
+    X = exact_gemm(A, B)
+    tol = 64 * k * Fraction(2) ** -104 * abs_gemm(A, B)
+    Gp = dd_value(*cz.cascade_gemm(A, B, kc=kc, scaling="panel"))
+    Gg = dd_value(*cz.cascade_gemm(A, B, kc=kc))
+    assert all(abs(Gp[idx] - X[idx]) <= tol[idx] for idx in np.ndindex(m, n))
+    assert sum(abs(Gg[idx] - X[idx]) > tol[idx] for idx in np.ndindex(m, n)) > m * n // 2
+
+
+def test_panel_scaling_ragged_last_panel_and_zero_panels():
+    m, n, k, kc = 7, 5, 45, 16
+    P = make_problem(m, n, k, cfg=90, variant="panels", panel=kc)
+    A = [x.copy() for x in P["A"]]
+    A[0][2, 16:32] = 0.0
+    A[1][2, 16:32] = 0.0
+    hi, lo, parts = cz.cascade_gemm(A, P["B"], P["C"], kc=kc, scaling="panel", return_parts=True)
+    assert parts["e"].shape == (3, m) and parts["f"].shape == (3, n)
+    assert parts["e"][1, 2] == 0
+    rh, rl, _ = dd_gemm_ref(A, P["B"], P["C"])
+    AB = np.abs(A[0]) @ np.abs(P["B"][0])
+    assert np.all(np.abs((hi - rh) + (lo - rl)) <= 64 * k * 2.0 ** -104 * AB)
