@@ -84,6 +84,22 @@ typedef enum {
   DD_ALGO_SLICES_I8 = 4
 } dd_algo;
 
+/* Where the cascade takes its powers of two Sigma (rows of op(A)) and T
+ * (columns of op(B)) from (Sec. 3.3-3.4, Appendix A). */
+typedef enum {
+  /* One exponent per row and per column, from the largest |hi| over the
+   * whole inner dimension; Sigma and T are applied once at the end. */
+  DD_SCALING_GLOBAL = 0,
+  /* One exponent per row and per column for every rank-kc panel (inner
+   * indices [b kc, (b + 1) kc)): each panel is split with its own powers of
+   * two and its FP64x2 result is scaled by them (exactly) before it is
+   * accumulated.  The same result as DD_SCALING_GLOBAL when k <= kc; keeps
+   * FP64x2 accuracy relative to |A||B| when the scale of a row or column
+   * changes from panel to panel (the paper splits one kc panel at a time,
+   * Sec. 4.3).  Workspace: 8 (mpad + npad) bytes per extra panel. */
+  DD_SCALING_PANEL = 1
+} dd_scaling;
+
 /* Options of dd_gemm_ex / dd_gemm_batched.  A NULL pointer means all zero. */
 typedef struct {
   int32_t algo;        /* dd_algo                                                  */
@@ -100,7 +116,8 @@ typedef struct {
                           every level is flushed every 4 steps (the fast
                           schedule); wider slices flush every step.  Both must
                           be 0 for the other algorithms.                         */
-  int32_t reserved0;   /* must be 0                                                */
+  int32_t scaling;     /* cascade: dd_scaling; must be 0 for the other algorithms
+                          and for the batched calls.                            */
   uint32_t* flags_out; /* cascade only, may be NULL: device bitmap of ceil(m n / 32)
                           words, bit (i + j m) for entry (i, j) of C.  The call
                           zeroes it, then sets the bit of every entry at risk of

@@ -124,7 +124,7 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
   int32_t kc = 256;
   if (opts) {
     if (opts->algo != DD_ALGO_CASCADE_F64 || opts->tile != 0 || opts->slices != 0 || opts->slice_bits != 0 ||
-        opts->reserved0 != 0 || opts->flags_out != nullptr)
+        opts->scaling != 0 || opts->flags_out != nullptr)
       return -8;
     if (opts->kc != 0) {
       if (opts->kc < 4 || opts->kc > 4096 || opts->kc % 4 != 0) return -8;

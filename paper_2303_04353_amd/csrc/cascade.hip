@@ -134,11 +134,21 @@ __device__ __forceinline__ void ten_products(Bins& B, const Ops& o) {
 // bin0 + (bin1 + (bin2 + bin36)) in FP64x2, added to the accumulator; bins reset.
 // With kFlags, bit (i * kWaveCB + g) of `flg` is set when this block's bin 0
 // is zero while a lower bin is not (cancellation, Sec. 3.7 and Sec. 4.4).
-template <bool kFlags>
+// With kPanel, the block's result is first scaled by its own Sigma and T,
+// 2^(ea[4 i] + fb[16 g]) (exact), so the accumulator holds unscaled values.
+template <bool kFlags, bool kPanel>
 __device__ __forceinline__ void combine(Bins& B, double (&acc_h)[kSub][kWaveCB],
-                                        double (&acc_l)[kSub][kWaveCB], uint32_t& flg) {
+                                        double (&acc_l)[kSub][kWaveCB], uint32_t& flg,
+                                        const int32_t* __restrict__ ea, const int32_t* __restrict__ fb) {
+  int fc[kWaveCB];
+  if constexpr (kPanel) {
 #pragma unroll
-  for (int i = 0; i < kSub; ++i)
+    for (int g = 0; g < kWaveCB; ++g) fc[g] = fb[g * 16];
+  }
+#pragma unroll
+  for (int i = 0; i < kSub; ++i) {
+    int er = 0;
+    if constexpr (kPanel) er = ea[i * 4];
 #pragma unroll
     for (int g = 0; g < kWaveCB; ++g) {
       if constexpr (kFlags) {
@@ -149,9 +159,14 @@ __device__ __forceinline__ void combine(Bins& B, double (&acc_h)[kSub][kWaveCB],
       two_sum(B.b2[i][g], B.b36[i][g], s, e);
       dd_add_d(s, e, B.b1[i][g], s, e);
       dd_add_d(s, e, B.b0[i][g], s, e);
+      if constexpr (kPanel) {
+        s = __builtin_ldexp(s, er + fc[g]);
+        e = __builtin_ldexp(e, er + fc[g]);
+      }
       dd_add(acc_h[i][g], acc_l[i][g], s, e, acc_h[i][g], acc_l[i][g]);
       B.b0[i][g] = B.b1[i][g] = B.b2[i][g] = B.b36[i][g] = 0.0;
     }
+  }
 }
 
 // Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD b % 8)
@@ -182,15 +197,21 @@ __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? 
 // One 64x64 output tile (tile row tm, tile column tn) of one GEMM, computed
 // by the whole workgroup.  `lds` is the workgroup's staging memory.  With
 // kFlags, entries at risk of cancellation get their bit set in the m x n
-// column-major bitmap `flags` (bit i + j*m).
-template <bool kFlags>
+// column-major bitmap `flags` (bit i + j*m).  With kPanel, the exponents of
+// Sigma and T of rank-kc block b are aexp[b * astride + i] and
+// bexp[b * bstride + j] and are applied to each block's result; otherwise
+// the maxima amax[i], bmax[j] give the exponents that scale the sum.
+template <bool kFlags, bool kPanel>
 __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const double* __restrict__ Apack,
                                              const double* __restrict__ Bpack,
                                              const uint64_t* __restrict__ amax,
                                              const uint64_t* __restrict__ bmax, int64_t K4, int32_t kcq,
                                              int64_t m, int64_t n, int64_t tm, int64_t tn,
                                              double* __restrict__ Chi, double* __restrict__ Clo,
-                                             int64_t ldc, uint32_t* __restrict__ flags) {
+                                             int64_t ldc, uint32_t* __restrict__ flags,
+                                             const int32_t* __restrict__ aexp = nullptr,
+                                             const int32_t* __restrict__ bexp = nullptr,
+                                             int64_t astride = 0, int64_t bstride = 0) {
   uint32_t flg = 0;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -269,14 +290,30 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   // during stage st-1) and the loads of stage st+2 are issued; after the
   // barrier the products of group 1 run while group 0 of stage st+1 is read
   // into ox.
-  int32_t inblk = 0;
+  // D lane 16i + 4b + j of (sub-block, group) holds row 4*sub + i, column
+  // 16*group + 4b + j, i.e. row lane/16 and column lane%16.
+  int32_t inblk = 0, blk = 0;
+  auto block_done = [&]() {
+    const int32_t* ea = nullptr;
+    const int32_t* fb = nullptr;
+    if constexpr (kPanel) {
+      // this block's exponents (padding rows and columns hold zero); the lane
+      // index is re-read here so that no address stays live across the loop
+      int l = threadIdx.x & 63;
+      asm volatile("" : "+v"(l));
+      ea = aexp + blk * astride + rb0 * 16 + (l >> 4);
+      fb = bexp + blk * bstride + cb0 * 16 + (l & 15);
+    }
+    combine<kFlags, kPanel>(bins, acc_h, acc_l, flg, ea, fb);
+    ++blk;
+  };
   for (int64_t st = 0; st < nst; ++st) {
     const int64_t last = nst - 1;
     read_ops(oy, a_ptr(st), b_ptr(st), 1);
     derive_b(ox);
     ten_products(bins, ox);
     interleave_reads();
-    if (++inblk == kcq) { inblk = 0; combine<kFlags>(bins, acc_h, acc_l, flg); }
+    if (++inblk == kcq) { inblk = 0; block_done(); }
     derive_b(oy);
     if (st < last) {
       store_stage(st + 1);
@@ -287,22 +324,21 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
     }
     ten_products(bins, oy);
     interleave_reads();
-    if (++inblk == kcq) { inblk = 0; combine<kFlags>(bins, acc_h, acc_l, flg); }
+    if (++inblk == kcq) { inblk = 0; block_done(); }
   }
-  if (inblk != 0) combine<kFlags>(bins, acc_h, acc_l, flg);
+  if (inblk != 0) block_done();
 
-  // Epilogue: D lane 16i + 4b + j of (sub-block, group) holds row 4*sub + i,
-  // column 16*group + 4b + j, i.e. row lane/16 and column lane%16.
+  // Epilogue: Sigma and T (unless applied per block), then C + result.
 #pragma unroll
   for (int i = 0; i < kSub; ++i) {
     const int64_t row = rb0 * 16 + i * 4 + (lane >> 4);
     if (row >= m) continue;
-    const int er = exp_of_bits(amax[row]);
+    const int er = kPanel ? 0 : exp_of_bits(amax[row]);
 #pragma unroll
     for (int g = 0; g < kWaveCB; ++g) {
       const int64_t col = (cb0 + g) * 16 + (lane & 15);
       if (col >= n) continue;
-      const int sh = er + exp_of_bits(bmax[col]);
+      const int sh = kPanel ? 0 : er + exp_of_bits(bmax[col]);
       const double h = __builtin_ldexp(acc_h[i][g], sh);
       const double l = __builtin_ldexp(acc_l[i][g], sh);
       const int64_t idx = row + col * ldc;
@@ -320,16 +356,18 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   }
 }
 
-template <bool kFlags>
+template <bool kFlags, bool kPanel>
 __global__ void __launch_bounds__(kWaves * 64)
 cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpack,
                const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax,
                int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t tiles_m, int64_t tiles_n,
-               double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc, uint32_t* __restrict__ flags) {
+               double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc, uint32_t* __restrict__ flags,
+               const int32_t* __restrict__ aexp, const int32_t* __restrict__ bexp) {
   __shared__ __attribute__((aligned(16))) double lds[kNBuf * kStage];
   int64_t tm, tn;
   tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  cascade_tile<kFlags>(lds, Apack, Bpack, amax, bmax, K4, kcq, m, n, tm, tn, Chi, Clo, ldc, flags);
+  cascade_tile<kFlags, kPanel>(lds, Apack, Bpack, amax, bmax, K4, kcq, m, n, tm, tn, Chi, Clo, ldc, flags,
+                               aexp, bexp, tiles_m * kTile, tiles_n * kTile);
 }
 
 // Persistent form for a batch of GEMMs: every workgroup takes tiles from the
@@ -352,7 +390,7 @@ cascade_batched_kernel(const BatchDesc* __restrict__ desc, const BatchTile* __re
     if (w >= ntiles) break;
     const BatchTile t = tiles[w];
     const BatchDesc d = desc[t.p];
-    cascade_tile<false>(lds, (const double*)(ws + d.off_apack), (const double*)(ws + d.off_bpack),
+    cascade_tile<false, false>(lds, (const double*)(ws + d.off_apack), (const double*)(ws + d.off_bpack),
                         (const uint64_t*)(ws + d.off_amax), (const uint64_t*)(ws + d.off_bmax), d.K4, d.kcq,
                         d.m, d.n, t.tm, t.tn, Chi[t.p], Clo[t.p], d.ldc, nullptr);
     __syncthreads();  // the next tile reuses the staging buffers
@@ -376,17 +414,27 @@ hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles,
 
 hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,
                           const uint64_t* amax, const uint64_t* bmax,
-                          double* Chi, double* Clo, int64_t ldc, uint32_t* flags, hipStream_t s) {
+                          double* Chi, double* Clo, int64_t ldc, uint32_t* flags, hipStream_t s,
+                          const int32_t* aexp, const int32_t* bexp) {
   if (L.tile_m != kTile || L.tile_n != kTile || L.K4 % kStageQ != 0) return hipErrorInvalidValue;
+  if (L.npanel > 1 && (!aexp || !bexp)) return hipErrorInvalidValue;
   const int64_t tiles_m = L.mpad / kTile, tiles_n = L.npad / kTile;
   const int64_t tiles = tiles_m * tiles_n;
   if (tiles <= 0 || tiles > 0x7fffffff) return hipErrorInvalidValue;
-  if (flags) {
-    cascade_kernel<true><<<(unsigned)tiles, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m,
-                                                                 L.n, tiles_m, tiles_n, Chi, Clo, ldc, flags);
+  const unsigned g = (unsigned)tiles;
+  const bool panel = L.npanel > 1;
+  if (flags && panel) {
+    cascade_kernel<true, true><<<g, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
+                                                         tiles_m, tiles_n, Chi, Clo, ldc, flags, aexp, bexp);
+  } else if (flags) {
+    cascade_kernel<true, false><<<g, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
+                                                          tiles_m, tiles_n, Chi, Clo, ldc, flags, aexp, bexp);
+  } else if (panel) {
+    cascade_kernel<false, true><<<g, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
+                                                          tiles_m, tiles_n, Chi, Clo, ldc, nullptr, aexp, bexp);
   } else {
-    cascade_kernel<false><<<(unsigned)tiles, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m,
-                                                                  L.n, tiles_m, tiles_n, Chi, Clo, ldc, nullptr);
+    cascade_kernel<false, false><<<g, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
+                                                           tiles_m, tiles_n, Chi, Clo, ldc, nullptr, aexp, bexp);
   }
   return hipGetLastError();
 }

@@ -13,7 +13,8 @@ namespace ddk {
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 // Largest |X| (|fl(X + Xlo)| if Xlo is given) per outer index, as bits.
 hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int64_t so, int64_t sr,
-                               uint64_t* out, hipStream_t s, const double* Xlo = nullptr);
+                               uint64_t* out, hipStream_t s, const double* Xlo = nullptr,
+                               int64_t plen = 0, int64_t ostride = 0);
 hipError_t launch_pack_a(const double* Ahi, const double* Alo, int64_t si, int64_t sp,
                          const CascadeLayout& L, const uint64_t* amax, double* Apack, hipStream_t s);
 hipError_t launch_pack_b(const double* Bhi, const double* Blo, int64_t sp, int64_t sj,
@@ -43,9 +44,12 @@ hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles,
 // combined in FP64x2, Sigma/T applied, C := C + result.  `flags` (may be
 // null): m x n bitmap, zeroed by the caller, of entries at risk of
 // cancellation (a block's bin 0 zero while a lower bin is not).
+// With L.npanel > 1, aexp / bexp are the per-panel exponents (int32, set b
+// at b * mpad / b * npad) and Sigma, T are applied per rank-kc block.
 hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,
                           const uint64_t* amax, const uint64_t* bmax,
-                          double* Chi, double* Clo, int64_t ldc, uint32_t* flags, hipStream_t s);
+                          double* Chi, double* Clo, int64_t ldc, uint32_t* flags, hipStream_t s,
+                          const int32_t* aexp = nullptr, const int32_t* bexp = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
 // Plain software double-double GEMM on the vector units.

@@ -38,7 +38,9 @@ struct CascadeLayout {
   int32_t kc;                    // rank-kc block actually used (min(kc, k))
   int32_t kcq;                   // kc in groups of four inner indices
   int32_t c[3];                  // split widths c0, c1, c2
+  int32_t npanel;                // exponent sets: 1, or one per rank-kc panel
   size_t off_amax, off_bmax, off_apack, off_bpack, bytes;
+  size_t off_aexp, off_bexp;     // per-panel exponents as int32 (npanel > 1 only)
 };
 
 inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
@@ -69,8 +71,12 @@ inline void split_widths(int64_t kc, int32_t c[3]) {
   c[2] = 53 - L - 2 - c0;
 }
 
+// With `panels`, Sigma and T are taken per rank-kc panel (inner indices
+// [4 kcq b, 4 kcq (b + 1))): the row maxima of op(A) are stored as npanel
+// sets of mpad words (set b at b * mpad), the column maxima of op(B) as
+// npanel sets of npad words.
 inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
-                                 int64_t tile_m, int64_t tile_n) {
+                                 int64_t tile_m, int64_t tile_n, bool panels = false) {
   CascadeLayout L{};
   L.m = m; L.n = n; L.k = k;
   L.tile_m = tile_m; L.tile_n = tile_n;
@@ -83,12 +89,18 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
   L.kc = (int32_t)kce;
   L.kcq = (int32_t)((kce + 3) / 4);
   split_widths(kce, L.c);
+  // panels are the runs of 4 kcq inner indices the product kernel combines
+  L.npanel = panels ? (int32_t)((L.K4 + L.kcq - 1) / L.kcq) : 1;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up((int64_t)(off + bytes), 256); return o; };
-  L.off_amax = take(sizeof(uint64_t) * (size_t)L.mpad);
-  L.off_bmax = take(sizeof(uint64_t) * (size_t)L.npad);
+  L.off_amax = take(sizeof(uint64_t) * (size_t)L.mpad * (size_t)L.npanel);
+  L.off_bmax = take(sizeof(uint64_t) * (size_t)L.npad * (size_t)L.npanel);
   L.off_apack = take(sizeof(double) * (size_t)kFragA * (size_t)L.mpad * (size_t)L.kpad);
   L.off_bpack = take(sizeof(double) * (size_t)kFragB * (size_t)L.npad * (size_t)L.kpad);
+  if (L.npanel > 1) {
+    L.off_aexp = take(sizeof(int32_t) * (size_t)L.mpad * (size_t)L.npanel);
+    L.off_bexp = take(sizeof(int32_t) * (size_t)L.npad * (size_t)L.npanel);
+  }
   L.bytes = off;
   return L;
 }

@@ -162,13 +162,19 @@ dd_status run_split(const Problem& p, const CascadeLayout& L, char* ws, hipStrea
   strides(p, a_si, a_sp, b_sp, b_sj);
   uint64_t* amax = (uint64_t*)(ws + L.off_amax);
   uint64_t* bmax = (uint64_t*)(ws + L.off_bmax);
-  DD_TRY(ddk::launch_fill_u64(amax, L.mpad, 0, s));
-  DD_TRY(ddk::launch_fill_u64(bmax, L.npad, 0, s));
-  // rows of op(A): outer i, reduced p;  columns of op(B): outer j, reduced p
-  DD_TRY(ddk::launch_max_abs_bits(p.Ahi, p.m, p.k, a_si, a_sp, amax, s));
-  DD_TRY(ddk::launch_max_abs_bits(p.Bhi, p.n, p.k, b_sj, b_sp, bmax, s));
+  DD_TRY(ddk::launch_fill_u64(amax, L.mpad * L.npanel, 0, s));
+  DD_TRY(ddk::launch_fill_u64(bmax, L.npad * L.npanel, 0, s));
+  // rows of op(A): outer i, reduced p;  columns of op(B): outer j, reduced p;
+  // with per-panel Sigma and T one maximum per run of 4 kcq inner indices
+  const int64_t plen = L.npanel > 1 ? 4 * (int64_t)L.kcq : 0;
+  DD_TRY(ddk::launch_max_abs_bits(p.Ahi, p.m, p.k, a_si, a_sp, amax, s, nullptr, plen, L.mpad));
+  DD_TRY(ddk::launch_max_abs_bits(p.Bhi, p.n, p.k, b_sj, b_sp, bmax, s, nullptr, plen, L.npad));
   DD_TRY(ddk::launch_pack_a(p.Ahi, p.Alo, a_si, a_sp, L, amax, (double*)(ws + L.off_apack), s));
   DD_TRY(ddk::launch_pack_b(p.Bhi, p.Blo, b_sp, b_sj, L, bmax, (double*)(ws + L.off_bpack), s));
+  if (L.npanel > 1) {
+    DD_TRY(ddk::launch_exps(amax, L.mpad * L.npanel, (int32_t*)(ws + L.off_aexp), s));
+    DD_TRY(ddk::launch_exps(bmax, L.npad * L.npanel, (int32_t*)(ws + L.off_bexp), s));
+  }
   return DD_OK;
 }
 
@@ -178,6 +184,7 @@ struct Opts {
   int32_t kc = kDefaultKc;
   int32_t S = 0, w = 0;   // slices variants
   uint32_t* flags = nullptr;   // cascade: cancellation bitmap (may be null)
+  bool panels = false;         // cascade: Sigma and T per rank-kc panel
   bool slices() const {
     return algo == DD_ALGO_SLICES_BF16 || algo == DD_ALGO_SLICES_F16 || algo == DD_ALGO_SLICES_I8;
   }
@@ -260,7 +267,7 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
     }
     return st;
   }
-  const CascadeLayout L = ddk::make_layout(p.m, p.n, p.k, kc, kTileM, kTileN);
+  const CascadeLayout L = ddk::make_layout(p.m, p.n, p.k, kc, kTileM, kTileN, o.panels);
   char* ws = (char*)workspace;
   if (internal_ws) {
     void* w = nullptr;
@@ -281,7 +288,8 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
   st = hip_status(ddk::launch_cascade(L, (const double*)(ws + L.off_apack),
                                       (const double*)(ws + L.off_bpack),
                                       (const uint64_t*)(ws + L.off_amax),
-                                      (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, o.flags, s));
+                                      (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, o.flags, s,
+                                      (const int32_t*)(ws + L.off_aexp), (const int32_t*)(ws + L.off_bexp)));
   if (pe.e2) {
     (void)hipEventRecord(pe.e2, s);
     std::lock_guard<std::mutex> lk(g_mu);
@@ -309,10 +317,13 @@ static bool read_opts(const dd_gemm_opts* o, Opts* out) {
   *out = Opts{};
   if (!o) return true;
   if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_SLICES_I8) return false;
-  if (o->tile != 0 || o->reserved0 != 0) return false;
+  if (o->tile != 0) return false;
+  if (o->scaling != DD_SCALING_GLOBAL && o->scaling != DD_SCALING_PANEL) return false;
   out->algo = o->algo;
   if (o->flags_out && o->algo != DD_ALGO_CASCADE_F64) return false;
+  if (o->scaling != DD_SCALING_GLOBAL && o->algo != DD_ALGO_CASCADE_F64) return false;
   out->flags = o->flags_out;
+  out->panels = o->scaling == DD_SCALING_PANEL;
   if (out->slices()) {
     if (o->kc != 0) return false;
     return slice_params(out->fmt(), o->slices, o->slice_bits, &out->S, &out->w);
@@ -330,7 +341,7 @@ size_t dd_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, 
   if ((transa != DD_OP_N && transa != DD_OP_T) || (transb != DD_OP_N && transb != DD_OP_T)) return 0;
   if (m <= 0 || n <= 0 || k <= 0 || o.algo == DD_ALGO_DD_VALU) return 0;
   if (o.slices()) return ddk::make_slices_layout(m, n, k, o.S, o.w, o.fmt()).bytes;
-  return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN).bytes;
+  return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN, o.panels).bytes;
 }
 
 dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,

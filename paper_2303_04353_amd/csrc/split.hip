@@ -28,46 +28,59 @@ __global__ void fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
+// The reduced range is cut into chunks of `chunk` indices; chunk c (taken by
+// blocks y = c, c + gridDim.y, ...) goes to out[o + c * ostride]: ostride = 0
+// folds every chunk into one maximum, ostride > 0 keeps one per chunk (the
+// per-panel maxima, chunk = the panel length).
+
 // Element (o, r) at X[o + r*ld]: consecutive threads take consecutive o.
 __global__ void __launch_bounds__(256)
 max_abs_bits_outer_contig(const double* __restrict__ X, const double* __restrict__ Xlo, int64_t outer,
-                          int64_t red, int64_t ld, int64_t chunk, uint64_t* __restrict__ out) {
+                          int64_t red, int64_t ld, int64_t chunk, int64_t ostride,
+                          uint64_t* __restrict__ out) {
   int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (o >= outer) return;
-  int64_t r0 = (int64_t)blockIdx.y * chunk;
-  int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
-  uint64_t mx = 0;
-  for (int64_t r = r0; r < r1; ++r) {
-    const double v = Xlo ? X[o + r * ld] + Xlo[o + r * ld] : X[o + r * ld];
-    uint64_t b = __builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull;
-    mx = b > mx ? b : mx;
+  const int64_t nchunk = (red + chunk - 1) / chunk;
+  for (int64_t c = blockIdx.y; c < nchunk; c += gridDim.y) {
+    int64_t r0 = c * chunk;
+    int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
+    uint64_t mx = 0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const double v = Xlo ? X[o + r * ld] + Xlo[o + r * ld] : X[o + r * ld];
+      uint64_t b = __builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull;
+      mx = b > mx ? b : mx;
+    }
+    atomicMax((unsigned long long*)&out[o + c * ostride], (unsigned long long)mx);
   }
-  if (r1 > r0) atomicMax((unsigned long long*)&out[o], (unsigned long long)mx);
 }
 
 // Element (o, r) at X[r + o*ld]: one wave per o, lanes stride over r.
 __global__ void __launch_bounds__(256)
 max_abs_bits_red_contig(const double* __restrict__ X, const double* __restrict__ Xlo, int64_t outer,
-                        int64_t red, int64_t ld, int64_t chunk, uint64_t* __restrict__ out) {
+                        int64_t red, int64_t ld, int64_t chunk, int64_t ostride,
+                        uint64_t* __restrict__ out) {
   int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (o >= outer) return;
-  int64_t r0 = (int64_t)blockIdx.y * chunk;
-  int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
-  uint64_t mx = 0;
   const double* col = X + o * ld;
   const double* col_lo = Xlo ? Xlo + o * ld : nullptr;
-  for (int64_t r = r0 + lane; r < r1; r += 64) {
-    const double v = col_lo ? col[r] + col_lo[r] : col[r];
-    uint64_t b = __builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull;
-    mx = b > mx ? b : mx;
-  }
+  const int64_t nchunk = (red + chunk - 1) / chunk;
+  for (int64_t c = blockIdx.y; c < nchunk; c += gridDim.y) {
+    int64_t r0 = c * chunk;
+    int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
+    uint64_t mx = 0;
+    for (int64_t r = r0 + lane; r < r1; r += 64) {
+      const double v = col_lo ? col[r] + col_lo[r] : col[r];
+      uint64_t b = __builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull;
+      mx = b > mx ? b : mx;
+    }
 #pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) {
-    uint64_t y = __shfl_xor(mx, s, 64);
-    mx = y > mx ? y : mx;
+    for (int s = 32; s >= 1; s >>= 1) {
+      uint64_t y = __shfl_xor(mx, s, 64);
+      mx = y > mx ? y : mx;
+    }
+    if (lane == 0) atomicMax((unsigned long long*)&out[o + c * ostride], (unsigned long long)mx);
   }
-  if (lane == 0 && r1 > r0) atomicMax((unsigned long long*)&out[o], (unsigned long long)mx);
 }
 
 __device__ __forceinline__ SplitParams make_params(int c0, int c1, int c2) {
@@ -86,10 +99,13 @@ __device__ __forceinline__ SplitParams make_params(int c0, int c1, int c2) {
 }
 
 // One 64-lane fragment of the packed A planes: op(A)(i, p) = A[i*si + p*sp_].
+// The exponent of entry (i, p) is amax[i] (pstride = 0), or with per-panel
+// Sigma amax[i + (p / plen) * pstride]; likewise for B.
 __device__ __forceinline__ void pack_a_frag(const double* __restrict__ Ahi, const double* __restrict__ Alo,
                                             int64_t si, int64_t sp_, int64_t m, int64_t k, int64_t K4,
                                             int64_t frag, int lane, const uint64_t* __restrict__ amax,
-                                            int c0, int c1, int c2, double* __restrict__ Apack) {
+                                            int c0, int c1, int c2, double* __restrict__ Apack,
+                                            int64_t plen = 1, int64_t pstride = 0) {
   int64_t rb = frag / K4, kq = frag - rb * K4;
   // position lane = s*16 + kk*4 + ii holds row rb*16 + s*4 + ii, inner index kq*4 + kk
   int64_t i = rb * 16 + (lane >> 4) * 4 + (lane & 3), p = kq * 4 + ((lane >> 2) & 3);
@@ -98,7 +114,7 @@ __device__ __forceinline__ void pack_a_frag(const double* __restrict__ Ahi, cons
     SplitParams spar = make_params(c0, c1, c2);
     int64_t idx = i * si + p * sp_;
     double xh, xl;
-    split_entry(Ahi[idx], Alo[idx], exp_of_bits(amax[i]), spar, w, xh, xl);
+    split_entry(Ahi[idx], Alo[idx], exp_of_bits(amax[i + (p / plen) * pstride]), spar, w, xh, xl);
   }
   double* dst = Apack + frag * (kFragA * kLanes) + lane;
 #pragma unroll
@@ -109,7 +125,8 @@ __device__ __forceinline__ void pack_a_frag(const double* __restrict__ Ahi, cons
 __device__ __forceinline__ void pack_b_frag(const double* __restrict__ Bhi, const double* __restrict__ Blo,
                                             int64_t sp_, int64_t sj, int64_t k, int64_t n, int64_t K4,
                                             int64_t frag, int lane, const uint64_t* __restrict__ bmax,
-                                            int c0, int c1, int c2, double* __restrict__ Bpack) {
+                                            int c0, int c1, int c2, double* __restrict__ Bpack,
+                                            int64_t plen = 1, int64_t pstride = 0) {
   int64_t cb = frag / K4, kq = frag - cb * K4;
   int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
   double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -117,7 +134,7 @@ __device__ __forceinline__ void pack_b_frag(const double* __restrict__ Bhi, cons
     SplitParams spar = make_params(c0, c1, c2);
     int64_t idx = p * sp_ + j * sj;
     double yh, yl;
-    split_entry(Bhi[idx], Blo[idx], exp_of_bits(bmax[j]), spar, w, yh, yl);
+    split_entry(Bhi[idx], Blo[idx], exp_of_bits(bmax[j + (p / plen) * pstride]), spar, w, yh, yl);
     w[4] = yh + yl;       // B6: the scaled entry itself, rounded once
   }
   double* dst = Bpack + frag * (kFragB * kLanes) + lane;
@@ -129,20 +146,20 @@ __device__ __forceinline__ void pack_b_frag(const double* __restrict__ Bhi, cons
 __global__ void __launch_bounds__(256)
 pack_a(const double* __restrict__ Ahi, const double* __restrict__ Alo, int64_t si, int64_t sp_,
        int64_t m, int64_t k, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ amax,
-       int c0, int c1, int c2, double* __restrict__ Apack) {
+       int c0, int c1, int c2, double* __restrict__ Apack, int64_t plen, int64_t pstride) {
   int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (frag >= nfrag) return;
-  pack_a_frag(Ahi, Alo, si, sp_, m, k, K4, frag, threadIdx.x & 63, amax, c0, c1, c2, Apack);
+  pack_a_frag(Ahi, Alo, si, sp_, m, k, K4, frag, threadIdx.x & 63, amax, c0, c1, c2, Apack, plen, pstride);
 }
 
 // One wave per fragment (cb, kq).
 __global__ void __launch_bounds__(256)
 pack_b(const double* __restrict__ Bhi, const double* __restrict__ Blo, int64_t sp_, int64_t sj,
        int64_t k, int64_t n, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ bmax,
-       int c0, int c1, int c2, double* __restrict__ Bpack) {
+       int c0, int c1, int c2, double* __restrict__ Bpack, int64_t plen, int64_t pstride) {
   int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (frag >= nfrag) return;
-  pack_b_frag(Bhi, Blo, sp_, sj, k, n, K4, frag, threadIdx.x & 63, bmax, c0, c1, c2, Bpack);
+  pack_b_frag(Bhi, Blo, sp_, sj, k, n, K4, frag, threadIdx.x & 63, bmax, c0, c1, c2, Bpack, plen, pstride);
 }
 
 // ------------------------------------------------------------ batched phase one
@@ -288,22 +305,28 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
 }
 
 // max |X(o, r)| bits over r for o < outer, X(o, r) = X[o*so + r*sr]; one of
-// so, sr is 1.  out must be zero on entry.
+// so, sr is 1.  out must be zero on entry.  With plen > 0, one maximum per
+// run of plen consecutive r: out[o + (r / plen) * ostride].
 hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int64_t so, int64_t sr,
-                               uint64_t* out, hipStream_t s, const double* Xlo) {
+                               uint64_t* out, hipStream_t s, const double* Xlo, int64_t plen,
+                               int64_t ostride) {
   if (outer <= 0 || red <= 0) return hipSuccess;
+  if (plen > 0 && ostride < outer) return hipErrorInvalidValue;
+  const int64_t step = so == 1 ? 256 : 4096;
+  int64_t chunk = plen > 0 ? plen : step;
+  int64_t gy = (red + chunk - 1) / chunk;
+  if (plen <= 0) {
+    while (gy > 65535) { chunk *= 2; gy = (red + chunk - 1) / chunk; }
+    ostride = 0;
+  } else if (gy > 65535) {
+    gy = 65535;   // blocks loop over the panels
+  }
   if (so == 1) {
-    int64_t chunk = 256;
-    int64_t gy = (red + chunk - 1) / chunk;
-    while (gy > 65535) { chunk *= 2; gy = (red + chunk - 1) / chunk; }
     dim3 grid(blocks_for(outer, 256), (unsigned)gy);
-    max_abs_bits_outer_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, sr, chunk, out);
+    max_abs_bits_outer_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, sr, chunk, ostride, out);
   } else {
-    int64_t chunk = 4096;
-    int64_t gy = (red + chunk - 1) / chunk;
-    while (gy > 65535) { chunk *= 2; gy = (red + chunk - 1) / chunk; }
     dim3 grid(blocks_for(outer, 4), (unsigned)gy);
-    max_abs_bits_red_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, so, chunk, out);
+    max_abs_bits_red_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, so, chunk, ostride, out);
   }
   return hipGetLastError();
 }
@@ -311,16 +334,18 @@ hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int6
 hipError_t launch_pack_a(const double* Ahi, const double* Alo, int64_t si, int64_t sp,
                          const CascadeLayout& L, const uint64_t* amax, double* Apack, hipStream_t s) {
   int64_t nfrag = (L.mpad / 16) * L.K4;
+  const int64_t plen = 4 * (int64_t)L.kcq, pstride = L.npanel > 1 ? L.mpad : 0;
   pack_a<<<blocks_for(nfrag, 4), 256, 0, s>>>(Ahi, Alo, si, sp, L.m, L.k, L.K4, nfrag, amax,
-                                              L.c[0], L.c[1], L.c[2], Apack);
+                                              L.c[0], L.c[1], L.c[2], Apack, plen, pstride);
   return hipGetLastError();
 }
 
 hipError_t launch_pack_b(const double* Bhi, const double* Blo, int64_t sp, int64_t sj,
                          const CascadeLayout& L, const uint64_t* bmax, double* Bpack, hipStream_t s) {
   int64_t nfrag = (L.npad / 16) * L.K4;
+  const int64_t plen = 4 * (int64_t)L.kcq, pstride = L.npanel > 1 ? L.npad : 0;
   pack_b<<<blocks_for(nfrag, 4), 256, 0, s>>>(Bhi, Blo, sp, sj, L.k, L.n, L.K4, nfrag, bmax,
-                                              L.c[0], L.c[1], L.c[2], Bpack);
+                                              L.c[0], L.c[1], L.c[2], Bpack, plen, pstride);
   return hipGetLastError();
 }
 

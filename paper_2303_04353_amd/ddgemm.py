@@ -29,6 +29,8 @@ DD_ALGO_DD_VALU = 1
 DD_ALGO_SLICES_BF16 = 2
 DD_ALGO_SLICES_F16 = 3
 DD_ALGO_SLICES_I8 = 4
+DD_SCALING_GLOBAL = 0
+DD_SCALING_PANEL = 1
 
 EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_slices_split", "dd_dot",
             "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",
@@ -39,7 +41,7 @@ EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split
 class dd_gemm_opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("kc", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("slices", ctypes.c_int32), ("slice_bits", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("flags_out", ctypes.c_void_p)]
+                ("scaling", ctypes.c_int32), ("flags_out", ctypes.c_void_p)]
 
 
 class DDError(RuntimeError):

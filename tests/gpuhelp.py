@@ -23,7 +23,7 @@ def down(t):
 
 
 def run_gemm(A, B, C, *, transa=False, transb=False, algo=dg.DD_ALGO_CASCADE_F64, kc=0,
-             plain=False, slices=0, slice_bits=0):
+             plain=False, slices=0, slice_bits=0, scaling=0):
     """op(A) op(B) + C on the GPU through the C ABI; A, B, C are numpy (hi, lo)
     pairs as stored.  Returns numpy (hi, lo)."""
     import torch
@@ -35,11 +35,12 @@ def run_gemm(A, B, C, *, transa=False, transb=False, algo=dg.DD_ALGO_CASCADE_F64
     n = B[0].shape[0] if transb else B[0].shape[1]
     lda, ldb, ldc = max(1, A[0].shape[0]), max(1, B[0].shape[0]), max(1, C[0].shape[0])
     if plain:
-        assert not transa and not transb and algo == dg.DD_ALGO_CASCADE_F64 and kc == 0
+        assert not transa and not transb and algo == dg.DD_ALGO_CASCADE_F64 and kc == 0 and scaling == 0
         st = dg.dd_gemm(m, n, k, Ah, Al, lda, Bh, Bl, ldb, Ch, Cl, ldc)
     else:
         st = dg.dd_gemm_ex(int(transa), int(transb), m, n, k, Ah, Al, lda, Bh, Bl, ldb, Ch, Cl, ldc,
-                           opts={"algo": algo, "kc": kc, "slices": slices, "slice_bits": slice_bits})
+                           opts={"algo": algo, "kc": kc, "slices": slices, "slice_bits": slice_bits,
+                                 "scaling": scaling})
     dg.check(st, "dd_gemm_ex")
     torch.cuda.synchronize()
     return down(Ch), down(Cl)
@@ -71,4 +72,24 @@ def cascade_order_bound(A, B, O, k, kc):
     nb = -(-k // kce)
     AB = np.abs(np.asarray(A[0])) @ np.abs(np.asarray(B[0]))
     return (scale * 64.0 * kce * k * 2.0 ** -(53 + D2)
+            + 8 * nb * 2.0 ** -106 * AB + 2.0 ** -103 * np.abs(O[0]))
+
+
+def panel_order_bound(A, B, O, k, kc):
+    """cascade_order_bound with Sigma and T per rank-kc panel: each block's
+    bin 3-6 order difference is bounded at that panel's scale, so the sum is
+    bounded by the largest panel scale times the whole-k term."""
+    from oracle import cascade as cz  # tests only
+    kce = min(kc, k)
+    c = cz.split_widths(kce)
+    D2 = sum(c)
+    top = None
+    for p0 in range(0, k, kce):
+        e = cz.exponents(A[0][:, p0:p0 + kce], axis=1).astype(np.int64)
+        f = cz.exponents(B[0][p0:p0 + kce, :], axis=0).astype(np.int64)
+        s = e[:, None] + f[None, :]
+        top = s if top is None else np.maximum(top, s)
+    nb = -(-k // kce)
+    AB = np.abs(np.asarray(A[0])) @ np.abs(np.asarray(B[0]))
+    return (np.ldexp(1.0, top) * 64.0 * kce * k * 2.0 ** -(53 + D2)
             + 8 * nb * 2.0 ** -106 * AB + 2.0 ** -103 * np.abs(O[0]))

@@ -80,6 +80,22 @@ def test_workspace_size_formula():
     assert dg.dd_gemm_workspace_size(0, 0, 0, 70, 300) == 0
 
 
+def test_panel_scaling_option_and_workspace():
+    m, n, k = 100, 70, 1000
+    mpad, npad, kpad = 128, 128, 1000
+    g = dg.dd_gemm_workspace_size(0, 0, m, n, k)
+    # four rank-256 panels: three more sets of maxima and four sets of int32 exponents
+    p = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"scaling": dg.DD_SCALING_PANEL})
+    extra = 8 * 3 * (mpad + npad) + 4 * 4 * (mpad + npad)
+    assert g + extra - 4 * 256 <= p <= g + extra + 4 * 256
+    assert 8 * (mpad + npad) + 8 * 9 * 128 * kpad <= g
+    # one panel: the global layout
+    assert dg.dd_gemm_workspace_size(0, 0, m, n, 200, {"scaling": 1}) == dg.dd_gemm_workspace_size(0, 0, m, n, 200)
+    for bad in ({"scaling": 2}, {"scaling": -1}, {"algo": dg.DD_ALGO_DD_VALU, "scaling": 1},
+                {"algo": dg.DD_ALGO_SLICES_BF16, "scaling": 1}):
+        assert dg.dd_gemm_workspace_size(0, 0, m, n, k, bad) == 0, bad
+
+
 def test_slices_options_and_workspace():
     bf, f16 = dg.DD_ALGO_SLICES_BF16, dg.DD_ALGO_SLICES_F16
     m, n, k = 100, 70, 300

@@ -6,7 +6,11 @@
   different summation order of bin 3-6 (bins 0-2 are exact, so only that
   order differs), and against the FP64x2 oracle within 64 k 2^-104 (|A||B|)_ij;
 * transposed storage gives bit-identical results (same packed planes);
-* worked example of Sec. 3.6, integer matrices, edge cases.
+* worked example of Sec. 3.6, integer matrices, edge cases;
+* Sigma and T per rank-kc panel: against the oracle's panel form and the
+  FP64x2 oracle, equal to the global form for one block, bitwise invariant
+  to per-panel power-of-two balancing, and within the tolerance on data
+  where one exponent per row and column is not.
 """
 import json
 import os
@@ -18,7 +22,8 @@ from oracle import cascade as cz
 from oracle.ref import dd_gemm_ref, dd_gemm_ref_entries
 from paper_2303_04353_amd import ddgemm as dg
 from paper_2303_04353_amd.inputs import make_problem, sample_entries
-from tests.gpuhelp import (cascade_order_bound, dd_diff, down, log, north_star_bound, run_gemm, up)
+from tests.gpuhelp import (cascade_order_bound, dd_diff, down, log, north_star_bound, panel_order_bound,
+                           run_gemm, up)
 
 pytestmark = pytest.mark.gpu
 
@@ -285,3 +290,92 @@ def test_flags_rejected_for_other_algorithms():
     base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
     for algo in (dg.DD_ALGO_DD_VALU, dg.DD_ALGO_SLICES_BF16):
         assert dg.dd_gemm_ex(0, 0, *base, opts={"algo": algo, "flags_out": words}) == -17
+
+
+# --- Sigma and T per rank-kc panel ------------------------------------------------
+
+PANEL = dg.DD_SCALING_PANEL
+PANEL_CASES = [(200, 96, 520, 128), (64, 64, 1000, 64), (100, 70, 300, 256), (3, 130, 257, 256),
+               (65, 33, 600, 256)]
+
+
+@pytest.mark.parametrize("m,n,k,kc", PANEL_CASES)
+def test_panel_scaling_matches_oracles(m, n, k, kc):
+    log(f"panel scaling m={m} n={n} k={k} kc={kc}")
+    P = make_problem(m, n, k, cfg=15, variant="panels", panel=kc)
+    G = run_gemm(P["A"], P["B"], P["C"], kc=kc, scaling=PANEL)
+    O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc, scaling="panel")
+    assert np.all(dd_diff(G, O) <= panel_order_bound(P["A"], P["B"], O, k, kc))
+    R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
+    assert np.all(dd_diff(G, R) <= north_star_bound(P["A"], P["B"], k))
+
+
+def test_panel_scaling_equals_global_for_one_block():
+    P = make_problem(90, 70, 200, cfg=16, variant="scaled")
+    G0 = run_gemm(P["A"], P["B"], P["C"], kc=256)
+    G1 = run_gemm(P["A"], P["B"], P["C"], kc=256, scaling=PANEL)
+    assert np.array_equal(G0[0], G1[0]) and np.array_equal(G0[1], G1[1])
+
+
+def test_panel_scaling_is_invariant_to_power_of_two_balancing():
+    m, n, k, kc = 70, 90, 700, 128
+    P = make_problem(m, n, k, cfg=17)
+    t = (np.arange(k) // kc * 13 % 61 - 30)
+    Af = (np.asfortranarray(np.ldexp(P["A"][0], t[None, :])), np.asfortranarray(np.ldexp(P["A"][1], t[None, :])))
+    Bf = (np.asfortranarray(np.ldexp(P["B"][0], -t[:, None])), np.asfortranarray(np.ldexp(P["B"][1], -t[:, None])))
+    G0 = run_gemm(P["A"], P["B"], P["C"], kc=kc, scaling=PANEL)
+    G1 = run_gemm(Af, Bf, P["C"], kc=kc, scaling=PANEL)
+    assert np.array_equal(G0[0], G1[0]) and np.array_equal(G0[1], G1[1])
+
+
+def test_panel_scaling_meets_the_tolerance_where_global_does_not():
+    m = n = 64
+    kc, k = 256, 512
+    rng = np.random.default_rng(18)
+    Ahi = rng.uniform(-1, 1, (m, k))
+    Bhi = rng.uniform(-1, 1, (k, n))
+    Ahi[:, kc:] *= 2.0 ** -90
+    Bhi[:kc, :] *= 2.0 ** -90
+    A = (np.asfortranarray(Ahi), np.asfortranarray(Ahi * 2.0 ** -53 * rng.uniform(-1, 1, (m, k))))
+    B = (np.asfortranarray(Bhi), np.asfortranarray(Bhi * 2.0 ** -53 * rng.uniform(-1, 1, (k, n))))
+    C = (np.zeros((m, n), order="F"), np.zeros((m, n), order="F"))
+    R = dd_gemm_ref(A, B, C)[:2]
+    tol = north_star_bound(A, B, k)
+    Gp = run_gemm(A, B, C, kc=kc, scaling=PANEL)
+    Gg = run_gemm(A, B, C, kc=kc)
+    assert np.all(dd_diff(Gp, R) <= tol)
+    assert np.mean(dd_diff(Gg, R) > tol) > 0.5
+
+
+def test_panel_scaling_with_cancellation_flags():
+    import torch
+    m, n, k, kc = 96, 80, 640, 128
+    P = make_problem(m, n, k, cfg=19, variant="panels", panel=kc)
+    Ahi, Alo = P["A"][0].copy(), P["A"][1].copy()
+    Bhi, Blo = P["B"][0].copy(), P["B"][1].copy()
+    # rows 3 and 40 against columns 5 and 60: the leading digits cancel in
+    # every block, whatever each panel's power of two
+    for r in (3, 40):
+        Ahi[r, :] = 0.75
+        Ahi[r, 1::2] = 0.75 + 2.0 ** -30
+        Ahi[r, :] *= np.ldexp(1.0, np.arange(k) // kc * 7 - 9)
+        Alo[r, :] = 0.0
+    for c in (5, 60):
+        Bhi[:, c] = 0.5
+        Bhi[1::2, c] = -0.5
+        Blo[:, c] = 0.0
+    A = (np.asfortranarray(Ahi), np.asfortranarray(Alo))
+    B = (np.asfortranarray(Bhi), np.asfortranarray(Blo))
+    O = cz.cascade_gemm(A, B, P["C"], kc=kc, scaling="panel", return_parts=True)
+    want = cz.cancellation_flags(O[2]["bins"])
+    Ch, Cl = up(P["C"][0]), up(P["C"][1])
+    flags = torch.full(((m * n + 31) // 32,), -1, dtype=torch.int32, device="cuda")
+    dg.check(dg.dd_gemm_ex(0, 0, m, n, k, up(A[0]), up(A[1]), m, up(B[0]), up(B[1]), k, Ch, Cl, m,
+                           opts={"kc": kc, "scaling": PANEL, "flags_out": flags}), "dd_gemm_ex")
+    torch.cuda.synchronize()
+    bits = np.unpackbits(flags.cpu().numpy().view(np.uint8), bitorder="little")[:m * n]
+    got = bits.reshape(n, m).T.astype(bool)
+    assert np.array_equal(got, want)
+    assert got[3, 5] and got[40, 60]
+    G = (down(Ch), down(Cl))
+    assert np.all(dd_diff(G, O[:2]) <= panel_order_bound(A, B, O, k, kc))
