@@ -265,6 +265,32 @@ def accuracy_workloads(torch, dg, n=240):
     return out
 
 
+def panel_scaling(torch, dg, m=512, n=512, k=4096, kc=256):
+    """Sigma and T per rank-kc panel against one exponent per row and column
+    on the 'panels' recipe (the scale of every row and column changes from
+    panel to panel by up to 2^80): max error over (|A||B|)_ij against the
+    FP64x2 oracle, and the share of entries within the tolerance
+    (CPU-baseline leg: the oracle is test infrastructure)."""
+    from oracle.ref import dd_gemm_ref
+    from paper_2303_04353_amd.inputs import make_problem
+    P = make_problem(m, n, k, cfg=3, variant="panels", panel=kc)
+    R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
+    AB = np.abs(P["A"][0]) @ np.abs(P["B"][0])
+    tol = 64 * k * 2.0 ** -104
+    dev = [dg.colmajor_to_device(x) for x in (*P["A"], *P["B"])]
+    out = {"workload": f"m={m} n={n} k={k} kc={kc}, 'panels' inputs (per (row, panel) and (panel, column) "
+                       "scales 2^U{-40..40})", "tolerance_over_absAabsB": tol}
+    for name, scaling in (("global", dg.DD_SCALING_GLOBAL), ("panel", dg.DD_SCALING_PANEL)):
+        Ch, Cl = dg.colmajor_to_device(P["C"][0]), dg.colmajor_to_device(P["C"][1])
+        dg.check(dg.dd_gemm_ex(0, 0, m, n, k, dev[0], dev[1], m, dev[2], dev[3], k, Ch, Cl, m,
+                               opts={"kc": kc, "scaling": scaling}))
+        torch.cuda.synchronize()
+        G = dg.colmajor_from_device(Ch), dg.colmajor_from_device(Cl)
+        r = np.abs((G[0] - R[0]) + (G[1] - R[1])) / AB
+        out[name] = {"max_err_over_absAabsB": float(r.max()), "frac_within_tolerance": float(np.mean(r <= tol))}
+    return out
+
+
 def bench_autograd(torch):
     """Forward and cascaded backward of L = sum((W2 (W1 X)) o G), W 2048^2, X, G 2048x512."""
     from paper_2303_04353_amd import autograd as ag
@@ -445,6 +471,22 @@ def main():
                            "cascade_time_over_dgemm": round(ms_per_step / gms, 2)}
         del Z
 
+    # Sigma and T per rank-kc panel: the same product kernel with a per-block
+    # scale in its combine; timed once at the headline shape
+    Ph, Pl = C0h.clone(), C0l.clone()
+    popts = {"scaling": dg.DD_SCALING_PANEL}
+    dg.check(dg.dd_gemm_ex(0, 0, m, n, k, Ah, Al, m, Bh, Bl, k, Ph, Pl, m, opts=popts, stream=stream))
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    dg.check(dg.dd_gemm_ex(0, 0, m, n, k, Ah, Al, m, Bh, Bl, k, Ph, Pl, m, opts=popts, stream=stream))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    result["panel_scaling"] = {"ms": round(ev0.elapsed_time(ev1), 3),
+                               "value": round(flops_eff / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 2),
+                               "unit": "GFLOP/s"}
+    del Ph, Pl
+
     if not args.no_cpu_baseline:
         from oracle.ref import dd_gemm_ref_entries  # CPU baseline leg only
         A, B, C = P["A"], P["B"], P["C"]
@@ -496,6 +538,8 @@ def main():
         if not args.no_cpu_baseline:
             log("accuracy workloads at n=240 against the exact product")
             result["accuracy_workloads"] = accuracy_workloads(torch, dg)
+            log("panel scaling against global scaling on panel-scaled inputs")
+            result["panel_scaling"].update(panel_scaling(torch, dg))
     print(json.dumps(result), flush=True)
 
 

@@ -2,8 +2,8 @@
  * TEST INFRASTRUCTURE -- not part of the product path.
  *
  * Plain FP64x2 (double-double) GEMM, C := op(A) op(B) + C, as a triple loop.
- * This is the "simple triple-nested loop in FP64x2 arithmetic" that the paper
- * measures the cascade against (Sec. 5.2, accuracy experiments; FP64x2 format
+ * This is the plain FP64x2 triple loop that the paper compares the cascade's
+ * accuracy with (Sec. 5.2, accuracy experiments; FP64x2 format
  * of Sec. 3.1, eq. (doubledouble)).  Only the tests, the smoke check and the
  * benchmark's CPU-baseline leg may call it.
  *

@@ -1,5 +1,5 @@
 """TEST INFRASTRUCTURE: the paper's ill-conditioned GEMM workload (Sec. 5.2,
-"ill-conditioned experiments").
+the ill-conditioned experiments).
 
 A = Q with orthonormal rows, from the Householder QR of a seeded random
 matrix computed in FP64x2 arithmetic (the paper uses quad precision); C has

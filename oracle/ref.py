@@ -2,7 +2,7 @@
 
 ``dd_gemm_ref`` computes C := op(A) op(B) + C in double-double arithmetic
 (TwoProd by FMA, accurate DD addition, p ascending, C added last): the
-"FP64x2 arithmetic" reference of Sec. 5.2.  Only tests, the smoke check and
+FP64x2-arithmetic reference of Sec. 5.2.  Only tests, the smoke check and
 the benchmark's CPU-baseline leg use it.
 """
 from __future__ import annotations
