@@ -17,15 +17,19 @@
 // Operand staging: per LDS stage (2 groups of 4 inner indices) the
 // workgroup's 64 rows of A (4 planes) and 64 columns of B (5 stored planes),
 // 36 KiB, are loaded from the packed planes into registers (16-byte loads,
-// 36 pieces of 1 KiB dealt round robin to the 8 waves) one stage ahead, then
-// written to the other of two LDS buffers; one barrier per stage.  (Direct
-// global-to-LDS copies would save the registers, but their completion is
-// tracked with the LDS counter as well, so every wait for an operand read
-// would also wait for the copies in flight.)  Waves read their operands from
-// LDS; the reads of the next group are spread over the current group's
-// MFMAs.  FP64 vector work does not overlap the matrix cores on gfx950, so
-// the loop keeps vector instructions to the two additions that form B4' and
-// B5'.
+// 36 pieces of 1 KiB dealt round robin to the 8 waves; a wave with four
+// pieces moves its first one twice, so every wave runs the same branch-free
+// code), then written to the other of two LDS buffers; one barrier per
+// stage.  (Direct global-to-LDS copies would save the registers, but their
+// completion is tracked with the LDS counter as well, so every wait for an
+// operand read would also wait for the copies in flight.)  Every memory
+// instruction is issued between MFMAs: group 0's MFMAs carry the reads of
+// group 1 and, at their end, the LDS writes of the next stage; group 1's
+// MFMAs carry, first, the global loads of the stage after that, then the
+// reads of the next stage's group 0.  Both waves of a SIMD meet at the
+// barrier, so nothing but the wait for the writes is left there.  FP64
+// vector work does not overlap the matrix cores on gfx950, so the loop
+// keeps vector instructions to the two additions that form B4' and B5'.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -62,14 +66,35 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
 __device__ __forceinline__ void lds_reads_done() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-// Ask the scheduler to spread the LDS reads of the next operand set (13
-// two-word reads) over the 80 MFMAs of the current set: one read, then six
-// MFMAs, repeated.
-__device__ __forceinline__ void interleave_reads() {
+// The scheduler's order for the 80 MFMAs of one group and the memory
+// instructions issued among them (the LDS reads of the next operand set are
+// 13 two-word reads).
+// Group 0: the 13 reads of the next operands, then the 5 LDS writes of the
+// staged stage, spread over the 80 MFMAs.
+__device__ __forceinline__ void interleave_reads_writes() {
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
     __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
-    __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);   // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);   // MFMA
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // DS write
+    __builtin_amdgcn_sched_group_barrier(0x008, 5, 0);   // MFMA
+  }
+}
+
+// Group 1: the 5 global loads of a later stage, then the 13 reads.
+__device__ __forceinline__ void interleave_reads_loads() {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // VMEM read
+    __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);   // MFMA
+  }
+#pragma unroll
+  for (int i = 0; i < 13; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
+    __builtin_amdgcn_sched_group_barrier(0x008, 5, 0);   // MFMA
   }
 }
 
@@ -250,20 +275,20 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   }
   const int64_t strideA = kStageQ * kFragA * kLanes, strideB = kStageQ * kFragB * kLanes;
   d2 stg[kPiecesMax];
+  // every wave moves kPiecesMax pieces; a wave with fewer repeats piece 0
+  // (the same data to the same place), so the code has no branch
+  (void)npiece;
+  int64_t pstride[kPiecesMax];
+#pragma unroll
+  for (int c = 0; c < kPiecesMax; ++c) pstride[c] = pdst[c] < kAStage ? strideA : strideB;
   auto load_stage = [&](int64_t st) {
 #pragma unroll
-    for (int c = 0; c < kPiecesMax; ++c) {
-      if (c < npiece) {
-        const bool isA = pdst[c] < kAStage;
-        stg[c] = *(const d2*)(psrc[c] + st * (isA ? strideA : strideB));
-      }
-    }
+    for (int c = 0; c < kPiecesMax; ++c) stg[c] = *(const d2*)(psrc[c] + st * pstride[c]);
   };
   auto store_stage = [&](int64_t st) {
     double* buf = lds + (int)(st % kNBuf) * kStage;
 #pragma unroll
-    for (int c = 0; c < kPiecesMax; ++c)
-      if (c < npiece) *(d2*)(buf + pdst[c]) = stg[c];
+    for (int c = 0; c < kPiecesMax; ++c) *(d2*)(buf + pdst[c]) = stg[c];
   };
 
   auto a_ptr = [&](int64_t st) {
@@ -277,28 +302,26 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
 
   // Prologue: stage 0 into LDS, stage 1 into the staging registers.
   const int64_t nst = K4 / kStageQ;
+  const int64_t last = nst - 1;
   load_stage(0);
   store_stage(0);
-  if (nst > 1) load_stage(1);
+  load_stage(nst > 1 ? 1 : 0);
   lds_reads_done();
   lds_barrier();
   Ops ox, oy;
   read_ops(ox, a_ptr(0), b_ptr(0), 0);
 
-  // Per stage st: the products of group 0 (ox) run while group 1 is read
-  // into oy; the staged stage st+1 is written to the other buffer (last read
-  // during stage st-1) and the loads of stage st+2 are issued; after the
-  // barrier the products of group 1 run while group 0 of stage st+1 is read
-  // into ox.
-  // D lane 16i + 4b + j of (sub-block, group) holds row 4*sub + i, column
-  // 16*group + 4b + j, i.e. row lane/16 and column lane%16.
+  // Per stage st: group 0's products (ox) run while group 1 is read into oy
+  // and stage st+1 (staged in registers) is written to the other buffer,
+  // whose last reads ended before the previous barrier; after the barrier
+  // group 1's products (oy) run while group 0 of stage st+1 is read into ox
+  // and stage st+2 is loaded.  The last iteration writes, reads and loads
+  // in-bounds copies that are not used.
   int32_t inblk = 0, blk = 0;
   auto block_done = [&]() {
     const int32_t* ea = nullptr;
     const int32_t* fb = nullptr;
     if constexpr (kPanel) {
-      // this block's exponents (padding rows and columns hold zero); the lane
-      // index is re-read here so that no address stays live across the loop
       int l = threadIdx.x & 63;
       asm volatile("" : "+v"(l));
       ea = aexp + blk * astride + rb0 * 16 + (l >> 4);
@@ -308,22 +331,19 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
     ++blk;
   };
   for (int64_t st = 0; st < nst; ++st) {
-    const int64_t last = nst - 1;
     read_ops(oy, a_ptr(st), b_ptr(st), 1);
     derive_b(ox);
+    store_stage(st + 1);
     ten_products(bins, ox);
-    interleave_reads();
+    interleave_reads_writes();
     if (++inblk == kcq) { inblk = 0; block_done(); }
     derive_b(oy);
-    if (st < last) {
-      store_stage(st + 1);
-      if (st + 2 <= last) load_stage(st + 2);
-      lds_reads_done();
-      lds_barrier();
-      read_ops(ox, a_ptr(st + 1), b_ptr(st + 1), 0);
-    }
+    lds_reads_done();
+    lds_barrier();
+    read_ops(ox, a_ptr(st + 1), b_ptr(st + 1), 0);
+    load_stage(st + 2 <= last ? st + 2 : last);
     ten_products(bins, oy);
-    interleave_reads();
+    interleave_reads_loads();
     if (++inblk == kcq) { inblk = 0; block_done(); }
   }
   if (inblk != 0) block_done();

@@ -82,12 +82,13 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
   L.tile_m = tile_m; L.tile_n = tile_n;
   L.mpad = round_up(m > 0 ? m : 1, tile_m);
   L.npad = round_up(n > 0 ? n : 1, tile_n);
-  L.kpad = round_up(k > 0 ? k : 1, 8);
+  L.kpad = round_up(k > 0 ? k : 1, 16);   // whole LDS stages of 16 inner indices
   L.K4 = L.kpad / 4;
   int64_t kce = k < kc ? k : kc;
   if (kce < 1) kce = 1;
   L.kc = (int32_t)kce;
-  L.kcq = (int32_t)((kce + 3) / 4);
+  // one block when k <= kc, padding included (no block of padding alone)
+  L.kcq = (int32_t)(k <= kc ? L.K4 : (kce + 3) / 4);
   split_widths(kce, L.c);
   // panels are the runs of 4 kcq inner indices the product kernel combines
   L.npanel = panels ? (int32_t)((L.K4 + L.kcq - 1) / L.kcq) : 1;

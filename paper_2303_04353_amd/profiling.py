@@ -24,7 +24,7 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-PRODUCT_KERNEL = "cascade_kernel"
+PRODUCT_KERNEL = "cascade_kernel<false, false>"   # the headline form: no flags, global Sigma and T
 PRODUCT_SOURCE = os.path.join(HERE, "csrc", "cascade.hip")
 
 
