@@ -172,9 +172,9 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
       d.off_amax = eoff * 8; eoff += d.mpad;
       d.off_bmax = eoff * 8; eoff += d.npad;
       d.off_apack = (int64_t)off;
-      off += (size_t)ddk::round_up((int64_t)(sizeof(double) * ddk::kFragA * d.mpad * L.kpad), 256);
+      off += (size_t)ddk::round_up((int64_t)(sizeof(double) * (d.mpad / 16) * ddk::a_block_stride(L.K4)), 256);
       d.off_bpack = (int64_t)off;
-      off += (size_t)ddk::round_up((int64_t)(sizeof(double) * ddk::kFragB * d.npad * L.kpad), 256);
+      off += (size_t)ddk::round_up((int64_t)(sizeof(double) * (d.npad / 16) * ddk::b_block_stride(L.K4)), 256);
     }
     pexpA[p + 1] = pexpA[p] + (active ? cdiv(d.m, 256) * cdiv(d.k, 256) : 0);
     pexpB[p + 1] = pexpB[p] + (active ? cdiv(d.n, 4) * cdiv(d.k, 4096) : 0);

@@ -265,11 +265,11 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
     const int d = c < npiece ? wave + c * kWaves : wave;   // unused slots repeat piece 0
     if (d < kPieceA) {
       const int blk = d >> 2, i = d & 3;
-      psrc[c] = Apack + ((tm * 4 + blk) * K4) * (kFragA * kLanes) + i * 128 + lane * 2;
+      psrc[c] = Apack + (tm * 4 + blk) * a_block_stride(K4) + i * 128 + lane * 2;
       pdst[c] = blk * (kStageQ * kFragA * kLanes) + i * 128 + lane * 2;
     } else {
       const int e = d - kPieceA, blk = e / 5, i = e % 5;
-      psrc[c] = Bpack + ((tn * 4 + blk) * K4) * (kFragB * kLanes) + i * 128 + lane * 2;
+      psrc[c] = Bpack + (tn * 4 + blk) * b_block_stride(K4) + i * 128 + lane * 2;
       pdst[c] = kAStage + blk * (kStageQ * kFragB * kLanes) + i * 128 + lane * 2;
     }
   }

@@ -31,6 +31,15 @@ constexpr int kFragB = 5;   // stored planes of op(B): B0', B1', B2', B3', B6'
 constexpr int kPlanesB = 7; // planes of op(B) in the products (with B4', B5')
 constexpr int kLanes = 64;
 
+// The packed planes of one 16-row block of op(A) (16-column block of op(B))
+// are contiguous over k; consecutive blocks are KPAD doubles further apart
+// than their size.  Without it the block stride is a multiple of 1 MiB for
+// k a multiple of 2048, so the pieces a workgroup loads from its four
+// blocks, and those of neighbouring tiles, fall on the same L2 sets.
+constexpr int64_t kBlockPad = 544;   // 4 KiB + 256 B
+constexpr int64_t a_block_stride(int64_t K4) { return K4 * kFragA * kLanes + kBlockPad; }
+constexpr int64_t b_block_stride(int64_t K4) { return K4 * kFragB * kLanes + kBlockPad; }
+
 struct CascadeLayout {
   int64_t m, n, k;
   int64_t mpad, npad, kpad, K4;  // padded sizes, K4 = kpad / 4
@@ -96,8 +105,8 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
   auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up((int64_t)(off + bytes), 256); return o; };
   L.off_amax = take(sizeof(uint64_t) * (size_t)L.mpad * (size_t)L.npanel);
   L.off_bmax = take(sizeof(uint64_t) * (size_t)L.npad * (size_t)L.npanel);
-  L.off_apack = take(sizeof(double) * (size_t)kFragA * (size_t)L.mpad * (size_t)L.kpad);
-  L.off_bpack = take(sizeof(double) * (size_t)kFragB * (size_t)L.npad * (size_t)L.kpad);
+  L.off_apack = take(sizeof(double) * (size_t)(L.mpad / 16) * (size_t)a_block_stride(L.K4));
+  L.off_bpack = take(sizeof(double) * (size_t)(L.npad / 16) * (size_t)b_block_stride(L.K4));
   if (L.npanel > 1) {
     L.off_aexp = take(sizeof(int32_t) * (size_t)L.mpad * (size_t)L.npanel);
     L.off_bexp = take(sizeof(int32_t) * (size_t)L.npad * (size_t)L.npanel);

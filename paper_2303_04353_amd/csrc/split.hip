@@ -116,7 +116,7 @@ __device__ __forceinline__ void pack_a_frag(const double* __restrict__ Ahi, cons
     double xh, xl;
     split_entry(Ahi[idx], Alo[idx], exp_of_bits(amax[i + (p / plen) * pstride]), spar, w, xh, xl);
   }
-  double* dst = Apack + frag * (kFragA * kLanes) + lane;
+  double* dst = Apack + rb * a_block_stride(K4) + kq * (kFragA * kLanes) + lane;
 #pragma unroll
   for (int t = 0; t < 4; ++t) dst[t * kLanes] = w[t];
 }
@@ -137,7 +137,7 @@ __device__ __forceinline__ void pack_b_frag(const double* __restrict__ Bhi, cons
     split_entry(Bhi[idx], Blo[idx], exp_of_bits(bmax[j + (p / plen) * pstride]), spar, w, yh, yl);
     w[4] = yh + yl;       // B6: the scaled entry itself, rounded once
   }
-  double* dst = Bpack + frag * (kFragB * kLanes) + lane;
+  double* dst = Bpack + cb * b_block_stride(K4) + kq * (kFragB * kLanes) + lane;
 #pragma unroll
   for (int t = 0; t < 5; ++t) dst[t * kLanes] = w[t];
 }
@@ -265,11 +265,11 @@ unpack_planes(const double* __restrict__ pack, int side, int64_t rows, int64_t c
   if (side == 0) {
     int64_t blk = r / 16, q = cidx / 4, kk = cidx % 4;
     int64_t lanepos = ((r % 16) / 4) * 16 + kk * 4 + (r % 4);
-    const double* src = pack + (blk * K4 + q) * (int64_t)(kFragA * kLanes) + lanepos;
+    const double* src = pack + blk * a_block_stride(K4) + q * (int64_t)(kFragA * kLanes) + lanepos;
     for (int t = 0; t < kFragA; ++t) planes[t * plane + idx] = src[t * kLanes];
   } else {
     int64_t blk = cidx / 16, q = r / 4, kk = r % 4;
-    const double* src = pack + (blk * K4 + q) * (int64_t)(kFragB * kLanes) + kk * 16 + (cidx % 16);
+    const double* src = pack + blk * b_block_stride(K4) + q * (int64_t)(kFragB * kLanes) + kk * 16 + (cidx % 16);
     double b[5];
     for (int t = 0; t < kFragB; ++t) b[t] = src[t * kLanes];
     const double b4 = b[2] + b[3];   // the same additions as the product kernel

@@ -73,7 +73,8 @@ def test_without_a_gpu_valid_calls_fail_cleanly():
 def test_workspace_size_formula():
     ws = dg.dd_gemm_workspace_size(0, 0, 100, 70, 300)
     mpad, npad, kpad = 128, 128, 304
-    need = 8 * (mpad + npad) + 8 * 4 * mpad * kpad + 8 * 5 * npad * kpad
+    # packed planes: per 16-row (16-column) block 4 (5) planes over kpad, plus 544 doubles of padding
+    need = 8 * (mpad + npad) + 8 * (mpad // 16) * (4 * 16 * kpad + 544) + 8 * (npad // 16) * (5 * 16 * kpad + 544)
     assert need <= ws <= need + 4 * 256
     assert dg.dd_gemm_workspace_size(0, 0, 100, 70, 300, {"algo": dg.DD_ALGO_DD_VALU}) == 0
     assert dg.dd_gemm_workspace_size(3, 0, 100, 70, 300) == 0
