@@ -144,10 +144,13 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
 
 /* Bytes of device workspace dd_gemm_ex needs for this problem and options
  * (0 for DD_ALGO_DD_VALU).  Returns 0 as well for invalid arguments.
- * The slices variants need b s (mpad + npad) kpad bytes of packed slices
- * (b = 2 for BF16/FP16, 1 for INT8; mpad, npad rounded up to 64, kpad to 64
- * for BF16/FP16 and to 128 for INT8) plus, for s > 9, 8 mpad npad
- * (ceil(s/3) - 3) bytes of FP64 group sums. */
+ * The cascade needs 32 mpad kpad + 40 npad kpad bytes of packed digit planes
+ * (mpad, npad rounded up to 64, kpad to 16) plus 4352 bytes of padding per
+ * 16 rows and columns.  The slices variants need b s (mpad + npad) kpad
+ * bytes of packed slices (b = 2 for BF16/FP16, 1 for INT8; kpad rounded up
+ * to 64 for BF16/FP16 and to 128 for INT8) plus 4352 bytes per 32 rows and
+ * columns, and, for s > 9, 8 mpad npad (ceil(s/3) - 3) bytes of FP64 group
+ * sums.  Both add the row and column maxima. */
 size_t dd_gemm_workspace_size(dd_op transa, dd_op transb,
                               int64_t m, int64_t n, int64_t k,
                               const dd_gemm_opts* opts);

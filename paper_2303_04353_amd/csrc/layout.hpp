@@ -9,12 +9,12 @@
 //      four planes A0'..A3'; within a plane the 4-row sub-block s, inner
 //      index kk and row i sit at s*16 + kk*4 + i (16 values per 4-row
 //      sub-block, read by all four MFMA blocks at once):
-//        Apack[((rb*K4 + kq)*4 + t)*64 + s*16 + kk*4 + i]
+//        Apack[rb*a_block_stride(K4) + (kq*4 + t)*64 + s*16 + kk*4 + i]
 //   B: for each 16-column block cb, five planes B0', B1', B2', B3', B6' (in
 //      that order), one 64-lane operand each (lane kk*16 + c holds inner index
 //      kk, column c); B4' = B2' + B3' and B5' = B1' + B4' are formed where
 //      they are used, with the same two FP64 additions:
-//        Bpack[((cb*K4 + kq)*5 + t)*64 + kk*16 + c]
+//        Bpack[cb*b_block_stride(K4) + (kq*5 + t)*64 + kk*16 + c]
 // Rows/columns are padded with zeros up to the workgroup tile and the inner
 // dimension up to a multiple of 8 (two groups of 4, one LDS stage of the
 // product kernel), so the product kernel needs no bounds checks in its main
@@ -125,7 +125,8 @@ constexpr int kSliceBF16 = 0, kSliceF16 = 1, kSliceI8 = 2;
 // for INT8) and each slice t, one 64-lane operand of 16 bytes per lane; lane
 // l holds row (column) rb*32 + l%32 and the step's inner indices
 // (l/32)*E .. (l/32)*E + E-1 (E = 8 two-byte or 16 one-byte values):
-//   pack[((rb*Q + q)*S + t)*64 + l]   (in 16-byte units)
+//   pack[rb*slices_block_stride(Q, S) + (q*S + t)*64 + l]   (in 16-byte units,
+// blocks padded like the cascade's planes)
 // Rows/columns are padded with zeros to the 64 x 64 workgroup tile and the
 // inner dimension to whole blocks of four steps (64 or 128 indices).
 struct SlicesLayout {
@@ -166,6 +167,12 @@ inline bool slices_params_ok(int w, int S, int fmt) {
   return 16.0 * S * __builtin_ldexp(1.0, 2 * w - 2) <= __builtin_ldexp(1.0, 24);
 }
 
+// 16-byte units from one 32-row (32-column) block of packed slices to the
+// next: the block plus 4 KiB + 256 B, so blocks loaded together do not share
+// L2 sets.
+constexpr int64_t kSlicePad = 272;
+constexpr int64_t slices_block_stride(int64_t Q, int64_t S) { return Q * S * 64 + kSlicePad; }
+
 inline SlicesLayout make_slices_layout(int64_t m, int64_t n, int64_t k, int S, int w, int fmt) {
   SlicesLayout L{};
   L.m = m; L.n = n; L.k = k;
@@ -184,11 +191,10 @@ inline SlicesLayout make_slices_layout(int64_t m, int64_t n, int64_t k, int S, i
   }
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (size_t)round_up((int64_t)(off + bytes), 256); return o; };
-  const size_t esize = fmt == kSliceI8 ? 1 : 2;
   L.off_amax = take(sizeof(uint64_t) * (size_t)L.mpad);
   L.off_bmax = take(sizeof(uint64_t) * (size_t)L.npad);
-  L.off_apack = take(esize * (size_t)S * (size_t)L.mpad * (size_t)L.kpad);
-  L.off_bpack = take(esize * (size_t)S * (size_t)L.npad * (size_t)L.kpad);
+  L.off_apack = take(16 * (size_t)(L.mpad / 32) * (size_t)slices_block_stride(L.Q, S));
+  L.off_bpack = take(16 * (size_t)(L.npad / 32) * (size_t)slices_block_stride(L.Q, S));
   const int upper_groups = S > kSlicesSplit ? (S + 2) / 3 - kSlicesSplit / 3 : 0;
   L.off_planes = take(sizeof(double) * (size_t)upper_groups * (size_t)L.mpad * (size_t)L.npad);
   L.bytes = off;

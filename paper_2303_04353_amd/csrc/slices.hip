@@ -126,7 +126,7 @@ slices_split(const double* __restrict__ Xhi, const double* __restrict__ Xlo, int
   }
   const int64_t rb = o / 32, q = rg / 2;
   const int lane = (int)(o % 32) + 32 * (int)(rg % 2);
-  u32x4* dst = pack + ((rb * Q + q) * S) * 64 + lane;
+  u32x4* dst = pack + rb * slices_block_stride(Q, S) + (q * S) * 64 + lane;
 #pragma unroll
   for (int t = 0; t < 16; ++t)
     if (t < S) dst[t * 64] = u32x4{words[t][0], words[t][1], words[t][2], words[t][3]};
@@ -230,8 +230,9 @@ __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
   tile_order(blockIdx.x, a.tiles_m, a.tiles_n, tm, tn);
   const int64_t rb = tm * 2 + (wv >> 1), cb = tn * 2 + (wv & 1);
   const int64_t step = (int64_t)a.S * 64;
-  const u32x4* Ap = a.Apack + rb * a.Q * step + lane;   // not restrict: the loads stay where written
-  const u32x4* Bp = a.Bpack + cb * a.Q * step + lane;
+  const int64_t bstride = slices_block_stride(a.Q, a.S);
+  const u32x4* Ap = a.Apack + rb * bstride + lane;   // not restrict: the loads stay where written
+  const u32x4* Bp = a.Bpack + cb * bstride + lane;
 
   Acc acc[NL];
   double grp[NGP][16];
@@ -477,7 +478,7 @@ slices_unpack(const uint8_t* __restrict__ pack, int64_t outer, int64_t red, int6
   const int64_t o = rest % outer, r = rest / outer;
   const int64_t rb = o / 32, q = r / (2 * E);
   const int lane = (int)(o % 32) + 32 * (int)((r % (2 * E)) / E);
-  const int64_t chunk = (((rb * Q + q) * S + t) * 64 + lane) * 16;   // byte offset of the lane's chunk
+  const int64_t chunk = (rb * slices_block_stride(Q, S) + (q * S + t) * 64 + lane) * 16;   // byte offset of the lane's chunk
   uint16_t v;
   if constexpr (FMT == kI8) {
     v = (uint16_t)(int16_t)(int8_t)pack[chunk + (r % E)];

@@ -103,11 +103,12 @@ def test_slices_options_and_workspace():
     mpad, npad, kpad = 128, 128, 320
     # default BF16: 14 slices of 8 bits, plus the upper pass's groups 3 and 4
     ws = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": bf})
-    need = 8 * (mpad + npad) + 2 * 14 * (mpad + npad) * kpad + 8 * 2 * mpad * npad
+    pad = 4352 * (mpad // 32 + npad // 32)   # 4 KiB + 256 B after every 32-row (column) block
+    need = 8 * (mpad + npad) + 2 * 14 * (mpad + npad) * kpad + pad + 8 * 2 * mpad * npad
     assert need <= ws <= need + 6 * 256
     # nine slices or fewer run in one pass: no group planes
     ws9 = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": bf, "slices": 9})
-    need9 = 8 * (mpad + npad) + 2 * 9 * (mpad + npad) * kpad
+    need9 = 8 * (mpad + npad) + 2 * 9 * (mpad + npad) * kpad + pad
     assert need9 <= ws9 <= need9 + 6 * 256
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": f16}) > 0
     for bad in ({"algo": bf, "slice_bits": 10}, {"algo": bf, "slices": 17}, {"algo": f16, "slice_bits": 10},
@@ -118,7 +119,7 @@ def test_slices_options_and_workspace():
     # INT8: 16 slices of 7 bits, one byte each, k padded to 128, groups 3..5 of the upper pass
     i8 = dg.DD_ALGO_SLICES_I8
     ws8 = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": i8})
-    need8 = 8 * (mpad + npad) + 16 * (mpad + npad) * 384 + 8 * 3 * mpad * npad
+    need8 = 8 * (mpad + npad) + 16 * (mpad + npad) * 384 + 4352 * (mpad // 32 + npad // 32) + 8 * 3 * mpad * npad
     assert need8 <= ws8 <= need8 + 6 * 256
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": i8, "slice_bits": 8}) == 0
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": 5}) == 0
