@@ -31,7 +31,9 @@ Steps, in the paper's order and notation:
    rank-kc results are accumulated in FP64x2 (Sec. 4.2, Fig. gemmrankk).
 6. Apply Sigma and T (Sec. 4.2) and add C last.  (Option: Sigma and T per
    rank-kc panel, each panel's result scaled before it is accumulated; the
-   paper packs and splits one kc panel at a time, Sec. 4.3.)
+   paper packs and splits one kc panel at a time, Sec. 4.3.)  (Option: a
+   power-of-two diagonal balancing F applied first, A B = (A F)(F^-1 B),
+   Sec. 6; see ``balance_exponents``.)
 7. Cancellation flags (Sec. 3.7, Sec. 4.4): an entry is flagged when bin 0
    of a rank-kc block is zero while a lower bin of that block is not.
 
@@ -187,7 +189,19 @@ def cancellation_flags(blocks):
     return flag
 
 
-def cascade_gemm(A, B, C=None, *, kc=256, c=None, scaling="global", return_parts=False):
+def balance_exponents(Ahi, Bhi):
+    """Power-of-two diagonal balancing F (Sec. 6, scaling and balancing:
+    A B = (A F)(F^-1 B)).  For inner index p, with e_A(p) the exponent of
+    column p of A and e_B(p) that of row p of B (step 2's exponent rule), the
+    balancing exponent is g_p = floor((e_B(p) - e_A(p)) / 2): A's column is
+    multiplied by 2^g_p and B's row by 2^-g_p, which leaves both near the
+    geometric mean of the two maxima."""
+    eA = exponents(Ahi, axis=0).astype(np.int64)
+    eB = exponents(Bhi, axis=1).astype(np.int64)
+    return (eB - eA) // 2
+
+
+def cascade_gemm(A, B, C=None, *, kc=256, c=None, scaling="global", balance=False, return_parts=False):
     """C + A B by the cascade; A (m×k), B (k×n), C (m×n) as (hi, lo) pairs.
 
     The rank-kc block is ``min(kc, k)`` and the split widths follow from it,
@@ -201,6 +215,13 @@ def cascade_gemm(A, B, C=None, *, kc=256, c=None, scaling="global", return_parts
     """
     if scaling not in ("global", "panel"):
         raise ValueError("scaling must be 'global' or 'panel'")
+    if balance:
+        # ``balance=True`` first multiplies column p of A by 2^g_p and row p of
+        # B by 2^-g_p (``balance_exponents``); the product is unchanged
+        # (exactly, barring underflow), the split sees balanced operands
+        g = balance_exponents(np.asarray(A[0], dtype=np.float64), np.asarray(B[0], dtype=np.float64))
+        A = tuple(np.ldexp(np.asarray(x, dtype=np.float64), g[None, :]) for x in A)
+        B = tuple(np.ldexp(np.asarray(x, dtype=np.float64), -g[:, None]) for x in B)
     Ahi, Alo = (np.asarray(x, dtype=np.float64) for x in A)
     Bhi, Blo = (np.asarray(x, dtype=np.float64) for x in B)
     m, k = Ahi.shape

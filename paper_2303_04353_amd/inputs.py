@@ -25,6 +25,10 @@ Workload recipes (Sec. 5.2, "uniformly random data" and "wide-range data"):
   uniform integers in ``[-40, 40]`` drawn independently per (row, panel)
   and (panel, column); C is scaled by ``2**max_b(e_ib + f_bj)``.  One
   exponent per whole row or column then fits only the largest panel.
+* ``skewed``: as ``uniform``, but column p of A is multiplied by ``2**s_p``
+  and row p of B by ``2**-s_p``, s_p a uniform integer in ``[-40, 40]``
+  per inner index: every product keeps its ``uniform`` size while the row
+  and column maxima are set by the most skewed index.
 
 All arrays are float64 in Fortran (column-major) order, matching the BLAS
 layout of the C ABI.
@@ -34,7 +38,7 @@ from __future__ import annotations
 import numpy as np
 
 SEED_ROOT = 230304353
-VARIANTS = {"uniform": 0, "scaled": 1, "wide": 2, "panels": 3}
+VARIANTS = {"uniform": 0, "scaled": 1, "wide": 2, "panels": 3, "skewed": 4}
 
 
 def _rng(cfg: int, variant: str, m: int, n: int, k: int, salt: int = 0):
@@ -68,6 +72,10 @@ def make_problem(m: int, n: int, k: int, *, cfg: int = 0, variant: str = "unifor
         Ahi *= np.ldexp(1.0, eA)[:, None]
         Bhi *= np.ldexp(1.0, fB)[None, :]
         Chi *= np.ldexp(1.0, eA[:, None] + fB[None, :])
+    elif variant == "skewed":
+        sp = rng.integers(-40, 41, size=k)
+        Ahi *= np.ldexp(1.0, sp)[None, :]
+        Bhi *= np.ldexp(1.0, -sp)[:, None]
     elif variant == "panels":
         nb = max(1, -(-k // panel))
         eA = rng.integers(-40, 41, size=(m, nb))

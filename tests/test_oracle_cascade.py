@@ -422,3 +422,76 @@ def test_panel_scaling_ragged_last_panel_and_zero_panels():
     rh, rl, _ = dd_gemm_ref(A, P["B"], P["C"])
     AB = np.abs(A[0]) @ np.abs(P["B"][0])
     assert np.all(np.abs((hi - rh) + (lo - rl)) <= 64 * k * 2.0 ** -104 * AB)
+
+
+# --- power-of-two diagonal balancing F (balance=True) ------------------------------
+
+def test_balancing_is_the_identity_on_balanced_operands():
+    # column maxima of A and row maxima of B in the same binade: F = I
+    P = make_problem(12, 9, 70, cfg=91)
+    A = [x.copy() for x in P["A"]]
+    B = [x.copy() for x in P["B"]]
+    A[0][0, :], A[1][0, :] = 0.75, 0.0
+    B[0][:, 0], B[1][:, 0] = -0.75, 0.0
+    assert np.all(cz.balance_exponents(A[0], B[0]) == 0)
+    a = cz.cascade_gemm(A, B, P["C"], kc=32)
+    b = cz.cascade_gemm(A, B, P["C"], kc=32, balance=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_balancing_evens_out_columns_of_A_and_rows_of_B():
+    P = make_problem(20, 15, 60, cfg=92, variant="skewed")
+    g = cz.balance_exponents(P["A"][0], P["B"][0])
+    A2 = np.ldexp(P["A"][0], g[None, :])
+    B2 = np.ldexp(P["B"][0], -g[:, None])
+    eA = cz.exponents(A2, axis=0)
+    eB = cz.exponents(B2, axis=1)
+    assert np.all(np.abs(eA - eB) <= 1)
+    # the skew of the inputs is large before
+    assert np.max(np.abs(cz.exponents(P["A"][0], axis=0) - cz.exponents(P["B"][0], axis=1))) > 40
+
+
+@pytest.mark.parametrize("scaling", ["global", "panel"])
+def test_balanced_cascade_is_invariant_to_power_of_two_diagonal_scaling(scaling):
+    # (A F0, F0^-1 B) balances to the same operands as (A, B), bit for bit
+    m, n, k, kc = 10, 8, 90, 32
+    P = make_problem(m, n, k, cfg=93, variant="skewed")
+    f0 = (np.arange(k) * 37 % 61) - 30
+    Af = tuple(np.ldexp(x, f0[None, :]) for x in P["A"])
+    Bf = tuple(np.ldexp(x, -f0[:, None]) for x in P["B"])
+    a = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc, scaling=scaling, balance=True)
+    b = cz.cascade_gemm(Af, Bf, P["C"], kc=kc, scaling=scaling, balance=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    u = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc, scaling=scaling)
+    v = cz.cascade_gemm(Af, Bf, P["C"], kc=kc, scaling=scaling)
+    assert not (np.array_equal(u[0], v[0]) and np.array_equal(u[1], v[1]))
+
+
+def test_balancing_meets_the_tolerance_on_skewed_operands():
+    # rows of A and columns of B take their scale from the most skewed inner
+    # index, so without balancing most products have FP64 digits only
+    m, n, k = 6, 5, 40
+    P = make_problem(m, n, k, cfg=94, variant="skewed")
+    X = exact_gemm(P["A"], P["B"], P["C"])
+    S = abs_gemm(P["A"], P["B"]) + np.abs(dd_value(*P["C"]))
+    tol = 64 * k * Fraction(2) ** -104 * S
+    Gb = dd_value(*cz.cascade_gemm(P["A"], P["B"], P["C"], kc=16, balance=True))
+    Gu = dd_value(*cz.cascade_gemm(P["A"], P["B"], P["C"], kc=16))
+    assert all(abs(Gb[idx] - X[idx]) <= tol[idx] for idx in np.ndindex(m, n))
+    assert sum(abs(Gu[idx] - X[idx]) > tol[idx] for idx in np.ndindex(m, n)) > m * n // 2
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+def test_balancing_with_zero_and_non_finite_slices():
+    m, n, k = 7, 6, 30
+    P = make_problem(m, n, k, cfg=95, variant="skewed")
+    A = [x.copy() for x in P["A"]]
+    A[0][:, 3] = 0.0
+    A[1][:, 3] = 0.0
+    hi, lo = cz.cascade_gemm(A, P["B"], P["C"], kc=16, balance=True)
+    rh, rl, _ = dd_gemm_ref(A, P["B"], P["C"])
+    AB = np.abs(A[0]) @ np.abs(P["B"][0]) + np.abs(P["C"][0])
+    assert np.all(np.abs((hi - rh) + (lo - rl)) <= 64 * k * 2.0 ** -104 * AB)
+    A[0][2, 5] = np.inf
+    hi, lo = cz.cascade_gemm(A, P["B"], P["C"], kc=16, balance=True)
+    assert np.all(np.isnan(hi[2, :])) and np.all(np.isfinite(np.delete(hi, 2, axis=0)))
