@@ -96,8 +96,19 @@ typedef enum {
    * accumulated.  The same result as DD_SCALING_GLOBAL when k <= kc; keeps
    * FP64x2 accuracy relative to |A||B| when the scale of a row or column
    * changes from panel to panel (the paper splits one kc panel at a time,
-   * Sec. 4.3).  Workspace: 8 (mpad + npad) bytes per extra panel. */
-  DD_SCALING_PANEL = 1
+   * Sec. 4.3).  Workspace: 12 (mpad + npad) bytes per panel. */
+  DD_SCALING_PANEL = 1,
+  /* Flag, may be OR-ed with either of the above: a power-of-two diagonal
+   * balancing F of the inner dimension first (Sec. 6, scaling and
+   * balancing: A B = (A F)(F^-1 B)).  Column p of op(A) is multiplied by
+   * 2^g_p and row p of op(B) by 2^-g_p, g_p = floor((e_B(p) - e_A(p)) / 2)
+   * with e_A(p), e_B(p) the exponents (as for Sigma and T) of the column's
+   * and the row's largest |hi|.  The product is unchanged (exactly, barring
+   * underflow); the split then sees operands whose scale does not hinge on
+   * a few skewed inner indices.  The result does not change when A and B
+   * are given as A F0, F0^-1 B for any power-of-two diagonal F0.
+   * Workspace: 20 kpad bytes more. */
+  DD_SCALING_BALANCE = 2
 } dd_scaling;
 
 /* Options of dd_gemm_ex / dd_gemm_batched.  A NULL pointer means all zero. */
@@ -116,8 +127,9 @@ typedef struct {
                           every level is flushed every 4 steps (the fast
                           schedule); wider slices flush every step.  Both must
                           be 0 for the other algorithms.                         */
-  int32_t scaling;     /* cascade: dd_scaling; must be 0 for the other algorithms
-                          and for the batched calls.                            */
+  int32_t scaling;     /* cascade: DD_SCALING_GLOBAL or DD_SCALING_PANEL, OR-ed
+                          with DD_SCALING_BALANCE or not; must be 0 for the
+                          other algorithms and for the batched calls.           */
   uint32_t* flags_out; /* cascade only, may be NULL: device bitmap of ceil(m n / 32)
                           words, bit (i + j m) for entry (i, j) of C.  The call
                           zeroes it, then sets the bit of every entry at risk of

@@ -14,11 +14,16 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 // Largest |X| (|fl(X + Xlo)| if Xlo is given) per outer index, as bits.
 hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int64_t so, int64_t sr,
                                uint64_t* out, hipStream_t s, const double* Xlo = nullptr,
-                               int64_t plen = 0, int64_t ostride = 0);
+                               int64_t plen = 0, int64_t ostride = 0, const int32_t* rscale = nullptr,
+                               int rsign = 1);
+hipError_t launch_balance_exps(const uint64_t* acol, const uint64_t* brow, int64_t k, int64_t kpad,
+                               int32_t* g, hipStream_t s);
 hipError_t launch_pack_a(const double* Ahi, const double* Alo, int64_t si, int64_t sp,
-                         const CascadeLayout& L, const uint64_t* amax, double* Apack, hipStream_t s);
+                         const CascadeLayout& L, const uint64_t* amax, double* Apack, hipStream_t s,
+                         const int32_t* gexp = nullptr);
 hipError_t launch_pack_b(const double* Bhi, const double* Blo, int64_t sp, int64_t sj,
-                         const CascadeLayout& L, const uint64_t* bmax, double* Bpack, hipStream_t s);
+                         const CascadeLayout& L, const uint64_t* bmax, double* Bpack, hipStream_t s,
+                         const int32_t* gexp = nullptr);
 hipError_t launch_unpack(const double* pack, int side, int64_t rows, int64_t cols, int64_t K4,
                          double* planes, hipStream_t s);
 hipError_t launch_exps(const uint64_t* bits, int64_t n, int32_t* e, hipStream_t s);

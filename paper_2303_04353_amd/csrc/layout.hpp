@@ -50,6 +50,9 @@ struct CascadeLayout {
   int32_t npanel;                // exponent sets: 1, or one per rank-kc panel
   size_t off_amax, off_bmax, off_apack, off_bpack, bytes;
   size_t off_aexp, off_bexp;     // per-panel exponents as int32 (npanel > 1 only)
+  bool balance;                  // diagonal balancing of the inner dimension
+  size_t off_acol, off_brow;     // balance: column maxima of op(A), row maxima of op(B)
+  size_t off_gexp;               // balance: int32 exponent g[p] per inner index
 };
 
 inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
@@ -85,7 +88,8 @@ inline void split_widths(int64_t kc, int32_t c[3]) {
 // sets of mpad words (set b at b * mpad), the column maxima of op(B) as
 // npanel sets of npad words.
 inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
-                                 int64_t tile_m, int64_t tile_n, bool panels = false) {
+                                 int64_t tile_m, int64_t tile_n, bool panels = false,
+                                 bool balance = false) {
   CascadeLayout L{};
   L.m = m; L.n = n; L.k = k;
   L.tile_m = tile_m; L.tile_n = tile_n;
@@ -110,6 +114,12 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
   if (L.npanel > 1) {
     L.off_aexp = take(sizeof(int32_t) * (size_t)L.mpad * (size_t)L.npanel);
     L.off_bexp = take(sizeof(int32_t) * (size_t)L.npad * (size_t)L.npanel);
+  }
+  L.balance = balance;
+  if (balance) {
+    L.off_acol = take(sizeof(uint64_t) * (size_t)L.kpad);
+    L.off_brow = take(sizeof(uint64_t) * (size_t)L.kpad);
+    L.off_gexp = take(sizeof(int32_t) * (size_t)L.kpad);
   }
   L.bytes = off;
   return L;

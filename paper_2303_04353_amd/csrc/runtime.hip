@@ -164,13 +164,26 @@ dd_status run_split(const Problem& p, const CascadeLayout& L, char* ws, hipStrea
   uint64_t* bmax = (uint64_t*)(ws + L.off_bmax);
   DD_TRY(ddk::launch_fill_u64(amax, L.mpad * L.npanel, 0, s));
   DD_TRY(ddk::launch_fill_u64(bmax, L.npad * L.npanel, 0, s));
+  // diagonal balancing: column maxima of op(A) and row maxima of op(B) give
+  // g[p]; every entry is then seen as A(i, p) 2^g[p], B(p, j) 2^-g[p]
+  const int32_t* gexp = nullptr;
+  if (L.balance) {
+    uint64_t* acol = (uint64_t*)(ws + L.off_acol);
+    uint64_t* brow = (uint64_t*)(ws + L.off_brow);
+    DD_TRY(ddk::launch_fill_u64(acol, L.kpad, 0, s));
+    DD_TRY(ddk::launch_fill_u64(brow, L.kpad, 0, s));
+    DD_TRY(ddk::launch_max_abs_bits(p.Ahi, p.k, p.m, a_sp, a_si, acol, s));
+    DD_TRY(ddk::launch_max_abs_bits(p.Bhi, p.k, p.n, b_sp, b_sj, brow, s));
+    DD_TRY(ddk::launch_balance_exps(acol, brow, p.k, L.kpad, (int32_t*)(ws + L.off_gexp), s));
+    gexp = (const int32_t*)(ws + L.off_gexp);
+  }
   // rows of op(A): outer i, reduced p;  columns of op(B): outer j, reduced p;
   // with per-panel Sigma and T one maximum per run of 4 kcq inner indices
   const int64_t plen = L.npanel > 1 ? 4 * (int64_t)L.kcq : 0;
-  DD_TRY(ddk::launch_max_abs_bits(p.Ahi, p.m, p.k, a_si, a_sp, amax, s, nullptr, plen, L.mpad));
-  DD_TRY(ddk::launch_max_abs_bits(p.Bhi, p.n, p.k, b_sj, b_sp, bmax, s, nullptr, plen, L.npad));
-  DD_TRY(ddk::launch_pack_a(p.Ahi, p.Alo, a_si, a_sp, L, amax, (double*)(ws + L.off_apack), s));
-  DD_TRY(ddk::launch_pack_b(p.Bhi, p.Blo, b_sp, b_sj, L, bmax, (double*)(ws + L.off_bpack), s));
+  DD_TRY(ddk::launch_max_abs_bits(p.Ahi, p.m, p.k, a_si, a_sp, amax, s, nullptr, plen, L.mpad, gexp, 1));
+  DD_TRY(ddk::launch_max_abs_bits(p.Bhi, p.n, p.k, b_sj, b_sp, bmax, s, nullptr, plen, L.npad, gexp, -1));
+  DD_TRY(ddk::launch_pack_a(p.Ahi, p.Alo, a_si, a_sp, L, amax, (double*)(ws + L.off_apack), s, gexp));
+  DD_TRY(ddk::launch_pack_b(p.Bhi, p.Blo, b_sp, b_sj, L, bmax, (double*)(ws + L.off_bpack), s, gexp));
   if (L.npanel > 1) {
     DD_TRY(ddk::launch_exps(amax, L.mpad * L.npanel, (int32_t*)(ws + L.off_aexp), s));
     DD_TRY(ddk::launch_exps(bmax, L.npad * L.npanel, (int32_t*)(ws + L.off_bexp), s));
@@ -185,6 +198,7 @@ struct Opts {
   int32_t S = 0, w = 0;   // slices variants
   uint32_t* flags = nullptr;   // cascade: cancellation bitmap (may be null)
   bool panels = false;         // cascade: Sigma and T per rank-kc panel
+  bool balance = false;        // cascade: diagonal balancing of the inner dimension
   bool slices() const {
     return algo == DD_ALGO_SLICES_BF16 || algo == DD_ALGO_SLICES_F16 || algo == DD_ALGO_SLICES_I8;
   }
@@ -267,7 +281,7 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
     }
     return st;
   }
-  const CascadeLayout L = ddk::make_layout(p.m, p.n, p.k, kc, kTileM, kTileN, o.panels);
+  const CascadeLayout L = ddk::make_layout(p.m, p.n, p.k, kc, kTileM, kTileN, o.panels, o.balance);
   char* ws = (char*)workspace;
   if (internal_ws) {
     void* w = nullptr;
@@ -318,12 +332,13 @@ static bool read_opts(const dd_gemm_opts* o, Opts* out) {
   if (!o) return true;
   if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_SLICES_I8) return false;
   if (o->tile != 0) return false;
-  if (o->scaling != DD_SCALING_GLOBAL && o->scaling != DD_SCALING_PANEL) return false;
+  if (o->scaling < 0 || o->scaling > (DD_SCALING_PANEL | DD_SCALING_BALANCE)) return false;
   out->algo = o->algo;
   if (o->flags_out && o->algo != DD_ALGO_CASCADE_F64) return false;
   if (o->scaling != DD_SCALING_GLOBAL && o->algo != DD_ALGO_CASCADE_F64) return false;
   out->flags = o->flags_out;
-  out->panels = o->scaling == DD_SCALING_PANEL;
+  out->panels = (o->scaling & DD_SCALING_PANEL) != 0;
+  out->balance = (o->scaling & DD_SCALING_BALANCE) != 0;
   if (out->slices()) {
     if (o->kc != 0) return false;
     return slice_params(out->fmt(), o->slices, o->slice_bits, &out->S, &out->w);
@@ -341,7 +356,7 @@ size_t dd_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, 
   if ((transa != DD_OP_N && transa != DD_OP_T) || (transb != DD_OP_N && transb != DD_OP_T)) return 0;
   if (m <= 0 || n <= 0 || k <= 0 || o.algo == DD_ALGO_DD_VALU) return 0;
   if (o.slices()) return ddk::make_slices_layout(m, n, k, o.S, o.w, o.fmt()).bytes;
-  return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN, o.panels).bytes;
+  return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN, o.panels, o.balance).bytes;
 }
 
 dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,

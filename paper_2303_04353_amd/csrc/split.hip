@@ -28,6 +28,8 @@ __global__ void fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
+// With rscale, element (o, r) is first multiplied by 2^(rsign * rscale[r])
+// (the diagonal balancing of the inner dimension).
 // The reduced range is cut into chunks of `chunk` indices; chunk c (taken by
 // blocks y = c, c + gridDim.y, ...) goes to out[o + c * ostride]: ostride = 0
 // folds every chunk into one maximum, ostride > 0 keeps one per chunk (the
@@ -37,7 +39,7 @@ __global__ void fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 __global__ void __launch_bounds__(256)
 max_abs_bits_outer_contig(const double* __restrict__ X, const double* __restrict__ Xlo, int64_t outer,
                           int64_t red, int64_t ld, int64_t chunk, int64_t ostride,
-                          uint64_t* __restrict__ out) {
+                          uint64_t* __restrict__ out, const int32_t* __restrict__ rscale, int rsign) {
   int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (o >= outer) return;
   const int64_t nchunk = (red + chunk - 1) / chunk;
@@ -46,7 +48,8 @@ max_abs_bits_outer_contig(const double* __restrict__ X, const double* __restrict
     int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
     uint64_t mx = 0;
     for (int64_t r = r0; r < r1; ++r) {
-      const double v = Xlo ? X[o + r * ld] + Xlo[o + r * ld] : X[o + r * ld];
+      double v = Xlo ? X[o + r * ld] + Xlo[o + r * ld] : X[o + r * ld];
+      if (rscale) v = __builtin_ldexp(v, rsign * rscale[r]);
       uint64_t b = __builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull;
       mx = b > mx ? b : mx;
     }
@@ -58,7 +61,7 @@ max_abs_bits_outer_contig(const double* __restrict__ X, const double* __restrict
 __global__ void __launch_bounds__(256)
 max_abs_bits_red_contig(const double* __restrict__ X, const double* __restrict__ Xlo, int64_t outer,
                         int64_t red, int64_t ld, int64_t chunk, int64_t ostride,
-                        uint64_t* __restrict__ out) {
+                        uint64_t* __restrict__ out, const int32_t* __restrict__ rscale, int rsign) {
   int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (o >= outer) return;
@@ -70,7 +73,8 @@ max_abs_bits_red_contig(const double* __restrict__ X, const double* __restrict__
     int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
     uint64_t mx = 0;
     for (int64_t r = r0 + lane; r < r1; r += 64) {
-      const double v = col_lo ? col[r] + col_lo[r] : col[r];
+      double v = col_lo ? col[r] + col_lo[r] : col[r];
+      if (rscale) v = __builtin_ldexp(v, rsign * rscale[r]);
       uint64_t b = __builtin_bit_cast(uint64_t, v) & 0x7fffffffffffffffull;
       mx = b > mx ? b : mx;
     }
@@ -100,12 +104,15 @@ __device__ __forceinline__ SplitParams make_params(int c0, int c1, int c2) {
 
 // One 64-lane fragment of the packed A planes: op(A)(i, p) = A[i*si + p*sp_].
 // The exponent of entry (i, p) is amax[i] (pstride = 0), or with per-panel
-// Sigma amax[i + (p / plen) * pstride]; likewise for B.
+// Sigma amax[i + (p / plen) * pstride]; likewise for B.  With gexp, the
+// entry is first multiplied by 2^gexp[p] (A) or 2^-gexp[p] (B): the
+// diagonal balancing of the inner dimension.
 __device__ __forceinline__ void pack_a_frag(const double* __restrict__ Ahi, const double* __restrict__ Alo,
                                             int64_t si, int64_t sp_, int64_t m, int64_t k, int64_t K4,
                                             int64_t frag, int lane, const uint64_t* __restrict__ amax,
                                             int c0, int c1, int c2, double* __restrict__ Apack,
-                                            int64_t plen = 1, int64_t pstride = 0) {
+                                            int64_t plen = 1, int64_t pstride = 0,
+                                            const int32_t* __restrict__ gexp = nullptr) {
   int64_t rb = frag / K4, kq = frag - rb * K4;
   // position lane = s*16 + kk*4 + ii holds row rb*16 + s*4 + ii, inner index kq*4 + kk
   int64_t i = rb * 16 + (lane >> 4) * 4 + (lane & 3), p = kq * 4 + ((lane >> 2) & 3);
@@ -114,7 +121,9 @@ __device__ __forceinline__ void pack_a_frag(const double* __restrict__ Ahi, cons
     SplitParams spar = make_params(c0, c1, c2);
     int64_t idx = i * si + p * sp_;
     double xh, xl;
-    split_entry(Ahi[idx], Alo[idx], exp_of_bits(amax[i + (p / plen) * pstride]), spar, w, xh, xl);
+    double h = Ahi[idx], l = Alo[idx];
+    if (gexp) { h = __builtin_ldexp(h, gexp[p]); l = __builtin_ldexp(l, gexp[p]); }
+    split_entry(h, l, exp_of_bits(amax[i + (p / plen) * pstride]), spar, w, xh, xl);
   }
   double* dst = Apack + rb * a_block_stride(K4) + kq * (kFragA * kLanes) + lane;
 #pragma unroll
@@ -126,7 +135,8 @@ __device__ __forceinline__ void pack_b_frag(const double* __restrict__ Bhi, cons
                                             int64_t sp_, int64_t sj, int64_t k, int64_t n, int64_t K4,
                                             int64_t frag, int lane, const uint64_t* __restrict__ bmax,
                                             int c0, int c1, int c2, double* __restrict__ Bpack,
-                                            int64_t plen = 1, int64_t pstride = 0) {
+                                            int64_t plen = 1, int64_t pstride = 0,
+                                            const int32_t* __restrict__ gexp = nullptr) {
   int64_t cb = frag / K4, kq = frag - cb * K4;
   int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
   double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -134,7 +144,9 @@ __device__ __forceinline__ void pack_b_frag(const double* __restrict__ Bhi, cons
     SplitParams spar = make_params(c0, c1, c2);
     int64_t idx = p * sp_ + j * sj;
     double yh, yl;
-    split_entry(Bhi[idx], Blo[idx], exp_of_bits(bmax[j + (p / plen) * pstride]), spar, w, yh, yl);
+    double h = Bhi[idx], l = Blo[idx];
+    if (gexp) { h = __builtin_ldexp(h, -gexp[p]); l = __builtin_ldexp(l, -gexp[p]); }
+    split_entry(h, l, exp_of_bits(bmax[j + (p / plen) * pstride]), spar, w, yh, yl);
     w[4] = yh + yl;       // B6: the scaled entry itself, rounded once
   }
   double* dst = Bpack + cb * b_block_stride(K4) + kq * (kFragB * kLanes) + lane;
@@ -146,20 +158,24 @@ __device__ __forceinline__ void pack_b_frag(const double* __restrict__ Bhi, cons
 __global__ void __launch_bounds__(256)
 pack_a(const double* __restrict__ Ahi, const double* __restrict__ Alo, int64_t si, int64_t sp_,
        int64_t m, int64_t k, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ amax,
-       int c0, int c1, int c2, double* __restrict__ Apack, int64_t plen, int64_t pstride) {
+       int c0, int c1, int c2, double* __restrict__ Apack, int64_t plen, int64_t pstride,
+       const int32_t* __restrict__ gexp) {
   int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (frag >= nfrag) return;
-  pack_a_frag(Ahi, Alo, si, sp_, m, k, K4, frag, threadIdx.x & 63, amax, c0, c1, c2, Apack, plen, pstride);
+  pack_a_frag(Ahi, Alo, si, sp_, m, k, K4, frag, threadIdx.x & 63, amax, c0, c1, c2, Apack, plen, pstride,
+              gexp);
 }
 
 // One wave per fragment (cb, kq).
 __global__ void __launch_bounds__(256)
 pack_b(const double* __restrict__ Bhi, const double* __restrict__ Blo, int64_t sp_, int64_t sj,
        int64_t k, int64_t n, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ bmax,
-       int c0, int c1, int c2, double* __restrict__ Bpack, int64_t plen, int64_t pstride) {
+       int c0, int c1, int c2, double* __restrict__ Bpack, int64_t plen, int64_t pstride,
+       const int32_t* __restrict__ gexp) {
   int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (frag >= nfrag) return;
-  pack_b_frag(Bhi, Blo, sp_, sj, k, n, K4, frag, threadIdx.x & 63, bmax, c0, c1, c2, Bpack, plen, pstride);
+  pack_b_frag(Bhi, Blo, sp_, sj, k, n, K4, frag, threadIdx.x & 63, bmax, c0, c1, c2, Bpack, plen, pstride,
+              gexp);
 }
 
 // ------------------------------------------------------------ batched phase one
@@ -284,6 +300,15 @@ unpack_planes(const double* __restrict__ pack, int side, int64_t rows, int64_t c
   }
 }
 
+// Diagonal balancing: g[p] = floor((e_B(p) - e_A(p)) / 2) from the column
+// maxima of op(A) and row maxima of op(B); 0 beyond k.
+__global__ void balance_exps(const uint64_t* __restrict__ acol, const uint64_t* __restrict__ brow,
+                             int64_t k, int64_t kpad, int32_t* __restrict__ g) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= kpad) return;
+  g[p] = p < k ? (exp_of_bits(brow[p]) - exp_of_bits(acol[p])) >> 1 : 0;
+}
+
 __global__ void exps_from_bits(const uint64_t* __restrict__ bits, int64_t n, int32_t* __restrict__ e) {
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) e[i] = exp_of_bits(bits[i]);
@@ -309,7 +334,7 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
 // run of plen consecutive r: out[o + (r / plen) * ostride].
 hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int64_t so, int64_t sr,
                                uint64_t* out, hipStream_t s, const double* Xlo, int64_t plen,
-                               int64_t ostride) {
+                               int64_t ostride, const int32_t* rscale, int rsign) {
   if (outer <= 0 || red <= 0) return hipSuccess;
   if (plen > 0 && ostride < outer) return hipErrorInvalidValue;
   const int64_t step = so == 1 ? 256 : 4096;
@@ -323,29 +348,31 @@ hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int6
   }
   if (so == 1) {
     dim3 grid(blocks_for(outer, 256), (unsigned)gy);
-    max_abs_bits_outer_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, sr, chunk, ostride, out);
+    max_abs_bits_outer_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, sr, chunk, ostride, out, rscale, rsign);
   } else {
     dim3 grid(blocks_for(outer, 4), (unsigned)gy);
-    max_abs_bits_red_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, so, chunk, ostride, out);
+    max_abs_bits_red_contig<<<grid, 256, 0, s>>>(X, Xlo, outer, red, so, chunk, ostride, out, rscale, rsign);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_pack_a(const double* Ahi, const double* Alo, int64_t si, int64_t sp,
-                         const CascadeLayout& L, const uint64_t* amax, double* Apack, hipStream_t s) {
+                         const CascadeLayout& L, const uint64_t* amax, double* Apack, hipStream_t s,
+                         const int32_t* gexp) {
   int64_t nfrag = (L.mpad / 16) * L.K4;
   const int64_t plen = 4 * (int64_t)L.kcq, pstride = L.npanel > 1 ? L.mpad : 0;
   pack_a<<<blocks_for(nfrag, 4), 256, 0, s>>>(Ahi, Alo, si, sp, L.m, L.k, L.K4, nfrag, amax,
-                                              L.c[0], L.c[1], L.c[2], Apack, plen, pstride);
+                                              L.c[0], L.c[1], L.c[2], Apack, plen, pstride, gexp);
   return hipGetLastError();
 }
 
 hipError_t launch_pack_b(const double* Bhi, const double* Blo, int64_t sp, int64_t sj,
-                         const CascadeLayout& L, const uint64_t* bmax, double* Bpack, hipStream_t s) {
+                         const CascadeLayout& L, const uint64_t* bmax, double* Bpack, hipStream_t s,
+                         const int32_t* gexp) {
   int64_t nfrag = (L.npad / 16) * L.K4;
   const int64_t plen = 4 * (int64_t)L.kcq, pstride = L.npanel > 1 ? L.npad : 0;
   pack_b<<<blocks_for(nfrag, 4), 256, 0, s>>>(Bhi, Blo, sp, sj, L.k, L.n, L.K4, nfrag, bmax,
-                                              L.c[0], L.c[1], L.c[2], Bpack, plen, pstride);
+                                              L.c[0], L.c[1], L.c[2], Bpack, plen, pstride, gexp);
   return hipGetLastError();
 }
 
@@ -370,6 +397,13 @@ hipError_t launch_batched_phase_one(const BatchDesc* desc, int count, const int6
   if (e != hipSuccess) return e;
   const unsigned gp = (unsigned)(units_pack < 65536 ? (units_pack > 0 ? units_pack : 1) : 65536);
   batched_pack<<<gp, 256, 0, s>>>(desc, count, prefPackA, prefPackB, Ahi, Alo, Bhi, Blo, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_balance_exps(const uint64_t* acol, const uint64_t* brow, int64_t k, int64_t kpad,
+                               int32_t* g, hipStream_t s) {
+  if (kpad <= 0) return hipSuccess;
+  balance_exps<<<blocks_for(kpad, 256), 256, 0, s>>>(acol, brow, k, kpad, g);
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ DD_ALGO_SLICES_F16 = 3
 DD_ALGO_SLICES_I8 = 4
 DD_SCALING_GLOBAL = 0
 DD_SCALING_PANEL = 1
+DD_SCALING_BALANCE = 2
 
 EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_slices_split", "dd_dot",
             "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",

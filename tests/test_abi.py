@@ -83,7 +83,7 @@ def test_workspace_size_formula():
 
 def test_panel_scaling_option_and_workspace():
     m, n, k = 100, 70, 1000
-    mpad, npad, kpad = 128, 128, 1000
+    mpad, npad, kpad = 128, 128, 1008
     g = dg.dd_gemm_workspace_size(0, 0, m, n, k)
     # four rank-256 panels: three more sets of maxima and four sets of int32 exponents
     p = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"scaling": dg.DD_SCALING_PANEL})
@@ -92,8 +92,13 @@ def test_panel_scaling_option_and_workspace():
     assert 8 * (mpad + npad) + 8 * 9 * 128 * kpad <= g
     # one panel: the global layout
     assert dg.dd_gemm_workspace_size(0, 0, m, n, 200, {"scaling": 1}) == dg.dd_gemm_workspace_size(0, 0, m, n, 200)
-    for bad in ({"scaling": 2}, {"scaling": -1}, {"algo": dg.DD_ALGO_DD_VALU, "scaling": 1},
-                {"algo": dg.DD_ALGO_SLICES_BF16, "scaling": 1}):
+    # balancing: column / row maxima (8 B each) and an int32 exponent per padded inner index
+    b = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"scaling": dg.DD_SCALING_BALANCE})
+    assert g + 20 * 1008 <= b <= g + 20 * 1008 + 3 * 256
+    pb = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"scaling": dg.DD_SCALING_PANEL | dg.DD_SCALING_BALANCE})
+    assert pb == p + (b - g)
+    for bad in ({"scaling": 4}, {"scaling": -1}, {"algo": dg.DD_ALGO_DD_VALU, "scaling": 1},
+                {"algo": dg.DD_ALGO_SLICES_BF16, "scaling": 1}, {"algo": dg.DD_ALGO_SLICES_I8, "scaling": 2}):
         assert dg.dd_gemm_workspace_size(0, 0, m, n, k, bad) == 0, bad
 
 

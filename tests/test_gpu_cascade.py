@@ -379,3 +379,63 @@ def test_panel_scaling_with_cancellation_flags():
     assert got[3, 5] and got[40, 60]
     G = (down(Ch), down(Cl))
     assert np.all(dd_diff(G, O[:2]) <= panel_order_bound(A, B, O, k, kc))
+
+
+# --- power-of-two diagonal balancing F ------------------------------------------------
+
+BAL = dg.DD_SCALING_BALANCE
+
+
+def _balanced(A, B):
+    g = cz.balance_exponents(A[0], B[0])
+    return (tuple(np.asfortranarray(np.ldexp(x, g[None, :])) for x in A),
+            tuple(np.asfortranarray(np.ldexp(x, -g[:, None])) for x in B))
+
+
+@pytest.mark.parametrize("m,n,k,kc,panel", [(200, 96, 520, 128, False), (100, 70, 300, 256, False),
+                                            (65, 33, 600, 256, True), (3, 130, 257, 64, True)])
+def test_balancing_matches_oracles(m, n, k, kc, panel):
+    log(f"balancing m={m} n={n} k={k} kc={kc} panel={panel}")
+    P = make_problem(m, n, k, cfg=20, variant="skewed")
+    sc = BAL | (PANEL if panel else 0)
+    G = run_gemm(P["A"], P["B"], P["C"], kc=kc, scaling=sc)
+    O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc, scaling="panel" if panel else "global", balance=True)
+    Ab, Bb = _balanced(P["A"], P["B"])
+    bound = (panel_order_bound if panel else cascade_order_bound)(Ab, Bb, O, k, kc)
+    assert np.all(dd_diff(G, O) <= bound)
+    R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
+    assert np.all(dd_diff(G, R) <= north_star_bound(P["A"], P["B"], k))
+
+
+def test_balancing_is_invariant_to_power_of_two_diagonal_scaling():
+    m, n, k = 90, 70, 700
+    P = make_problem(m, n, k, cfg=21, variant="skewed")
+    f0 = (np.arange(k) * 37 % 61) - 30
+    Af = tuple(np.asfortranarray(np.ldexp(x, f0[None, :])) for x in P["A"])
+    Bf = tuple(np.asfortranarray(np.ldexp(x, -f0[:, None])) for x in P["B"])
+    for sc in (BAL, BAL | PANEL):
+        G0 = run_gemm(P["A"], P["B"], P["C"], scaling=sc)
+        G1 = run_gemm(Af, Bf, P["C"], scaling=sc)
+        assert np.array_equal(G0[0], G1[0]) and np.array_equal(G0[1], G1[1])
+
+
+def test_balancing_meets_the_tolerance_on_skewed_operands():
+    m, n, k = 96, 80, 512
+    P = make_problem(m, n, k, cfg=22, variant="skewed")
+    R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
+    tol = north_star_bound(P["A"], P["B"], k) + 64 * k * 2.0 ** -104 * np.abs(P["C"][0])
+    Gb = run_gemm(P["A"], P["B"], P["C"], scaling=BAL)
+    Gu = run_gemm(P["A"], P["B"], P["C"])
+    assert np.all(dd_diff(Gb, R) <= tol)
+    assert np.mean(dd_diff(Gu, R) > tol) > 0.5
+
+
+@pytest.mark.parametrize("ta,tb", [(True, False), (False, True)])
+def test_balancing_with_transposed_storage_is_bit_identical(ta, tb):
+    P = make_problem(70, 90, 333, cfg=23, variant="skewed")
+    A, B, C = P["A"], P["B"], P["C"]
+    G0 = run_gemm(A, B, C, scaling=BAL)
+    At = (np.asfortranarray(A[0].T), np.asfortranarray(A[1].T)) if ta else A
+    Bt = (np.asfortranarray(B[0].T), np.asfortranarray(B[1].T)) if tb else B
+    G1 = run_gemm(At, Bt, C, transa=ta, transb=tb, scaling=BAL)
+    assert np.array_equal(G0[0], G1[0]) and np.array_equal(G0[1], G1[1])
