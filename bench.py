@@ -265,22 +265,23 @@ def accuracy_workloads(torch, dg, n=240):
     return out
 
 
-def panel_scaling(torch, dg, m=512, n=512, k=4096, kc=256):
-    """Sigma and T per rank-kc panel against one exponent per row and column
-    on the 'panels' recipe (the scale of every row and column changes from
-    panel to panel by up to 2^80): max error over (|A||B|)_ij against the
-    FP64x2 oracle, and the share of entries within the tolerance
-    (CPU-baseline leg: the oracle is test infrastructure)."""
+def scaling_accuracy(torch, dg, variant, modes, m=512, n=512, k=4096, kc=256):
+    """Global Sigma and T against per-panel scaling or diagonal balancing on
+    inputs built to need them ('panels': the scale of every row and column
+    changes from panel to panel by up to 2^80; 'skewed': column p of A and
+    row p of B carry 2^s_p and 2^-s_p, |s_p| <= 40): max error over
+    (|A||B| + |C|)_ij against the FP64x2 oracle, and the share of entries
+    within the tolerance (CPU-baseline leg: the oracle is test
+    infrastructure)."""
     from oracle.ref import dd_gemm_ref
     from paper_2303_04353_amd.inputs import make_problem
-    P = make_problem(m, n, k, cfg=3, variant="panels", panel=kc)
+    P = make_problem(m, n, k, cfg=3, variant=variant, panel=kc)
     R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
-    AB = np.abs(P["A"][0]) @ np.abs(P["B"][0])
+    AB = np.abs(P["A"][0]) @ np.abs(P["B"][0]) + np.abs(P["C"][0])
     tol = 64 * k * 2.0 ** -104
     dev = [dg.colmajor_to_device(x) for x in (*P["A"], *P["B"])]
-    out = {"workload": f"m={m} n={n} k={k} kc={kc}, 'panels' inputs (per (row, panel) and (panel, column) "
-                       "scales 2^U{-40..40})", "tolerance_over_absAabsB": tol}
-    for name, scaling in (("global", dg.DD_SCALING_GLOBAL), ("panel", dg.DD_SCALING_PANEL)):
+    out = {"workload": f"m={m} n={n} k={k} kc={kc}, '{variant}' inputs", "tolerance_over_absAabsB": tol}
+    for name, scaling in modes:
         Ch, Cl = dg.colmajor_to_device(P["C"][0]), dg.colmajor_to_device(P["C"][1])
         dg.check(dg.dd_gemm_ex(0, 0, m, n, k, dev[0], dev[1], m, dev[2], dev[3], k, Ch, Cl, m,
                                opts={"kc": kc, "scaling": scaling}))
@@ -289,6 +290,15 @@ def panel_scaling(torch, dg, m=512, n=512, k=4096, kc=256):
         r = np.abs((G[0] - R[0]) + (G[1] - R[1])) / AB
         out[name] = {"max_err_over_absAabsB": float(r.max()), "frac_within_tolerance": float(np.mean(r <= tol))}
     return out
+
+
+def panel_scaling(torch, dg):
+    return scaling_accuracy(torch, dg, "panels", (("global", dg.DD_SCALING_GLOBAL), ("panel", dg.DD_SCALING_PANEL)))
+
+
+def balancing(torch, dg):
+    return scaling_accuracy(torch, dg, "skewed", (("global", dg.DD_SCALING_GLOBAL),
+                                                  ("balanced", dg.DD_SCALING_BALANCE)))
 
 
 def bench_autograd(torch):
@@ -486,6 +496,19 @@ def main():
                                "value": round(flops_eff / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 2),
                                "unit": "GFLOP/s"}
     del Ph, Pl
+    # power-of-two diagonal balancing: two more reductions in the split
+    Ph, Pl = C0h.clone(), C0l.clone()
+    bopts = {"scaling": dg.DD_SCALING_BALANCE}
+    dg.check(dg.dd_gemm_ex(0, 0, m, n, k, Ah, Al, m, Bh, Bl, k, Ph, Pl, m, opts=bopts, stream=stream))
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    dg.check(dg.dd_gemm_ex(0, 0, m, n, k, Ah, Al, m, Bh, Bl, k, Ph, Pl, m, opts=bopts, stream=stream))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    result["balancing"] = {"ms": round(ev0.elapsed_time(ev1), 3),
+                           "value": round(flops_eff / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 2),
+                           "unit": "GFLOP/s"}
+    del Ph, Pl
 
     if not args.no_cpu_baseline:
         from oracle.ref import dd_gemm_ref_entries  # CPU baseline leg only
@@ -540,6 +563,8 @@ def main():
             result["accuracy_workloads"] = accuracy_workloads(torch, dg)
             log("panel scaling against global scaling on panel-scaled inputs")
             result["panel_scaling"].update(panel_scaling(torch, dg))
+            log("balancing against global scaling on skewed inputs")
+            result["balancing"].update(balancing(torch, dg))
     print(json.dumps(result), flush=True)
 
 
