@@ -439,3 +439,22 @@ def test_balancing_with_transposed_storage_is_bit_identical(ta, tb):
     Bt = (np.asfortranarray(B[0].T), np.asfortranarray(B[1].T)) if tb else B
     G1 = run_gemm(At, Bt, C, transa=ta, transb=tb, scaling=BAL)
     assert np.array_equal(G0[0], G1[0]) and np.array_equal(G0[1], G1[1])
+
+
+@pytest.mark.parametrize("m,n,k,kc", [(1, 1, 1, 4), (7, 5, 5, 4), (3, 130, 9, 4), (66, 2, 31, 8), (5, 5, 16, 16)])
+@pytest.mark.parametrize("sc", [1, 2, 3])
+def test_scaling_modes_on_tiny_and_ragged_shapes(m, n, k, kc, sc):
+    P = make_problem(m, n, k, cfg=24, variant="skewed")
+    G = run_gemm(P["A"], P["B"], P["C"], kc=kc, scaling=sc)
+    panel, bal = bool(sc & PANEL), bool(sc & BAL)
+    O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc, scaling="panel" if panel else "global", balance=bal)
+    Ab, Bb = _balanced(P["A"], P["B"]) if bal else (P["A"], P["B"])
+    bound = (panel_order_bound if panel else cascade_order_bound)(Ab, Bb, O, k, kc)
+    assert np.all(dd_diff(G, O) <= bound)
+
+
+def test_scaling_modes_with_k_zero_leave_C():
+    P = make_problem(9, 7, 0, cfg=25)
+    for sc in (1, 2, 3):
+        G = run_gemm(P["A"], P["B"], P["C"], scaling=sc)
+        assert np.array_equal(G[0], P["C"][0]) and np.array_equal(G[1], P["C"][1])
