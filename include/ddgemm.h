@@ -81,7 +81,16 @@ typedef enum {
    * bounded by k s 2^(2w-2) <= 2^31 - 1 as well.  Slices need |a| <= 127,
    * i.e. w <= 7; defaults w = 7, s = 16 (111 bits, 136 products).  Results
    * equal DD_ALGO_SLICES_BF16 at the same (w, s) while k fits one chunk. */
-  DD_ALGO_SLICES_I8 = 4
+  DD_ALGO_SLICES_I8 = 4,
+  /* The paper's simple form of the cascade (Sec. 4.2): the same split, then
+   * per rank-kc update ten plain FP64 GEMMs of the vendor library (rocBLAS)
+   * into four bin matrices in device memory, a combine pass, and the same
+   * epilogue.  Bins 0-2 are exact as in the fused form; bin 3-6 is summed in
+   * the library's order, so results differ from DD_ALGO_CASCADE_F64 only
+   * there.  A comparator for the fused kernel; not for use under graph
+   * capture (the library may allocate).  kc applies; flags and scaling do
+   * not. */
+  DD_ALGO_SIMPLE_UNFUSED = 5
 } dd_algo;
 
 /* Where the cascade takes its powers of two Sigma (rows of op(A)) and T
@@ -156,6 +165,8 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
 
 /* Bytes of device workspace dd_gemm_ex needs for this problem and options
  * (0 for DD_ALGO_DD_VALU).  Returns 0 as well for invalid arguments.
+ * DD_ALGO_SIMPLE_UNFUSED needs, besides the cascade's, 8 (4 m k + 7 k n +
+ * 6 m n) bytes of plain planes, bins and accumulator.
  * The cascade needs 32 mpad kpad + 40 npad kpad bytes of packed digit planes
  * (mpad, npad rounded up to 64, kpad to 16) plus 4352 bytes of padding per
  * 16 rows and columns.  The slices variants need b s (mpad + npad) kpad

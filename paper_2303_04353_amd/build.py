@@ -27,7 +27,8 @@ def sources():
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *HIPCC_FLAGS, *sources(), "-o", tmp]
+    # rocBLAS: the plain FP64 GEMMs of the unfused comparator form
+    cmd = ["hipcc", *HIPCC_FLAGS, *sources(), "-o", tmp, "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -57,6 +57,11 @@ hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const dou
                           const int32_t* aexp = nullptr, const int32_t* bexp = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
+// The unfused form (after the split into L's packed planes): plain planes,
+// ten library GEMMs and a combine per rank-kc block, then the epilogue.
+hipError_t run_simple_products(const CascadeLayout& L, char* ws, const uint64_t* amax, const uint64_t* bmax,
+                               double* Chi, double* Clo, int64_t ldc, hipStream_t s);
+
 // Plain software double-double GEMM on the vector units.
 hipError_t launch_dd_valu(int64_t m, int64_t n, int64_t k,
                           const double* Ahi, const double* Alo, int64_t a_si, int64_t a_sp,

@@ -53,6 +53,8 @@ struct CascadeLayout {
   bool balance;                  // diagonal balancing of the inner dimension
   size_t off_acol, off_brow;     // balance: column maxima of op(A), row maxima of op(B)
   size_t off_gexp;               // balance: int32 exponent g[p] per inner index
+  // simple (unfused) form: plain column-major digit planes, bins, accumulator
+  size_t off_aplain, off_bplain, off_bins, off_acc;
 };
 
 inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
@@ -87,9 +89,12 @@ inline void split_widths(int64_t kc, int32_t c[3]) {
 // [4 kcq b, 4 kcq (b + 1))): the row maxima of op(A) are stored as npanel
 // sets of mpad words (set b at b * mpad), the column maxima of op(B) as
 // npanel sets of npad words.
+// With `simple`, also room for the unfused form: A0'..A3' as m x k and
+// B0'..B6' as k x n column-major planes, the four bins and the FP64x2
+// accumulator as m x n planes.
 inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
                                  int64_t tile_m, int64_t tile_n, bool panels = false,
-                                 bool balance = false) {
+                                 bool balance = false, bool simple = false) {
   CascadeLayout L{};
   L.m = m; L.n = n; L.k = k;
   L.tile_m = tile_m; L.tile_n = tile_n;
@@ -114,6 +119,12 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
   if (L.npanel > 1) {
     L.off_aexp = take(sizeof(int32_t) * (size_t)L.mpad * (size_t)L.npanel);
     L.off_bexp = take(sizeof(int32_t) * (size_t)L.npad * (size_t)L.npanel);
+  }
+  if (simple) {
+    L.off_aplain = take(sizeof(double) * (size_t)kFragA * (size_t)m * (size_t)k);
+    L.off_bplain = take(sizeof(double) * (size_t)kPlanesB * (size_t)k * (size_t)n);
+    L.off_bins = take(sizeof(double) * 4 * (size_t)m * (size_t)n);
+    L.off_acc = take(sizeof(double) * 2 * (size_t)m * (size_t)n);
   }
   L.balance = balance;
   if (balance) {

@@ -281,7 +281,8 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
     }
     return st;
   }
-  const CascadeLayout L = ddk::make_layout(p.m, p.n, p.k, kc, kTileM, kTileN, o.panels, o.balance);
+  const bool simple = algo == DD_ALGO_SIMPLE_UNFUSED;
+  const CascadeLayout L = ddk::make_layout(p.m, p.n, p.k, kc, kTileM, kTileN, o.panels, o.balance, simple);
   char* ws = (char*)workspace;
   if (internal_ws) {
     void* w = nullptr;
@@ -295,6 +296,16 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
   st = run_split(p, L, ws, s);
   if (st != DD_OK) return st;
   if (pe.e1) (void)hipEventRecord(pe.e1, s);
+  if (simple) {
+    st = hip_status(ddk::run_simple_products(L, ws, (const uint64_t*)(ws + L.off_amax),
+                                             (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, s));
+    if (pe.e2) {
+      (void)hipEventRecord(pe.e2, s);
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_prof_events.push_back(pe);
+    }
+    return st;
+  }
   if (o.flags) {
     st = hip_status(ddk::launch_fill_u32(o.flags, (p.m * p.n + 31) / 32, 0u, s));
     if (st != DD_OK) return st;
@@ -330,7 +341,7 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
 static bool read_opts(const dd_gemm_opts* o, Opts* out) {
   *out = Opts{};
   if (!o) return true;
-  if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_SLICES_I8) return false;
+  if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_SIMPLE_UNFUSED) return false;
   if (o->tile != 0) return false;
   if (o->scaling < 0 || o->scaling > (DD_SCALING_PANEL | DD_SCALING_BALANCE)) return false;
   out->algo = o->algo;
@@ -356,7 +367,8 @@ size_t dd_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, 
   if ((transa != DD_OP_N && transa != DD_OP_T) || (transb != DD_OP_N && transb != DD_OP_T)) return 0;
   if (m <= 0 || n <= 0 || k <= 0 || o.algo == DD_ALGO_DD_VALU) return 0;
   if (o.slices()) return ddk::make_slices_layout(m, n, k, o.S, o.w, o.fmt()).bytes;
-  return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN, o.panels, o.balance).bytes;
+  return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN, o.panels, o.balance,
+                         o.algo == DD_ALGO_SIMPLE_UNFUSED).bytes;
 }
 
 dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,

@@ -29,6 +29,7 @@ DD_ALGO_DD_VALU = 1
 DD_ALGO_SLICES_BF16 = 2
 DD_ALGO_SLICES_F16 = 3
 DD_ALGO_SLICES_I8 = 4
+DD_ALGO_SIMPLE_UNFUSED = 5
 DD_SCALING_GLOBAL = 0
 DD_SCALING_PANEL = 1
 DD_SCALING_BALANCE = 2

@@ -102,6 +102,18 @@ def test_panel_scaling_option_and_workspace():
         assert dg.dd_gemm_workspace_size(0, 0, m, n, k, bad) == 0, bad
 
 
+def test_simple_unfused_options_and_workspace():
+    m, n, k = 100, 70, 300
+    g = dg.dd_gemm_workspace_size(0, 0, m, n, k)
+    u = dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": dg.DD_ALGO_SIMPLE_UNFUSED})
+    extra = 8 * (4 * m * k + 7 * k * n + 6 * m * n)
+    assert g + extra <= u <= g + extra + 4 * 256
+    assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": dg.DD_ALGO_SIMPLE_UNFUSED, "kc": 64}) == u
+    for bad in ({"algo": dg.DD_ALGO_SIMPLE_UNFUSED, "scaling": 1}, {"algo": dg.DD_ALGO_SIMPLE_UNFUSED, "slices": 4},
+                {"algo": dg.DD_ALGO_SIMPLE_UNFUSED, "kc": 6}):
+        assert dg.dd_gemm_workspace_size(0, 0, m, n, k, bad) == 0, bad
+
+
 def test_slices_options_and_workspace():
     bf, f16 = dg.DD_ALGO_SLICES_BF16, dg.DD_ALGO_SLICES_F16
     m, n, k = 100, 70, 300
@@ -118,7 +130,7 @@ def test_slices_options_and_workspace():
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": f16}) > 0
     for bad in ({"algo": bf, "slice_bits": 10}, {"algo": bf, "slices": 17}, {"algo": f16, "slice_bits": 10},
                 {"algo": bf, "kc": 256}, {"algo": 0, "slices": 4}, {"algo": 1, "slice_bits": 8},
-                {"algo": f16, "slice_bits": 12, "slices": 1}, {"algo": 5}):
+                {"algo": f16, "slice_bits": 12, "slices": 1}, {"algo": 6}):
         assert dg.dd_gemm_workspace_size(0, 0, m, n, k, bad) == 0, bad
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": f16, "slice_bits": 11, "slices": 1}) > 0
     # INT8: 16 slices of 7 bits, one byte each, k padded to 128, groups 3..5 of the upper pass
@@ -127,7 +139,7 @@ def test_slices_options_and_workspace():
     need8 = 8 * (mpad + npad) + 16 * (mpad + npad) * 384 + 4352 * (mpad // 32 + npad // 32) + 8 * 3 * mpad * npad
     assert need8 <= ws8 <= need8 + 6 * 256
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": i8, "slice_bits": 8}) == 0
-    assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": 5}) == 0
+    assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": 6}) == 0
     base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
     assert dg.dd_gemm_ex(0, 0, *base, opts={"algo": bf, "slices": 20}, stream=0) == -17
 

@@ -458,3 +458,37 @@ def test_scaling_modes_with_k_zero_leave_C():
     for sc in (1, 2, 3):
         G = run_gemm(P["A"], P["B"], P["C"], scaling=sc)
         assert np.array_equal(G[0], P["C"][0]) and np.array_equal(G[1], P["C"][1])
+
+
+# --- the unfused form: ten library GEMMs per rank-kc update ------------------------
+
+SIMPLE = dg.DD_ALGO_SIMPLE_UNFUSED
+
+
+@pytest.mark.parametrize("m,n,k,variant,kc", [(128, 128, 128, "uniform", 256), (100, 70, 300, "uniform", 256),
+                                              (65, 33, 17, "scaled", 256), (1, 1, 1, "uniform", 256),
+                                              (200, 96, 520, "scaled", 128), (64, 64, 1000, "uniform", 64)])
+def test_simple_unfused_matches_oracles(m, n, k, variant, kc):
+    log(f"simple unfused m={m} n={n} k={k} variant={variant} kc={kc}")
+    P = make_problem(m, n, k, cfg=11, variant=variant)
+    G = run_gemm(P["A"], P["B"], P["C"], kc=kc, algo=SIMPLE)
+    O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc)
+    assert np.all(dd_diff(G, O) <= cascade_order_bound(P["A"], P["B"], O, k, kc))
+    R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
+    assert np.all(dd_diff(G, R) <= north_star_bound(P["A"], P["B"], k))
+
+
+def test_simple_unfused_integer_matrices_exact_and_transposes():
+    rng = np.random.default_rng(26)
+    m, n, k = 70, 50, 700
+    A = np.asfortranarray(rng.integers(-2 ** 20, 2 ** 20 + 1, size=(m, k)).astype(float))
+    B = np.asfortranarray(rng.integers(-2 ** 20, 2 ** 20 + 1, size=(k, n)).astype(float))
+    z = lambda s: np.zeros(s, order="F")
+    G = run_gemm((A, z(A.shape)), (B, z(B.shape)), (z((m, n)), z((m, n))), algo=SIMPLE)
+    want = A.astype(object) @ B.astype(object)
+    assert np.all(G[0].astype(object) == want) and np.all(G[1] == 0)
+    P = make_problem(70, 90, 333, cfg=27)
+    G0 = run_gemm(P["A"], P["B"], P["C"], algo=SIMPLE)
+    At = (np.asfortranarray(P["A"][0].T), np.asfortranarray(P["A"][1].T))
+    G1 = run_gemm(At, P["B"], P["C"], transa=True, algo=SIMPLE)
+    assert np.array_equal(G0[0], G1[0]) and np.array_equal(G0[1], G1[1])
