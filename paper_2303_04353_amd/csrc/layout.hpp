@@ -100,7 +100,7 @@ inline CascadeLayout make_layout(int64_t m, int64_t n, int64_t k, int32_t kc,
   L.tile_m = tile_m; L.tile_n = tile_n;
   L.mpad = round_up(m > 0 ? m : 1, tile_m);
   L.npad = round_up(n > 0 ? n : 1, tile_n);
-  L.kpad = round_up(k > 0 ? k : 1, 16);   // whole LDS stages of 16 inner indices
+  L.kpad = round_up(k > 0 ? k : 1, 16);   // whole LDS stages (8 inner indices each), in pairs
   L.K4 = L.kpad / 4;
   int64_t kce = k < kc ? k : kc;
   if (kce < 1) kce = 1;
