@@ -451,6 +451,20 @@ def test_balancing_evens_out_columns_of_A_and_rows_of_B():
     assert np.max(np.abs(cz.exponents(P["A"][0], axis=0) - cz.exponents(P["B"][0], axis=1))) > 40
 
 
+def test_balancing_exponents_absorb_any_power_of_two_diagonal():
+    # g(A F0, F0^-1 B) = g(A, B) - f0 for every integer f0_p: the balanced
+    # operands do not depend on F0 (a rounding of (e_B - e_A)/2 toward zero
+    # would break this for odd differences)
+    P = make_problem(9, 7, 400, cfg=96, variant="skewed")
+    A, B = P["A"][0], P["B"][0]
+    g = cz.balance_exponents(A, B)
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        f0 = rng.integers(-50, 51, size=400)
+        g2 = cz.balance_exponents(np.ldexp(A, f0[None, :]), np.ldexp(B, -f0[:, None]))
+        assert np.array_equal(g2, g - f0)
+
+
 @pytest.mark.parametrize("scaling", ["global", "panel"])
 def test_balanced_cascade_is_invariant_to_power_of_two_diagonal_scaling(scaling):
     # (A F0, F0^-1 B) balances to the same operands as (A, B), bit for bit
