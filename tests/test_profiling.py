@@ -1,0 +1,54 @@
+"""The rocprofv3 summary helpers (CPU only): kernel-trace table, HBM traffic
+from FETCH_SIZE / WRITE_SIZE scaled by a calibration copy, and the stored
+measurement's match to the kernel source."""
+import csv
+import json
+
+from paper_2303_04353_amd import profiling as pf
+
+
+def _write(path, header, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_trace_table_names_and_units(tmp_path):
+    p = tmp_path / "stats.csv"
+    _write(p, ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs"],
+           [["void ddk::cascade_kernel<false, false>(double const*, double const*)", 7, 7e9, 1.654e8, 60.0,
+             1.650e8, 1.660e8],
+            ["(anonymous namespace)::helper(int)", 2, 10, 5.0, 0.1, 4.0, 6.0]])
+    t = pf.trace_table(str(p)).splitlines()
+    assert t[2].startswith("| ddk::cascade_kernel<false, false> | 7 | 165400.0 |")
+    assert t[3].startswith("| helper | 2 | 0.0 |")
+
+
+def test_traffic_scales_by_the_calibration_copy(tmp_path):
+    mib = 1024
+    copy_bytes = mib << 20
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    # the copy reads each byte once but FETCH_SIZE counts half of it (x2),
+    # WRITE_SIZE counts it all (x1); the product kernel fetches 10 GiB, writes 1 GiB
+    fetch = [["vectorized_elementwise_kernel<copy>", "FETCH_SIZE", copy_bytes / 2 / 1024],
+             [pf.PRODUCT_KERNEL + "(double const*)", "FETCH_SIZE", 5 * (1 << 30) / 1024],
+             [pf.PRODUCT_KERNEL + "(double const*)", "FETCH_SIZE", 5 * (1 << 30) / 1024],
+             ["cascade_kernel<false, true>(double const*)", "FETCH_SIZE", 1.0]]
+    write = [["vectorized_elementwise_kernel<copy>", "WRITE_SIZE", copy_bytes / 1024],
+             [pf.PRODUCT_KERNEL + "(double const*)", "WRITE_SIZE", (1 << 30) / 1024]]
+    _write(tmp_path / "f.csv", hdr, fetch)
+    _write(tmp_path / "w.csv", hdr, write)
+    r = pf.traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), mib, 8, 8, 8)
+    assert abs(r["fetch_scale"] - 2.0) < 1e-12 and abs(r["write_scale"] - 1.0) < 1e-12
+    assert abs(r["fetch_bytes_per_launch"] - 10 * (1 << 30)) < 1
+    assert abs(r["bytes_per_launch"] - 11 * (1 << 30)) < 1
+    assert r["dispatches"] == [2, 1] and r["source_sha256_16"] == pf.source_hash()
+    # a stored measurement counts only for the same shape and kernel source
+    out = tmp_path / "t.json"
+    out.write_text(json.dumps(r))
+    assert pf.load_traffic(str(out), 8, 8, 8) == r["bytes_per_launch"]
+    assert pf.load_traffic(str(out), 8, 8, 16) is None
+    r["source_sha256_16"] = "0" * 16
+    out.write_text(json.dumps(r))
+    assert pf.load_traffic(str(out), 8, 8, 8) is None
