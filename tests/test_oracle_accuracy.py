@@ -255,3 +255,33 @@ def test_cascade_on_wide_range_inputs():
     tol = 64 * 64 * 2.0 ** -104 * AB[I, J]
     assert np.all(np.abs(eg) <= tol) and np.all(np.abs(ed) <= tol)
     assert np.mean(np.abs(eg) <= np.abs(ed)) > 0.9
+
+
+# --- Sec. 3.6 discussion (eq. fp642err): a nonzero bin 0 bounds the error ------------
+
+@pytest.mark.parametrize("name", ["ill-1e-14", "ill-1e-19", "wide", "uniform"])
+def test_nonzero_bin0_bounds_the_relative_error(name):
+    # With one rank-kc block (k <= kc): a nonzero bin 0 needs a product of two
+    # nonzero leading digits, i.e. |x_p| >= 2^-c0 sigma and |y_p| >= 2^-c0 tau
+    # (rounding to the grid 2^(1-c0) gives 0 below half a grid step), so
+    # |x|^T |y| >= 2^-(2 c0 + 2) ||x|| ||y||.  Put into eq. (cascerr), the error
+    # is then at most (2^-106 + 40 k kc eps~ 2^(2 c0 + 2)) |x|^T |y|.
+    n = 64
+    P = ic.ill_conditioned(n, float(name[4:]), seed=6) if name.startswith("ill") else \
+        make_problem(n, n, n, cfg=126, variant=name)
+    hi, lo, parts = cascade_gemm(P["A"], P["B"], P["C"], kc=256, return_parts=True)
+    assert len(parts["bins"]) == 1
+    bin0 = parts["bins"][0][0]
+    c0 = parts["c"][0]
+    eps_t = 2.0 ** -(sum(parts["c"]) + 53)
+    ex, err, I, J = _errors(P, (hi, lo))
+    absx_absy = (np.abs(P["A"][0]) @ np.abs(P["B"][0]))[I, J]
+    xinf = np.max(np.abs(P["A"][0]), axis=1)[I]
+    yinf = np.max(np.abs(P["B"][0]), axis=0)[J]
+    nz = bin0[I, J] != 0
+    assert np.mean(nz) > 0.5
+    # the lower bound, with a margin for the FP64 evaluation of |x|^T |y|
+    assert np.all(absx_absy[nz] >= (1 - 1e-12) * 2.0 ** -(2 * c0 + 2) * xinf[nz] * yinf[nz])
+    bound = (2.0 ** -106 + 40 * n * n * eps_t * 2.0 ** (2 * c0 + 2)) * absx_absy
+    C = np.abs(P["C"][0][I, J])
+    assert np.all(np.abs(err[nz]) <= bound[nz] + 2.0 ** -104 * C[nz])
