@@ -111,6 +111,33 @@ def _wide(rng, m, n, k):
             "ranges": {"A": (a0, a1), "B": (b0, b1)}}
 
 
+def make_problem3(m: int, n: int, k: int, *, cfg: int = 0, variant: str = "uniform", salt: int = 0):
+    """FP64x3 operands: ``dict(A=(x0, x1, x2), B=..., C=...)`` with
+    ``x0 ~ U[-1, 1)``, ``x1 = (x0 2**-53) U[-1, 1)``, ``x2 = (x1 2**-53) U[-1, 1)``
+    (about 159 significant bits); ``scaled`` multiplies rows of A and columns
+    of B (and C accordingly) by ``2**e``, e uniform in [-30, 30]."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 33, int(cfg), VARIANTS[variant],
+                                                        int(m), int(n), int(k), int(salt)]))
+
+    def words(shape):
+        x0 = rng.uniform(-1.0, 1.0, size=shape)
+        x1 = (x0 * 2.0 ** -53) * rng.uniform(-1.0, 1.0, size=shape)
+        x2 = (x1 * 2.0 ** -53) * rng.uniform(-1.0, 1.0, size=shape)
+        return [x0, x1, x2]
+
+    A, B, C = words((m, k)), words((k, n)), words((m, n))
+    if variant == "scaled":
+        eA = rng.integers(-30, 31, size=m)
+        fB = rng.integers(-30, 31, size=n)
+        A = [x * np.ldexp(1.0, eA)[:, None] for x in A]
+        B = [x * np.ldexp(1.0, fB)[None, :] for x in B]
+        C = [x * np.ldexp(1.0, eA[:, None] + fB[None, :]) for x in C]
+    elif variant != "uniform":
+        raise ValueError("FP64x3 operands: uniform or scaled")
+    f = lambda ws: tuple(np.asfortranarray(x) for x in ws)
+    return {"A": f(A), "B": f(B), "C": f(C)}
+
+
 def make_pair(shape, *, seed: int):
     """A single FP64x2 matrix of the ``uniform`` recipe (used by the autograd chain)."""
     rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 99, int(seed)] + list(shape)))
