@@ -322,6 +322,29 @@ const char* dd_status_string(dd_status status);
 /* Library version, major*10000 + minor*100 + patch. */
 int32_t dd_version(void);
 
+/* ------------------------------------------------------------------------
+ * FP64x3 (triple-word) GEMM: C := op(A) op(B) + C with every entry the sum
+ * of three doubles (x0 + x1 + x2, about 159 bits when |x1| <= ulp(x0) and
+ * |x2| <= ulp(x1)), by the cascade with six FP64 digits (the case Sec. 6.2
+ * names).  Per rank-kc block the widths c0..c4 are the largest for which
+ * bins 0..4 are exact (about 156 bits in all at kc = 256), Sigma / T come
+ * from the largest |x0| per row / column, and the 21 products run as plain
+ * FP64 GEMMs of the vendor library (rocBLAS) into six bin matrices, which
+ * this library's kernels turn into triple words (a fixed error-free
+ * summation), accumulate and add to C.  Planes x0, x1, x2 of each operand
+ * share one leading dimension; all device pointers, column-major.  kc: 0 =
+ * 256, else a multiple of 4 in [4, 4096].  Status and quick returns as for
+ * dd_gemm_ex; argument i invalid gives -i.  Not for graph capture (the
+ * library may allocate); workspace NULL with ws_bytes 0 uses the cached one.
+ * ------------------------------------------------------------------------ */
+size_t td_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k, int32_t kc);
+
+dd_status td_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+                     const double* A0, const double* A1, const double* A2, int64_t lda,
+                     const double* B0, const double* B1, const double* B2, int64_t ldb,
+                     double* C0, double* C1, double* C2, int64_t ldc,
+                     void* workspace, size_t ws_bytes, int32_t kc, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,18 @@ hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const dou
                           const int32_t* aexp = nullptr, const int32_t* bexp = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
+// FP64x3: workspace offsets (bytes) and the whole product (split, 21
+// library GEMMs and a combine per rank-kc block, epilogue).
+struct TdOffsets {
+  size_t amax, bmax, aplanes, bplanes, bins, acc;
+};
+size_t td_workspace_bytes(int64_t m, int64_t n, int64_t k, TdOffsets* off);
+hipError_t run_td(int64_t m, int64_t n, int64_t k, int64_t kc, const double* A0, const double* A1,
+                  const double* A2, int64_t a_si, int64_t a_sp, const double* B0, const double* B1,
+                  const double* B2, int64_t b_sp, int64_t b_sj, double* C0, double* C1, double* C2,
+                  int64_t ldc, char* ws, hipStream_t s);
+void td_widths(int64_t kc, int c[5]);
+
 // The unfused form (after the split into L's packed planes): plain planes,
 // ten library GEMMs and a combine per rank-kc block, then the epilogue.
 hipError_t run_simple_products(const CascadeLayout& L, char* ws, const uint64_t* amax, const uint64_t* bmax,

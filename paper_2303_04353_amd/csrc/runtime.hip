@@ -577,4 +577,67 @@ const char* dd_status_string(dd_status s) {
 
 int32_t dd_version(void) { return 100; }
 
+// ------------------------------------------------------------------ FP64x3
+size_t td_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k, int32_t kc) {
+  if ((transa != DD_OP_N && transa != DD_OP_T) || (transb != DD_OP_N && transb != DD_OP_T)) return 0;
+  if (m <= 0 || n <= 0 || k <= 0) return 0;
+  if (kc != 0 && !valid_kc(kc)) return 0;
+  return ddk::td_workspace_bytes(m, n, k, nullptr);
+}
+
+dd_status td_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+                     const double* A0, const double* A1, const double* A2, int64_t lda,
+                     const double* B0, const double* B1, const double* B2, int64_t ldb,
+                     double* C0, double* C1, double* C2, int64_t ldc,
+                     void* workspace, size_t ws_bytes, int32_t kc, hipStream_t stream) {
+  if (transa != DD_OP_N && transa != DD_OP_T) return -1;
+  if (transb != DD_OP_N && transb != DD_OP_T) return -2;
+  if (m < 0) return -3;
+  if (n < 0) return -4;
+  if (k < 0) return -5;
+  const int64_t arows = transa ? k : m, acols = transa ? m : k;
+  const int64_t brows = transb ? n : k, bcols = transb ? k : n;
+  if (lda < (arows > 1 ? arows : 1)) return -9;
+  if (ldb < (brows > 1 ? brows : 1)) return -13;
+  if (ldc < (m > 1 ? m : 1)) return -17;
+  if (kc != 0 && !valid_kc(kc)) return -20;
+  const bool internal = workspace == nullptr && ws_bytes == 0;
+  if (!internal && workspace == nullptr) return -18;
+  if (m == 0 || n == 0) return DD_OK;
+  double* Cw[3] = {C0, C1, C2};
+  for (int w = 0; w < 3; ++w)
+    if (!Cw[w]) return -(14 + w);
+  if (k == 0) return DD_OK;
+  const double* Aw[3] = {A0, A1, A2};
+  const double* Bw[3] = {B0, B1, B2};
+  for (int w = 0; w < 3; ++w) {
+    if (!Aw[w]) return -(6 + w);
+    if (!Bw[w]) return -(10 + w);
+  }
+  const size_t cb = span_bytes(m, n, ldc), ab = span_bytes(arows, acols, lda), bb = span_bytes(brows, bcols, ldb);
+  for (int w = 0; w < 3; ++w) {
+    for (int v = w + 1; v < 3; ++v)
+      if (overlaps(Cw[w], cb, Cw[v], cb)) return -(14 + v);
+    for (int v = 0; v < 3; ++v)
+      if (overlaps(Cw[w], cb, Aw[v], ab) || overlaps(Cw[w], cb, Bw[v], bb)) return -(14 + w);
+  }
+  int dev = 0;
+  dd_status st = check_device(&dev);
+  if (st != DD_OK) return st;
+  const size_t need = ddk::td_workspace_bytes(m, n, k, nullptr);
+  char* ws = (char*)workspace;
+  if (internal) {
+    void* w = nullptr;
+    st = cached_workspace(dev, stream, need, &w);
+    if (st != DD_OK) return st;
+    ws = (char*)w;
+  } else if (ws_bytes < need || ((uintptr_t)ws & 255u) != 0) {
+    return DD_ERR_WORKSPACE;
+  }
+  const int64_t a_si = transa ? lda : 1, a_sp = transa ? 1 : lda;
+  const int64_t b_sp = transb ? ldb : 1, b_sj = transb ? 1 : ldb;
+  return hip_status(ddk::run_td(m, n, k, kc ? kc : kDefaultKc, A0, A1, A2, a_si, a_sp, B0, B1, B2, b_sp, b_sj,
+                                C0, C1, C2, ldc, ws, stream));
+}
+
 }  // extern "C"

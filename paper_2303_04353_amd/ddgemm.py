@@ -37,7 +37,8 @@ DD_SCALING_BALANCE = 2
 EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_slices_split", "dd_dot",
             "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",
             "dd_batched_plan_schedule", "dd_batched_plan_info", "dd_batched_plan_destroy",
-            "dd_gemm_batched", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version")
+            "dd_gemm_batched", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version",
+            "td_gemm_workspace_size", "td_gemm_ex")
 
 
 class dd_gemm_opts(ctypes.Structure):
@@ -106,6 +107,11 @@ def lib():
         L.dd_status_string.restype = ctypes.c_char_p
         L.dd_version.argtypes = []
         L.dd_version.restype = i32
+        L.td_gemm_workspace_size.argtypes = [i32, i32, i64, i64, i64, i32]
+        L.td_gemm_workspace_size.restype = sz
+        L.td_gemm_ex.argtypes = [i32, i32, i64, i64, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp, i64,
+                                 vp, sz, i32, vp]
+        L.td_gemm_ex.restype = i32
         _lib = L
     return _lib
 
@@ -161,6 +167,17 @@ def dd_gemm_ex(transa, transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, 
     return int(lib().dd_gemm_ex(int(transa), int(transb), m, n, k, _ptr(A_hi), _ptr(A_lo), lda,
                                 _ptr(B_hi), _ptr(B_lo), ldb, _ptr(C_hi), _ptr(C_lo), ldc,
                                 _ptr(workspace), int(ws_bytes), _opts(opts), _stream(stream)))
+
+
+def td_gemm_workspace_size(transa, transb, m, n, k, kc=0) -> int:
+    return int(lib().td_gemm_workspace_size(int(transa), int(transb), m, n, k, int(kc)))
+
+
+def td_gemm_ex(transa, transb, m, n, k, A0, A1, A2, lda, B0, B1, B2, ldb, C0, C1, C2, ldc,
+               workspace=None, ws_bytes=0, kc=0, stream=None) -> int:
+    return int(lib().td_gemm_ex(int(transa), int(transb), m, n, k, _ptr(A0), _ptr(A1), _ptr(A2), lda,
+                                _ptr(B0), _ptr(B1), _ptr(B2), ldb, _ptr(C0), _ptr(C1), _ptr(C2), ldc,
+                                _ptr(workspace), int(ws_bytes), int(kc), _stream(stream)))
 
 
 def dd_cascade_split(side, trans, rows, cols, X_hi, X_lo, ldx, kc, exps, planes, stream=None) -> int:

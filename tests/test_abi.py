@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "ddgemm.h")
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dd_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:dd|td)_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_header_declares_the_binding_names():
@@ -100,6 +100,30 @@ def test_panel_scaling_option_and_workspace():
     for bad in ({"scaling": 4}, {"scaling": -1}, {"algo": dg.DD_ALGO_DD_VALU, "scaling": 1},
                 {"algo": dg.DD_ALGO_SLICES_BF16, "scaling": 1}, {"algo": dg.DD_ALGO_SLICES_I8, "scaling": 2}):
         assert dg.dd_gemm_workspace_size(0, 0, m, n, k, bad) == 0, bad
+
+
+def test_td_workspace_and_argument_checks():
+    m, n, k = 100, 70, 300
+    ws = dg.td_gemm_workspace_size(0, 0, m, n, k)
+    need = 8 * (m + n) + 8 * (6 * m * k + 11 * k * n + 9 * m * n)
+    assert need <= ws <= need + 6 * 256
+    assert dg.td_gemm_workspace_size(0, 0, m, n, k, 64) == ws
+    assert dg.td_gemm_workspace_size(0, 0, m, n, k, 6) == 0
+    assert dg.td_gemm_workspace_size(2, 0, m, n, k) == 0 and dg.td_gemm_workspace_size(0, 0, 0, n, k) == 0
+    p = 1 << 20
+    base = dict(transa=0, transb=0, m=4, n=4, k=4, A0=p, A1=2 * p, A2=3 * p, lda=4, B0=4 * p, B1=5 * p, B2=6 * p,
+                ldb=4, C0=7 * p, C1=8 * p, C2=9 * p, ldc=4)
+    def call(**kw):
+        a = dict(base, **kw)
+        return dg.td_gemm_ex(a["transa"], a["transb"], a["m"], a["n"], a["k"], a["A0"], a["A1"], a["A2"], a["lda"],
+                             a["B0"], a["B1"], a["B2"], a["ldb"], a["C0"], a["C1"], a["C2"], a["ldc"],
+                             kc=a.get("kc", 0), stream=0)
+    assert call(transa=3) == -1 and call(transb=3) == -2 and call(m=-1) == -3 and call(k=-2) == -5
+    assert call(lda=3) == -9 and call(ldb=3) == -13 and call(ldc=3) == -17 and call(kc=10) == -20
+    assert call(A1=0) == -7 and call(B2=0) == -12 and call(C0=0) == -14
+    assert call(C1=7 * p + 8) == -15          # C planes overlap
+    assert call(C2=2 * p) == -16              # C overlaps A
+    assert call(m=0, C0=0) == dg.DD_OK         # nothing to do, nothing read
 
 
 def test_simple_unfused_options_and_workspace():
