@@ -301,6 +301,48 @@ def balancing(torch, dg):
                                                   ("balanced", dg.DD_SCALING_BALANCE)))
 
 
+def bench_td(torch, dg, stream, n=4096, check_n=256):
+    """FP64x3 (triple-word) GEMM at n^3: time of td_gemm_ex (split, 21
+    library DGEMMs and a combine per rank-256 block, epilogue) on seeded
+    three-word operands, and, in the CPU-baseline leg, the largest
+    difference from the FP64x3 oracle at check_n^3 over |A||B|."""
+    from paper_2303_04353_amd.inputs import make_problem3
+    P = make_problem3(n, n, n, cfg=5)
+    Ad = [dg.colmajor_to_device(x) for x in P["A"]]
+    Bd = [dg.colmajor_to_device(x) for x in P["B"]]
+    C0 = [dg.colmajor_to_device(x) for x in P["C"]]
+    Cd = [x.clone() for x in C0]
+    dg.check(dg.td_gemm_ex(0, 0, n, n, n, *Ad, n, *Bd, n, *Cd, n, stream=stream))
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    dg.check(dg.td_gemm_ex(0, 0, n, n, n, *Ad, n, *Bd, n, *Cd, n, stream=stream))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    return {"workload": f"FP64x3 GEMM C := A*B + C, m=n=k={n}, three-word operands (about 159 bits), "
+                        "6 FP64 digits, 21 products per rank-256 block as rocBLAS DGEMMs",
+            "ms": round(ms, 3), "value": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+            "dgemm_flops_tflops": round(21 * 2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2)}
+
+
+def td_accuracy(torch, dg, out, n=256):
+    """FP64x3 result at n^3 against the FP64x3 oracle (CPU-baseline leg)."""
+    from oracle.cascade3 import cascade3_gemm
+    from paper_2303_04353_amd.inputs import make_problem3
+    P = make_problem3(n, n, n, cfg=6)
+    Ad = [dg.colmajor_to_device(x) for x in P["A"]]
+    Bd = [dg.colmajor_to_device(x) for x in P["B"]]
+    Cd = [dg.colmajor_to_device(x) for x in P["C"]]
+    dg.check(dg.td_gemm_ex(0, 0, n, n, n, *Ad, n, *Bd, n, *Cd, n))
+    torch.cuda.synchronize()
+    G = [dg.colmajor_from_device(x) for x in Cd]
+    O = cascade3_gemm(P["A"], P["B"], P["C"], kc=256)
+    d = np.abs(((G[0] - O[0]) + (G[1] - O[1])) + (G[2] - O[2]))
+    AB = np.abs(P["A"][0]) @ np.abs(P["B"][0])
+    out["check"] = {"n": n, "max_diff_from_oracle_over_absAabsB": float(np.max(d / AB))}
+
+
 def bench_autograd(torch):
     """Forward and cascaded backward of L = sum((W2 (W1 X)) o G), W 2048^2, X, G 2048x512."""
     from paper_2303_04353_amd import autograd as ag
@@ -577,6 +619,10 @@ def main():
             log("slices accuracy against the oracles (sampled entries)")
             slices_accuracy(sres, samples, IJ)
         result["slices"] = sres
+        log("FP64x3 at 4096^3")
+        result["fp64x3"] = bench_td(torch, dg, stream)
+        if not args.no_cpu_baseline:
+            td_accuracy(torch, dg, result["fp64x3"])
         if not args.no_cpu_baseline:
             log("accuracy workloads at n=240 against the exact product")
             result["accuracy_workloads"] = accuracy_workloads(torch, dg)
