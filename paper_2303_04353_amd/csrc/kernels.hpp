@@ -4,7 +4,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 #include <stdint.h>
+
+#include <mutex>
 
 #include "layout.hpp"
 
@@ -71,6 +74,16 @@ void td_widths(int64_t kc, int c[5]);
 
 // The unfused form (after the split into L's packed planes): plain planes,
 // ten library GEMMs and a combine per rank-kc block, then the epilogue.
+// The vendor BLAS handle of the current device (created on first use) with
+// its stream set to `s`.  The lock is held until the lease ends, so calls on
+// several host threads do not change the stream under each other.
+struct BlasLease {
+  std::unique_lock<std::mutex> lock;
+  rocblas_handle h = nullptr;
+  hipError_t status = hipSuccess;
+};
+BlasLease blas_lease(hipStream_t s);
+
 hipError_t run_simple_products(const CascadeLayout& L, char* ws, const uint64_t* amax, const uint64_t* bmax,
                                double* Chi, double* Clo, int64_t ldc, hipStream_t s);
 

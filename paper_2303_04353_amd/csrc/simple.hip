@@ -63,12 +63,26 @@ __global__ void fill_f64(double* p, int64_t n) {
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// One library handle per device, created on first use; its stream is set
-// per call under the lock.
 std::mutex g_blas_mu;
 std::unordered_map<int, rocblas_handle> g_blas;
 
 }  // namespace
+
+BlasLease blas_lease(hipStream_t s) {
+  BlasLease r;
+  r.lock = std::unique_lock<std::mutex>(g_blas_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { r.status = hipErrorInvalidDevice; return r; }
+  auto it = g_blas.find(dev);
+  if (it == g_blas.end()) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) { r.status = hipErrorNotInitialized; return r; }
+    it = g_blas.emplace(dev, h).first;
+  }
+  r.h = it->second;
+  if (rocblas_set_stream(r.h, s) != rocblas_status_success) r.status = hipErrorInvalidHandle;
+  return r;
+}
 
 hipError_t run_simple_products(const CascadeLayout& L, char* ws, const uint64_t* amax, const uint64_t* bmax,
                                double* Chi, double* Clo, int64_t ldc, hipStream_t s) {
@@ -86,18 +100,9 @@ hipError_t run_simple_products(const CascadeLayout& L, char* ws, const uint64_t*
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
-  std::lock_guard<std::mutex> lk(g_blas_mu);
-  rocblas_handle h = nullptr;
-  auto it = g_blas.find(dev);
-  if (it == g_blas.end()) {
-    if (rocblas_create_handle(&h) != rocblas_status_success) return hipErrorNotInitialized;
-    g_blas[dev] = h;
-  } else {
-    h = it->second;
-  }
-  if (rocblas_set_stream(h, s) != rocblas_status_success) return hipErrorInvalidHandle;
+  BlasLease lease = blas_lease(s);
+  if (lease.status != hipSuccess) return lease.status;
+  rocblas_handle h = lease.h;
 
   // (bin, A plane, B plane) of the ten products, bin 3-6 with B4', B5', B6'
   static const int prod[10][3] = {{0, 0, 0}, {1, 0, 1}, {1, 1, 0}, {2, 0, 2}, {2, 1, 1},

@@ -23,6 +23,7 @@
 #include <rocblas/rocblas.h>
 #include <stdint.h>
 
+#include <array>
 #include <cmath>
 #include <mutex>
 #include <unordered_map>
@@ -177,8 +178,6 @@ __global__ void td_fill(double* p, int64_t n) {
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-std::mutex g_td_mu;
-std::unordered_map<int, rocblas_handle> g_td_blas;
 
 }  // namespace
 
@@ -198,8 +197,19 @@ bool td_widths_ok(const int c[5], int64_t kc) {
   return true;
 }
 
-// Largest total, then lexicographically largest widths in [14, 26].
+// Largest total, then lexicographically largest widths in [14, 26].  The
+// search takes some 20 ms on the host, so its result is kept per kc.
 void td_widths(int64_t kc, int c[5]) {
+  static std::mutex mu;
+  static std::unordered_map<int64_t, std::array<int, 5>> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(kc);
+    if (it != cache.end()) {
+      for (int t = 0; t < 5; ++t) c[t] = it->second[t];
+      return;
+    }
+  }
   int best[5] = {0, 0, 0, 0, 0}, best_sum = -1;
   int w[5];
   for (w[0] = 26; w[0] >= 14; --w[0])
@@ -217,7 +227,10 @@ void td_widths(int64_t kc, int c[5]) {
             if (better) { best_sum = s; for (int t = 0; t < 5; ++t) best[t] = w[t]; }
             break;
           }
-  for (int t = 0; t < 5; ++t) c[t] = best[t];
+  std::array<int, 5> r;
+  for (int t = 0; t < 5; ++t) c[t] = r[t] = best[t];
+  std::lock_guard<std::mutex> lk(mu);
+  cache[kc] = r;
 }
 
 size_t td_workspace_bytes(int64_t m, int64_t n, int64_t k, TdOffsets* off) {
@@ -270,18 +283,9 @@ hipError_t run_td(int64_t m, int64_t n, int64_t k, int64_t kc_in, const double* 
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
-  std::lock_guard<std::mutex> lk(g_td_mu);
-  rocblas_handle h = nullptr;
-  auto it = g_td_blas.find(dev);
-  if (it == g_td_blas.end()) {
-    if (rocblas_create_handle(&h) != rocblas_status_success) return hipErrorNotInitialized;
-    g_td_blas[dev] = h;
-  } else {
-    h = it->second;
-  }
-  if (rocblas_set_stream(h, s) != rocblas_status_success) return hipErrorInvalidHandle;
+  BlasLease lease = blas_lease(s);
+  if (lease.status != hipSuccess) return lease.status;
+  rocblas_handle h = lease.h;
 
   const double one = 1.0, zero = 0.0;
   const int64_t pa = m * k, pb = k * n;
