@@ -3,7 +3,7 @@
 Against: the exactness rule behind the split widths and their maximality;
 exact reconstruction of every entry from its six digits (rationals); bins
 0..4 equal to exact sums, including worst-case digits; the triple-word sum
-against rationals, with cancellation; results against exact rational
+against rationals, with cancellation (also across several levels); results against exact rational
 C + A B within the analogue of eq. (cascerr); integer matrices; power-of-two
 row/column invariance; k = 0.
 """
@@ -103,6 +103,30 @@ def test_triple_word_sum_against_rationals():
         # the words come out in decreasing order, each within the last's ulp
         r0, r1, r2 = (float(x[0]) for x in r)
         assert abs(r1) <= abs(np.spacing(r0)) and abs(r2) <= abs(np.spacing(r1)) + 1e-320
+
+
+def test_triple_word_sum_with_multilevel_cancellation():
+    """A triple word plus pairs of large terms that cancel up to a small
+    remainder (up to 2^60 above the sum), in random order and in increasing
+    magnitude: the three words must hold the exact sum to 2^-157 relative.
+    (The full sequence reaches 2^-161 here; one VecSum pass fewer for the
+    first word leaves 2^-151.)"""
+    rng = np.random.default_rng(8)
+    for trial in range(1000):
+        n = int(rng.integers(3, 13))
+        s0 = rng.uniform(-1, 1)
+        vals = [s0, s0 * 2.0 ** -60 * rng.uniform(-1, 1), s0 * 2.0 ** -120 * rng.uniform(-1, 1)]
+        while len(vals) < n:
+            big = float(np.ldexp(rng.uniform(0.5, 1), int(rng.integers(1, 60)))) * float(rng.choice([-1, 1]))
+            small = float(np.ldexp(rng.uniform(-1, 1), int(rng.integers(-170, -1))))
+            vals += [big, -big + small]
+        vals = [vals[i] for i in rng.permutation(n)]
+        if trial % 2:
+            vals.sort(key=abs)
+        terms = [np.array([v]) for v in vals]
+        S = sum(F(v) for v in vals)
+        got = sum(F(float(x[0])) for x in c3.td_from_terms(terms))
+        assert abs(got - S) <= F(1, 2 ** 157) * abs(S), trial
 
 
 @pytest.mark.parametrize("m,n,k,kc,variant", [(5, 4, 40, 16, "uniform"), (4, 6, 70, 32, "scaled"),
