@@ -321,7 +321,7 @@ def bench_td(torch, dg, stream, n=4096, check_n=256):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     return {"workload": f"FP64x3 GEMM C := A*B + C, m=n=k={n}, three-word operands (about 159 bits), "
-                        "6 FP64 digits, 21 products per rank-256 block as rocBLAS DGEMMs",
+                        "6 FP64 digits, 21 products per rank-256 block as six stacked rocBLAS DGEMMs (one per bin)",
             "ms": round(ms, 3), "value": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
             "dgemm_flops_tflops": round(21 * 2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2)}
 

@@ -328,8 +328,9 @@ int32_t dd_version(void);
  * |x2| <= ulp(x1)), by the cascade with six FP64 digits (the case Sec. 6.2
  * names).  Per rank-kc block the widths c0..c4 are the largest for which
  * bins 0..4 are exact (about 156 bits in all at kc = 256), Sigma / T come
- * from the largest |x0| per row / column, and the 21 products run as plain
- * FP64 GEMMs of the vendor library (rocBLAS) into six bin matrices, which
+ * from the largest |x0| per row / column, and the 21 products run as six
+ * plain FP64 GEMMs of the vendor library (rocBLAS), one per bin with its
+ * products stacked along the inner dimension, into six bin matrices, which
  * this library's kernels turn into triple words (a fixed error-free
  * summation), accumulate and add to C.  Planes x0, x1, x2 of each operand
  * share one leading dimension; all device pointers, column-major.  kc: 0 =

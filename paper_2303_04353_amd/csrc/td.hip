@@ -1,8 +1,20 @@
 // FP64x3 (triple-word) GEMM by the cascade with six FP64 digits (the case
 // Sec. 6.2 names: FP64x3 in terms of FP64).  Unfused: this library's split
-// into plain column-major digit planes, per rank-kc update 21 plain FP64
-// GEMMs of the vendor library (rocBLAS) into six bin matrices, this
-// library's combine into a triple-word accumulator, and its epilogue.
+// into column-major digit panels, per rank-kc update the 21 products as six
+// plain FP64 GEMMs of the vendor library (rocBLAS), one per bin (the
+// products of a bin stacked along the inner dimension), this library's
+// combine into a triple-word accumulator, and its epilogue.
+//
+// Layout per rank-kc block b (kb columns of op(A), kb rows of op(B)):
+//  * A: the six m x kb digit panels side by side in descending order,
+//    [A_5' | A_4' | ... | A_0'] (ld m), at b * 6 kc m;
+//  * B: the six kb x n digit panels stacked in ascending order,
+//    [B_0'; B_1'; ...; B_5'] (ld 6 kb), at b * 6 kc n; and the suffix sums
+//    stacked the same way, [U_0'; ...; U_5'] (U_5' = B_5'), after all of B.
+// Bin L <= 4 is then [A_L' | ... | A_0'] times [B_0'; ...; B_L'], one GEMM of
+// inner dimension (L+1) kb, and the tail bin [A_5' | ... | A_0'] times
+// [U_0'; ...; U_5'].  Bins 0..4 stay exact in any summation order: the
+// widths rule bounds the sum of the magnitudes of all their products.
 //
 // Steps (the same as the test oracle's):
 //  * widths c0..c4 for a rank-kc block: the largest (in total, then in
@@ -73,43 +85,57 @@ __device__ __forceinline__ void split_entry3(double x0, double x1, double x2, in
   out[5] = ((a[5] + b[5]) + c[5]) * W.w[5];
 }
 
-// op(A) entries (i, p): six planes m x k (ld m).
+// Block of inner index p (blocks of kc, the last one kb = k - b kc wide).
+struct BlockPos {
+  int64_t b, pl, kb;
+};
+__device__ __forceinline__ BlockPos block_pos(int64_t p, int64_t k, int64_t kc) {
+  const int64_t b = p / kc, first = b * kc;
+  return {b, p - first, k - first < kc ? k - first : kc};
+}
+
+// op(A) entries (i, p) into the descending digit panels of their block.
 __global__ void __launch_bounds__(256)
 td_split_a(const double* __restrict__ X0, const double* __restrict__ X1, const double* __restrict__ X2,
-           int64_t si, int64_t sp, int64_t m, int64_t k, const uint64_t* __restrict__ amax, Widths3 W,
-           double* __restrict__ planes) {
+           int64_t si, int64_t sp, int64_t m, int64_t k, int64_t kc, const uint64_t* __restrict__ amax, Widths3 W,
+           double* __restrict__ panels) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= m * k) return;
   const int64_t i = t % m, p = t / m, idx = i * si + p * sp;
   double out[6], ys[3];
   split_entry3(X0[idx], X1[idx], X2[idx], exp_of_bits(amax[i]), W, out, ys);
-  const int64_t plane = m * k;
+  const BlockPos q = block_pos(p, k, kc);
+  double* base = panels + q.b * 6 * kc * m + q.pl * m + i;
 #pragma unroll
-  for (int l = 0; l < 6; ++l) planes[l * plane + t] = out[l];
+  for (int l = 0; l < 6; ++l) base[(5 - l) * q.kb * m] = out[l];
 }
 
-// op(B) entries (p, j): six planes k x n (ld k), then U_0' .. U_4' (U_5' is
-// plane 5): U_t' = B_t' + U_(t+1)' from the last plane up, U_0' the scaled
-// value (y0 + y1) + y2.
+// op(B) entries (p, j) into the ascending digit panels of their block and
+// the suffix sums U_t' = B_t' + U_(t+1)' (from the last plane up; U_0' the
+// scaled value (y0 + y1) + y2) into the U panels, which start at `upanels`.
 __global__ void __launch_bounds__(256)
 td_split_b(const double* __restrict__ X0, const double* __restrict__ X1, const double* __restrict__ X2,
-           int64_t sp, int64_t sj, int64_t k, int64_t n, const uint64_t* __restrict__ bmax, Widths3 W,
-           double* __restrict__ planes) {
+           int64_t sp, int64_t sj, int64_t k, int64_t n, int64_t kc, const uint64_t* __restrict__ bmax, Widths3 W,
+           double* __restrict__ panels, double* __restrict__ upanels) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= k * n) return;
   const int64_t p = t % k, j = t / k, idx = p * sp + j * sj;
   double out[6], ys[3];
   split_entry3(X0[idx], X1[idx], X2[idx], exp_of_bits(bmax[j]), W, out, ys);
-  const int64_t plane = k * n;
+  const BlockPos q = block_pos(p, k, kc);
+  const int64_t off = q.b * 6 * kc * n + j * 6 * q.kb + q.pl;
+  double* base = panels + off;
+  double* ub = upanels + off;
 #pragma unroll
-  for (int l = 0; l < 6; ++l) planes[l * plane + t] = out[l];
+  for (int l = 0; l < 6; ++l) base[l * q.kb] = out[l];
   double u = out[5];
+  ub[5 * q.kb] = u;
 #pragma unroll
   for (int l = 4; l >= 1; --l) {
     u = out[l] + u;
-    planes[(6 + l) * plane + t] = u;
+    ub[l * q.kb] = u;
   }
-  planes[6 * plane + t] = (ys[0] + ys[1]) + ys[2];
+  ub[0] = (ys[0] + ys[1]) + ys[2];
 }
 
 __device__ __forceinline__ void vec_sum6(double a[6]) {
@@ -240,7 +266,7 @@ size_t td_workspace_bytes(int64_t m, int64_t n, int64_t k, TdOffsets* off) {
   t.amax = take(sizeof(uint64_t) * (size_t)m);
   t.bmax = take(sizeof(uint64_t) * (size_t)n);
   t.aplanes = take(sizeof(double) * 6 * (size_t)m * (size_t)k);
-  t.bplanes = take(sizeof(double) * 11 * (size_t)k * (size_t)n);
+  t.bplanes = take(sizeof(double) * 12 * (size_t)k * (size_t)n);   // digit panels, then U panels
   t.bins = take(sizeof(double) * 6 * (size_t)m * (size_t)n);
   t.acc = take(sizeof(double) * 3 * (size_t)m * (size_t)n);
   if (off) *off = t;
@@ -276,8 +302,9 @@ hipError_t run_td(int64_t m, int64_t n, int64_t k, int64_t kc_in, const double* 
   if (e == hipSuccess) e = launch_max_abs_bits(A0, m, k, a_si, a_sp, amax, s);
   if (e == hipSuccess) e = launch_max_abs_bits(B0, n, k, b_sj, b_sp, bmax, s);
   if (e != hipSuccess) return e;
-  td_split_a<<<nblk(m * k), 256, 0, s>>>(A0, A1, A2, a_si, a_sp, m, k, amax, W, Ap);
-  td_split_b<<<nblk(k * n), 256, 0, s>>>(B0, B1, B2, b_sp, b_sj, k, n, bmax, W, Bp);
+  double* Up = Bp + 6 * k * n;
+  td_split_a<<<nblk(m * k), 256, 0, s>>>(A0, A1, A2, a_si, a_sp, m, k, kc, amax, W, Ap);
+  td_split_b<<<nblk(k * n), 256, 0, s>>>(B0, B1, B2, b_sp, b_sj, k, n, kc, bmax, W, Bp, Up);
   const int64_t mn = m * n;
   td_fill<<<nblk(3 * mn), 256, 0, s>>>(acc, 3 * mn);
   e = hipGetLastError();
@@ -288,23 +315,21 @@ hipError_t run_td(int64_t m, int64_t n, int64_t k, int64_t kc_in, const double* 
   rocblas_handle h = lease.h;
 
   const double one = 1.0, zero = 0.0;
-  const int64_t pa = m * k, pb = k * n;
   for (int64_t p0 = 0; p0 < k; p0 += kc) {
     const int64_t kb = p0 + kc < k ? kc : k - p0;
-    // (bin, A plane, B plane): bins 0..4 from the digit planes, the tail
-    // bin from A_i' and U_(5-i)' (U_5' is B plane 5, U_t' plane 6 + t)
+    const double* Ablk = Ap + p0 * 6 * m;   // [A_5' | ... | A_0'], each m x kb
+    const double* Bblk = Bp + p0 * 6 * n;   // [B_0'; ...; B_5'], ld 6 kb
+    const double* Ublk = Up + p0 * 6 * n;   // [U_0'; ...; U_5'], ld 6 kb
+    // bin L <= 4: [A_L' | ... | A_0'] [B_0'; ...; B_L']; tail: all six A
+    // panels times the U panels
     for (int L = 0; L < 6; ++L) {
-      const int terms = L < 5 ? L + 1 : 6;
-      for (int i = 0; i < terms; ++i) {
-        const int bp = L < 5 ? L - i : (5 - i == 5 ? 5 : 6 + (5 - i));
-        const double* A = Ap + i * pa + p0 * m;
-        const double* B = Bp + bp * pb + p0;
-        const rocblas_status st = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none,
-                                                (rocblas_int)m, (rocblas_int)n, (rocblas_int)kb, &one, A,
-                                                (rocblas_int)m, B, (rocblas_int)k, i ? &one : &zero,
-                                                bins + L * mn, (rocblas_int)m);
-        if (st != rocblas_status_success) return hipErrorLaunchFailure;
-      }
+      const int64_t np = L < 5 ? L + 1 : 6;
+      const double* A = Ablk + (6 - np) * kb * m;
+      const double* B = L < 5 ? Bblk : Ublk;
+      const rocblas_status st = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)m,
+                                              (rocblas_int)n, (rocblas_int)(np * kb), &one, A, (rocblas_int)m, B,
+                                              (rocblas_int)(6 * kb), &zero, bins + L * mn, (rocblas_int)m);
+      if (st != rocblas_status_success) return hipErrorLaunchFailure;
     }
     td_combine<<<nblk(mn), 256, 0, s>>>(bins, mn, acc);
     e = hipGetLastError();

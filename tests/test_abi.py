@@ -105,7 +105,7 @@ def test_panel_scaling_option_and_workspace():
 def test_td_workspace_and_argument_checks():
     m, n, k = 100, 70, 300
     ws = dg.td_gemm_workspace_size(0, 0, m, n, k)
-    need = 8 * (m + n) + 8 * (6 * m * k + 11 * k * n + 9 * m * n)
+    need = 8 * (m + n) + 8 * (6 * m * k + 12 * k * n + 9 * m * n)
     assert need <= ws <= need + 6 * 256
     assert dg.td_gemm_workspace_size(0, 0, m, n, k, 64) == ws
     assert dg.td_gemm_workspace_size(0, 0, m, n, k, 6) == 0
