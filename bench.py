@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--slices-only", action="store_true",
                     help="time only the narrow-slice variant at 4096^3 (for profiling it); "
                          "not the headline workload")
+    ap.add_argument("--fp64x3-only", action="store_true",
+                    help="time only the FP64x3 GEMM at 4096^3 (for profiling it); not the headline workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy of MIB MiB (reads and writes that many "
                          "bytes once), the reference for scaling HBM byte counters")
@@ -301,11 +303,12 @@ def balancing(torch, dg):
                                                   ("balanced", dg.DD_SCALING_BALANCE)))
 
 
-def bench_td(torch, dg, stream, n=4096, check_n=256):
-    """FP64x3 (triple-word) GEMM at n^3: time of td_gemm_ex (split, 21
-    library DGEMMs and a combine per rank-256 block, epilogue) on seeded
-    three-word operands, and, in the CPU-baseline leg, the largest
-    difference from the FP64x3 oracle at check_n^3 over |A||B|."""
+def bench_td(torch, dg, stream, n=4096, reps=1):
+    """FP64x3 (triple-word) GEMM at n^3: average time of td_gemm_ex (split,
+    six library DGEMMs (one per bin) and a combine per rank-256 block,
+    epilogue) on seeded three-word operands over `reps` calls.  The
+    CPU-baseline leg adds the difference from the FP64x3 oracle
+    (td_accuracy)."""
     from paper_2303_04353_amd.inputs import make_problem3
     P = make_problem3(n, n, n, cfg=5)
     Ad = [dg.colmajor_to_device(x) for x in P["A"]]
@@ -316,10 +319,11 @@ def bench_td(torch, dg, stream, n=4096, check_n=256):
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
-    dg.check(dg.td_gemm_ex(0, 0, n, n, n, *Ad, n, *Bd, n, *Cd, n, stream=stream))
+    for _ in range(reps):
+        dg.check(dg.td_gemm_ex(0, 0, n, n, n, *Ad, n, *Bd, n, *Cd, n, stream=stream))
     ev1.record(stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    ms = ev0.elapsed_time(ev1) / reps
     return {"workload": f"FP64x3 GEMM C := A*B + C, m=n=k={n}, three-word operands (about 159 bits), "
                         "6 FP64 digits, 21 products per rank-256 block as six stacked rocBLAS DGEMMs (one per bin)",
             "ms": round(ms, 3), "value": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
@@ -388,6 +392,12 @@ def main():
         if not args.no_cpu_baseline:
             slices_accuracy(sres, samples, IJ)
         print(json.dumps({"slices": sres}), flush=True)
+        return
+    if args.fp64x3_only:
+        tres = bench_td(torch, dg, torch.cuda.current_stream(), reps=max(1, args.steps))
+        if not args.no_cpu_baseline:
+            td_accuracy(torch, dg, tres)
+        print(json.dumps({"fp64x3": tres}), flush=True)
         return
     N = args.size
     m = n = k = N
