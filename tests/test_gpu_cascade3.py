@@ -4,7 +4,8 @@ Bins 0..4 are exact on both sides and the split, the triple-word sums and
 the epilogue are the same fixed sequences of round-to-nearest operations,
 so the results may differ only through the order in which the library and
 numpy sum the tail bin; the bound below covers that.  Also: exact rationals
-on a small problem, integer matrices, transposed storage, k = 0.
+on a small problem, integer matrices, transposed storage, k = 0, non-finite
+entries (NaN only in their rows and columns), padded leading dimensions.
 """
 from fractions import Fraction
 
@@ -97,3 +98,48 @@ def test_td_k_zero_leaves_C():
     P = make_problem3(9, 7, 0, cfg=34)
     G = run_td(P["A"], P["B"], P["C"])
     assert all(np.array_equal(G[w], P["C"][w]) for w in range(3))
+
+
+def test_td_non_finite_rows_and_columns_become_nan_only_there():
+    m, n, k = 20, 12, 40
+    P = make_problem3(m, n, k, cfg=35)
+    A = tuple(x.copy(order="F") for x in P["A"])
+    B = tuple(x.copy(order="F") for x in P["B"])
+    A[0][3, 7] = np.inf        # leading word
+    A[2][11, 2] = np.nan       # third word of a finite leading word
+    B[1][5, 4] = -np.inf       # second word of a column of B
+    G = run_td(A, B, P["C"], kc=16)
+    badr = np.zeros(m, bool)
+    badr[[3, 11]] = True
+    badc = np.zeros(n, bool)
+    badc[4] = True
+    bad = badr[:, None] | badc[None, :]
+    assert np.all(np.isnan(G[0][bad]))
+    assert all(np.all(np.isfinite(G[w][~bad])) for w in range(3))
+    Af = tuple(x[~badr] for x in A)
+    Bf = tuple(x[:, ~badc] for x in B)
+    Cf = tuple(x[~badr][:, ~badc] for x in P["C"])
+    O = c3.cascade3_gemm(Af, Bf, Cf, kc=16)
+    Gf = tuple(x[~badr][:, ~badc] for x in G)
+    assert np.all(_diff(Gf, O) <= _order_bound(Af, Bf, O, k, 16))
+
+
+def test_td_padded_leading_dimensions_bit_identical():
+    import torch
+    m, n, k = 37, 29, 300
+    P = make_problem3(m, n, k, cfg=36)
+    G0 = run_td(P["A"], P["B"], P["C"])
+    lda, ldb, ldc = m + 3, k + 5, m + 2
+    def pad(x, ld):
+        out = np.full((ld, x.shape[1]), 7.0, order="F")
+        out[:x.shape[0]] = x
+        return out
+    Ad = [up(pad(x, lda)) for x in P["A"]]
+    Bd = [up(pad(x, ldb)) for x in P["B"]]
+    Cd = [up(pad(x, ldc)) for x in P["C"]]
+    dg.check(dg.td_gemm_ex(0, 0, m, n, k, *Ad, lda, *Bd, ldb, *Cd, ldc), "td_gemm_ex")
+    torch.cuda.synchronize()
+    G1 = [down(x) for x in Cd]
+    for w in range(3):
+        assert np.array_equal(G1[w][:m], G0[w])
+        assert np.all(G1[w][m:] == 7.0)   # rows beyond m untouched
