@@ -317,6 +317,11 @@ def bench_td(torch, dg, stream, n=4096, reps=1):
     Cd = [x.clone() for x in C0]
     dg.check(dg.td_gemm_ex(0, 0, n, n, n, *Ad, n, *Bd, n, *Cd, n, stream=stream))
     torch.cuda.synchronize()
+    # sampled entries of this first (untimed) result, for the CPU-baseline leg
+    from paper_2303_04353_amd.inputs import sample_entries
+    I, J = sample_entries(n, n, 256, seed=17)
+    ti, tj = torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()
+    samples = [x.T[ti, tj].cpu().numpy() for x in Cd]   # the tensors hold C transposed
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(reps):
@@ -327,13 +332,43 @@ def bench_td(torch, dg, stream, n=4096, reps=1):
     return {"workload": f"FP64x3 GEMM C := A*B + C, m=n=k={n}, three-word operands (about 159 bits), "
                         "6 FP64 digits, 21 products per rank-256 block as six stacked rocBLAS DGEMMs (one per bin)",
             "ms": round(ms, 3), "value": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
-            "dgemm_flops_tflops": round(21 * 2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2)}
+            "dgemm_flops_tflops": round(21 * 2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2),
+            "_samples": (P, I, J, samples)}
+
+
+def td_sampled_check(P, I, J, S):
+    """Sampled entries S (three word arrays) of the FP64x3 result C + A B at
+    positions (I, J) against the oracle, each entry from its row of A and
+    column of B alone, within the bound for the tail bin's summation order."""
+    from oracle.cascade3 import cascade3_gemm, widths3
+    k = P["A"][0].shape[1]
+    worst, ok = 0.0, True
+    for t, (i, j) in enumerate(zip(I, J)):
+        a = tuple(x[i:i + 1, :] for x in P["A"])
+        b = tuple(x[:, j:j + 1] for x in P["B"])
+        c = tuple(x[i:i + 1, j:j + 1] for x in P["C"])
+        o = cascade3_gemm(a, b, c, kc=256)
+        d = abs(((S[0][t] - o[0][0, 0]) + (S[1][t] - o[1][0, 0])) + (S[2][t] - o[2][0, 0]))
+        ab = float((np.abs(a[0]) @ np.abs(b[0]))[0, 0])
+        # tail bins: 6 kc products summed in another order, per block
+        ea, eb = np.frexp(np.max(np.abs(a[0])))[1], np.frexp(np.max(np.abs(b[0])))[1]
+        bound = (k // 256) * 1024.0 * 256 * 256 * 2.0 ** (int(ea) + int(eb) - 53 - sum(widths3(256))) \
+            + 2.0 ** -150 * (abs(o[0][0, 0]) + ab)
+        ok &= bool(d <= bound)
+        worst = max(worst, d / ab)
+    return {"entries": int(len(I)), "max_diff_from_oracle_over_absAabsB": float(worst),
+            "within_order_bound": ok}
 
 
 def td_accuracy(torch, dg, out, n=256):
-    """FP64x3 result at n^3 against the FP64x3 oracle (CPU-baseline leg)."""
+    """FP64x3 results against the FP64x3 oracle (CPU-baseline leg): every
+    entry at n^3, and 256 sampled entries of the timed 4096^3 problem (the
+    oracle computes entry (i, j) from row i of A and column j of B alone:
+    the powers of two are per row and per column), the latter within the
+    bound for the tail bin's summation order."""
     from oracle.cascade3 import cascade3_gemm
     from paper_2303_04353_amd.inputs import make_problem3
+    out["check_sampled_4096"] = td_sampled_check(*out.pop("_samples"))
     P = make_problem3(n, n, n, cfg=6)
     Ad = [dg.colmajor_to_device(x) for x in P["A"]]
     Bd = [dg.colmajor_to_device(x) for x in P["B"]]
@@ -397,6 +432,7 @@ def main():
         tres = bench_td(torch, dg, torch.cuda.current_stream(), reps=max(1, args.steps))
         if not args.no_cpu_baseline:
             td_accuracy(torch, dg, tres)
+        tres.pop("_samples", None)
         print(json.dumps({"fp64x3": tres}), flush=True)
         return
     N = args.size
@@ -633,6 +669,7 @@ def main():
         result["fp64x3"] = bench_td(torch, dg, stream)
         if not args.no_cpu_baseline:
             td_accuracy(torch, dg, result["fp64x3"])
+        result["fp64x3"].pop("_samples", None)
         if not args.no_cpu_baseline:
             log("accuracy workloads at n=240 against the exact product")
             result["accuracy_workloads"] = accuracy_workloads(torch, dg)
