@@ -47,6 +47,7 @@ max_abs_bits_outer_contig(const double* __restrict__ X, const double* __restrict
     int64_t r0 = c * chunk;
     int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
     uint64_t mx = 0;
+#pragma unroll 8
     for (int64_t r = r0; r < r1; ++r) {
       double v = Xlo ? X[o + r * ld] + Xlo[o + r * ld] : X[o + r * ld];
       if (rscale) v = __builtin_ldexp(v, rsign * rscale[r]);
@@ -337,7 +338,15 @@ hipError_t launch_max_abs_bits(const double* X, int64_t outer, int64_t red, int6
                                int64_t ostride, const int32_t* rscale, int rsign) {
   if (outer <= 0 || red <= 0) return hipSuccess;
   if (plen > 0 && ostride < outer) return hipErrorInvalidValue;
-  const int64_t step = so == 1 ? 256 : 4096;
+  // Rows of r per block: for consecutive o (so == 1) each thread walks its
+  // chunk of r alone, so small matrices get short chunks (down to 16) until
+  // the grid has about 2048 blocks; one wave per o walks 4096 per block.
+  int64_t step = 4096;
+  if (so == 1) {
+    const int64_t bx = (outer + 255) / 256;
+    step = 256;
+    while (step > 16 && bx * ((red + step - 1) / step) < 2048) step /= 2;
+  }
   int64_t chunk = plen > 0 ? plen : step;
   int64_t gy = (red + chunk - 1) / chunk;
   if (plen <= 0) {
