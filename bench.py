@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--slices-only", action="store_true",
                     help="time only the narrow-slice variant at 4096^3 (for profiling it); "
                          "not the headline workload")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the 512 uneven batched GEMMs (for profiling them); not the headline workload")
     ap.add_argument("--fp64x3-only", action="store_true",
                     help="time only the FP64x3 GEMM at 4096^3 (for profiling it); not the headline workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -427,6 +429,9 @@ def main():
         if not args.no_cpu_baseline:
             slices_accuracy(sres, samples, IJ)
         print(json.dumps({"slices": sres}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": bench_batched(torch, dg, torch.cuda.current_stream())}), flush=True)
         return
     if args.fp64x3_only:
         tres = bench_td(torch, dg, torch.cuda.current_stream(), reps=max(1, args.steps))
