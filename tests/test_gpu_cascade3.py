@@ -92,6 +92,9 @@ def test_td_integer_matrices_exact_and_transposes():
     Bt = tuple(np.asfortranarray(x.T) for x in P["B"])
     G1 = run_td(At, Bt, P["C"], transa=True, transb=True)
     assert all(np.array_equal(G0[w], G1[w]) for w in range(3))
+    G2 = run_td(At, P["B"], P["C"], transa=True)
+    G3 = run_td(P["A"], Bt, P["C"], transb=True)
+    assert all(np.array_equal(G0[w], G2[w]) and np.array_equal(G0[w], G3[w]) for w in range(3))
 
 
 def test_td_k_zero_leaves_C():
