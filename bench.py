@@ -215,9 +215,10 @@ ACCURACY_WORKLOADS = ("uniform", "wide", "ill-1e-9", "ill-1e-14", "ill-1e-19")
 ACCURACY_SIZES = (128, 256, 257, 384)   # ill-conditioned, t = 1e-14, kc = 256
 
 
-def _accuracy_case(torch, dg, name, n):
-    """Cascade and FP64x2 comparator on the GPU for one accuracy workload,
-    every entry's relative error against the exact product."""
+def _accuracy_case(torch, dg, name, n, slices=False):
+    """Cascade and FP64x2 comparator (and, with `slices`, the INT8 slices
+    variant) on the GPU for one accuracy workload, every entry's relative
+    error against the exact product."""
     from oracle.illcond import ill_conditioned
     from oracle.ref import exact_entries
     from paper_2303_04353_amd.inputs import make_problem
@@ -227,7 +228,10 @@ def _accuracy_case(torch, dg, name, n):
     I, J = I.ravel(), J.ravel()
     dev = [dg.colmajor_to_device(x) for x in (*P["A"], *P["B"])]
     rel, case = {}, {}
-    for label, algo in (("cascade", dg.DD_ALGO_CASCADE_F64), ("fp64x2", dg.DD_ALGO_DD_VALU)):
+    algos = [("cascade", dg.DD_ALGO_CASCADE_F64), ("fp64x2", dg.DD_ALGO_DD_VALU)]
+    if slices:
+        algos.append(("slices_i8", dg.DD_ALGO_SLICES_I8))
+    for label, algo in algos:
         Ch, Cl = dg.colmajor_to_device(P["C"][0]), dg.colmajor_to_device(P["C"][1])
         opts = {"algo": algo}
         flags = None
@@ -249,14 +253,14 @@ def _accuracy_case(torch, dg, name, n):
 def accuracy_workloads(torch, dg, n=240):
     """The paper's element-wise accuracy study (Sec. 5.2) at n = 240: uniform,
     wide-range and ill-conditioned (t = 1e-9, 1e-14, 1e-19) inputs, the
-    cascade and the FP64x2 comparator kernel on the GPU, every entry's
+    cascade, the FP64x2 comparator kernel and the INT8 slices on the GPU, every entry's
     relative error against the exact product; then the largest error by
     problem size around kc = 256, where the cascade starts to accumulate
     several rank-kc blocks in FP64x2 (CPU-baseline leg: the exact reference
     and the generators are test infrastructure)."""
     out = {"n": n, "reference": "exact (expansion arithmetic)", "cases": {}, "by_size_ill_1e-14": {}}
     for name in ACCURACY_WORKLOADS:
-        rel, case = _accuracy_case(torch, dg, name, n)
+        rel, case = _accuracy_case(torch, dg, name, n, slices=True)
         ratio = np.sort(rel["fp64x2"] / np.maximum(rel["cascade"], 1e-300))
         case["frac_cascade_at_least_as_accurate"] = round(float(np.mean(rel["cascade"] <= rel["fp64x2"])), 4)
         case["ratio_fp64x2_over_cascade_quantiles"] = {
