@@ -4,12 +4,17 @@
   reference of Sec. 5.2); also timed as the CPU baseline.
 * ``cascade``: the cascade itself (Sec. 3.2-3.4, 3.6, Appendix A) in numpy,
   step by step, for bit-level checks of the split and the exact bins.
-* ``slices``: the narrow-slice (BF16/FP16) variant written out the same way.
+* ``slices``: the narrow-slice (BF16/FP16/INT8) variant written out the same way.
+* ``cascade3``: the FP64x3 cascade (six digits, triple-word results).
+* ``illcond``: the ill-conditioned generator of the accuracy study.
 
 Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The product path never does.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against exact rational arithmetic, closed forms, invariants or the paper's
-worked example; none is "parity unpinned".
+worked example.  What no pin can fix is listed as "parity unpinned" where it
+occurs: the rounding of the cascade's bin 3-6 sum (its order is free; only a
+bound holds), and the FP64x3 device's triple-word summation, which is held
+to the exact rounding of ``cascade3.td_round`` within a bound.
 """

@@ -20,19 +20,18 @@ digits instead of four:
    A_t' = 2^-D_(t-1) D_t.
 4. Products per rank-kc block: bins L = 0..4 are sum_(i+j=L) A_i' B_j'
    (exact); the tail bin is sum_i A_i' U_(5-i)' with the suffix sums
-   U_t' = B_t' + ... + B_5' of B's planes (each addition rounded once, from
-   the last plane up; U_0' is the scaled value itself, rounded once) --
-   the analogue of B4', B5', B6' (Sec. 3.4).
-5. The six bins, least significant first, are turned into a triple word by
-   a fixed error-free summation (``td_from_terms``), the rank-kc results
-   accumulated the same way, Sigma and T applied (exact), C added last.
+   U_t' = B_t' + U_(t+1)' of B's planes (U_5' = B_5', each addition
+   rounded once, from the last plane up to U_0') -- the analogue of B4',
+   B5', B6' (Sec. 3.4).
+5. The six bins are summed exactly and rounded to a triple word
+   (``td_round``), the rank-kc results accumulated the same way (the exact
+   sum of the two triple words, rounded), Sigma and T applied (exact), C
+   added last.
 
-``td_from_terms`` (the triple-word arithmetic of the oracle and the device
-path alike): three passes of VecSum (Ogita, Rump and Oishi: a chain of
-TwoSums that keeps the sum exact and moves it to the last element), the
-last element taken as the first word; two more passes over the rest for
-the second word; the third word the plain sum of what remains; then one
-renormalising TwoSum chain.
+``td_round`` is the plain definition of triple-word rounding: the exact
+sum S of the terms (rational arithmetic), w0 = RN(S), w1 = RN(S - w0),
+w2 = RN(S - w0 - w1).  It stands for any faithful triple-word summation:
+the device's error-free sequence of TwoSums is held to it within a bound.
 
 Readings where the paper is silent are listed in the design notes (FP64x3
 section).
@@ -41,6 +40,7 @@ from __future__ import annotations
 
 import functools
 import math
+from fractions import Fraction
 
 import numpy as np
 
@@ -121,50 +121,81 @@ def split3(words, e, axis, c):
     return [Dl[t] * weights[t] for t in range(6)], scaled
 
 
-def suffix_planes(Bp, scaled):
-    """U_t' = B_t' + ... + B_5' (t = 1..5, rounded once per addition from the
-    last plane up) and U_0' = the scaled value, rounded once."""
+def suffix_planes(Bp):
+    """U_5' = B_5' and U_t' = B_t' + U_(t+1)' for t = 4 .. 0, each addition
+    rounded once (from the last plane up)."""
     U = [None] * 6
     U[5] = Bp[5]
-    for t in range(4, 0, -1):
+    for t in range(4, -1, -1):
         U[t] = Bp[t] + U[t + 1]
-    U[0] = (scaled[0] + scaled[1]) + scaled[2]
     return U
 
 
-def vec_sum(a):
-    """One VecSum pass over the list a (in place semantics, returns a new
-    list): a[i], a[i-1] <- TwoSum(a[i], a[i-1]) for i = 1..n-1."""
-    a = list(a)
-    for i in range(1, len(a)):
-        a[i], a[i - 1] = two_sum(a[i], a[i - 1])
-    return a
+def _rn_scaled(num: int, exp: int) -> float:
+    """RN(num * 2^exp) for an integer num.  float(num) is the correctly
+    rounded (to nearest, ties to even) conversion; scaling by 2^exp is exact
+    unless the result leaves the normal range, where the rational value is
+    rounded directly instead."""
+    if num == 0:
+        return 0.0
+    if abs(num).bit_length() > 1000:
+        return float(Fraction(num) * Fraction(2) ** exp)
+    try:
+        w = math.ldexp(float(num), exp)
+    except OverflowError:
+        w = math.inf
+    if abs(w) < 2.0 ** -1021 or math.isinf(w):
+        return float(Fraction(num) * Fraction(2) ** exp)
+    return w
 
 
-def td_from_terms(terms):
-    """The triple word nearest (as step 5 computes it) to the exact sum of
-    ``terms`` (arrays, least significant first)."""
-    a = list(terms)
+def _round3(num: int, exp: int):
+    """(w0, w1, w2) with w0 = RN(S), w1 = RN(S - w0), w2 = RN(S - w0 - w1)
+    for S = num * 2^exp."""
+    out = []
     for _ in range(3):
-        a = vec_sum(a)
-    r0 = a[-1]
-    rest = a[:-1]
-    for _ in range(2):
-        rest = vec_sum(rest)
-    r1 = rest[-1] if rest else np.zeros_like(r0)
-    tail = rest[:-1]
-    r2 = tail[0] if tail else np.zeros_like(r0)
-    for x in tail[1:]:
-        r2 = r2 + x
-    r1, r2 = two_sum(r1, r2)
-    r0, r1 = two_sum(r0, r1)
-    r1, r2 = two_sum(r1, r2)
-    return r0, r1, r2
+        w = _rn_scaled(num, exp)
+        out.append(w)
+        if w != 0.0:
+            mant, ex = math.frexp(w)                 # w = mant 2^ex, a multiple of 2^exp
+            sh = ex - 53 - exp
+            wi = int(math.ldexp(mant, 53))
+            num -= wi << sh if sh >= 0 else wi >> -sh
+    return tuple(out)
+
+
+def td_round(terms):
+    """The exact sum of ``terms`` (arrays of one shape) rounded to a triple
+    word, entry by entry.  Every double is an integer times 2^-1074, so the
+    sum is taken exactly as an integer over the smallest exponent present.
+    An entry with a non-finite term gives NaN words."""
+    arrs = [np.asarray(t, dtype=np.float64) for t in terms]
+    shape = arrs[0].shape
+    flat = [a.reshape(-1) for a in arrs]
+    out = np.empty((3, flat[0].size))
+    for q in range(flat[0].size):
+        vals = [float(a[q]) for a in flat]
+        if not all(math.isfinite(v) for v in vals):
+            out[:, q] = np.nan
+            continue
+        parts = []
+        for v in vals:
+            if v != 0.0:
+                mant, ex = math.frexp(v)                 # v = mant 2^ex, 0.5 <= |mant| < 1
+                parts.append((int(math.ldexp(mant, 53)), ex - 53))
+        if not parts:
+            out[:, q] = 0.0
+            continue
+        e0 = min(ex for _, ex in parts)
+        num = sum(mant << (ex - e0) for mant, ex in parts)
+        out[:, q] = _round3(num, e0)
+    return tuple(out[w].reshape(shape) for w in range(3))
 
 
 def td_add(x, y):
-    """x + y for triple words x = (x0, x1, x2), y likewise."""
-    return td_from_terms([x[2], y[2], x[1], y[1], x[0], y[0]])
+    """x + y for triple words x = (x0, x1, x2), y likewise: the exact sum
+    rounded to a triple word."""
+    return td_round([x[0], x[1], x[2], y[0], y[1], y[2]])
 
 
 def bins3_block(Ap, Bp, U, p0, p1):
@@ -199,14 +230,14 @@ def cascade3_gemm(A, B, C=None, *, kc=256, return_parts=False):
     e = exponents(A[0], axis=1)
     f = exponents(B[0], axis=0)
     Ap, _ = split3(A, e, 1, c)
-    Bp, ys = split3(B, f, 0, c)
-    U = suffix_planes(Bp, ys)
+    Bp, _ = split3(B, f, 0, c)
+    U = suffix_planes(Bp)
     acc = (np.zeros((m, n)), np.zeros((m, n)), np.zeros((m, n)))
     blocks = []
     for p0 in range(0, k, kce):
         p1 = min(k, p0 + kce)
         bins = bins3_block(Ap, Bp, U, p0, p1)
-        blk = td_from_terms([bins[5], bins[4], bins[3], bins[2], bins[1], bins[0]])
+        blk = td_round(bins)
         acc = td_add(acc, blk)
         if return_parts:
             blocks.append(bins)

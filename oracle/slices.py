@@ -61,7 +61,12 @@ from .cascade import dd_add, dd_add_d, two_sum
 # 2^8 (BF16, 8 significant bits), 2^11 (FP16), 127 (INT8)
 FORMAT_MAX = {"bf16": 2 ** 8, "f16": 2 ** 11, "i8": 127}
 FORMAT_BITS = {"bf16": 8, "f16": 11}  # significant bits of the floating-point formats
-GROUP = 3                              # levels per FP64 group
+# Levels per FP64 group: three is the most for which a group stays an exact
+# FP64 integer at the default widths over inner dimensions of interest.  A
+# group of g levels at w = 8, s = 14 is exact for k s 2^14 2^(8(g-1)) below
+# about 2^53: some 596,000 inner indices for g = 3, but only about 2,300 for
+# g = 4 (a 4096-deep product would then need two chunks).
+GROUP = 3
 
 
 # ---------------------------------------------------------------- parameters
@@ -94,15 +99,16 @@ def flush_depths(w: int, s: int):
 
 
 def chunk_limit(w: int, s: int, fmt: str = "bf16"):
-    """Largest inner-dimension chunk for which every level group sum stays an
-    exact FP64 integer (a multiple of 64); for INT8 also every level sum an
-    INT32 (|sum| <= 2^31 - 1; a multiple of 128)."""
+    """Largest number of inner indices per chunk allowed by the exactness
+    bounds alone: every level group sum an exact FP64 integer,
+    k s 2^(2w-2) (2^2w + 2^w + 1) <= 2^53, and for INT8 also every level sum
+    an INT32, k s 2^(2w-2) <= 2^31 - 1.  Chunk c covers inner indices
+    [c * limit, (c + 1) * limit)."""
     per = s * 2 ** (2 * w - 2) * (2 ** (2 * w) + 2 ** w + 1)
     lim = 2 ** 53 // per
     if fmt == "i8":
         lim = min(lim, (2 ** 31 - 1) // (s * 2 ** (2 * w - 2)))
-        return lim // 128 * 128
-    return lim // 64 * 64
+    return lim
 
 
 def n_products(s: int) -> int:

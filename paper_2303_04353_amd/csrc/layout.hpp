@@ -148,13 +148,17 @@ constexpr int kSliceBF16 = 0, kSliceF16 = 1, kSliceI8 = 2;
 // (l/32)*E .. (l/32)*E + E-1 (E = 8 two-byte or 16 one-byte values):
 //   pack[rb*slices_block_stride(Q, S) + (q*S + t)*64 + l]   (in 16-byte units,
 // blocks padded like the cascade's planes)
-// Rows/columns are padded with zeros to the 64 x 64 workgroup tile and the
-// inner dimension to whole blocks of four steps (64 or 128 indices).
+// Rows/columns are padded with zeros to the 64 x 64 workgroup tile.  The
+// inner dimension is cut into chunks of `chunk` indices (one product pass
+// each); every chunk starts a new step and is padded with zeros to whole
+// blocks of four steps (64 or 128 indices), so packed inner index
+// c * chunk_q * kstep + r holds source index c * chunk + r.
 struct SlicesLayout {
   int64_t m, n, k;
   int64_t mpad, npad, kpad, Q;  // Q = kpad / kstep steps
   int32_t S, w, fmt, kstep;     // slice count, width, format, inner indices per step
-  int32_t chunk_q;              // steps per inner-dimension chunk (sums exact), a multiple of 4
+  int64_t chunk;                // inner indices per chunk (every group sum exact), min(limit, k)
+  int64_t chunk_q;              // packed steps per whole chunk: chunk padded to a multiple of 4 steps
   int32_t flush_mask[16];       // BF16/FP16: level L may go flush_mask[L] + 1 steps between flushes
   size_t off_amax, off_bmax, off_apack, off_bpack, off_planes, bytes;
 };
@@ -165,17 +169,19 @@ constexpr int kSlicesSplit = 9;
 
 // Largest chunk of the inner dimension keeping every FP64 level-group sum an
 // exact integer, k s 2^(2w-2) (2^2w + 2^w + 1) <= 2^53, and for INT8 every
-// level sum an INT32, k s 2^(2w-2) <= 2^31 - 1; a multiple of four steps.
+// level sum an INT32, k s 2^(2w-2) <= 2^31 - 1 (the exactness bounds alone;
+// chunk c covers inner indices [c limit, (c + 1) limit)).  Integer division
+// of 2^53 by the exact integer factor, so the limit is exact.
 inline int64_t slices_chunk_limit(int w, int S, int fmt) {
-  const double per = (double)S * __builtin_ldexp(1.0, 2 * w - 2) *
-                     (__builtin_ldexp(1.0, 2 * w) + __builtin_ldexp(1.0, w) + 1.0);
-  int64_t lim = (int64_t)(__builtin_ldexp(1.0, 53) / per);
+  const unsigned __int128 per = (unsigned __int128)S * ((unsigned __int128)1 << (2 * w - 2)) *
+                                (((unsigned __int128)1 << (2 * w)) + ((unsigned __int128)1 << w) + 1);
+  const unsigned __int128 lim = ((unsigned __int128)1 << 53) / per;
+  int64_t out = lim > (unsigned __int128)INT64_MAX ? INT64_MAX : (int64_t)lim;
   if (fmt == kSliceI8) {
     const int64_t l32 = ((int64_t(1) << 31) - 1) / ((int64_t)S << (2 * w - 2));
-    lim = lim < l32 ? lim : l32;
-    return lim / 128 * 128;
+    out = out < l32 ? out : l32;
   }
-  return lim / 64 * 64;
+  return out;
 }
 
 // (w, S) usable in the format: slices (|a| <= 2^(w-1)) exact in it, and for
@@ -201,9 +207,14 @@ inline SlicesLayout make_slices_layout(int64_t m, int64_t n, int64_t k, int S, i
   L.kstep = fmt == kSliceI8 ? 32 : 16;
   L.mpad = round_up(m > 0 ? m : 1, 64);
   L.npad = round_up(n > 0 ? n : 1, 64);
-  L.kpad = round_up(k > 0 ? k : 1, 4 * L.kstep);
-  L.Q = L.kpad / L.kstep;
-  L.chunk_q = (int32_t)(slices_chunk_limit(w, S, fmt) / L.kstep);
+  const int64_t kk = k > 0 ? k : 1;
+  const int64_t lim = slices_chunk_limit(w, S, fmt);
+  L.chunk = lim < kk ? lim : kk;
+  L.chunk_q = round_up(L.chunk, 4 * L.kstep) / L.kstep;
+  const int64_t nchunk = (kk + L.chunk - 1) / L.chunk;
+  const int64_t last = kk - (nchunk - 1) * L.chunk;   // indices of the last chunk
+  L.Q = (nchunk - 1) * L.chunk_q + round_up(last, 4 * L.kstep) / L.kstep;
+  L.kpad = L.Q * L.kstep;
   for (int lv = 0; lv < 16; ++lv) {
     // largest power-of-two number of steps with 16 * steps * (lv+1) * 2^(2w-2) <= 2^24
     int64_t steps = 1;

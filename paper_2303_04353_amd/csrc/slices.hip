@@ -83,19 +83,24 @@ __device__ __forceinline__ uint32_t slice_bits(double a) {
   }
 }
 
-// One thread per (outer index o, group rg of kPerLane inner indices): the
-// entries X(o, rg * kPerLane + e) = X[o*so + r*sr] are split and written as
-// one 16-byte chunk per slice.
+// One thread per (outer index o, group rg of kPerLane packed inner indices):
+// packed index rg * kPerLane + e lies in chunk c at offset r (chunks are
+// cpk = chunk_q * kstep packed indices apart), so it holds the entry
+// X(o, c * chunk + r) = X[o*so + (c*chunk + r)*sr], or zero past the end of
+// the chunk or of the inner dimension.  The entries are split and written
+// as one 16-byte piece per slice.
 template <int FMT>
 __global__ void __launch_bounds__(256)
 slices_split(const double* __restrict__ Xhi, const double* __restrict__ Xlo, int64_t so, int64_t sr,
-             int64_t outer, int64_t red, int64_t opad, int64_t Q, int S, int w,
+             int64_t outer, int64_t red, int64_t opad, int64_t Q, int S, int w, int64_t chunk, int64_t cpk,
              const uint64_t* __restrict__ maxbits, u32x4* __restrict__ pack) {
   constexpr int E = kPerLane<FMT>;
   constexpr int PER_WORD = FMT == kI8 ? 4 : 2;     // values per 32-bit word
   const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (u >= opad * Q * 2) return;
   const int64_t o = u % opad, rg = u / opad;
+  // the kPerLane values of a thread share one step, hence one chunk
+  const int64_t ch = (rg * E) / cpk, off0 = rg * E - ch * cpk;
   const int ex = o < outer ? exp_of_bits(maxbits[o]) : 0;
   uint32_t words[16][4];
 #pragma unroll
@@ -104,9 +109,9 @@ slices_split(const double* __restrict__ Xhi, const double* __restrict__ Xlo, int
     for (int h = 0; h < 4; ++h) words[t][h] = 0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int64_t r = rg * E + e;
+    const int64_t off = off0 + e, r = ch * chunk + off;
     double xh = 0.0, xl = 0.0;
-    if (o < outer && r < red) {
+    if (o < outer && off < chunk && r < red) {
       xh = __builtin_ldexp(Xhi[o * so + r * sr], -ex);
       xl = __builtin_ldexp(Xlo[o * so + r * sr], -ex);
     }
@@ -464,28 +469,30 @@ hipError_t launch_passes(const SlicesLayout& L, const ProductArgs& a, int64_t bl
 
 // Diagnostic copy of packed slices into plain column-major 16-bit planes:
 // element (o, r) of slice t goes to out[t*plane + o*oo + r*ro] (INT8 slices
-// sign-extended to 16 bits).
+// sign-extended to 16 bits).  Source index r sits at packed index
+// (r / chunk) * cpk + r % chunk.
 template <int FMT>
 __global__ void __launch_bounds__(256)
 slices_unpack(const uint8_t* __restrict__ pack, int64_t outer, int64_t red, int64_t Q, int S,
-              int64_t oo, int64_t ro, uint16_t* __restrict__ out) {
+              int64_t chunk, int64_t cpk, int64_t oo, int64_t ro, uint16_t* __restrict__ out) {
   constexpr int E = kPerLane<FMT>;
   const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t plane = outer * red;
   if (u >= plane * S) return;
   const int t = (int)(u / plane);
   const int64_t rest = u - (int64_t)t * plane;
-  const int64_t o = rest % outer, r = rest / outer;
+  const int64_t o = rest % outer, rs = rest / outer;
+  const int64_t r = (rs / chunk) * cpk + rs % chunk;
   const int64_t rb = o / 32, q = r / (2 * E);
   const int lane = (int)(o % 32) + 32 * (int)((r % (2 * E)) / E);
-  const int64_t chunk = (rb * slices_block_stride(Q, S) + (q * S + t) * 64 + lane) * 16;   // byte offset of the lane's chunk
+  const int64_t at = (rb * slices_block_stride(Q, S) + (q * S + t) * 64 + lane) * 16;   // byte offset of the lane's piece
   uint16_t v;
   if constexpr (FMT == kI8) {
-    v = (uint16_t)(int16_t)(int8_t)pack[chunk + (r % E)];
+    v = (uint16_t)(int16_t)(int8_t)pack[at + (r % E)];
   } else {
-    v = ((const uint16_t*)(pack + chunk))[r % E];
+    v = ((const uint16_t*)(pack + at))[r % E];
   }
-  out[t * plane + o * oo + r * ro] = v;
+  out[t * plane + o * oo + rs * ro] = v;
 }
 
 }  // namespace
@@ -495,15 +502,16 @@ hipError_t launch_slices_split(const double* Xhi, const double* Xlo, int64_t so,
                                void* pack, hipStream_t s) {
   const int64_t units = opad * L.Q * 2;
   const unsigned blocks = (unsigned)((units + 255) / 256);
+  const int64_t cpk = L.chunk_q * L.kstep;
   if (L.fmt == kI8) {
-    slices_split<kI8><<<blocks, 256, 0, s>>>(Xhi, Xlo, so, sr, outer, red, opad, L.Q, L.S, L.w, maxbits,
-                                             (u32x4*)pack);
+    slices_split<kI8><<<blocks, 256, 0, s>>>(Xhi, Xlo, so, sr, outer, red, opad, L.Q, L.S, L.w, L.chunk, cpk,
+                                             maxbits, (u32x4*)pack);
   } else if (L.fmt == kF16) {
-    slices_split<kF16><<<blocks, 256, 0, s>>>(Xhi, Xlo, so, sr, outer, red, opad, L.Q, L.S, L.w, maxbits,
-                                              (u32x4*)pack);
+    slices_split<kF16><<<blocks, 256, 0, s>>>(Xhi, Xlo, so, sr, outer, red, opad, L.Q, L.S, L.w, L.chunk, cpk,
+                                              maxbits, (u32x4*)pack);
   } else {
-    slices_split<kBF16><<<blocks, 256, 0, s>>>(Xhi, Xlo, so, sr, outer, red, opad, L.Q, L.S, L.w, maxbits,
-                                               (u32x4*)pack);
+    slices_split<kBF16><<<blocks, 256, 0, s>>>(Xhi, Xlo, so, sr, outer, red, opad, L.Q, L.S, L.w, L.chunk, cpk,
+                                               maxbits, (u32x4*)pack);
   }
   return hipGetLastError();
 }
@@ -512,10 +520,13 @@ hipError_t launch_slices_unpack(const void* pack, int64_t outer, int64_t red, co
                                 int64_t oo, int64_t ro, uint16_t* out, hipStream_t s) {
   const int64_t units = outer * red * L.S;
   const unsigned blocks = (unsigned)((units + 255) / 256);
+  const int64_t cpk = L.chunk_q * L.kstep;
   if (L.fmt == kI8) {
-    slices_unpack<kI8><<<blocks, 256, 0, s>>>((const uint8_t*)pack, outer, red, L.Q, L.S, oo, ro, out);
+    slices_unpack<kI8><<<blocks, 256, 0, s>>>((const uint8_t*)pack, outer, red, L.Q, L.S, L.chunk, cpk, oo, ro,
+                                              out);
   } else {
-    slices_unpack<kBF16><<<blocks, 256, 0, s>>>((const uint8_t*)pack, outer, red, L.Q, L.S, oo, ro, out);
+    slices_unpack<kBF16><<<blocks, 256, 0, s>>>((const uint8_t*)pack, outer, red, L.Q, L.S, L.chunk, cpk, oo, ro,
+                                                out);
   }
   return hipGetLastError();
 }

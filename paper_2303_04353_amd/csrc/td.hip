@@ -16,7 +16,7 @@
 // [U_0'; ...; U_5'].  Bins 0..4 stay exact in any summation order: the
 // widths rule bounds the sum of the magnitudes of all their products.
 //
-// Steps (the same as the test oracle's):
+// Steps:
 //  * widths c0..c4 for a rank-kc block: the largest (in total, then in
 //    order) for which bins 0..4 are exact with digits of up to 3 level units
 //    (three words each contribute at most one);
@@ -25,12 +25,14 @@
 //    remainder, digits added level by level, remainders rounded in order;
 //    planes pre-weighted by 2^-D_(t-1);
 //  * bins L = 0..4: sum over i + j = L of A_i' B_j' (exact); tail bin: sum
-//    over i of A_i' U_(5-i)', U the suffix sums of B's planes (U_0' the
-//    scaled value rounded once);
-//  * triple words from bins, accumulator and C by a fixed error-free
-//    summation: three VecSum passes, the last element the first word, two
-//    more passes for the second, the plain sum of the rest the third, one
-//    renormalising TwoSum chain.
+//    over i of A_i' U_(5-i)', U the suffix sums of B's planes (each
+//    addition rounded once, from the last plane up to U_0');
+//  * triple words from bins, accumulator and C by a fixed sequence of
+//    error-free transforms: three VecSum passes (Ogita, Rump and Oishi), the
+//    last element the first word, two more passes for the second, the plain
+//    sum of the rest the third, one renormalising TwoSum chain.  It is a
+//    faithful stand-in for rounding the exact sum to three words (a few
+//    units of 2^-158 relative, plus 2^-200 of the terms' magnitudes).
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <stdint.h>
@@ -111,8 +113,8 @@ td_split_a(const double* __restrict__ X0, const double* __restrict__ X1, const d
 }
 
 // op(B) entries (p, j) into the ascending digit panels of their block and
-// the suffix sums U_t' = B_t' + U_(t+1)' (from the last plane up; U_0' the
-// scaled value (y0 + y1) + y2) into the U panels, which start at `upanels`.
+// the suffix sums U_5' = B_5', U_t' = B_t' + U_(t+1)' (from the last plane
+// up to U_0') into the U panels, which start at `upanels`.
 __global__ void __launch_bounds__(256)
 td_split_b(const double* __restrict__ X0, const double* __restrict__ X1, const double* __restrict__ X2,
            int64_t sp, int64_t sj, int64_t k, int64_t n, int64_t kc, const uint64_t* __restrict__ bmax, Widths3 W,
@@ -131,11 +133,10 @@ td_split_b(const double* __restrict__ X0, const double* __restrict__ X1, const d
   double u = out[5];
   ub[5 * q.kb] = u;
 #pragma unroll
-  for (int l = 4; l >= 1; --l) {
+  for (int l = 4; l >= 0; --l) {
     u = out[l] + u;
     ub[l * q.kb] = u;
   }
-  ub[0] = (ys[0] + ys[1]) + ys[2];
 }
 
 __device__ __forceinline__ void vec_sum6(double a[6]) {

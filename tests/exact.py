@@ -51,3 +51,41 @@ def abs_gemm(A, B):
                 s += a[i, p] * b[p, j]
             out[i, j] = s
     return out
+
+
+# ---- IEEE binary64 operations defined by rounding the exact rational result
+def rn(x: Fraction) -> float:
+    """Round a rational to the nearest double, ties to even (CPython's
+    int / int true division is correctly rounded)."""
+    return float(x)
+
+
+def add_rn(a: float, b: float) -> float:
+    return rn(Fraction(a) + Fraction(b))
+
+
+def sub_rn(a: float, b: float) -> float:
+    return rn(Fraction(a) - Fraction(b))
+
+
+def two_sum_exact(a: float, b: float):
+    """The error-free sum by its definition: s = RN(a + b) and the exact
+    remainder a + b - s (a double whenever no overflow occurs)."""
+    s = add_rn(a, b)
+    e = Fraction(a) + Fraction(b) - Fraction(s)
+    assert rn(e) == e
+    return s, rn(e)
+
+
+def quick_two_sum_ops(a: float, b: float):
+    """Dekker's fast two-sum as its three rounded operations:
+    s = RN(a + b), e = RN(b - RN(s - a))."""
+    s = add_rn(a, b)
+    return s, sub_rn(b, sub_rn(s, a))
+
+
+def dd_add_d_ops(h: float, l: float, y: float):
+    """FP64x2 (h, l) plus an FP64 y: error-free sum of the high parts, the
+    low part added with one rounding, then a fast two-sum."""
+    s, e = two_sum_exact(h, y)
+    return quick_two_sum_ops(s, add_rn(e, l))

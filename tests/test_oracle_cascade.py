@@ -4,8 +4,10 @@ Against: the split widths printed in Sec. 3.3; exact rounding to the digit
 grid (Appendix A) computed with rationals; exact reconstruction and the
 conversion bound (eq. error_scalar); exactness of bins 0-2 (Sec. 3.3-3.4)
 against integer arithmetic, including worst-case digits; the worked example of
-Sec. 3.6; integer matrices; the forward bound eq. (cascerr) against exact
-results; row/column power-of-two invariance; identity.
+Sec. 3.6; the order of the bin sum (least significant bin first, Sec. 3.3
+and Sec. 3.6) on bins where the two orders round differently; integer
+matrices; the forward bound eq. (cascerr) against exact results;
+row/column power-of-two invariance; identity.
 """
 import json
 import os
@@ -17,7 +19,7 @@ import pytest
 from oracle import cascade as cz
 from oracle.ref import dd_gemm_ref
 from paper_2303_04353_amd.inputs import make_problem
-from tests.exact import abs_gemm, dd_value, exact_gemm
+from tests.exact import abs_gemm, dd_add_d_ops, dd_value, exact_gemm, two_sum_exact
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 U2 = 2.0 ** -106
@@ -509,3 +511,113 @@ def test_balancing_with_zero_and_non_finite_slices():
     A[0][2, 5] = np.inf
     hi, lo = cz.cascade_gemm(A, P["B"], P["C"], kc=16, balance=True)
     assert np.all(np.isnan(hi[2, :])) and np.all(np.isfinite(np.delete(hi, 2, axis=0)))
+
+
+def _bins_lsf_model(b0, b1, b2, b36):
+    """bin0 + (bin1 + (bin2 + bin36)) with every operation taken as the
+    rounding of its exact rational result (Sec. 3.6's expression for
+    fl_casc; the bins are summed least significant first)."""
+    h, l = two_sum_exact(b2, b36)
+    h, l = dd_add_d_ops(h, l, b1)
+    return dd_add_d_ops(h, l, b0)
+
+
+def _bins_msf_model(b0, b1, b2, b36):
+    """The reversed order, bin 0 first: what a wrong order would give."""
+    h, l = two_sum_exact(b0, b1)
+    h, l = dd_add_d_ops(h, l, b2)
+    return dd_add_d_ops(h, l, b36)
+
+
+def test_bin_sum_adds_the_least_significant_bin_first():
+    """Sec. 3.3 and Sec. 3.6 add the bins from the least significant one up.
+    Bins 1, 2^-53, 2^-106, 2^-106: adding bin 0 first rounds 1 + 2^-53 to
+    the even 1 and keeps 2^-53 as the low word, which then swallows each
+    2^-106 (a tie again).  Added from the bottom, 2^-106 + 2^-106 = 2^-105
+    survives, lifts 1 + 2^-53 above the tie, and the pair holds the exact
+    sum 1 + 2^-53 + 2^-105."""
+    arr = lambda *v: [np.array([x]) for x in v]
+    b = (1.0, 2.0 ** -53, 2.0 ** -106, 2.0 ** -106)
+    h, l = cz.combine_bins(*arr(*b))
+    exact = Fraction(1) + Fraction(2) ** -53 + Fraction(2) ** -105
+    assert Fraction(float(h[0])) + Fraction(float(l[0])) == exact
+    assert (float(h[0]), float(l[0])) == (1.0 + 2.0 ** -52, -2.0 ** -53 + 2.0 ** -105)
+    rh, rl = _bins_msf_model(*b)
+    assert Fraction(rh) + Fraction(rl) == 1 + Fraction(2) ** -53      # the other order loses 2^-105
+    # with total cancellation of the leading bins the least-significant-first
+    # order loses the smallest bin instead: bins 1, -1, 2^-60, 2^-120 give
+    # 2^-60 exactly (bin2 + bin36 = 2^-60 + 2^-120 is kept as a pair, adding
+    # -1 moves 2^-60 to the low word, where 2^-120 rounds away)
+    h, l = cz.combine_bins(*arr(1.0, -1.0, 2.0 ** -60, 2.0 ** -120))
+    assert (float(h[0]), float(l[0])) == (2.0 ** -60, 0.0)
+    assert _bins_msf_model(1.0, -1.0, 2.0 ** -60, 2.0 ** -120) == (2.0 ** -60, 2.0 ** -120)
+    # bin 2 before bin 1: bins 1, -1, 2^-54, 3 2^-107.  bin2 + bin36 rounds
+    # (a tie) to 2^-54 + 2^-105 and keeps -2^-107; adding -1 and 1 then
+    # leaves the pair exact: 2^-54 + 3 2^-107.  Taking bin 1 with bin 3-6
+    # first loses the -2^-107 when 1 and -1 meet.
+    b = (1.0, -1.0, 2.0 ** -54, 3 * 2.0 ** -107)
+    h, l = cz.combine_bins(*arr(*b))
+    exact = Fraction(2) ** -54 + 3 * Fraction(2) ** -107
+    assert Fraction(float(h[0])) + Fraction(float(l[0])) == exact
+    hs, ls = two_sum_exact(b[1], b[3])
+    hs, ls = dd_add_d_ops(hs, ls, b[2])
+    hs, ls = dd_add_d_ops(hs, ls, b[0])
+    assert Fraction(hs) + Fraction(ls) != exact
+
+
+def test_fp64x2_addition_keeps_both_low_words():
+    """The accurate FP64x2 addition (used for the rank-kc accumulation and
+    for C) adds the low words with an error-free sum and folds its error in
+    last.  When the high words cancel, that error is the result's low word:
+    (1, 2^-60) + (-1, 3 2^-114) = 2^-60 + 3 2^-114 exactly, held as
+    (2^-60 + 2^-112, -2^-114).  On random pairs with heavy cancellation the
+    relative error stays within 3 2^-106, the published bound of this
+    algorithm (Joldes, Muller and Popescu, 2017: AccurateDWPlusDW)."""
+    h, l = cz.dd_add(np.array([1.0]), np.array([2.0 ** -60]), np.array([-1.0]), np.array([3 * 2.0 ** -114]))
+    assert (float(h[0]), float(l[0])) == (2.0 ** -60 + 2.0 ** -112, -2.0 ** -114)
+    rng = np.random.default_rng(79)
+    n = 20000
+    xh = rng.uniform(-1, 1, n) * np.ldexp(1.0, rng.integers(-20, 20, n))
+    xl = xh * rng.uniform(-1, 1, n) * 2.0 ** -53
+    xh, xl = cz.quick_two_sum(xh, xl)              # canonical pairs
+    # y close to -x: high words cancel to a few bits
+    yh = -xh * (1 + rng.integers(-8, 9, n) * 2.0 ** -52)
+    yl = yh * rng.uniform(-1, 1, n) * 2.0 ** -53
+    yh, yl = cz.quick_two_sum(yh, yl)
+    h, l = cz.dd_add(xh, xl, yh, yl)
+    for t in range(n):
+        exact = Fraction(float(xh[t])) + Fraction(float(xl[t])) + Fraction(float(yh[t])) + Fraction(float(yl[t]))
+        err = abs(Fraction(float(h[t])) + Fraction(float(l[t])) - exact)
+        assert err <= 3 * Fraction(2) ** -106 * abs(exact), t
+
+
+def test_bin_sum_matches_the_rational_model_bit_for_bit():
+    """Random bins with the magnitudes of a rank-kc block (bin L near
+    2^-21 L, bin 3-6 near 2^-64, on the grids of the split), plus planted
+    cancellation and ties: combine_bins equals the operation-by-operation
+    rational model of the least-significant-first order, and on the cases
+    where the reversed order differs it is the first that is returned."""
+    rng = np.random.default_rng(77)
+    nb = 4000
+    b0 = np.ldexp(np.round(rng.uniform(-2 ** 44, 2 ** 44, nb)), -44)
+    b1 = np.ldexp(np.round(rng.uniform(-2 ** 52, 2 ** 52, nb)), -74)
+    b2 = np.ldexp(np.round(rng.uniform(-2 ** 52, 2 ** 52, nb)), -96)
+    b36 = np.ldexp(rng.uniform(-1, 1, nb), -64)
+    b0[::7] = -np.round(b1[::7] * 2 ** 22) * 2.0 ** -22           # bin 0 cancels bin 1's top
+    b1[::5] = 0.0
+    b36[::11] = np.ldexp(np.sign(b0[::11]) * 0.5, -52) * np.abs(b0[::11])   # ties with bin 0's ulp
+    # every third entry: bin 1 exactly half an ulp of bin 0 (a tie), bins 2
+    # and 3-6 each at most half an ulp of bin 1, of random signs
+    q = np.arange(0, nb, 3)
+    u0 = np.spacing(np.abs(b0[q]))
+    b1[q] = np.where(rng.uniform(size=q.size) < 0.5, -0.5, 0.5) * u0
+    u1 = np.spacing(np.abs(b1[q]))
+    b2[q] = np.where(rng.uniform(size=q.size) < 0.5, -0.5, 0.5) * u1 * rng.integers(0, 2, q.size)
+    b36[q] = np.where(rng.uniform(size=q.size) < 0.5, -0.5, 0.5) * u1 * rng.choice([0.5, 1.0, 0.75], q.size)
+    h, l = cz.combine_bins(b0, b1, b2, b36)
+    differ = 0
+    for t in range(nb):
+        want = _bins_lsf_model(float(b0[t]), float(b1[t]), float(b2[t]), float(b36[t]))
+        assert (float(h[t]), float(l[t])) == want, t
+        differ += _bins_msf_model(float(b0[t]), float(b1[t]), float(b2[t]), float(b36[t])) != want
+    assert differ > nb // 20   # the test can tell the two orders apart

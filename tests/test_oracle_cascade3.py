@@ -2,8 +2,10 @@
 
 Against: the exactness rule behind the split widths and their maximality;
 exact reconstruction of every entry from its six digits (rationals); bins
-0..4 equal to exact sums, including worst-case digits; the triple-word sum
-against rationals, with cancellation (also across several levels); results against exact rational
+0..4 equal to exact sums, including worst-case digits; the suffix planes as
+rounded running sums; the triple-word rounding against hand-worked values
+and against rationals, with cancellation (also across several levels);
+results against exact rational
 C + A B within the analogue of eq. (cascerr); integer matrices; power-of-two
 row/column invariance; k = 0.
 """
@@ -77,7 +79,7 @@ def test_bins_0_to_4_are_exact_with_worst_case_digits():
         if same_sign:
             Ap = [np.abs(x) for x in Ap]
             Bp = [np.abs(x) for x in Bp]
-        U = c3.suffix_planes(Bp, [Bp[0], Bp[1], Bp[2]])
+        U = c3.suffix_planes(Bp)
         bins = c3.bins3_block(Ap, Bp, U, 0, kc)
         for L in range(5):
             for i in range(m):
@@ -85,6 +87,44 @@ def test_bins_0_to_4_are_exact_with_worst_case_digits():
                     want = sum(F(float(Ap[a][i, p])) * F(float(Bp[L - a][p, j]))
                                for a in range(L + 1) for p in range(kc))
                     assert F(float(bins[L][i, j])) == want, (L, i, j, same_sign)
+
+
+def _ulp(x):
+    return F(float(np.spacing(abs(x)))) if x != 0 else F(0)
+
+
+def _check_round3(vals, words):
+    """The words are the rounding of the exact sum S: w0 within half an ulp
+    of S, w1 within half an ulp of S - w0, w2 within half an ulp of
+    S - w0 - w1 (each the nearest double to what is left)."""
+    S = sum(F(v) for v in vals)
+    w0, w1, w2 = (float(x) for x in words)
+    for w, rest in ((w0, S), (w1, S - F(w0)), (w2, S - F(w0) - F(w1))):
+        assert abs(F(w) - rest) <= _ulp(w) / 2 or (w == 0.0 and rest == 0), (vals, words)
+    return S
+
+
+def test_triple_word_rounding_closed_forms():
+    """Values whose triple-word rounding is known by hand: non-overlapping
+    powers of two keep their first three, a tie goes to the even neighbour,
+    a complete cancellation leaves the small terms."""
+    one = lambda *v: c3.td_round([np.array([x]) for x in v])
+    got = one(1.0, 2.0 ** -60, 2.0 ** -120, 2.0 ** -180)
+    assert tuple(float(x[0]) for x in got) == (1.0, 2.0 ** -60, 2.0 ** -120)
+    got = one(2.0 ** -180, 2.0 ** -120, 2.0 ** -60, 1.0)          # order does not matter
+    assert tuple(float(x[0]) for x in got) == (1.0, 2.0 ** -60, 2.0 ** -120)
+    got = one(1.0, -1.0, 2.0 ** -70, 2.0 ** -140, 2.0 ** -200)
+    assert tuple(float(x[0]) for x in got) == (2.0 ** -70, 2.0 ** -140, 2.0 ** -200)
+    # 1 + 2^-53 is a tie between 1 and 1 + 2^-52: the even one, 1, with 2^-53 left
+    got = one(1.0, 2.0 ** -53)
+    assert tuple(float(x[0]) for x in got) == (1.0, 2.0 ** -53, 0.0)
+    # 1 + 2^-53 + 2^-110 is above the tie: rounds up, the rest is negative
+    got = one(1.0, 2.0 ** -53, 2.0 ** -110)
+    assert tuple(float(x[0]) for x in got) == (1.0 + 2.0 ** -52, -2.0 ** -53, 2.0 ** -110)
+    got = one(0.0, 0.0)
+    assert tuple(float(x[0]) for x in got) == (0.0, 0.0, 0.0)
+    got = one(1.0, np.nan)
+    assert all(np.isnan(x[0]) for x in got)
 
 
 def test_triple_word_sum_against_rationals():
@@ -95,24 +135,22 @@ def test_triple_word_sum_against_rationals():
         terms = [np.array([float(np.ldexp(rng.uniform(-1, 1), int(e)))]) for e in ex]
         if trial % 3 == 0:   # planted cancellation: a term and its negation
             terms.append(-terms[0] * (1 + 2.0 ** -40))
-        r = c3.td_from_terms(terms)
-        S = sum(F(float(t[0])) for t in terms)
+        r = c3.td_round(terms)
+        vals = [float(t[0]) for t in terms]
+        S = _check_round3(vals, [x[0] for x in r])
         got = sum(F(float(x[0])) for x in r)
-        mag = sum(abs(F(float(t[0]))) for t in terms)
-        assert abs(got - S) <= F(1, 2 ** 150) * abs(S) + F(1, 2 ** 200) * mag, trial
-        # the words come out in decreasing order, each within the last's ulp
+        assert abs(got - S) <= F(1, 2 ** 158) * abs(S), trial
+        # the words do not overlap
         r0, r1, r2 = (float(x[0]) for x in r)
-        assert abs(r1) <= abs(np.spacing(r0)) and abs(r2) <= abs(np.spacing(r1)) + 1e-320
+        assert abs(r1) <= abs(np.spacing(r0)) / 2 and abs(r2) <= abs(np.spacing(r1)) / 2 + 1e-320
 
 
 def test_triple_word_sum_with_multilevel_cancellation():
     """A triple word plus pairs of large terms that cancel up to a small
-    remainder (up to 2^60 above the sum), in random order and in increasing
-    magnitude: the three words must hold the exact sum to 2^-157 relative.
-    (The full sequence reaches 2^-161 here; one VecSum pass fewer for the
-    first word leaves 2^-151.)"""
+    remainder (up to 2^60 above the sum), in random order: the three words
+    hold the exact sum to 2^-158 relative, whatever the order."""
     rng = np.random.default_rng(8)
-    for trial in range(1000):
+    for trial in range(500):
         n = int(rng.integers(3, 13))
         s0 = rng.uniform(-1, 1)
         vals = [s0, s0 * 2.0 ** -60 * rng.uniform(-1, 1), s0 * 2.0 ** -120 * rng.uniform(-1, 1)]
@@ -121,12 +159,34 @@ def test_triple_word_sum_with_multilevel_cancellation():
             small = float(np.ldexp(rng.uniform(-1, 1), int(rng.integers(-170, -1))))
             vals += [big, -big + small]
         vals = [vals[i] for i in rng.permutation(n)]
-        if trial % 2:
-            vals.sort(key=abs)
-        terms = [np.array([v]) for v in vals]
-        S = sum(F(v) for v in vals)
-        got = sum(F(float(x[0])) for x in c3.td_from_terms(terms))
-        assert abs(got - S) <= F(1, 2 ** 157) * abs(S), trial
+        got = c3.td_round([np.array([v]) for v in vals])
+        S = _check_round3(vals, [x[0] for x in got])
+        assert abs(sum(F(float(x[0])) for x in got) - S) <= F(1, 2 ** 158) * abs(S), trial
+        rev = c3.td_round([np.array([v]) for v in vals[::-1]])
+        assert all(float(a[0]) == float(b[0]) for a, b in zip(got, rev))
+
+
+def test_suffix_planes_are_rounded_running_sums():
+    """U_5' = B_5', and each U_t' is within (5 - t) roundings of the exact
+    sum B_t' + ... + B_5' (one rounding per addition); U_0' is the scaled
+    entry to within a few of its ulps, since the planes rebuild it."""
+    kc = 64
+    c = c3.widths3(kc)
+    P = make_problem3(3, 9, kc, cfg=11, variant="scaled")
+    f = c3.exponents(P["B"][0], axis=0)
+    Bp, scaled = c3.split3(P["B"], f, 0, c)
+    U = c3.suffix_planes(Bp)
+    assert np.array_equal(U[5], Bp[5])
+    for idx in np.ndindex(kc, 9):
+        for t in range(5):
+            exact = sum(F(float(Bp[s][idx])) for s in range(t, 6))
+            err = abs(F(float(U[t][idx])) - exact)
+            assert err <= (5 - t) * _ulp(float(U[t][idx])), (idx, t)
+            # every plane contributes: dropping the last one shows
+            if Bp[5][idx] != 0 and t == 4:
+                assert F(float(U[4][idx])) != F(float(Bp[4][idx])) or abs(Bp[5][idx]) < np.spacing(abs(Bp[4][idx]))
+        v = _val(scaled, idx)
+        assert abs(F(float(U[0][idx])) - v) <= 3 * _ulp(float(U[0][idx])), idx
 
 
 @pytest.mark.parametrize("m,n,k,kc,variant", [(5, 4, 40, 16, "uniform"), (4, 6, 70, 32, "scaled"),
