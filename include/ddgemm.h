@@ -196,6 +196,33 @@ dd_status dd_gemm_ex(dd_op transa, dd_op transb,
                      const dd_gemm_opts* opts, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dd_gemm_ex
+ * without a workspace argument.  The workspace is a fixed array of
+ * DD_NOALLOC_SCRATCH_BYTES bytes inside the library, one per device, held
+ * from the library's first use on that device until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree, events or library handles)
+ * and launches the same kernels as dd_gemm_ex, so results are bit-identical
+ * to it.  Arguments as for dd_gemm_ex (opts is argument 15, stream 16);
+ * DD_ALGO_SIMPLE_UNFUSED is rejected (-15).  A problem whose
+ * dd_gemm_workspace_size exceeds DD_NOALLOC_SCRATCH_BYTES is rejected with
+ * DD_ERR_WORKSPACE before anything is launched: 1024 x 1024 x 1024 with the
+ * cascade needs about 73 MiB; square cascades fit up to m = n = k = 1344.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind (each call clears what must start at zero), so calls that
+ * overlap on one device, on any streams, race on it: order them on one
+ * stream, or with events.  The first call on a device looks the array's
+ * address up (hipGetSymbolAddress, which may load the library's device
+ * code); make that call before any graph capture.
+ */
+#define DD_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+dd_status dd_gemm_noalloc(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+                          const double* A_hi, const double* A_lo, int64_t lda,
+                          const double* B_hi, const double* B_lo, int64_t ldb,
+                          double* C_hi, double* C_lo, int64_t ldc,
+                          const dd_gemm_opts* opts, hipStream_t stream);
+
+/*
  * Batches of independent GEMMs of uneven shapes, C_p := A_p B_p + C_p for
  * p < count (each as dd_gemm, no transposes; kc from opts as in dd_gemm_ex).
  * The cascade is the one of dd_gemm; the whole batch runs as one phase-one

@@ -70,14 +70,44 @@ dd_status cached_workspace(int dev, hipStream_t stream, size_t bytes, void** out
   return DD_OK;
 }
 
+}  // namespace
+
+// ------------------------------------------------------ no-alloc scratch
+// Workspace of dd_gemm_noalloc: a fixed array in this file's code object.
+// Every device the library runs on holds its own copy, at its own address,
+// until the process ends.  In host code `scratch` only names the symbol; its
+// device address comes from hipGetSymbolAddress (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[DD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::map<int, char*> g_scratch;  // device -> address of its copy of `scratch`
+
+// Called with `dev` current (the device the call runs on).
+dd_status scratch_address(int dev, char** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      return DD_ERR_HIP;
+    }
+    it = g_scratch.emplace(dev, (char*)ptr).first;
+  }
+  *out = it->second;
+  return DD_OK;
+}
+
 // ------------------------------------------------------------ phase timing
 struct PhaseEvents { hipEvent_t e0, e1, e2; };
 bool g_prof = false;
 std::vector<PhaseEvents> g_prof_events;
 
-PhaseEvents prof_begin(hipStream_t s) {
+PhaseEvents prof_begin(hipStream_t s, bool allowed = true) {
   PhaseEvents pe{nullptr, nullptr, nullptr};
-  if (!g_prof) return pe;
+  if (!g_prof || !allowed) return pe;
   if (hipEventCreate(&pe.e0) != hipSuccess || hipEventCreate(&pe.e1) != hipSuccess ||
       hipEventCreate(&pe.e2) != hipSuccess) {
     (void)hipGetLastError();
@@ -245,8 +275,10 @@ dd_status run_slices_product(const Problem& p, const ddk::SlicesLayout& L, char*
   return DD_OK;
 }
 
+// With `fixed` the workspace is the caller's (or the scratch array) and the
+// call creates nothing: no phase-timing events either.
 dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes, bool internal_ws,
-              hipStream_t s) {
+              hipStream_t s, bool fixed = false) {
   const int32_t algo = o.algo, kc = o.kc;
   int dev = 0;
   dd_status st = check_device(&dev);
@@ -269,7 +301,7 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
     } else if (ws_bytes < L.bytes || ((uintptr_t)ws & 255u) != 0) {
       return DD_ERR_WORKSPACE;
     }
-    PhaseEvents pe = prof_begin(s);
+    PhaseEvents pe = prof_begin(s, !fixed);
     st = run_slices_split(p, L, ws, s);
     if (st != DD_OK) return st;
     if (pe.e1) (void)hipEventRecord(pe.e1, s);
@@ -292,7 +324,7 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
   } else if (ws_bytes < L.bytes || ((uintptr_t)ws & 255u) != 0) {
     return DD_ERR_WORKSPACE;
   }
-  PhaseEvents pe = prof_begin(s);
+  PhaseEvents pe = prof_begin(s, !fixed);
   st = run_split(p, L, ws, s);
   if (st != DD_OK) return st;
   if (pe.e1) (void)hipEventRecord(pe.e1, s);
@@ -360,15 +392,20 @@ static bool read_opts(const dd_gemm_opts* o, Opts* out) {
   return true;
 }
 
+// Workspace bytes of a problem with validated options (0 when nothing runs).
+static size_t workspace_bytes(int64_t m, int64_t n, int64_t k, const Opts& o) {
+  if (m <= 0 || n <= 0 || k <= 0 || o.algo == DD_ALGO_DD_VALU) return 0;
+  if (o.slices()) return ddk::make_slices_layout(m, n, k, o.S, o.w, o.fmt()).bytes;
+  return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN, o.panels, o.balance,
+                         o.algo == DD_ALGO_SIMPLE_UNFUSED).bytes;
+}
+
 size_t dd_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
                               const dd_gemm_opts* opts) {
   Opts o;
   if (!read_opts(opts, &o)) return 0;
   if ((transa != DD_OP_N && transa != DD_OP_T) || (transb != DD_OP_N && transb != DD_OP_T)) return 0;
-  if (m <= 0 || n <= 0 || k <= 0 || o.algo == DD_ALGO_DD_VALU) return 0;
-  if (o.slices()) return ddk::make_slices_layout(m, n, k, o.S, o.w, o.fmt()).bytes;
-  return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN, o.panels, o.balance,
-                         o.algo == DD_ALGO_SIMPLE_UNFUSED).bytes;
+  return workspace_bytes(m, n, k, o);
 }
 
 dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
@@ -386,6 +423,30 @@ dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k
   const bool internal = workspace == nullptr && ws_bytes == 0;
   if (!internal && workspace == nullptr) return -15;
   return run(p, o, workspace, ws_bytes, internal, stream);
+}
+
+dd_status dd_gemm_noalloc(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+                          const double* A_hi, const double* A_lo, int64_t lda,
+                          const double* B_hi, const double* B_lo, int64_t ldb,
+                          double* C_hi, double* C_lo, int64_t ldc,
+                          const dd_gemm_opts* opts, hipStream_t stream) {
+  static const int pos[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15};
+  Problem p{(int)transa, (int)transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc};
+  Arg a = validate(p);
+  if (a != ARG_OK) return -pos[a];
+  Opts o;
+  if (!read_opts(opts, &o)) return -15;
+  // the unfused form runs the vendor BLAS, whose handle and calls may allocate
+  if (o.algo == DD_ALGO_SIMPLE_UNFUSED) return -15;
+  int dev = 0;
+  dd_status st = check_device(&dev);
+  if (st != DD_OK) return st;
+  if (m == 0 || n == 0 || k == 0) return DD_OK;
+  if (workspace_bytes(m, n, k, o) > (size_t)DD_NOALLOC_SCRATCH_BYTES) return DD_ERR_WORKSPACE;
+  char* ws = nullptr;
+  st = scratch_address(dev, &ws);
+  if (st != DD_OK) return st;
+  return run(p, o, ws, (size_t)DD_NOALLOC_SCRATCH_BYTES, false, stream, true);
 }
 
 dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,

@@ -33,12 +33,13 @@ DD_ALGO_SIMPLE_UNFUSED = 5
 DD_SCALING_GLOBAL = 0
 DD_SCALING_PANEL = 1
 DD_SCALING_BALANCE = 2
+DD_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_slices_split", "dd_dot",
             "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",
             "dd_batched_plan_schedule", "dd_batched_plan_info", "dd_batched_plan_destroy",
             "dd_gemm_batched", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version",
-            "td_gemm_workspace_size", "td_gemm_ex")
+            "td_gemm_workspace_size", "td_gemm_ex", "dd_gemm_noalloc")
 
 
 class dd_gemm_opts(ctypes.Structure):
@@ -112,6 +113,9 @@ def lib():
         L.td_gemm_ex.argtypes = [i32, i32, i64, i64, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp, i64,
                                  vp, sz, i32, vp]
         L.td_gemm_ex.restype = i32
+        L.dd_gemm_noalloc.argtypes = [i32, i32, i64, i64, i64, vp, vp, i64, vp, vp, i64, vp, vp, i64,
+                                      ctypes.POINTER(dd_gemm_opts), vp]
+        L.dd_gemm_noalloc.restype = i32
         _lib = L
     return _lib
 
@@ -167,6 +171,13 @@ def dd_gemm_ex(transa, transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, 
     return int(lib().dd_gemm_ex(int(transa), int(transb), m, n, k, _ptr(A_hi), _ptr(A_lo), lda,
                                 _ptr(B_hi), _ptr(B_lo), ldb, _ptr(C_hi), _ptr(C_lo), ldc,
                                 _ptr(workspace), int(ws_bytes), _opts(opts), _stream(stream)))
+
+
+def dd_gemm_noalloc(transa, transb, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc,
+                    opts=None, stream=None) -> int:
+    return int(lib().dd_gemm_noalloc(int(transa), int(transb), m, n, k, _ptr(A_hi), _ptr(A_lo), lda,
+                                     _ptr(B_hi), _ptr(B_lo), ldb, _ptr(C_hi), _ptr(C_lo), ldc,
+                                     _opts(opts), _stream(stream)))
 
 
 def td_gemm_workspace_size(transa, transb, m, n, k, kc=0) -> int:

@@ -178,3 +178,17 @@ def test_slices_split_rejects_bad_arguments():
     assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 0, 0, 10, 32, 64, stream=0) == -9
     assert dg.dd_slices_split(0, 0, 4, 4, 0, 16, 4, 0, 0, 0, 32, 64, stream=0) == -5
     assert dg.dd_slices_split(0, 0, 4, 4, 8, 16, 4, 0, 0, 0, 0, 64, stream=0) == -11
+
+
+def test_noalloc_rejects_bad_arguments_on_host():
+    base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
+    assert dg.dd_gemm_noalloc(2, 0, *base, stream=0) == -1
+    assert dg.dd_gemm_noalloc(0, 0, 4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 3,
+                              stream=0) == -14
+    assert dg.dd_gemm_noalloc(0, 0, *base, opts={"kc": 6}, stream=0) == -15
+    # the unfused form runs the vendor BLAS, which may allocate
+    assert dg.dd_gemm_noalloc(0, 0, *base, opts={"algo": dg.DD_ALGO_SIMPLE_UNFUSED}, stream=0) == -15
+    assert dg.DD_NOALLOC_SCRATCH_BYTES == 128 << 20
+    # the largest square cascade the scratch array holds, and the first one it does not
+    assert dg.dd_gemm_workspace_size(0, 0, 1344, 1344, 1344) <= dg.DD_NOALLOC_SCRATCH_BYTES
+    assert dg.dd_gemm_workspace_size(0, 0, 1360, 1360, 1360) > dg.DD_NOALLOC_SCRATCH_BYTES
