@@ -52,6 +52,8 @@ def parse():
                          "not the headline workload")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the 512 uneven batched GEMMs (for profiling them); not the headline workload")
+    ap.add_argument("--sizes-only", action="store_true",
+                    help="time only the square-size sweep (128^3 to 8192^3, uniform and ill-scaled)")
     ap.add_argument("--fp64x3-only", action="store_true",
                     help="time only the FP64x3 GEMM at 4096^3 (for profiling it); not the headline workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -109,11 +111,12 @@ def bench_batched(torch, dg, stream):
                                     stream))
         loop()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        e0.record(stream)
         for _ in range(reps):
             loop()
+        e1.record(stream)
         torch.cuda.synchronize()
-        lms = (time.perf_counter() - t0) * 1e3 / reps
+        lms = e0.elapsed_time(e1) / reps
         del g
     finally:
         dg.dd_batched_plan_destroy(plan)
@@ -195,20 +198,159 @@ def slices_accuracy(out, samples, IJ, n=4096):
         P = samples[("problem", variant)]
         Rh, Rl, _ = dd_gemm_ref_entries(P["A"], P["B"], P["C"], I, J)
         k = 96   # exact slices-oracle entries (each a full split of one row and one column)
-        AB = np.array([np.abs(P["A"][0][i]) @ np.abs(P["B"][0][:, j]) for i, j in zip(I[:1024], J[:1024])])
+        AB = abs_ab_entries(P["A"][0], P["B"][0], I, J)
         for fmt, w, s in SLICES_FORMATS:
             Sh, Sl = slices_gemm_entries(P["A"], P["B"], P["C"], I[:k], J[:k], w=w, s=s, fmt=fmt)
             Gh, Gl = samples[(fmt, variant)]
             diff = np.abs((Gh - Rh) + (Gl - Rl))
             nz = np.abs(Rh) > 0
             rel = diff[nz] / np.abs(Rh[nz])
-            normed = diff[:1024] / AB
+            normed = diff / AB
             out["cases"][f"{fmt}_{variant}"].update({
                 "sampled_entries": int(len(I)), "max_rel_err": float(np.max(rel)),
                 "median_rel_err": float(np.median(rel)),
                 "max_err_over_absAabsB": float(np.max(normed)),
+                "median_err_over_absAabsB": float(np.median(normed)),
+                "tolerance_checked_entries": int(len(normed)),
                 "within_tolerance": bool(np.all(normed <= 64 * n * 2.0 ** -104)),
+                "slices_oracle_entries": k,
                 "bitwise_equal_to_slices_oracle": bool(np.array_equal(Gh[:k], Sh) and np.array_equal(Gl[:k], Sl))})
+
+
+def abs_ab_entries(Ahi, Bhi, I, J, chunk=1 << 16):
+    """(|A_hi| |B_hi|)_ij at the positions (I, J): the scale of the tolerance
+    64 k 2^-104 (|A||B|)_ij, in FP64.  One host product of the absolute
+    values (BLAS on the host cores), then gathered."""
+    AB = np.abs(Ahi) @ np.abs(Bhi)
+    return np.concatenate([AB[I[c:c + chunk], J[c:c + chunk]] for c in range(0, len(I), chunk)])
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_single_thread_rate(n=1024, entries=16384):
+    """DD multiply-adds per second of the FP64x2 oracle on one host core, on
+    sampled entries of a uniform n^3 problem (each a full length-n dot
+    product)."""
+    from oracle.ref import dd_gemm_ref_entries
+    from paper_2303_04353_amd.inputs import make_problem, sample_entries
+    P = make_problem(n, n, n, cfg=1)
+    I, J = sample_entries(n, n, entries, seed=23)
+    t = time.perf_counter()
+    _, _, used = dd_gemm_ref_entries(P["A"], P["B"], P["C"], I, J, threads=1)
+    dt = time.perf_counter() - t
+    return {"n": n, "entries": entries, "threads": int(used), "dd_mac_per_s": round(entries * n / dt)}
+
+
+SIZES = ((128, "uniform"), (1024, "uniform"), (1024, "scaled"), (4096, "uniform"), (4096, "scaled"),
+         (8192, "scaled"))
+
+
+def bench_sizes(torch, dg, stream, cpu=True):
+    """The square sizes of the performance study (Sec. 5.1 measures square
+    m = n = k): dd_gemm at 128^3, 1024^3, 4096^3 (uniform and ill-scaled) and
+    8192^3 ill-scaled, timed with events on the GEMM's stream, with the
+    product kernel's share (phase events) against the FP64 matrix peak and
+    the software double-double kernel beside it up to 4096^3.  With `cpu`,
+    the FP64x2 oracle on every entry (128^3, 1024^3) or 4096 seeded entries
+    (larger sizes): max and median relative error and error over
+    (|A||B|)_ij, the tolerance, and whether the comparator equals the
+    oracle there."""
+    from oracle.ref import dd_gemm_ref_entries
+    from paper_2303_04353_amd.inputs import make_problem, sample_entries
+    out = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    for N, variant in SIZES:
+        log(f"sizes: {N}^3 {variant}")
+        P = make_problem(N, N, N, cfg=1, variant=variant)
+        Ah, Al, Bh, Bl, C0h, C0l = (dg.colmajor_to_device(x) for x in (*P["A"], *P["B"], *P["C"]))
+        Ch, Cl = C0h.clone(), C0l.clone()
+        reps = 50 if N <= 128 else (20 if N <= 1024 else (5 if N <= 4096 else 3))
+
+        def call():
+            dg.check(dg.dd_gemm(N, N, N, Ah, Al, N, Bh, Bl, N, Ch, Cl, N, stream), "dd_gemm")
+        call()
+        call()
+        torch.cuda.synchronize()
+        dg.dd_profile_enable(1)
+        dg.dd_phase_times()
+        ms = timed(call, reps)
+        st, sp, pr, calls = dg.dd_phase_times()
+        dg.dd_profile_enable(0)
+        dg.check(st, "dd_phase_times")
+        pr, sp = pr / max(calls, 1), sp / max(calls, 1)
+        flops, mfma = 2.0 * N ** 3, 20.0 * N ** 3
+        case = {"ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+                "split_ms": round(sp, 4), "product_ms": round(pr, 4),
+                "fp64_mfma_tflops": round(mfma / (pr * 1e-3) / 1e12, 2),
+                "pct_of_fp64_mfma_peak": round(100 * mfma / (pr * 1e-3) / 1e12 / PEAK_FP64_MFMA_TFLOPS, 1),
+                "algorithmic_gbps": round((16 * 2 * N * N + 32 * N * N) / (ms * 1e-3) / 1e9, 1)}
+        Ch.copy_(C0h)
+        Cl.copy_(C0l)
+        call()
+        torch.cuda.synchronize()
+        if N <= 1024:
+            I, J = (x.ravel() for x in np.meshgrid(np.arange(N), np.arange(N), indexing="ij"))
+        else:
+            I, J = sample_entries(N, N, 4096, seed=N + 1)
+        ti, tj = torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()
+        Gh, Gl = Ch.T[ti, tj].cpu().numpy(), Cl.T[ti, tj].cpu().numpy()
+        V = None
+        if N <= 4096:
+            Vh, Vl = C0h.clone(), C0l.clone()
+            vopts = {"algo": dg.DD_ALGO_DD_VALU}
+
+            def vcall():
+                dg.check(dg.dd_gemm_ex(0, 0, N, N, N, Ah, Al, N, Bh, Bl, N, Vh, Vl, N, opts=vopts, stream=stream))
+            vcall()
+            torch.cuda.synchronize()
+            Vh.copy_(C0h)
+            Vl.copy_(C0l)
+            vms = timed(vcall, 1)
+            V = (Vh.T[ti, tj].cpu().numpy(), Vl.T[ti, tj].cpu().numpy())
+            case["comparator_ms"] = round(vms, 4)
+            case["comparator_gflops"] = round(flops / (vms * 1e-3) / 1e9, 1)
+            del Vh, Vl
+        if cpu:
+            t = time.perf_counter()
+            Rh, Rl, used = dd_gemm_ref_entries(P["A"], P["B"], P["C"], I, J)
+            dt = time.perf_counter() - t
+            diff = np.abs((Gh - Rh) + (Gl - Rl))
+            nz = np.abs(Rh) > 0
+            rel = diff[nz] / np.abs(Rh[nz])
+            normed = diff / abs_ab_entries(P["A"][0], P["B"][0], I, J)
+            case.update({
+                "oracle": "every entry" if N <= 1024 else f"{len(I)} seeded entries",
+                "oracle_s": round(dt, 3), "oracle_threads": int(used),
+                "max_rel_err": float(np.max(rel)), "median_rel_err": float(np.median(rel)),
+                "max_err_over_absAabsB": float(np.max(normed)),
+                "median_err_over_absAabsB": float(np.median(normed)),
+                "tolerance_over_absAabsB": 64 * N * 2.0 ** -104,
+                "within_tolerance": bool(np.all(normed <= 64 * N * 2.0 ** -104))})
+            if V is not None:
+                case["comparator_bitwise_equal_to_oracle"] = bool(np.array_equal(V[0], Rh) and
+                                                                  np.array_equal(V[1], Rl))
+        out[f"{N}_{variant}"] = case
+        del Ah, Al, Bh, Bl, C0h, C0l, Ch, Cl, P
+        torch.cuda.empty_cache()
+    return out
 
 
 ACCURACY_WORKLOADS = ("uniform", "wide", "ill-1e-9", "ill-1e-14", "ill-1e-19")
@@ -437,6 +579,10 @@ def main():
     if args.batched_only:
         print(json.dumps({"batched": bench_batched(torch, dg, torch.cuda.current_stream())}), flush=True)
         return
+    if args.sizes_only:
+        print(json.dumps({"sizes": bench_sizes(torch, dg, torch.cuda.current_stream(),
+                                               cpu=not args.no_cpu_baseline)}), flush=True)
+        return
     if args.fp64x3_only:
         tres = bench_td(torch, dg, torch.cuda.current_stream(), reps=max(1, args.steps))
         if not args.no_cpu_baseline:
@@ -528,8 +674,17 @@ def main():
                      "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "algorithmic": "20*m*n*k FP64 flops per launch (10 products)",
-                     "algorithmic_bytes": (4 + 5) * 8 * (m * k + k * n) + 32 * m * n},
+                     # the minimum: A and B as hi/lo planes read once, C read and written
+                     "algorithmic_bytes": 16 * (m * k + k * n) + 32 * m * n,
+                     # what the kernel must at least read as designed: 4 + 5 packed digit planes, C
+                     "packed_plane_bytes": (4 + 5) * 8 * (m * k + k * n) + 32 * m * n},
     }
+    rf = result["roofline"]
+    if traffic is not None:
+        rf["traffic_over_algorithmic_bytes"] = round(traffic / rf["algorithmic_bytes"], 2)
+        rf["traffic_over_packed_plane_bytes"] = round(traffic / rf["packed_plane_bytes"], 2)
+        rf["hbm_gbps"] = round(traffic / (prod_avg_ms * 1e-3) / 1e9, 1)
+        rf["hbm_frac"] = round(rf["hbm_gbps"] / PEAK_HBM_GBS, 4)
 
     I, J = sample_entries(m, n, 1 << 20, seed=7)
     Gh = Ch.T[torch.from_numpy(I).cuda(), torch.from_numpy(J).cuda()].cpu().numpy()
@@ -643,17 +798,22 @@ def main():
             "kind": "oracle",
             "sample": f"{S} seeded output entries (i, j) of the same {m}x{n}x{k} problem, each a full "
                       f"length-{k} FP64x2 dot product plus C; {dt:.1f} s wall",
-            "projected_full_s": round(dt * (m * n) / S, 1)}
+            "projected_full_s": round(dt * (m * n) / S, 1),
+            "cpu_model": cpu_model(), "host_threads_available": os.cpu_count()}
+        log("oracle on one host core at 1024")
+        result["cpu_baseline"]["single_thread"] = oracle_single_thread_rate()
         diff = np.abs((Gh[:S] - Rh) + (Gl[:S] - Rl))
         denom = np.abs(Rh)
         nz = denom > 0
         rel = diff[nz] / denom[nz]
-        ABs = np.array([np.abs(A[0][i]) @ np.abs(B[0][:, j]) for i, j in zip(I[:min(S, 4096)], J[:min(S, 4096)])])
-        normed = diff[:len(ABs)] / ABs
+        log("tolerance scale |A||B| on every sampled entry")
+        normed = diff / abs_ab_entries(A[0], B[0], I[:S], J[:S])
         result["accuracy"] = {
             "sampled_entries": S, "max_rel_err": float(np.max(rel)), "median_rel_err": float(np.median(rel)),
             "excluded_zero": int(np.sum(~nz)),
+            "tolerance_checked_entries": int(len(normed)),
             "max_err_over_absAabsB": float(np.max(normed)),
+            "median_err_over_absAabsB": float(np.median(normed)),
             "tolerance_over_absAabsB": 64 * k * 2.0 ** -104,
             "within_tolerance": bool(np.all(normed <= 64 * k * 2.0 ** -104))}
         if "comparator" in result:
@@ -666,9 +826,10 @@ def main():
         result["batched"] = bench_batched(torch, dg, stream)
         log("differentiation chain")
         result["autograd"] = bench_autograd(torch)
-        log("slices variant at 4096^3")
         del Ah, Al, Bh, Bl, Ch, Cl, C0h, C0l, dev
         torch.cuda.empty_cache()
+        result["sizes"] = bench_sizes(torch, dg, stream, cpu=not args.no_cpu_baseline)
+        log("slices variant at 4096^3")
         sres, samples, IJ = bench_slices(torch, dg, stream)
         if not args.no_cpu_baseline:
             log("slices accuracy against the oracles (sampled entries)")

@@ -321,13 +321,28 @@ dd_status dd_dot(int64_t n, const double* x_hi, const double* x_lo, int64_t incx
                  double* result, hipStream_t stream);
 
 /*
- * y := alpha * x in FP64x2 (alpha = alpha_hi + alpha_lo given on the host),
- * entry by entry with the double-double product.  y may equal x (same
- * pointers and stride); otherwise they must not overlap.
+ * y := alpha * x in FP64x2, entry by entry with the double-double product
+ * (TwoProd of the high words by FMA plus the two cross products, one
+ * renormalisation).  alpha is a DEVICE pointer to two doubles, alpha[0] +
+ * alpha[1], read when the kernel runs, so a scale the device has just
+ * computed (the seed of a backward pass) needs no host synchronisation.
+ * y may equal x (same pointers and stride); otherwise they must not overlap.
  */
-dd_status dd_scal(int64_t n, double alpha_hi, double alpha_lo,
+dd_status dd_scal(int64_t n, const double* alpha,
                   const double* x_hi, const double* x_lo, int64_t incx,
                   double* y_hi, double* y_lo, int64_t incy, hipStream_t stream);
+
+/*
+ * z := x + y in FP64x2, entry by entry with the accurate double-double
+ * addition (TwoSum of the high words and of the low words, two
+ * renormalisations; relative error below 3 2^-106, Sec. 3.1 arithmetic of
+ * FP64x2 numbers).  Used to accumulate the gradients of an FP64x2 tensor
+ * that feeds several products.  z may equal x or y (same pointers and
+ * stride); otherwise it must overlap neither.  Strides >= 1, in elements.
+ */
+dd_status dd_add(int64_t n, const double* x_hi, const double* x_lo, int64_t incx,
+                 const double* y_hi, const double* y_lo, int64_t incy,
+                 double* z_hi, double* z_lo, int64_t incz, hipStream_t stream);
 
 /*
  * Phase timing (Fig. breakdown of Sec. 5.1 measures the same split).  While

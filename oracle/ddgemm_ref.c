@@ -92,6 +92,18 @@ static dd_t dot_entry(int64_t i, int64_t j, int64_t k, int transa, int transb,
 
 int oracle_max_threads(void) { return omp_get_max_threads(); }
 
+/* z = x + y entry by entry with the accurate FP64x2 addition above (the one
+ * the triple loop accumulates with).  z may be x or y. */
+void oracle_dd_add_vec(int64_t n, const double *xh, const double *xl, const double *yh, const double *yl,
+                       double *zh, double *zl) {
+    for (int64_t i = 0; i < n; ++i) {
+        dd_t x = {xh[i], xl[i]}, y = {yh[i], yl[i]};
+        dd_t z = dd_add(x, y);
+        zh[i] = z.hi;
+        zl[i] = z.lo;
+    }
+}
+
 /* C := op(A) op(B) + C over the whole m x n output. Returns the threads used. */
 int oracle_dd_gemm(int64_t m, int64_t n, int64_t k, int transa, int transb,
                    const double *Ahi, const double *Alo, int64_t lda,

@@ -34,6 +34,8 @@ def _load():
         lib.oracle_exact_entries.argtypes = [i64, vp, vp, i64, vp, vp, i64, vp, vp, i64, vp, vp, i64,
                                              vp, vp, vp, vp, ci]
         lib.oracle_exact_entries.restype = ci
+        lib.oracle_dd_add_vec.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+        lib.oracle_dd_add_vec.restype = None
         _lib = lib
     return _lib
 
@@ -113,3 +115,16 @@ def exact_entries(A, B, C, I, J, R, *, threads=0):
     if st < 0:
         raise RuntimeError("expansion too long (exponent range of the inputs too wide)")
     return exact, err
+
+
+def dd_add_ref(x, y):
+    """Entry-wise accurate FP64x2 sum of two ``(hi, lo)`` pairs of arrays of
+    equal shape: ``(hi, lo)`` of x + y, the addition the triple loop
+    accumulates with (TwoSum of both words, two renormalisations)."""
+    xh, xl = (np.ascontiguousarray(v, dtype=np.float64) for v in x)
+    yh, yl = (np.ascontiguousarray(v, dtype=np.float64) for v in y)
+    if not (xh.shape == xl.shape == yh.shape == yl.shape):
+        raise ValueError("dd_add_ref: shapes differ")
+    zh, zl = np.empty_like(xh), np.empty_like(xh)
+    _load().oracle_dd_add_vec(xh.size, _ptr(xh), _ptr(xl), _ptr(yh), _ptr(yl), _ptr(zh), _ptr(zl))
+    return zh, zl

@@ -1,7 +1,9 @@
 // FP64x2 vector kernels used around the GEMM: a dot product (the reduction
-// of sum(Y o G) in the differentiation chain) and a scaling y = alpha x.
-// Both use the same double-double arithmetic as the comparator GEMM (TwoProd
-// by FMA, accurate DD addition).
+// of sum(Y o G) in the differentiation chain), a scaling y = alpha x with
+// alpha in device memory, and an addition z = x + y (the accumulation of
+// the gradients of a tensor used more than once).  All use the same
+// double-double arithmetic as the comparator GEMM (TwoProd by FMA, accurate
+// DD addition).
 //
 // dd_dot: pass 1, each of `nblk` workgroups accumulates a strided subset of
 // the products in FP64x2 per thread and reduces its 256 partial sums in
@@ -67,15 +69,30 @@ dd_dot_final(int nblk, const double* __restrict__ part, double* __restrict__ res
   }
 }
 
+// alpha = (alpha[0], alpha[1]) is read from device memory, so a scale
+// computed on the device needs no trip through the host.
 __global__ void __launch_bounds__(256)
-dd_scal_kernel(int64_t n, double ah, double al, const double* __restrict__ xh, const double* __restrict__ xl,
-               int64_t incx, double* __restrict__ yh, double* __restrict__ yl, int64_t incy) {
+dd_scal_kernel(int64_t n, const double* __restrict__ alpha, const double* xh, const double* xl,
+               int64_t incx, double* yh, double* yl, int64_t incy) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   double rh, rl;
-  dd_mul(ah, al, xh[i * incx], xl[i * incx], rh, rl);
+  dd_mul(alpha[0], alpha[1], xh[i * incx], xl[i * incx], rh, rl);
   yh[i * incy] = rh;
   yl[i * incy] = rl;
+}
+
+// z = x + y with the accurate FP64x2 addition; z may be x or y (each
+// element is read before it is written, by the same thread).
+__global__ void __launch_bounds__(256)
+dd_add_kernel(int64_t n, const double* xh, const double* xl, int64_t incx, const double* yh,
+              const double* yl, int64_t incy, double* zh, double* zl, int64_t incz) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double rh, rl;
+  dd_add(xh[i * incx], xl[i * incx], yh[i * incy], yl[i * incy], rh, rl);
+  zh[i * incz] = rh;
+  zl[i * incz] = rl;
 }
 
 int dd_dot_blocks(int64_t n) {
@@ -92,10 +109,19 @@ hipError_t launch_dd_dot(int64_t n, const double* xh, const double* xl, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_dd_scal(int64_t n, double ah, double al, const double* xh, const double* xl, int64_t incx,
+hipError_t launch_dd_scal(int64_t n, const double* alpha, const double* xh, const double* xl, int64_t incx,
                           double* yh, double* yl, int64_t incy, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  dd_scal_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, ah, al, xh, xl, incx, yh, yl, incy);
+  if ((n + 255) / 256 > 0x7fffffff) return hipErrorInvalidValue;
+  dd_scal_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, alpha, xh, xl, incx, yh, yl, incy);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd_add(int64_t n, const double* xh, const double* xl, int64_t incx, const double* yh,
+                         const double* yl, int64_t incy, double* zh, double* zl, int64_t incz, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if ((n + 255) / 256 > 0x7fffffff) return hipErrorInvalidValue;
+  dd_add_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, xh, xl, incx, yh, yl, incy, zh, zl, incz);
   return hipGetLastError();
 }
 

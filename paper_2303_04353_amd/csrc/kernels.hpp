@@ -93,14 +93,17 @@ hipError_t launch_dd_valu(int64_t m, int64_t n, int64_t k,
                           const double* Bhi, const double* Blo, int64_t b_sp, int64_t b_sj,
                           double* Chi, double* Clo, int64_t ldc, hipStream_t s);
 
-// FP64x2 dot product (two passes; `part` holds 2*dd_dot_blocks(n) doubles)
-// and scaling y = alpha x.
+// FP64x2 dot product (two passes; `part` holds 2*dd_dot_blocks(n) doubles),
+// scaling y = alpha x (alpha: two doubles in device memory) and addition
+// z = x + y.
 int dd_dot_blocks(int64_t n);
 hipError_t launch_dd_dot(int64_t n, const double* xh, const double* xl, int64_t incx,
                          const double* yh, const double* yl, int64_t incy,
                          double* part, double* res, hipStream_t s);
-hipError_t launch_dd_scal(int64_t n, double ah, double al, const double* xh, const double* xl, int64_t incx,
+hipError_t launch_dd_scal(int64_t n, const double* alpha, const double* xh, const double* xl, int64_t incx,
                           double* yh, double* yl, int64_t incy, hipStream_t s);
+hipError_t launch_dd_add(int64_t n, const double* xh, const double* xl, int64_t incx, const double* yh,
+                         const double* yl, int64_t incy, double* zh, double* zl, int64_t incz, hipStream_t s);
 
 // The narrow-slice variant: split of op(A) (outer = m) or op(B) (outer = n)
 // into packed BF16/FP16 slices, X(o, r) at X[o*so + r*sr] (r the inner index;

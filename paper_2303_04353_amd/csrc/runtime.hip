@@ -571,27 +571,67 @@ dd_status dd_dot(int64_t n, const double* x_hi, const double* x_lo, int64_t incx
   return hip_status(ddk::launch_dd_dot(n, x_hi, x_lo, incx, y_hi, y_lo, incy, (double*)part, result, stream));
 }
 
-dd_status dd_scal(int64_t n, double alpha_hi, double alpha_lo,
+// The output (zh, zl, incz) of an elementwise FP64x2 operation either is one
+// of the inputs (same pointers and stride) or overlaps none of them; its two
+// planes never overlap each other.  Returns 0, or 1 for the output's high
+// plane, 2 for its low plane.
+static int output_overlap(int64_t n, const double* zh, const double* zl, int64_t incz,
+                          const double* const* in_h, const double* const* in_l, const int64_t* inc, int nin) {
+  const size_t zb = (size_t)((n - 1) * incz + 1) * sizeof(double);
+  if (overlaps(zl, zb, zh, zb)) return 2;
+  for (int v = 0; v < nin; ++v) {
+    if (zh == in_h[v] && zl == in_l[v] && incz == inc[v]) continue;
+    const size_t xb = (size_t)((n - 1) * inc[v] + 1) * sizeof(double);
+    if (overlaps(zh, zb, in_h[v], xb) || overlaps(zh, zb, in_l[v], xb)) return 1;
+    if (overlaps(zl, zb, in_h[v], xb) || overlaps(zl, zb, in_l[v], xb)) return 2;
+  }
+  return 0;
+}
+
+dd_status dd_scal(int64_t n, const double* alpha,
                   const double* x_hi, const double* x_lo, int64_t incx,
                   double* y_hi, double* y_lo, int64_t incy, hipStream_t stream) {
   if (n < 0) return -1;
   if (n == 0) return DD_OK;
-  if (!x_hi) return -4;
-  if (!x_lo) return -5;
-  if (incx < 1) return -6;
-  if (!y_hi) return -7;
-  if (!y_lo) return -8;
-  if (incy < 1) return -9;
-  const bool same = x_hi == y_hi && x_lo == y_lo && incx == incy;
-  if (!same) {
-    const size_t xb = (size_t)((n - 1) * incx + 1) * sizeof(double);
-    const size_t yb = (size_t)((n - 1) * incy + 1) * sizeof(double);
-    if (overlaps(y_hi, yb, x_hi, xb) || overlaps(y_hi, yb, x_lo, xb)) return -7;
-    if (overlaps(y_lo, yb, x_hi, xb) || overlaps(y_lo, yb, x_lo, xb) || overlaps(y_lo, yb, y_hi, yb)) return -8;
-  }
+  if (!alpha) return -2;
+  if (!x_hi) return -3;
+  if (!x_lo) return -4;
+  if (incx < 1) return -5;
+  if (!y_hi) return -6;
+  if (!y_lo) return -7;
+  if (incy < 1) return -8;
+  const double* ih[1] = {x_hi};
+  const double* il[1] = {x_lo};
+  const int64_t inc[1] = {incx};
+  const int ov = output_overlap(n, y_hi, y_lo, incy, ih, il, inc, 1);
+  if (ov) return ov == 1 ? -6 : -7;
   dd_status st = check_device(nullptr);
   if (st != DD_OK) return st;
-  return hip_status(ddk::launch_dd_scal(n, alpha_hi, alpha_lo, x_hi, x_lo, incx, y_hi, y_lo, incy, stream));
+  return hip_status(ddk::launch_dd_scal(n, alpha, x_hi, x_lo, incx, y_hi, y_lo, incy, stream));
+}
+
+dd_status dd_add(int64_t n, const double* x_hi, const double* x_lo, int64_t incx,
+                 const double* y_hi, const double* y_lo, int64_t incy,
+                 double* z_hi, double* z_lo, int64_t incz, hipStream_t stream) {
+  if (n < 0) return -1;
+  if (n == 0) return DD_OK;
+  if (!x_hi) return -2;
+  if (!x_lo) return -3;
+  if (incx < 1) return -4;
+  if (!y_hi) return -5;
+  if (!y_lo) return -6;
+  if (incy < 1) return -7;
+  if (!z_hi) return -8;
+  if (!z_lo) return -9;
+  if (incz < 1) return -10;
+  const double* ih[2] = {x_hi, y_hi};
+  const double* il[2] = {x_lo, y_lo};
+  const int64_t inc[2] = {incx, incy};
+  const int ov = output_overlap(n, z_hi, z_lo, incz, ih, il, inc, 2);
+  if (ov) return ov == 1 ? -8 : -9;
+  dd_status st = check_device(nullptr);
+  if (st != DD_OK) return st;
+  return hip_status(ddk::launch_dd_add(n, x_hi, x_lo, incx, y_hi, y_lo, incy, z_hi, z_lo, incz, stream));
 }
 
 dd_status dd_profile_enable(int32_t enable) {

@@ -39,7 +39,7 @@ EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split
             "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",
             "dd_batched_plan_schedule", "dd_batched_plan_info", "dd_batched_plan_destroy",
             "dd_gemm_batched", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version",
-            "td_gemm_workspace_size", "td_gemm_ex", "dd_gemm_noalloc")
+            "td_gemm_workspace_size", "td_gemm_ex", "dd_gemm_noalloc", "dd_add")
 
 
 class dd_gemm_opts(ctypes.Structure):
@@ -79,8 +79,10 @@ def lib():
         L.dd_slices_split.restype = i32
         L.dd_dot.argtypes = [i64, vp, vp, i64, vp, vp, i64, vp, vp]
         L.dd_dot.restype = i32
-        L.dd_scal.argtypes = [i64, ctypes.c_double, ctypes.c_double, vp, vp, i64, vp, vp, i64, vp]
+        L.dd_scal.argtypes = [i64, vp, vp, vp, i64, vp, vp, i64, vp]
         L.dd_scal.restype = i32
+        L.dd_add.argtypes = [i64, vp, vp, i64, vp, vp, i64, vp, vp, i64, vp]
+        L.dd_add.restype = i32
         pi64 = ctypes.POINTER(ctypes.c_int64)
         L.dd_batched_plan_create.argtypes = [i32, pi64, pi64, pi64, pi64, pi64, pi64,
                                              ctypes.POINTER(dd_gemm_opts), ctypes.POINTER(vp)]
@@ -207,9 +209,15 @@ def dd_dot(n, x_hi, x_lo, incx, y_hi, y_lo, incy, result, stream=None) -> int:
                             _stream(stream)))
 
 
-def dd_scal(n, alpha_hi, alpha_lo, x_hi, x_lo, incx, y_hi, y_lo, incy, stream=None) -> int:
-    return int(lib().dd_scal(n, float(alpha_hi), float(alpha_lo), _ptr(x_hi), _ptr(x_lo), incx,
+def dd_scal(n, alpha, x_hi, x_lo, incx, y_hi, y_lo, incy, stream=None) -> int:
+    """``alpha``: device memory of two doubles (a tensor or a pointer)."""
+    return int(lib().dd_scal(n, _ptr(alpha), _ptr(x_hi), _ptr(x_lo), incx,
                              _ptr(y_hi), _ptr(y_lo), incy, _stream(stream)))
+
+
+def dd_add(n, x_hi, x_lo, incx, y_hi, y_lo, incy, z_hi, z_lo, incz, stream=None) -> int:
+    return int(lib().dd_add(n, _ptr(x_hi), _ptr(x_lo), incx, _ptr(y_hi), _ptr(y_lo), incy,
+                            _ptr(z_hi), _ptr(z_lo), incz, _stream(stream)))
 
 
 def _i64arr(v):

@@ -192,3 +192,22 @@ def test_noalloc_rejects_bad_arguments_on_host():
     # the largest square cascade the scratch array holds, and the first one it does not
     assert dg.dd_gemm_workspace_size(0, 0, 1344, 1344, 1344) <= dg.DD_NOALLOC_SCRATCH_BYTES
     assert dg.dd_gemm_workspace_size(0, 0, 1360, 1360, 1360) > dg.DD_NOALLOC_SCRATCH_BYTES
+
+
+def test_vector_calls_reject_bad_arguments_on_host():
+    # dd_scal(n, alpha, x_hi, x_lo, incx, y_hi, y_lo, incy): alpha is a device pointer
+    assert dg.dd_scal(-1, 8, 16, 24, 1, 32, 40, 1, stream=0) == -1
+    assert dg.dd_scal(4, 0, 16, 24, 1, 1 << 20, 1 << 21, 1, stream=0) == -2
+    assert dg.dd_scal(4, 8, 1 << 20, 1 << 21, 0, 1 << 22, 1 << 23, 1, stream=0) == -5
+    assert dg.dd_scal(4, 8, 1 << 20, 1 << 21, 1, 1 << 20, 1 << 23, 1, stream=0) == -6   # y_hi over x_hi, not equal pair
+    assert dg.dd_scal(4, 8, 1 << 20, 1 << 21, 1, 1 << 22, 1 << 22, 1, stream=0) == -7  # y_lo over y_hi
+    # dd_add(n, x_hi, x_lo, incx, y_hi, y_lo, incy, z_hi, z_lo, incz)
+    x = (1 << 20, 1 << 21)
+    y = (1 << 22, 1 << 23)
+    assert dg.dd_add(-1, *x, 1, *y, 1, 1 << 24, 1 << 25, 1, stream=0) == -1
+    assert dg.dd_add(4, 0, x[1], 1, *y, 1, 1 << 24, 1 << 25, 1, stream=0) == -2
+    assert dg.dd_add(4, *x, 1, *y, 0, 1 << 24, 1 << 25, 1, stream=0) == -7
+    assert dg.dd_add(4, *x, 1, *y, 1, 1 << 24, 1 << 25, 0, stream=0) == -10
+    assert dg.dd_add(4, *x, 1, *y, 1, x[0] + 8, 1 << 25, 1, stream=0) == -8          # z_hi inside x_hi
+    assert dg.dd_add(4, *x, 1, *y, 1, 1 << 24, y[1] + 16, 1, stream=0) == -9         # z_lo inside y_lo
+    assert dg.dd_add(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, stream=0) == 0

@@ -163,3 +163,142 @@ def test_config_size_gradients_and_finite_differences(h):
             r = dd_gemm_ref((W1[0][:, i:i + 1].T, W1[1][:, i:i + 1].T), dhc)[:2]
         g = dd_val(grads[name][0][idx], grads[name][1][idx])
         assert abs(g - dd_val(r[0][0, 0], r[1][0, 0])) <= Fraction(2 * 64 * n * U * S[key_s[name]][idx])
+
+
+def test_dd_add_and_device_scalar_against_oracle():
+    """dd_add equals the oracle's accurate FP64x2 addition bit for bit
+    (heavy cancellation, strides, in place); dd_scal takes its scalar from
+    device memory: a dot product computed on the device scales a vector with
+    no host round trip, equal to the oracle's DD product."""
+    import torch
+    from oracle.ref import dd_add_ref
+    from paper_2303_04353_amd import ddgemm as dg
+    rng = np.random.default_rng(83)
+    n = 100003
+    xh = rng.uniform(-1, 1, n) * np.ldexp(1.0, rng.integers(-30, 30, n))
+    xl = xh * rng.uniform(-1, 1, n) * 2.0 ** -53
+    yh = -xh * (1 + rng.integers(-8, 9, n) * 2.0 ** -52)
+    yh[::3] = rng.uniform(-1, 1, len(yh[::3]))
+    yl = yh * rng.uniform(-1, 1, n) * 2.0 ** -53
+    want = dd_add_ref((xh, xl), (yh, yl))
+    d = [torch.from_numpy(v.copy()).cuda() for v in (xh, xl, yh, yl)]
+    zh, zl = torch.empty_like(d[0]), torch.empty_like(d[0])
+    dg.check(dg.dd_add(n, d[0], d[1], 1, d[2], d[3], 1, zh, zl, 1), "dd_add")
+    torch.cuda.synchronize()
+    assert np.array_equal(zh.cpu().numpy(), want[0]) and np.array_equal(zl.cpu().numpy(), want[1])
+    # strided operands (every third entry of x, every second of y), result in place over y
+    m = n // 3
+    dg.check(dg.dd_add(m, d[0], d[1], 3, d[2], d[3], 2, d[2], d[3], 2), "dd_add strided")
+    torch.cuda.synchronize()
+    w2 = dd_add_ref((xh[::3][:m], xl[::3][:m]), (yh[::2][:m], yl[::2][:m]))
+    assert np.array_equal(d[2].cpu().numpy()[::2][:m], w2[0]) and np.array_equal(d[3].cpu().numpy()[::2][:m], w2[1])
+    assert np.array_equal(d[2].cpu().numpy()[1::2], yh[1::2])        # untouched between the strides
+    # the scalar of dd_scal comes from a device computation
+    x = make_pair((1, 4097), seed=15)
+    y = make_pair((4097, 1), seed=16)
+    r = ag.dd_dot_raw(dd_t(x), dd_t((y[0].T, y[1].T)))          # on the device
+    X = dd_t(make_pair((33, 7), seed=17))
+    Y = ag.dd_scale(r, X)
+    alpha = r.cpu().numpy()
+    Ra = dd_gemm_ref((np_pair(X)[0].reshape(-1, 1), np_pair(X)[1].reshape(-1, 1)),
+                     (np.array([[alpha[0]]]), np.array([[alpha[1]]])))[:2]
+    got = np_pair(Y)
+    assert np.array_equal(got[0].reshape(-1, 1), Ra[0]) and np.array_equal(got[1].reshape(-1, 1), Ra[1])
+
+
+def reuse_ref(W, X, G):
+    """Oracle gradients of L = sum((W (W X)) o G): dW = G H^T + W^T G X^T
+    (the two uses of W, added in FP64x2), dX = W^T (W^T G)."""
+    from oracle.ref import dd_add_ref
+    H = dd_gemm_ref(W, X)[:2]
+    Y = dd_gemm_ref(W, H)[:2]
+    n = Y[0].size
+    L = dd_gemm_ref((Y[0].reshape(1, n), Y[1].reshape(1, n)), (G[0].reshape(n, 1), G[1].reshape(n, 1)))[:2]
+    dH = dd_gemm_ref(W, G, transa=True)[:2]
+    dW = dd_add_ref(dd_gemm_ref(G, H, transb=True)[:2], dd_gemm_ref(dH, X, transb=True)[:2])
+    return {"L": (L[0][0, 0], L[1][0, 0]), "dW": dW, "dX": dd_gemm_ref(W, dH, transa=True)[:2]}
+
+
+def reuse_abs(W, X, G):
+    aw, ax, ag_ = (np.abs(M[0]) for M in (W, X, G))
+    aH = aw @ ax
+    adH = aw.T @ ag_
+    return {"dW": ag_ @ aH.T + adH @ ax.T, "dX": aw.T @ adH, "L": float(np.sum((aw @ aH) * ag_)),
+            "quad": ag_ @ ax.T}
+
+
+def reuse_loss(W, X, G):
+    return ag.dot(ag.matmul(W, ag.matmul(W, X)), G)
+
+
+def test_reused_weight_small_full_against_oracle():
+    """A DD tensor used twice: L = sum((W (W X)) o G).  The gradient of W is
+    the FP64x2 sum of the two uses' gradients (a DDGrad accumulation), held
+    to the oracle's within four times the GEMM tolerance of each term;
+    plane-by-plane addition would miss it by about 2^-53 |dW|."""
+    n, b = 96, 40
+    W, X, G = make_pair((n, n), seed=21), make_pair((n, b), seed=22), make_pair((n, b), seed=23)
+    tW, tX, tG = (dd_t(M).requires_grad_() for M in (W, X, G))
+    L = reuse_loss(tW, tX, tG)
+    L.backward(torch_ones())
+    assert isinstance(tW.grad, ag.DDGrad)
+    R = reuse_ref(W, X, G)
+    S = reuse_abs(W, X, G)
+    assert abs(dd_val(*L.detach().cpu().numpy()) - dd_val(*R["L"])) <= Fraction(3 * 64 * n * U * S["L"])
+    for key, t in (("dW", tW), ("dX", tX)):
+        tol = 4 * 64 * n * U * S[key] + 2.0 ** -100 * np.abs(R[key][0])
+        assert np.all(diff(np_pair(t.grad), R[key]) <= tol), key
+    # the same gradient formed plane by plane misses the tolerance
+    import torch
+    g1 = ag.gemm(dd_t(G), ag.gemm(dd_t(W), dd_t(X)), transY=True)
+    g2 = ag.gemm(ag.gemm(dd_t(W), dd_t(G), transX=True), dd_t(X), transY=True)
+    planes = np_pair(g1 + g2)
+    assert not np.all(diff(planes, R["dW"]) <= 4 * 64 * n * U * S["dW"])
+    torch.cuda.synchronize()
+
+
+def test_reused_weight_config_size_finite_differences():
+    """L = sum((W (W X)) o G) with W 2048^2, X, G 2048 x 512: gradients of 64
+    entries (43 of W, 21 of X) against FP64x2 central differences.  L is
+    linear in X and in every off-diagonal entry of W, and quadratic in a
+    diagonal entry W_aa with coefficient (G X^T)_aa, so the difference over
+    the steps actually taken is exact up to (G X^T)_aa (w+ + w- - 2 w)."""
+    import torch
+    n, b, h = 2048, 512, 2.0 ** -20
+    W, X, G = make_pair((n, n), seed=31), make_pair((n, b), seed=32), make_pair((n, b), seed=33)
+    log(f"reused weight chain W {n}x{n}, X {n}x{b}")
+    tW, tX, tG = (dd_t(M).requires_grad_() for M in (W, X, G))
+    reuse_loss(tW, tX, tG).backward(torch_ones())
+    torch.cuda.synchronize()
+    grads = {"W": np_pair(tW.grad), "X": np_pair(tX.grad)}
+    S = reuse_abs(W, X, G)
+    errL = 3 * 64 * n * U * S["L"]
+    rng = np.random.default_rng(2304)
+    picks = ([("W", (int(i), int(j))) for i, j in rng.integers(0, n, size=(40, 2))]
+             + [("W", (int(i), int(i))) for i in rng.integers(0, n, 3)]
+             + [("X", (int(i), int(j))) for i, j in zip(rng.integers(0, n, 21), rng.integers(0, b, 21))])
+    mats, base = {"W": W, "X": X}, {"W": tW.detach(), "X": tX.detach()}
+    worst = 0.0
+    for name, idx in picks:
+        Lpm, steps = [], []
+        for sgn in (+1, -1):
+            pert, w = _perturbed(base[name], mats[name], idx, sgn * h)
+            args = dict(base)
+            args[name] = pert
+            with torch.no_grad():
+                Lpm.append(dd_val(*reuse_loss(args["W"], args["X"], tG.detach()).cpu().numpy()))
+            steps.append(w)
+        delta = steps[0] - steps[1]
+        g_fd = (Lpm[0] - Lpm[1]) / delta
+        g = dd_val(grads[name][0][idx], grads[name][1][idx])
+        key = "d" + name
+        tol_g = 2 * 64 * n * U * S[key][idx] + 3 * U * abs(float(g))
+        quad = 0
+        if name == "W" and idx[0] == idx[1]:
+            w0 = dd_val(mats["W"][0][idx], mats["W"][1][idx])
+            quad = Fraction(float(S["quad"][idx])) * abs(steps[0] + steps[1] - 2 * w0)
+        bound = Fraction(2 * errL) / abs(delta) + Fraction(tol_g) + quad
+        err = abs(g_fd - g)
+        worst = max(worst, float(err / bound))
+        assert err <= bound, (name, idx, float(err), float(bound))
+    log(f"reused weight, finite differences: worst error / bound = {worst:.3e}")

@@ -109,3 +109,36 @@ def test_entries_equal_full_bitwise_and_threads():
     J = np.array([0, 12, 5, 0, 11])
     h1, l1, _ = dd_gemm_ref_entries(P["A"], P["B"], P["C"], I, J)
     assert np.array_equal(h1, h0[I, J]) and np.array_equal(l1, l0[I, J])
+
+
+def test_dd_add_vector_against_rationals():
+    """The entry-wise accurate FP64x2 addition of the C oracle (the one its
+    triple loop accumulates with).  When the high words cancel, the low
+    words' error-free sum survives: (1, 2^-60) + (-1, 3 2^-114) is
+    2^-60 + 3 2^-114 exactly, held as (2^-60 + 2^-112, -2^-114); two
+    disjoint words add exactly; x + 0 = x; on random pairs with heavy
+    cancellation the relative error is within 3 2^-106, the published bound
+    of this algorithm (Joldes, Muller and Popescu, 2017: AccurateDWPlusDW),
+    and the result is a normalised pair (|lo| <= ulp(hi) / 2)."""
+    from oracle.ref import dd_add_ref
+    h, l = dd_add_ref((np.array([1.0, 0.5, 0.75]), np.array([2.0 ** -60, 0.0, 2.0 ** -60])),
+                      (np.array([-1.0, 2.0 ** -70, 0.0]), np.array([3 * 2.0 ** -114, 0.0, 0.0])))
+    assert (float(h[0]), float(l[0])) == (2.0 ** -60 + 2.0 ** -112, -2.0 ** -114)
+    assert (float(h[1]), float(l[1])) == (0.5, 2.0 ** -70)
+    assert (float(h[2]), float(l[2])) == (0.75, 2.0 ** -60)
+    rng = np.random.default_rng(81)
+    n = 20000
+    xh = rng.uniform(-1, 1, n) * np.ldexp(1.0, rng.integers(-20, 20, n))
+    xl = xh * rng.uniform(-1, 1, n) * 2.0 ** -53
+    yh = -xh * (1 + rng.integers(-8, 9, n) * 2.0 ** -52)
+    yh[::3] = rng.uniform(-1, 1, (n + 2) // 3)            # and some without cancellation
+    yl = yh * rng.uniform(-1, 1, n) * 2.0 ** -53
+    # normalised pairs, as the bound assumes (QuickTwoSum: |hi| >= |lo|)
+    qs = lambda a, b: (a + b, b - ((a + b) - a))
+    (xh, xl), (yh, yl) = qs(xh, xl), qs(yh, yl)
+    h, l = dd_add_ref((xh, xl), (yh, yl))
+    for t in range(n):
+        exact = Fraction(float(xh[t])) + Fraction(float(xl[t])) + Fraction(float(yh[t])) + Fraction(float(yl[t]))
+        got = Fraction(float(h[t])) + Fraction(float(l[t]))
+        assert abs(got - exact) <= 3 * U2 * abs(exact), t
+        assert h[t] == 0 or abs(l[t]) <= np.spacing(abs(h[t])) / 2, t
