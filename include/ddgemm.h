@@ -370,15 +370,18 @@ int32_t dd_version(void);
  * |x2| <= ulp(x1)), by the cascade with six FP64 digits (the case Sec. 6.2
  * names).  Per rank-kc block the widths c0..c4 are the largest for which
  * bins 0..4 are exact (about 156 bits in all at kc = 256), Sigma / T come
- * from the largest |x0| per row / column, and the 21 products run as six
- * plain FP64 GEMMs of the vendor library (rocBLAS), one per bin with its
- * products stacked along the inner dimension, into six bin matrices, which
- * this library's kernels turn into triple words (a fixed error-free
- * summation), accumulate and add to C.  Planes x0, x1, x2 of each operand
- * share one leading dimension; all device pointers, column-major.  kc: 0 =
- * 256, else a multiple of 4 in [4, 4096].  Status and quick returns as for
- * dd_gemm_ex; argument i invalid gives -i.  Not for graph capture (the
- * library may allocate); workspace NULL with ws_bytes 0 uses the cached one.
+ * from the largest |x0| per row / column, and the 21 products run on the
+ * FP64 matrix cores in one fused kernel of this library: bins 0..4 exact,
+ * a tail bin over the suffix sums of B's planes, the six bins turned into a
+ * triple word per block by a fixed error-free summation and accumulated
+ * the same way, C added last.  Planes x0, x1, x2 of each operand share one
+ * leading dimension; all device pointers, column-major.  kc: 0 = 256, else
+ * a multiple of 4 in [4, 4096].  Status and quick returns as for
+ * dd_gemm_ex; argument i invalid gives -i.  The workspace holds the row and
+ * column maxima and 48 (mpad + npad) kpad bytes of packed digit planes
+ * (mpad, npad rounded up to 64, kpad to 8), plus 4352 bytes per 16 rows and
+ * columns; workspace NULL with ws_bytes 0 uses the library's cached one
+ * (which may allocate, so not under graph capture).
  * ------------------------------------------------------------------------ */
 size_t td_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k, int32_t kc);
 

@@ -194,27 +194,6 @@ __device__ __forceinline__ void combine(Bins& B, double (&acc_h)[kSub][kWaveCB],
   }
 }
 
-// Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD b % 8)
-// and each XCD has its own L2.  Give every XCD a contiguous range of tiles
-// and walk that range in groups of kGroupM tile rows, so the workgroups that
-// run together on one XCD share a few A and B strips in its L2.
-constexpr int64_t kXcds = 8;
-constexpr int64_t kGroupM = 8;
-
-__device__ __forceinline__ void tile_of_block(int64_t b, int64_t tiles_m, int64_t tiles_n,
-                                              int64_t& tm, int64_t& tn) {
-  const int64_t T = tiles_m * tiles_n;
-  int64_t L = b;
-  if (T % kXcds == 0) L = (b % kXcds) * (T / kXcds) + b / kXcds;
-  const int64_t per_group = kGroupM * tiles_n;
-  const int64_t g = L / per_group;
-  const int64_t first_m = g * kGroupM;
-  const int64_t gm = tiles_m - first_m < kGroupM ? tiles_m - first_m : kGroupM;
-  const int64_t r = L - g * per_group;
-  tm = first_m + r % gm;
-  tn = r / gm;
-}
-
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
 }  // namespace

@@ -60,10 +60,10 @@ hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const dou
                           const int32_t* aexp = nullptr, const int32_t* bexp = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
-// FP64x3: workspace offsets (bytes) and the whole product (split, 21
-// library GEMMs and a combine per rank-kc block, epilogue).
+// FP64x3: workspace offsets (bytes: row/column maxima, packed digit planes)
+// and the whole product (maxima, split, the fused product kernel).
 struct TdOffsets {
-  size_t amax, bmax, aplanes, bplanes, bins, acc;
+  size_t amax, bmax, aplanes, bplanes;
 };
 size_t td_workspace_bytes(int64_t m, int64_t n, int64_t k, TdOffsets* off);
 hipError_t run_td(int64_t m, int64_t n, int64_t k, int64_t kc, const double* A0, const double* A1,

@@ -1,40 +1,48 @@
 // FP64x3 (triple-word) GEMM by the cascade with six FP64 digits (the case
-// Sec. 6.2 names: FP64x3 in terms of FP64).  Unfused: this library's split
-// into column-major digit panels, per rank-kc update the 21 products as six
-// plain FP64 GEMMs of the vendor library (rocBLAS), one per bin (the
-// products of a bin stacked along the inner dimension), this library's
-// combine into a triple-word accumulator, and its epilogue.
+// Sec. 6.2 names: FP64x3 in terms of FP64), products fused on the FP64
+// matrix cores.
 //
-// Layout per rank-kc block b (kb columns of op(A), kb rows of op(B)):
-//  * A: the six m x kb digit panels side by side in descending order,
-//    [A_5' | A_4' | ... | A_0'] (ld m), at b * 6 kc m;
-//  * B: the six kb x n digit panels stacked in ascending order,
-//    [B_0'; B_1'; ...; B_5'] (ld 6 kb), at b * 6 kc n; and the suffix sums
-//    stacked the same way, [U_0'; ...; U_5'] (U_5' = B_5'), after all of B.
-// Bin L <= 4 is then [A_L' | ... | A_0'] times [B_0'; ...; B_L'], one GEMM of
-// inner dimension (L+1) kb, and the tail bin [A_5' | ... | A_0'] times
-// [U_0'; ...; U_5'].  Bins 0..4 stay exact in any summation order: the
-// widths rule bounds the sum of the magnitudes of all their products.
-//
-// Steps:
+// Phase one (HBM bound):
 //  * widths c0..c4 for a rank-kc block: the largest (in total, then in
 //    order) for which bins 0..4 are exact with digits of up to 3 level units
 //    (three words each contribute at most one);
 //  * Sigma / T from the largest |x0| per row of op(A) / column of op(B);
 //  * each scaled word cut as in Appendix A into five digits and a
 //    remainder, digits added level by level, remainders rounded in order;
-//    planes pre-weighted by 2^-D_(t-1);
-//  * bins L = 0..4: sum over i + j = L of A_i' B_j' (exact); tail bin: sum
-//    over i of A_i' U_(5-i)', U the suffix sums of B's planes (each
-//    addition rounded once, from the last plane up to U_0');
-//  * triple words from bins, accumulator and C by a fixed sequence of
-//    error-free transforms: three VecSum passes (Ogita, Rump and Oishi), the
-//    last element the first word, two more passes for the second, the plain
-//    sum of the rest the third, one renormalising TwoSum chain.  It is a
-//    faithful stand-in for rounding the exact sum to three words (a few
-//    units of 2^-158 relative, plus 2^-200 of the terms' magnitudes).
+//    planes pre-weighted by 2^-D_(t-1) and packed for v_mfma_f64_4x4x4_4b_f64
+//    as the FP64x2 planes are: A per 16-row block and group of 4 inner
+//    indices, the six planes A_0'..A_5', position s*16 + kk*4 + i within a
+//    plane; B per 16-column block the six planes B_0'..B_5', lane kk*16 + c.
+//
+// Phases two and three (FP64 MFMA bound), one kernel: a workgroup of 8
+// waves (two per SIMD) owns a 64x64 tile of C, each wave 16x32.  Per group
+// of 4 inner indices the 21 products: bin L = 0..4 takes A_i' B_j' with
+// i + j = L (exact, by the widths rule), the tail bin A_i' U_(5-i)' with the
+// suffix sums U_5' = B_5', U_t' = B_t' + U_(t+1)' formed in registers just
+// before they are used (the same roundings, in the same order, as the
+// oracle's).  The products go by plane of A (A_0' with six planes of B,
+// A_1' with five, ...), ordered so that the same bin is updated at most
+// every other product.  Per rank-kc block the six bins become a triple word
+// by a fixed sequence of error-free transforms and are added to the
+// triple-word accumulator the same way; Sigma / T and C at the end.
+//
+// Operand staging: one LDS stage per group of 4 inner indices (24 KiB: six
+// planes of four 16-row blocks of A and four 16-column blocks of B), three
+// stage buffers.  Each group runs in two halves around one barrier: the
+// first half (products of A_0', A_1') writes the next stage, which was
+// loaded into registers during the previous group; the second half (A_2'
+// .. A_5') reads the next group's B planes and A_0' from the stage just
+// written and loads the stage after it.  With three buffers the stage
+// written in a first half is one whose last reads ended before the
+// previous barrier.
+//
+// Triple words: three VecSum passes (Ogita, Rump and Oishi) over the terms,
+// least significant first, the last element the first word, two more
+// passes over the rest for the second word, the plain sum of what remains
+// the third, one renormalising TwoSum chain.  It stands in for rounding the
+// exact sum to three words, within a few units of 2^-158 of the sum plus
+// 2^-200 of the terms' magnitudes.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 #include <stdint.h>
 
 #include <array>
@@ -51,6 +59,19 @@ namespace ddk {
 namespace {
 
 constexpr int kD = 53;
+constexpr int kP3 = 6;                        // digit planes per operand
+constexpr int kWaves3 = 8;
+constexpr int kFrag3 = kP3 * kLanes;          // doubles per block and group (384)
+constexpr int kAStage3 = 4 * kFrag3;          // A part of an LDS stage: four 16-row blocks
+constexpr int kStage3 = 2 * kAStage3;         // doubles per stage (24 KiB)
+constexpr int kNBuf3 = 3;
+constexpr int kPieces3 = kStage3 / 128;       // 1 KiB pieces per stage (24), three per wave
+
+// Packed planes of one 16-row (16-column) block are contiguous over k; the
+// blocks are 4 KiB + 256 B further apart than their size (L2 sets).
+constexpr int64_t td_block_stride(int64_t K4) { return K4 * kFrag3 + kBlockPad; }
+
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 struct Widths3 {
   int c[5];
@@ -70,73 +91,59 @@ __device__ __forceinline__ void split6(double v, const Widths3& W, double d[6]) 
   d[5] = v;
 }
 
-// Planes of op(X) entry (r, c) at X[r*sr + c*sc] scaled by 2^-e: out[t] =
-// pre-weighted level t (levels 0..4 exact sums, level 5 rounded in order)
-// and the three scaled words.
+// Pre-weighted levels of an entry (x0, x1, x2) scaled by 2^-e: levels 0..4
+// exact sums of the three words' digits, level 5 the remainders rounded in
+// order.
 __device__ __forceinline__ void split_entry3(double x0, double x1, double x2, int e, const Widths3& W,
-                                             double out[6], double ys[3]) {
-  ys[0] = __builtin_ldexp(x0, -e);
-  ys[1] = __builtin_ldexp(x1, -e);
-  ys[2] = __builtin_ldexp(x2, -e);
+                                             double out[6]) {
   double a[6], b[6], c[6];
-  split6(ys[0], W, a);
-  split6(ys[1], W, b);
-  split6(ys[2], W, c);
+  split6(__builtin_ldexp(x0, -e), W, a);
+  split6(__builtin_ldexp(x1, -e), W, b);
+  split6(__builtin_ldexp(x2, -e), W, c);
 #pragma unroll
-  for (int t = 0; t < 5; ++t) out[t] = ((a[t] + b[t]) + c[t]) * W.w[t];
-  out[5] = ((a[5] + b[5]) + c[5]) * W.w[5];
+  for (int t = 0; t < 6; ++t) out[t] = ((a[t] + b[t]) + c[t]) * W.w[t];
 }
 
-// Block of inner index p (blocks of kc, the last one kb = k - b kc wide).
-struct BlockPos {
-  int64_t b, pl, kb;
-};
-__device__ __forceinline__ BlockPos block_pos(int64_t p, int64_t k, int64_t kc) {
-  const int64_t b = p / kc, first = b * kc;
-  return {b, p - first, k - first < kc ? k - first : kc};
-}
-
-// op(A) entries (i, p) into the descending digit panels of their block.
+// One wave per 64-lane fragment (16-row block rb, group kq) of op(A),
+// op(A)(i, p) = X[i*si + p*sp]; zero outside m, k.
 __global__ void __launch_bounds__(256)
-td_split_a(const double* __restrict__ X0, const double* __restrict__ X1, const double* __restrict__ X2,
-           int64_t si, int64_t sp, int64_t m, int64_t k, int64_t kc, const uint64_t* __restrict__ amax, Widths3 W,
-           double* __restrict__ panels) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= m * k) return;
-  const int64_t i = t % m, p = t / m, idx = i * si + p * sp;
-  double out[6], ys[3];
-  split_entry3(X0[idx], X1[idx], X2[idx], exp_of_bits(amax[i]), W, out, ys);
-  const BlockPos q = block_pos(p, k, kc);
-  double* base = panels + q.b * 6 * kc * m + q.pl * m + i;
-#pragma unroll
-  for (int l = 0; l < 6; ++l) base[(5 - l) * q.kb * m] = out[l];
-}
-
-// op(B) entries (p, j) into the ascending digit panels of their block and
-// the suffix sums U_5' = B_5', U_t' = B_t' + U_(t+1)' (from the last plane
-// up to U_0') into the U panels, which start at `upanels`.
-__global__ void __launch_bounds__(256)
-td_split_b(const double* __restrict__ X0, const double* __restrict__ X1, const double* __restrict__ X2,
-           int64_t sp, int64_t sj, int64_t k, int64_t n, int64_t kc, const uint64_t* __restrict__ bmax, Widths3 W,
-           double* __restrict__ panels, double* __restrict__ upanels) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= k * n) return;
-  const int64_t p = t % k, j = t / k, idx = p * sp + j * sj;
-  double out[6], ys[3];
-  split_entry3(X0[idx], X1[idx], X2[idx], exp_of_bits(bmax[j]), W, out, ys);
-  const BlockPos q = block_pos(p, k, kc);
-  const int64_t off = q.b * 6 * kc * n + j * 6 * q.kb + q.pl;
-  double* base = panels + off;
-  double* ub = upanels + off;
-#pragma unroll
-  for (int l = 0; l < 6; ++l) base[l * q.kb] = out[l];
-  double u = out[5];
-  ub[5 * q.kb] = u;
-#pragma unroll
-  for (int l = 4; l >= 0; --l) {
-    u = out[l] + u;
-    ub[l * q.kb] = u;
+td_pack_a(const double* __restrict__ X0, const double* __restrict__ X1, const double* __restrict__ X2,
+          int64_t si, int64_t sp, int64_t m, int64_t k, int64_t K4, int64_t nfrag,
+          const uint64_t* __restrict__ amax, Widths3 W, double* __restrict__ Apack) {
+  const int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (frag >= nfrag) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t rb = frag / K4, kq = frag - rb * K4;
+  const int64_t i = rb * 16 + (lane >> 4) * 4 + (lane & 3), p = kq * 4 + ((lane >> 2) & 3);
+  double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i < m && p < k) {
+    const int64_t idx = i * si + p * sp;
+    split_entry3(X0[idx], X1[idx], X2[idx], exp_of_bits(amax[i]), W, out);
   }
+  double* dst = Apack + rb * td_block_stride(K4) + kq * kFrag3 + lane;
+#pragma unroll
+  for (int t = 0; t < kP3; ++t) dst[t * kLanes] = out[t];
+}
+
+// One wave per fragment (16-column block cb, group kq) of op(B),
+// op(B)(p, j) = X[p*sp + j*sj].
+__global__ void __launch_bounds__(256)
+td_pack_b(const double* __restrict__ X0, const double* __restrict__ X1, const double* __restrict__ X2,
+          int64_t sp, int64_t sj, int64_t k, int64_t n, int64_t K4, int64_t nfrag,
+          const uint64_t* __restrict__ bmax, Widths3 W, double* __restrict__ Bpack) {
+  const int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (frag >= nfrag) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t cb = frag / K4, kq = frag - cb * K4;
+  const int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
+  double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (j < n && p < k) {
+    const int64_t idx = p * sp + j * sj;
+    split_entry3(X0[idx], X1[idx], X2[idx], exp_of_bits(bmax[j]), W, out);
+  }
+  double* dst = Bpack + cb * td_block_stride(K4) + kq * kFrag3 + lane;
+#pragma unroll
+  for (int t = 0; t < kP3; ++t) dst[t * kLanes] = out[t];
 }
 
 __device__ __forceinline__ void vec_sum6(double a[6]) {
@@ -148,7 +155,7 @@ __device__ __forceinline__ void vec_sum5(double a[5]) {
   for (int i = 1; i < 5; ++i) two_sum(a[i], a[i - 1], a[i], a[i - 1]);
 }
 
-// The triple word of six terms, least significant first.
+// The triple word of six terms given least significant first.
 __device__ __forceinline__ void td_from6(double a[6], double& r0, double& r1, double& r2) {
   vec_sum6(a);
   vec_sum6(a);
@@ -164,47 +171,272 @@ __device__ __forceinline__ void td_from6(double a[6], double& r0, double& r1, do
   two_sum(r1, r2, r1, r2);
 }
 
-// acc := acc + TD(bins), bins six m x n planes (bins 0..4, tail).
-__global__ void __launch_bounds__(256)
-td_combine(const double* __restrict__ bins, int64_t mn, double* __restrict__ acc) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= mn) return;
-  double t[6] = {bins[5 * mn + i], bins[4 * mn + i], bins[3 * mn + i], bins[2 * mn + i], bins[mn + i], bins[i]};
-  double b0, b1, b2;
-  td_from6(t, b0, b1, b2);
-  double u[6] = {acc[2 * mn + i], b2, acc[mn + i], b1, acc[i], b0};
-  td_from6(u, b0, b1, b2);
-  acc[i] = b0;
-  acc[mn + i] = b1;
-  acc[2 * mn + i] = b2;
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
+__device__ __forceinline__ void lds_reads_done() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+constexpr int kSub3 = 4;   // 4-row sub-blocks per wave
+constexpr int kCG3 = 2;    // 16-column groups per wave
+constexpr int kTail = 5;   // index of the tail bin
+
+struct Bins3 {
+  double b[6][kSub3][kCG3];   // bins 0..4, tail
+};
+
+// One product: 8 independent MFMAs into bin `L`.
+__device__ __forceinline__ void product(Bins3& B, int L, const double (&a)[kSub3], const double (&b)[kCG3]) {
+#pragma unroll
+  for (int s = 0; s < kSub3; ++s)
+#pragma unroll
+    for (int g = 0; g < kCG3; ++g) B.b[L][s][g] = mfma4(a[s], b[g], B.b[L][s][g]);
 }
 
-// C := C + acc 2^(e_i + f_j).
-__global__ void __launch_bounds__(256)
-td_epilogue(const double* __restrict__ acc, int64_t m, int64_t n, const uint64_t* __restrict__ amax,
-            const uint64_t* __restrict__ bmax, double* __restrict__ C0, double* __restrict__ C1,
-            double* __restrict__ C2, int64_t ldc) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t mn = m * n;
-  if (t >= mn) return;
-  const int64_t i = t % m, j = t / m, c = i + j * ldc;
-  const int sh = exp_of_bits(amax[i]) + exp_of_bits(bmax[j]);
-  double u[6] = {C2[c], __builtin_ldexp(acc[2 * mn + t], sh), C1[c], __builtin_ldexp(acc[mn + t], sh),
-                 C0[c], __builtin_ldexp(acc[t], sh)};
-  double r0, r1, r2;
-  td_from6(u, r0, r1, r2);
-  C0[c] = r0;
-  C1[c] = r1;
-  C2[c] = r2;
+__device__ __forceinline__ void read_a(double (&a)[kSub3], const double* sA, int t) {
+#pragma unroll
+  for (int s = 0; s < kSub3; ++s) a[s] = sA[t * kLanes + s * 16];
 }
 
-__global__ void td_fill(double* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = 0.0;
+__device__ __forceinline__ void read_b(double (&b)[kP3][kCG3], const double* sB) {
+#pragma unroll
+  for (int t = 0; t < kP3; ++t)
+#pragma unroll
+    for (int g = 0; g < kCG3; ++g) b[t][g] = sB[g * kFrag3 + t * kLanes];
+}
+
+__device__ __forceinline__ void add_u(double (&u)[kCG3], const double (&b)[kCG3]) {
+#pragma unroll
+  for (int g = 0; g < kCG3; ++g) u[g] = b[g] + u[g];
+}
+
+// Where the memory instructions of a group go among its 168 MFMAs.  Each
+// plane of A is read during the products of the plane before it, and the
+// next group's operands only once A_2' and A_3' are no longer needed, which
+// bounds the registers in flight.
+// First half, 88 MFMAs (A_0': 48, A_1': 40): reads of A_1', the three LDS
+// writes of the next stage, reads of A_2'.
+__device__ __forceinline__ void interleave_first_half() {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read (A_1')
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);   // MFMA
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // DS write (next stage)
+    __builtin_amdgcn_sched_group_barrier(0x008, 10, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read (A_2')
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, 24, 0);
+}
+
+// Second half, 80 MFMAs (A_2': 32, A_3': 24, A_4': 16, A_5': 8): the three
+// global loads of the stage after next, reads of A_3', A_4', A_5', then the
+// next group's B planes and A_0' (16 reads).
+__device__ __forceinline__ void interleave_second_half() {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // VMEM read
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read (A_3')
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read (A_4', A_5')
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read (next B planes, A_0')
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+  }
+}
+
+// Bins of a rank-kc block to a triple word, added to the accumulator; bins reset.
+__device__ __forceinline__ void combine3(Bins3& B, double (&r0)[kSub3][kCG3], double (&r1)[kSub3][kCG3],
+                                         double (&r2)[kSub3][kCG3]) {
+#pragma unroll
+  for (int s = 0; s < kSub3; ++s)
+#pragma unroll
+    for (int g = 0; g < kCG3; ++g) {
+      double t[6] = {B.b[kTail][s][g], B.b[4][s][g], B.b[3][s][g], B.b[2][s][g], B.b[1][s][g], B.b[0][s][g]};
+      double w0, w1, w2;
+      td_from6(t, w0, w1, w2);
+      double u[6] = {r2[s][g], w2, r1[s][g], w1, r0[s][g], w0};
+      td_from6(u, r0[s][g], r1[s][g], r2[s][g]);
+#pragma unroll
+      for (int L = 0; L < 6; ++L) B.b[L][s][g] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kWaves3 * 64)
+td_cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpack,
+                  const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax, int64_t K4, int32_t kcq,
+                  int64_t m, int64_t n, int64_t tiles_m, int64_t tiles_n, double* __restrict__ C0,
+                  double* __restrict__ C1, double* __restrict__ C2, int64_t ldc) {
+  __shared__ __attribute__((aligned(16))) double lds[kNBuf3 * kStage3];
+  int64_t tm, tn;
+  tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave >> 1, wn = wave & 1;     // 16-row block wm, 32-column half wn
+  const int64_t rb0 = tm * 4 + wm, cb0 = tn * 4 + wn * kCG3;
+
+  Bins3 bins;
+  double r0[kSub3][kCG3], r1[kSub3][kCG3], r2[kSub3][kCG3];
+#pragma unroll
+  for (int s = 0; s < kSub3; ++s)
+#pragma unroll
+    for (int g = 0; g < kCG3; ++g) {
+#pragma unroll
+      for (int L = 0; L < 6; ++L) bins.b[L][s][g] = 0.0;
+      r0[s][g] = r1[s][g] = r2[s][g] = 0.0;
+    }
+
+  // Piece d of a stage (d = wave, wave + 8, wave + 16): d < 12 is chunk d%3
+  // of 16-row block d/3 of A, else chunk e%3 of 16-column block e/3 of B
+  // (e = d - 12).  A block's group is 384 contiguous doubles, 3 pieces.
+  const double* psrc[3];
+  int pdst[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int d = wave + c * kWaves3;
+    if (d < 12) {
+      const int blk = d / 3, i = d % 3;
+      psrc[c] = Apack + (tm * 4 + blk) * td_block_stride(K4) + i * 128 + lane * 2;
+      pdst[c] = blk * kFrag3 + i * 128 + lane * 2;
+    } else {
+      const int e = d - 12, blk = e / 3, i = e % 3;
+      psrc[c] = Bpack + (tn * 4 + blk) * td_block_stride(K4) + i * 128 + lane * 2;
+      pdst[c] = kAStage3 + blk * kFrag3 + i * 128 + lane * 2;
+    }
+  }
+  d2 stg[3];
+  const int64_t last = K4 - 1;
+  auto load_stage = [&](int64_t st) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) stg[c] = *(const d2*)(psrc[c] + st * kFrag3);
+  };
+  auto store_stage = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) *(d2*)(lds + buf * kStage3 + pdst[c]) = stg[c];
+  };
+  const int aoff = wm * kFrag3 + (lane >> 4) * 4 + (lane & 3);
+  const int boff = kAStage3 + wn * kCG3 * kFrag3 + lane;
+
+  // Prologue: stage 0 in buffer 0, stage 1 in the staging registers; the
+  // first group's B planes and A_0' in registers.
+  load_stage(0);
+  store_stage(0);
+  load_stage(last > 0 ? 1 : 0);
+  lds_reads_done();
+  lds_barrier();
+  double bx[kP3][kCG3], by[kP3][kCG3], ax0[kSub3], ay0[kSub3];
+  read_b(bx, lds + boff);
+  read_a(ax0, lds + aoff, 0);
+
+  int32_t inblk = 0;
+  int cur = 0;                                 // buffer of the current group
+  // One group: bc / ac0 hold its B planes and A_0'; bn / an0 receive the
+  // next group's.  The last group reads and loads in-bounds copies that are
+  // not used.
+  auto group = [&](int64_t st, double (&bc)[kP3][kCG3], double (&ac0)[kSub3], double (&bn)[kP3][kCG3],
+                   double (&an0)[kSub3]) {
+    const int nxt = cur == kNBuf3 - 1 ? 0 : cur + 1;
+    const double* sA = lds + cur * kStage3 + aoff;
+    double a1[kSub3], a2[kSub3], a3[kSub3], a4[kSub3], a5[kSub3];
+    double u[kCG3];
+    // first half: A_0' with B_0'..B_4' and U_5' = B_5', A_1' with B_0'..B_3' and U_4'
+    read_a(a1, sA, 1);
+    product(bins, 0, ac0, bc[0]);
+    product(bins, 1, ac0, bc[1]);
+    product(bins, 2, ac0, bc[2]);
+    product(bins, 3, ac0, bc[3]);
+    product(bins, 4, ac0, bc[4]);
+    u[0] = bc[5][0];
+    u[1] = bc[5][1];
+    product(bins, kTail, ac0, u);
+    read_a(a2, sA, 2);
+    store_stage(nxt);
+    product(bins, 1, a1, bc[0]);
+    product(bins, 2, a1, bc[1]);
+    add_u(u, bc[4]);                           // U_4'
+    product(bins, kTail, a1, u);
+    product(bins, 3, a1, bc[2]);
+    product(bins, 4, a1, bc[3]);
+    interleave_first_half();
+    lds_reads_done();
+    lds_barrier();
+    // second half: A_2'..A_5'; the next group's operands from the stage
+    // just written, the stage after it from memory
+    load_stage(st + 2 <= last ? st + 2 : last);
+    read_a(a3, sA, 3);
+    read_a(a4, sA, 4);
+    read_a(a5, sA, 5);
+    product(bins, 2, a2, bc[0]);
+    add_u(u, bc[3]);                           // U_3'
+    product(bins, kTail, a2, u);
+    product(bins, 3, a2, bc[1]);
+    product(bins, 4, a2, bc[2]);
+    product(bins, 3, a3, bc[0]);
+    add_u(u, bc[2]);                           // U_2'
+    product(bins, kTail, a3, u);
+    product(bins, 4, a3, bc[1]);
+    add_u(u, bc[1]);                           // U_1'
+    product(bins, kTail, a4, u);
+    product(bins, 4, a4, bc[0]);
+    add_u(u, bc[0]);                           // U_0'
+    product(bins, kTail, a5, u);
+    read_b(bn, lds + nxt * kStage3 + boff);
+    read_a(an0, lds + nxt * kStage3 + aoff, 0);
+    interleave_second_half();
+    cur = nxt;
+    if (++inblk == kcq) {
+      inblk = 0;
+      combine3(bins, r0, r1, r2);
+    }
+  };
+  for (int64_t st = 0; st < K4; st += 2) {
+    group(st, bx, ax0, by, ay0);
+    group(st + 1, by, ay0, bx, ax0);
+  }
+  if (inblk != 0) combine3(bins, r0, r1, r2);
+
+  // Epilogue: C + acc 2^(e_i + f_j) as triple words.
+#pragma unroll
+  for (int s = 0; s < kSub3; ++s) {
+    const int64_t row = rb0 * 16 + s * 4 + (lane >> 4);
+    if (row >= m) continue;
+    const int er = exp_of_bits(amax[row]);
+#pragma unroll
+    for (int g = 0; g < kCG3; ++g) {
+      const int64_t col = (cb0 + g) * 16 + (lane & 15);
+      if (col >= n) continue;
+      const int sh = er + exp_of_bits(bmax[col]);
+      const int64_t c = row + col * ldc;
+      double u[6] = {C2[c], __builtin_ldexp(r2[s][g], sh), C1[c], __builtin_ldexp(r1[s][g], sh), C0[c],
+                     __builtin_ldexp(r0[s][g], sh)};
+      double w0, w1, w2;
+      td_from6(u, w0, w1, w2);
+      C0[c] = w0;
+      C1[c] = w1;
+      C2[c] = w2;
+    }
+  }
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
-
 
 }  // namespace
 
@@ -260,16 +492,23 @@ void td_widths(int64_t kc, int c[5]) {
   cache[kc] = r;
 }
 
+// Padded sizes: m, n to the 64x64 tile, k to whole pairs of groups (8).
+static void td_sizes(int64_t m, int64_t n, int64_t k, int64_t* mpad, int64_t* npad, int64_t* K4) {
+  *mpad = round_up(m > 0 ? m : 1, 64);
+  *npad = round_up(n > 0 ? n : 1, 64);
+  *K4 = round_up(k > 0 ? k : 1, 8) / 4;
+}
+
 size_t td_workspace_bytes(int64_t m, int64_t n, int64_t k, TdOffsets* off) {
+  int64_t mpad, npad, K4;
+  td_sizes(m, n, k, &mpad, &npad, &K4);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = (size_t)round_up((int64_t)(o + bytes), 256); return r; };
   TdOffsets t{};
-  t.amax = take(sizeof(uint64_t) * (size_t)m);
-  t.bmax = take(sizeof(uint64_t) * (size_t)n);
-  t.aplanes = take(sizeof(double) * 6 * (size_t)m * (size_t)k);
-  t.bplanes = take(sizeof(double) * 12 * (size_t)k * (size_t)n);   // digit panels, then U panels
-  t.bins = take(sizeof(double) * 6 * (size_t)m * (size_t)n);
-  t.acc = take(sizeof(double) * 3 * (size_t)m * (size_t)n);
+  t.amax = take(sizeof(uint64_t) * (size_t)mpad);
+  t.bmax = take(sizeof(uint64_t) * (size_t)npad);
+  t.aplanes = take(sizeof(double) * (size_t)(mpad / 16) * (size_t)td_block_stride(K4));
+  t.bplanes = take(sizeof(double) * (size_t)(npad / 16) * (size_t)td_block_stride(K4));
   if (off) *off = t;
   return o;
 }
@@ -278,16 +517,19 @@ hipError_t run_td(int64_t m, int64_t n, int64_t k, int64_t kc_in, const double* 
                   const double* A2, int64_t a_si, int64_t a_sp, const double* B0, const double* B1,
                   const double* B2, int64_t b_sp, int64_t b_sj, double* C0, double* C1, double* C2,
                   int64_t ldc, char* ws, hipStream_t s) {
-  if (m > 0x7fffffff || n > 0x7fffffff || k > 0x7fffffff) return hipErrorInvalidValue;
+  int64_t mpad, npad, K4;
+  td_sizes(m, n, k, &mpad, &npad, &K4);
+  const int64_t tiles = (mpad / 64) * (npad / 64);
+  if (tiles <= 0 || tiles > 0x7fffffff) return hipErrorInvalidValue;
   TdOffsets off;
   td_workspace_bytes(m, n, k, &off);
   uint64_t* amax = (uint64_t*)(ws + off.amax);
   uint64_t* bmax = (uint64_t*)(ws + off.bmax);
   double* Ap = (double*)(ws + off.aplanes);
   double* Bp = (double*)(ws + off.bplanes);
-  double* bins = (double*)(ws + off.bins);
-  double* acc = (double*)(ws + off.acc);
+  // one block when k <= kc (padding included), else blocks of kc (a multiple of 4)
   const int64_t kc = k < kc_in ? k : kc_in;
+  const int32_t kcq = (int32_t)(k <= kc_in ? K4 : kc_in / 4);
   Widths3 W;
   td_widths(kc, W.c);
   int D = 0;
@@ -298,45 +540,16 @@ hipError_t run_td(int64_t m, int64_t n, int64_t k, int64_t kc_in, const double* 
     D += W.c[t];
     W.w[t + 1] = std::ldexp(1.0, -D);
   }
-  hipError_t e = launch_fill_u64(amax, m, 0, s);
-  if (e == hipSuccess) e = launch_fill_u64(bmax, n, 0, s);
+  hipError_t e = launch_fill_u64(amax, mpad, 0, s);
+  if (e == hipSuccess) e = launch_fill_u64(bmax, npad, 0, s);
   if (e == hipSuccess) e = launch_max_abs_bits(A0, m, k, a_si, a_sp, amax, s);
   if (e == hipSuccess) e = launch_max_abs_bits(B0, n, k, b_sj, b_sp, bmax, s);
   if (e != hipSuccess) return e;
-  double* Up = Bp + 6 * k * n;
-  td_split_a<<<nblk(m * k), 256, 0, s>>>(A0, A1, A2, a_si, a_sp, m, k, kc, amax, W, Ap);
-  td_split_b<<<nblk(k * n), 256, 0, s>>>(B0, B1, B2, b_sp, b_sj, k, n, kc, bmax, W, Bp, Up);
-  const int64_t mn = m * n;
-  td_fill<<<nblk(3 * mn), 256, 0, s>>>(acc, 3 * mn);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-
-  BlasLease lease = blas_lease(s);
-  if (lease.status != hipSuccess) return lease.status;
-  rocblas_handle h = lease.h;
-
-  const double one = 1.0, zero = 0.0;
-  for (int64_t p0 = 0; p0 < k; p0 += kc) {
-    const int64_t kb = p0 + kc < k ? kc : k - p0;
-    const double* Ablk = Ap + p0 * 6 * m;   // [A_5' | ... | A_0'], each m x kb
-    const double* Bblk = Bp + p0 * 6 * n;   // [B_0'; ...; B_5'], ld 6 kb
-    const double* Ublk = Up + p0 * 6 * n;   // [U_0'; ...; U_5'], ld 6 kb
-    // bin L <= 4: [A_L' | ... | A_0'] [B_0'; ...; B_L']; tail: all six A
-    // panels times the U panels
-    for (int L = 0; L < 6; ++L) {
-      const int64_t np = L < 5 ? L + 1 : 6;
-      const double* A = Ablk + (6 - np) * kb * m;
-      const double* B = L < 5 ? Bblk : Ublk;
-      const rocblas_status st = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)m,
-                                              (rocblas_int)n, (rocblas_int)(np * kb), &one, A, (rocblas_int)m, B,
-                                              (rocblas_int)(6 * kb), &zero, bins + L * mn, (rocblas_int)m);
-      if (st != rocblas_status_success) return hipErrorLaunchFailure;
-    }
-    td_combine<<<nblk(mn), 256, 0, s>>>(bins, mn, acc);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  td_epilogue<<<nblk(mn), 256, 0, s>>>(acc, m, n, amax, bmax, C0, C1, C2, ldc);
+  const int64_t nfa = (mpad / 16) * K4, nfb = (npad / 16) * K4;
+  td_pack_a<<<(unsigned)((nfa + 3) / 4), 256, 0, s>>>(A0, A1, A2, a_si, a_sp, m, k, K4, nfa, amax, W, Ap);
+  td_pack_b<<<(unsigned)((nfb + 3) / 4), 256, 0, s>>>(B0, B1, B2, b_sp, b_sj, k, n, K4, nfb, bmax, W, Bp);
+  td_cascade_kernel<<<(unsigned)tiles, kWaves3 * 64, 0, s>>>(Ap, Bp, amax, bmax, K4, kcq, m, n, mpad / 64,
+                                                              npad / 64, C0, C1, C2, ldc);
   return hipGetLastError();
 }
 

@@ -105,8 +105,11 @@ def test_panel_scaling_option_and_workspace():
 def test_td_workspace_and_argument_checks():
     m, n, k = 100, 70, 300
     ws = dg.td_gemm_workspace_size(0, 0, m, n, k)
-    need = 8 * (m + n) + 8 * (6 * m * k + 12 * k * n + 9 * m * n)
-    assert need <= ws <= need + 6 * 256
+    mpad, npad, K4 = 128, 128, 304 // 4
+    # maxima, then six packed digit planes per 16-row (16-column) block over
+    # kpad, plus 544 doubles of padding per block
+    need = 8 * (mpad + npad) + 8 * (mpad // 16 + npad // 16) * (6 * 64 * K4 + 544)
+    assert need <= ws <= need + 4 * 256
     assert dg.td_gemm_workspace_size(0, 0, m, n, k, 64) == ws
     assert dg.td_gemm_workspace_size(0, 0, m, n, k, 6) == 0
     assert dg.td_gemm_workspace_size(2, 0, m, n, k) == 0 and dg.td_gemm_workspace_size(0, 0, 0, n, k) == 0
