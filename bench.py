@@ -86,7 +86,7 @@ def bench_batched(torch, dg, stream):
     dg.check(st, "dd_batched_plan_create")
     try:
         dg.check(dg.dd_batched_plan_tune(plan, pa[0], pa[1], pb[0], pb[1], pc[0], pc[1], 3, stream=stream))
-        _, ntiles, dyn, lpt, nbytes = dg.dd_batched_plan_info(plan)
+        _, ntiles, dyn, lpt, policy, nbytes = dg.dd_batched_plan_info(plan)
         g = torch.cuda.CUDAGraph()
         cap = torch.cuda.Stream()
         with torch.cuda.stream(cap):
@@ -121,7 +121,8 @@ def bench_batched(torch, dg, stream):
     finally:
         dg.dd_batched_plan_destroy(plan)
     return {"workload": "512 FP64x2 GEMMs, m, n, k each round(exp(U[ln 32, ln 1024])), uniform inputs",
-            "sum_2mnk": flops, "tiles": ntiles, "schedule": {"atomic_counter": bool(dyn), "lpt": bool(lpt)},
+            "sum_2mnk": flops, "tiles": ntiles,
+            "schedule": {"atomic_counter": bool(dyn), "lpt": bool(lpt), "tile_policy": policy},
             "graph_ms": round(gms, 3), "graph_gflops": round(flops / (gms * 1e-3) / 1e9, 1),
             "loop_of_dd_gemm_ms": round(lms, 3), "loop_gflops": round(flops / (lms * 1e-3) / 1e9, 1),
             "speedup": round(lms / gms, 2), "plan_device_bytes": nbytes}
@@ -784,6 +785,31 @@ def main():
                            "value": round(flops_eff / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 2),
                            "unit": "GFLOP/s"}
     del Ph, Pl
+
+    # the split done while operands are staged (no digit planes in memory):
+    # the same products and bits, the split repeated by every workgroup
+    Ph, Pl = C0h.clone(), C0l.clone()
+    oopts = {"algo": dg.DD_ALGO_CASCADE_ON_LOAD}
+    dg.check(dg.dd_gemm_ex(0, 0, m, n, k, Ah, Al, m, Bh, Bl, k, Ph, Pl, m, opts=oopts, stream=stream))
+    torch.cuda.synchronize()
+    Ph.copy_(C0h)
+    Pl.copy_(C0l)
+    ev0.record(stream)
+    dg.check(dg.dd_gemm_ex(0, 0, m, n, k, Ah, Al, m, Bh, Bl, k, Ph, Pl, m, opts=oopts, stream=stream))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    oms = ev0.elapsed_time(ev1)
+    Ch2, Cl2 = C0h.clone(), C0l.clone()
+    step_into = (Ch2, Cl2)
+    dg.check(dg.dd_gemm(m, n, k, Ah, Al, m, Bh, Bl, k, step_into[0], step_into[1], m, stream), "dd_gemm")
+    torch.cuda.synchronize()
+    result["split_on_load"] = {
+        "ms": round(oms, 3), "value": round(flops_eff / (oms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+        "time_over_packed_cascade": round(oms / ms_per_step, 4),
+        "workspace_bytes": dg.dd_gemm_workspace_size(0, 0, m, n, k, oopts),
+        "packed_workspace_bytes": dg.dd_gemm_workspace_size(0, 0, m, n, k),
+        "bitwise_equal_to_packed_cascade": bool(torch.equal(Ph, Ch2) and torch.equal(Pl, Cl2))}
+    del Ph, Pl, Ch2, Cl2
 
     if not args.no_cpu_baseline:
         from oracle.ref import dd_gemm_ref_entries  # CPU baseline leg only

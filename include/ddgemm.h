@@ -49,6 +49,8 @@ typedef int32_t dd_status;
 #define DD_ERR_UNSUPPORTED 3  /* the current device is not gfx950                */
 #define DD_ERR_INTERNAL 4     /* internal invariant violated (a library bug)     */
 
+/* Operation codes (the transa / transb / trans arguments, taken as int32_t
+ * so that any value can be passed and rejected). */
 typedef enum { DD_OP_N = 0, DD_OP_T = 1 } dd_op;
 
 typedef enum {
@@ -90,7 +92,18 @@ typedef enum {
    * there.  A comparator for the fused kernel; not for use under graph
    * capture (the library may allocate).  kc applies; flags and scaling do
    * not. */
-  DD_ALGO_SIMPLE_UNFUSED = 5
+  DD_ALGO_SIMPLE_UNFUSED = 5,
+  /* The cascade with the split done while operands are staged (the paper
+   * cascades while it packs, Sec. 4.3): after the row and column maxima,
+   * one kernel reads the caller's hi/lo planes, splits each staged entry as
+   * Appendix A does and runs the ten products from there.  No digit planes
+   * are stored, so the workspace is only the maxima (8 (mpad + npad)
+   * bytes); every workgroup splits the operand tiles it stages, so the
+   * split runs n/64 (m/64) times per entry, on the vector units, which do
+   * not overlap the FP64 matrix cores.  Bit-identical to
+   * DD_ALGO_CASCADE_F64.  kc and flags apply; scaling must be global, tile
+   * 0 or DD_TILE_64x64. */
+  DD_ALGO_CASCADE_ON_LOAD = 6
 } dd_algo;
 
 /* Where the cascade takes its powers of two Sigma (rows of op(A)) and T
@@ -120,6 +133,12 @@ typedef enum {
   DD_SCALING_BALANCE = 2
 } dd_scaling;
 
+/* Output tile shapes of the cascade's product kernel (rows x columns of C
+ * per workgroup).  Every shape computes every entry with the same
+ * arithmetic, so results do not depend on the shape; smaller tiles give
+ * more workgroups to small problems and less padding to ragged ones. */
+typedef enum { DD_TILE_AUTO = 0, DD_TILE_64x64 = 1, DD_TILE_32x64 = 2, DD_TILE_64x32 = 3 } dd_tile;
+
 /* Options of dd_gemm_ex / dd_gemm_batched.  A NULL pointer means all zero. */
 typedef struct {
   int32_t algo;        /* dd_algo                                                  */
@@ -127,7 +146,10 @@ typedef struct {
                           0 = 256.  Must be a multiple of 4 in [4, 4096].  The
                           split widths follow from min(kc, k) by the constraints
                           of Sec. 3.3.  Must be 0 for the slices variants.      */
-  int32_t tile;        /* must be 0 (tile configuration chosen by the library)    */
+  int32_t tile;        /* cascade: dd_tile; DD_TILE_AUTO = 64 x 64, or the shape
+                          dd_tune recorded for this problem when use_tuned = 1.
+                          Must be 0 for the other algorithms and the batched
+                          calls (a batched plan chooses per problem).           */
   int32_t slices;      /* slices variants: s in [1, 16]; 0 = 14 (BF16, FP16) or
                           16 (INT8)                                              */
   int32_t slice_bits;  /* slices variants: w; 0 = 8 (BF16, FP16) or 7 (INT8).
@@ -147,6 +169,9 @@ typedef struct {
                           is zero while a lower bin of that block is not.  No
                           correction is applied.  Must be NULL for the other
                           algorithms and for the batched calls.                  */
+  int32_t use_tuned;   /* cascade, 0 or 1: with tile = DD_TILE_AUTO, take the tile
+                          shape dd_tune recorded for (m, n, k, kc, scaling), if
+                          any (must be 0 for the other algorithms)              */
 } dd_gemm_opts;
 
 /*
@@ -173,8 +198,9 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
  * bytes of packed slices (b = 2 for BF16/FP16, 1 for INT8; kpad rounded up
  * to 64 for BF16/FP16 and to 128 for INT8) plus 4352 bytes per 32 rows and
  * columns, and, for s > 9, 8 mpad npad (ceil(s/3) - 3) bytes of FP64 group
- * sums.  Both add the row and column maxima. */
-size_t dd_gemm_workspace_size(dd_op transa, dd_op transb,
+ * sums.  Both add the row and column maxima.  DD_ALGO_CASCADE_ON_LOAD needs
+ * the maxima only. */
+size_t dd_gemm_workspace_size(int32_t transa, int32_t transb,
                               int64_t m, int64_t n, int64_t k,
                               const dd_gemm_opts* opts);
 
@@ -187,13 +213,30 @@ size_t dd_gemm_workspace_size(dd_op transa, dd_op transb,
  * allocate, so not under graph capture).  The workspace is in use until the
  * call's work on `stream` has finished.
  */
-dd_status dd_gemm_ex(dd_op transa, dd_op transb,
+dd_status dd_gemm_ex(int32_t transa, int32_t transb,
                      int64_t m, int64_t n, int64_t k,
                      const double* A_hi, const double* A_lo, int64_t lda,
                      const double* B_hi, const double* B_lo, int64_t ldb,
                      double* C_hi, double* C_lo, int64_t ldc,
                      void* workspace, size_t ws_bytes,
                      const dd_gemm_opts* opts, hipStream_t stream);
+
+/*
+ * The tuner of the cascade's output tile shape (the blocking parameters the
+ * paper leaves to the machine, Sec. 4.3): for each of the `count` shapes
+ * (host arrays m, n, k; op(A) = A, op(B) = B) it times the cascade with
+ * every tile shape, `repeats` times each after a warm-up, on zero operands
+ * it allocates itself (so not for graph capture; the time of the kernels
+ * does not depend on the values), and records the fastest for (m, n, k,
+ * kc, scaling) of `opts` (cascade only; tile 0, flags_out NULL).  Records
+ * are kept for the process and appended, as lines "s m n k kc scaling
+ * shape", to the file named by DDGEMM_TUNE_CACHE (read at first use), so a
+ * later process finds them too.  Calls with use_tuned = 1 then use them.
+ * shapes_out (host, may be NULL) receives the chosen dd_tile per shape (0
+ * for an empty one).  Synchronous.
+ */
+dd_status dd_tune(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                  const dd_gemm_opts* opts, int32_t repeats, int32_t* shapes_out, hipStream_t stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph
@@ -216,7 +259,7 @@ dd_status dd_gemm_ex(dd_op transa, dd_op transb,
  * code); make that call before any graph capture.
  */
 #define DD_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
-dd_status dd_gemm_noalloc(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+dd_status dd_gemm_noalloc(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
                           const double* A_hi, const double* A_lo, int64_t lda,
                           const double* B_hi, const double* B_lo, int64_t ldb,
                           double* C_hi, double* C_lo, int64_t ldc,
@@ -239,11 +282,16 @@ dd_status dd_gemm_noalloc(dd_op transa, dd_op transb, int64_t m, int64_t n, int6
  * when the kernels run.  Calls of one plan that overlap (on different
  * streams) race on its workspace.  Problems with m, n or k = 0 are no-ops.
  *
- * Schedule of the persistent kernel: tiles in decreasing cost (LPT) or
- * problem order, taken with a fixed stride or from an atomic counter.  The
- * default is LPT with a counter, unless the tuning cache (file named by
- * DDGEMM_TUNE_CACHE) holds a choice for these shapes.  dd_batched_plan_tune
- * times every candidate `repeats` times with the given operands (C is
+ * Tiles: a problem's output tiles are 64 x 64, or 32 x 64 / 64 x 32 when
+ * that shape's padded area is smaller, as the tile policy says: 0, always
+ * 64 x 64; 1, the smaller shape for problems with k >= 256; 2, the smaller
+ * shape wherever it cuts the padding.  Every shape gives the same bits.
+ * Schedule of the persistent kernel: tiles in decreasing cost (LPT: inner
+ * dimension times tile area) or problem order, taken with a fixed stride or
+ * from an atomic counter.  The default is policy 0, LPT with a counter,
+ * unless the tuning cache (file named by DDGEMM_TUNE_CACHE) holds a choice
+ * for these shapes.  dd_batched_plan_tune times every combination (3
+ * policies x 4 schedules) `repeats` times with the given operands (C is
  * updated by every run!), keeps the fastest and appends it to the cache.
  */
 typedef struct dd_batched_plan_s* dd_batched_plan;
@@ -259,10 +307,12 @@ dd_status dd_batched_plan_tune(dd_batched_plan plan,
                                const double* const* B_hi, const double* const* B_lo,
                                double* const* C_hi, double* const* C_lo, int32_t repeats,
                                hipStream_t stream);
-/* Sets the schedule directly (dynamic: 1 = atomic counter, lpt: 1 = decreasing cost). */
-dd_status dd_batched_plan_schedule(dd_batched_plan plan, int32_t dynamic, int32_t lpt, hipStream_t stream);
+/* Sets the schedule and tiles directly (dynamic: 1 = atomic counter, lpt:
+ * 1 = decreasing cost, tile_policy 0..2 as above). */
+dd_status dd_batched_plan_schedule(dd_batched_plan plan, int32_t dynamic, int32_t lpt, int32_t tile_policy,
+                                   hipStream_t stream);
 dd_status dd_batched_plan_info(dd_batched_plan plan, int64_t* ntiles, int32_t* dynamic, int32_t* lpt,
-                               size_t* device_bytes);
+                               int32_t* tile_policy, size_t* device_bytes);
 /* Waits for the device, then frees the plan and its memory. */
 dd_status dd_batched_plan_destroy(dd_batched_plan plan);
 
@@ -285,7 +335,7 @@ dd_status dd_gemm_batched(int32_t count, const int64_t* m, const int64_t* n, con
  * kc has the meaning of dd_gemm_opts.kc, with the inner size k = cols
  * (side 0) or rows (side 1).  exps and planes are device pointers.
  */
-dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
+dd_status dd_cascade_split(int32_t side, int32_t trans, int64_t rows, int64_t cols,
                            const double* X_hi, const double* X_lo, int64_t ldx,
                            int32_t kc, int32_t* exps, double* planes,
                            hipStream_t stream);
@@ -302,7 +352,7 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
  * slice_bits as in dd_gemm_opts (0 = the format's default).  exps and out
  * are device pointers.
  */
-dd_status dd_slices_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
+dd_status dd_slices_split(int32_t side, int32_t trans, int64_t rows, int64_t cols,
                           const double* X_hi, const double* X_lo, int64_t ldx,
                           int32_t fmt, int32_t slices, int32_t slice_bits,
                           int32_t* exps, uint16_t* out, hipStream_t stream);
@@ -383,9 +433,9 @@ int32_t dd_version(void);
  * columns; workspace NULL with ws_bytes 0 uses the library's cached one
  * (which may allocate, so not under graph capture).
  * ------------------------------------------------------------------------ */
-size_t td_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k, int32_t kc);
+size_t td_gemm_workspace_size(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, int32_t kc);
 
-dd_status td_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+dd_status td_gemm_ex(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
                      const double* A0, const double* A1, const double* A2, int64_t lda,
                      const double* B0, const double* B1, const double* B2, int64_t ldb,
                      double* C0, double* C1, double* C2, int64_t ldc,

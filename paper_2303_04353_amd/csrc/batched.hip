@@ -2,13 +2,16 @@
 // phase-one pass and one persistent product launch.
 //
 // A plan fixes the shapes: it numbers the units of work of every problem
-// (prefix sums), lists the 64x64 output tiles of all problems in decreasing
-// cost (LPT order), lays out one workspace for all packed operands and
-// uploads all of it once.  Executing a plan launches three kernels and
-// allocates nothing, so it can be captured in a HIP graph.  The schedule of
-// the persistent kernel (fixed stride or atomic counter, LPT or problem
-// order) is chosen by timing the candidates (dd_batched_plan_tune); choices
-// are kept in a small cache file keyed by the shapes.
+// (prefix sums), lists the output tiles of all problems in decreasing cost
+// (LPT order), lays out one workspace for all packed operands and uploads
+// all of it once.  Executing a plan launches three kernels and allocates
+// nothing, so it can be captured in a HIP graph.  Tiles are 64 x 64, or
+// 32 x 64 / 64 x 32 for a problem whose padded area that shrinks, as the
+// tile policy says (never; for inner dimensions of 256 or more; always).
+// The policy and the schedule of the persistent kernel (fixed stride or
+// atomic counter, LPT or problem order) are chosen by timing the
+// candidates (dd_batched_plan_tune); choices are kept in a small cache file
+// keyed by the shapes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,7 +36,9 @@ struct dd_batched_plan_s {
   int32_t count = 0;
   int32_t kc = 256;
   std::vector<BatchDesc> desc;
+  std::vector<int32_t> small_shape;   // per problem: the smaller tile that cuts padding, or 0
   std::vector<BatchTile> tiles_lpt, tiles_natural;
+  int64_t max_tiles = 0;              // over the tile policies
   uint64_t key = 0;
   char* dmem = nullptr;          // one device allocation for everything below
   size_t dmem_bytes = 0;
@@ -46,6 +51,7 @@ struct dd_batched_plan_s {
   int grid = 256;
   int dynamic = 1;
   int lpt = 1;
+  int policy = 0;                     // tile policy, 0..2
 };
 
 namespace {
@@ -67,29 +73,35 @@ std::string cache_path() {
   return e ? std::string(e) : std::string();
 }
 
-// Cache file lines: "<key hex> <dynamic> <lpt>".
-bool cache_lookup(uint64_t key, int* dynamic, int* lpt) {
+// Cache file lines of batched plans: "b <key hex> <dynamic> <lpt> <policy>"
+// (single GEMMs keep "s ..." lines in the same file).
+bool cache_lookup(uint64_t key, int* dynamic, int* lpt, int* policy) {
   std::string path = cache_path();
   if (path.empty()) return false;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   FILE* f = std::fopen(path.c_str(), "r");
   if (!f) return false;
-  unsigned long long k;
-  int d, l;
   bool found = false;
-  while (std::fscanf(f, "%llx %d %d", &k, &d, &l) == 3)
-    if (k == key) { *dynamic = d; *lpt = l; found = true; }
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    unsigned long long k;
+    int d, l, q;
+    if (std::sscanf(line, "b %llx %d %d %d", &k, &d, &l, &q) == 4 && k == key && d >= 0 && d <= 1 &&
+        l >= 0 && l <= 1 && q >= 0 && q <= 2) {
+      *dynamic = d; *lpt = l; *policy = q; found = true;
+    }
+  }
   std::fclose(f);
   return found;
 }
 
-void cache_store(uint64_t key, int dynamic, int lpt) {
+void cache_store(uint64_t key, int dynamic, int lpt, int policy) {
   std::string path = cache_path();
   if (path.empty()) return;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   FILE* f = std::fopen(path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%016llx %d %d\n", (unsigned long long)key, dynamic, lpt);
+  std::fprintf(f, "b %016llx %d %d %d\n", (unsigned long long)key, dynamic, lpt, policy);
   std::fclose(f);
 }
 
@@ -97,6 +109,38 @@ dd_status hip_st(hipError_t e) {
   if (e == hipSuccess) return DD_OK;
   if (e == hipErrorOutOfMemory) return DD_ERR_WORKSPACE;
   return DD_ERR_HIP;
+}
+
+// Shape of problem p's tiles under a tile policy: 0, all 64 x 64; 1, the
+// smaller tile where it cuts the padded area and k >= 256; 2, wherever it
+// cuts the padded area.
+int32_t tile_shape(const dd_batched_plan_s* P, int32_t p, int policy) {
+  const int32_t small = P->small_shape[p];
+  if (small == 0 || policy == 0 || (policy == 1 && P->desc[p].k < 256)) return ddk::kTile64x64;
+  return small;
+}
+
+// The tile lists of a policy: problem order, and decreasing cost (inner
+// dimension times tile area, stable).
+void build_tiles(dd_batched_plan_s* P, int policy) {
+  P->tiles_natural.clear();
+  for (int32_t p = 0; p < P->count; ++p) {
+    const BatchDesc& d = P->desc[p];
+    if (d.m <= 0 || d.n <= 0 || d.k <= 0) continue;
+    const int32_t sh = tile_shape(P, p, policy);
+    const int64_t tm_n = cdiv(d.m, ddk::tile_rows(sh)), tn_n = cdiv(d.n, ddk::tile_cols(sh));
+    for (int64_t tm = 0; tm < tm_n; ++tm)
+      for (int64_t tn = 0; tn < tn_n; ++tn)
+        P->tiles_natural.push_back(BatchTile{p, (int32_t)tm, (int32_t)tn, sh});
+  }
+  P->ntiles = (int64_t)P->tiles_natural.size();
+  P->tiles_lpt = P->tiles_natural;
+  auto cost = [&](const BatchTile& t) {
+    return P->desc[t.p].K4 * (int64_t)ddk::tile_rows(t.shape) * ddk::tile_cols(t.shape);
+  };
+  std::stable_sort(P->tiles_lpt.begin(), P->tiles_lpt.end(),
+                   [&](const BatchTile& a, const BatchTile& b) { return cost(a) > cost(b); });
+  P->policy = policy;
 }
 
 dd_status upload_tiles(dd_batched_plan_s* P, hipStream_t s) {
@@ -180,19 +224,24 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
     pexpB[p + 1] = pexpB[p] + (active ? cdiv(d.n, 4) * cdiv(d.k, 4096) : 0);
     ppackA[p + 1] = ppackA[p] + (active ? cdiv((d.mpad / 16) * d.K4, 4) : 0);
     ppackB[p + 1] = ppackB[p] + (active ? cdiv((d.npad / 16) * d.K4, 4) : 0);
-    if (active)
-      for (int64_t tm = 0; tm < d.tiles_m; ++tm)
-        for (int64_t tn = 0; tn < d.tiles_n; ++tn)
-          P->tiles_natural.push_back(BatchTile{p, (int32_t)tm, (int32_t)tn, 0});
+    // the smaller tile (32 x 64 or 64 x 32) with the least padded area, if
+    // that is less than the 64 x 64 tiles'
+    int32_t small = 0;
+    if (active) {
+      const int64_t a64 = ddk::round_up(d.m, 64) * ddk::round_up(d.n, 64);
+      const int64_t a3264 = ddk::round_up(d.m, 32) * ddk::round_up(d.n, 64);
+      const int64_t a6432 = ddk::round_up(d.m, 64) * ddk::round_up(d.n, 32);
+      if (std::min(a3264, a6432) < a64) small = a3264 <= a6432 ? ddk::kTile32x64 : ddk::kTile64x32;
+    }
+    P->small_shape.push_back(small);
   }
   P->nexps = eoff;
   P->units_exp = pexpA[count] + pexpB[count];
   P->units_pack = ppackA[count] + ppackB[count];
-  P->ntiles = (int64_t)P->tiles_natural.size();
-  P->tiles_lpt = P->tiles_natural;
-  std::stable_sort(P->tiles_lpt.begin(), P->tiles_lpt.end(), [&](const BatchTile& a, const BatchTile& b) {
-    return P->desc[a.p].K4 > P->desc[b.p].K4;
-  });
+  for (int q = 2; q >= 0; --q) {               // policy 2 has the most tiles
+    build_tiles(P, q);
+    P->max_tiles = std::max(P->max_tiles, P->ntiles);
+  }
   const size_t ws_bytes = off;
 
   // device memory: descriptors, prefix arrays, tiles, counter, workspace
@@ -201,7 +250,7 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
   const size_t o_desc = take(sizeof(BatchDesc) * std::max(count, 1));
   const size_t o_pa = take(sizeof(int64_t) * (count + 1)), o_pb = take(sizeof(int64_t) * (count + 1));
   const size_t o_qa = take(sizeof(int64_t) * (count + 1)), o_qb = take(sizeof(int64_t) * (count + 1));
-  const size_t o_tiles = take(sizeof(BatchTile) * std::max<int64_t>(P->ntiles, 1));
+  const size_t o_tiles = take(sizeof(BatchTile) * std::max<int64_t>(P->max_tiles, 1));
   const size_t o_ctr = take(sizeof(uint64_t));
   const size_t o_ws = take(std::max<size_t>(ws_bytes, 256));
   P->dmem_bytes = o;
@@ -228,8 +277,9 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
   }
   P->key = key;
   P->grid = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  int dyn = 1, lpt = 1;
-  if (cache_lookup(key, &dyn, &lpt)) { P->dynamic = dyn; P->lpt = lpt; }
+  int dyn = 1, lpt = 1, policy = 0;
+  if (cache_lookup(key, &dyn, &lpt, &policy)) { P->dynamic = dyn; P->lpt = lpt; }
+  build_tiles(P, policy);
 
   dd_status st = DD_OK;
   if (count > 0) {
@@ -282,55 +332,63 @@ dd_status dd_batched_plan_tune(dd_batched_plan P, const double* const* A_hi, con
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DD_ERR_HIP;
   float best = 1e30f;
-  int best_dyn = P->dynamic, best_lpt = P->lpt;
+  int best_dyn = P->dynamic, best_lpt = P->lpt, best_policy = P->policy;
   dd_status st = DD_OK;
-  for (int lpt = 1; lpt >= 0 && st == DD_OK; --lpt) {
-    P->lpt = lpt;
-    st = upload_tiles(P, stream);
-    for (int dyn = 1; dyn >= 0 && st == DD_OK; --dyn) {
-      P->dynamic = dyn;
-      st = dd_gemm_batched_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, stream);  // warm-up
-      std::vector<float> t;
-      for (int r = 0; r < repeats && st == DD_OK; ++r) {
-        (void)hipEventRecord(e0, stream);
-        st = dd_gemm_batched_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, stream);
-        (void)hipEventRecord(e1, stream);
-        if (hipEventSynchronize(e1) != hipSuccess) st = DD_ERR_HIP;
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        t.push_back(ms);
+  for (int policy = 0; policy <= 2 && st == DD_OK; ++policy) {
+    build_tiles(P, policy);
+    for (int lpt = 1; lpt >= 0 && st == DD_OK; --lpt) {
+      P->lpt = lpt;
+      st = upload_tiles(P, stream);
+      for (int dyn = 1; dyn >= 0 && st == DD_OK; --dyn) {
+        P->dynamic = dyn;
+        st = dd_gemm_batched_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, stream);  // warm-up
+        std::vector<float> t;
+        for (int r = 0; r < repeats && st == DD_OK; ++r) {
+          (void)hipEventRecord(e0, stream);
+          st = dd_gemm_batched_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, stream);
+          (void)hipEventRecord(e1, stream);
+          if (hipEventSynchronize(e1) != hipSuccess) st = DD_ERR_HIP;
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          t.push_back(ms);
+        }
+        if (st != DD_OK) break;
+        std::sort(t.begin(), t.end());
+        const float med = t[t.size() / 2];
+        if (med < best) { best = med; best_dyn = dyn; best_lpt = lpt; best_policy = policy; }
       }
-      if (st != DD_OK) break;
-      std::sort(t.begin(), t.end());
-      const float med = t[t.size() / 2];
-      if (med < best) { best = med; best_dyn = dyn; best_lpt = lpt; }
     }
   }
+  build_tiles(P, best_policy);
   P->dynamic = best_dyn;
   P->lpt = best_lpt;
   if (st == DD_OK) st = upload_tiles(P, stream);
   if (st == DD_OK) st = hip_st(hipStreamSynchronize(stream));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st == DD_OK) cache_store(P->key, best_dyn, best_lpt);
+  if (st == DD_OK) cache_store(P->key, best_dyn, best_lpt, best_policy);
   return st;
 }
 
-dd_status dd_batched_plan_schedule(dd_batched_plan P, int32_t dynamic, int32_t lpt, hipStream_t stream) {
+dd_status dd_batched_plan_schedule(dd_batched_plan P, int32_t dynamic, int32_t lpt, int32_t tile_policy,
+                                   hipStream_t stream) {
   if (!P) return -1;
   if (dynamic != 0 && dynamic != 1) return -2;
   if (lpt != 0 && lpt != 1) return -3;
+  if (tile_policy < 0 || tile_policy > 2) return -4;
+  build_tiles(P, tile_policy);
   P->dynamic = dynamic;
   P->lpt = lpt;
   return upload_tiles(P, stream);
 }
 
 dd_status dd_batched_plan_info(dd_batched_plan P, int64_t* ntiles, int32_t* dynamic, int32_t* lpt,
-                               size_t* device_bytes) {
+                               int32_t* tile_policy, size_t* device_bytes) {
   if (!P) return -1;
   if (ntiles) *ntiles = P->ntiles;
   if (dynamic) *dynamic = P->dynamic;
   if (lpt) *lpt = P->lpt;
+  if (tile_policy) *tile_policy = P->policy;
   if (device_bytes) *device_bytes = P->dmem_bytes;
   return DD_OK;
 }

@@ -54,10 +54,20 @@ hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles,
 // cancellation (a block's bin 0 zero while a lower bin is not).
 // With L.npanel > 1, aexp / bexp are the per-panel exponents (int32, set b
 // at b * mpad / b * npad) and Sigma, T are applied per rank-kc block.
+// `shape` is the output tile shape (kTile64x64, kTile32x64, kTile64x32).
 hipError_t launch_cascade(const CascadeLayout& L, const double* Apack, const double* Bpack,
                           const uint64_t* amax, const uint64_t* bmax,
                           double* Chi, double* Clo, int64_t ldc, uint32_t* flags, hipStream_t s,
-                          const int32_t* aexp = nullptr, const int32_t* bexp = nullptr);
+                          const int32_t* aexp = nullptr, const int32_t* bexp = nullptr,
+                          int shape = kTile64x64);
+// The product kernel with the split done while staging (64 x 64 tiles,
+// global Sigma / T): operands from the caller's planes, op(A)(i, p) at
+// A[i*a_si + p*a_sp], op(B)(p, j) at B[p*b_sp + j*b_sj]; amax / bmax from
+// launch_max_abs_bits.  Gives the same bits as launch_cascade.
+hipError_t launch_cascade_onload(const CascadeLayout& L, const double* Ahi, const double* Alo, int64_t a_si,
+                                 int64_t a_sp, const double* Bhi, const double* Blo, int64_t b_sp, int64_t b_sj,
+                                 const uint64_t* amax, const uint64_t* bmax, double* Chi, double* Clo, int64_t ldc,
+                                 uint32_t* flags, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
 // FP64x3: workspace offsets (bytes: row/column maxima, packed digit planes)

@@ -69,9 +69,16 @@ struct BatchDesc {
   int32_t kcq, c0, c1, c2;
 };
 
-// A tile of the persistent product kernel: problem p, tile row tm, column tn.
+// Output tile shapes of the product kernel (rows x columns per workgroup);
+// every shape computes every entry with the same arithmetic.
+constexpr int kTile64x64 = 1, kTile32x64 = 2, kTile64x32 = 3;
+inline int tile_rows(int shape) { return shape == kTile32x64 ? 32 : 64; }
+inline int tile_cols(int shape) { return shape == kTile64x32 ? 32 : 64; }
+
+// A tile of the persistent product kernel: problem p, tile row tm, column tn
+// (in units of the tile shape), and the shape.
 struct BatchTile {
-  int32_t p, tm, tn, pad;
+  int32_t p, tm, tn, shape;
 };
 
 // ceil(log2 kc) and the widths of Sec. 3.3 (bins 0-2 exact for kc terms).

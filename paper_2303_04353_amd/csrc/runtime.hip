@@ -4,7 +4,10 @@
 // kernel.  See include/ddgemm.h for the contract of every entry point.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -229,6 +232,9 @@ struct Opts {
   uint32_t* flags = nullptr;   // cascade: cancellation bitmap (may be null)
   bool panels = false;         // cascade: Sigma and T per rank-kc panel
   bool balance = false;        // cascade: diagonal balancing of the inner dimension
+  int32_t tile = 0;            // cascade: output tile shape, 0 = the library's choice
+  bool use_tuned = false;      // cascade: take the shape recorded by dd_tune, if any
+  int32_t scaling = 0;
   bool slices() const {
     return algo == DD_ALGO_SLICES_BF16 || algo == DD_ALGO_SLICES_F16 || algo == DD_ALGO_SLICES_I8;
   }
@@ -277,13 +283,75 @@ dd_status run_slices_product(const Problem& p, const ddk::SlicesLayout& L, char*
 
 // With `fixed` the workspace is the caller's (or the scratch array) and the
 // call creates nothing: no phase-timing events either.
+// ------------------------------------------------------ tuned tile shapes
+// Output tile shapes recorded by dd_tune, per (m, n, k, kc, scaling); kept
+// in memory and, when DDGEMM_TUNE_CACHE names a file, appended to it as
+// lines "s <m> <n> <k> <kc> <scaling> <shape>" (read once, at first use).
+struct TuneKey {
+  int64_t m, n, k;
+  int32_t kc, scaling;
+  bool operator<(const TuneKey& o) const {
+    if (m != o.m) return m < o.m;
+    if (n != o.n) return n < o.n;
+    if (k != o.k) return k < o.k;
+    if (kc != o.kc) return kc < o.kc;
+    return scaling < o.scaling;
+  }
+};
+std::map<TuneKey, int32_t> g_tuned;
+bool g_tuned_loaded = false;
+
+void load_tuned_locked() {
+  if (g_tuned_loaded) return;
+  g_tuned_loaded = true;
+  const char* path = std::getenv("DDGEMM_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    long long m, n, k;
+    int kc, sc, sh;
+    if (std::sscanf(line, "s %lld %lld %lld %d %d %d", &m, &n, &k, &kc, &sc, &sh) == 6 &&
+        sh >= ddk::kTile64x64 && sh <= ddk::kTile64x32)
+      g_tuned[TuneKey{m, n, k, kc, sc}] = sh;
+  }
+  std::fclose(f);
+}
+
+void record_tuned(const TuneKey& key, int32_t shape) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_tuned_locked();
+  g_tuned[key] = shape;
+  const char* path = std::getenv("DDGEMM_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "s %lld %lld %lld %d %d %d\n", (long long)key.m, (long long)key.n, (long long)key.k, key.kc,
+               key.scaling, shape);
+  std::fclose(f);
+}
+
+// The output tile shape of a cascade: the one asked for, else the tuned one
+// (with use_tuned), else 64 x 64.
+int32_t tile_shape(const Problem& p, const Opts& o) {
+  if (o.tile != 0) return o.tile;
+  if (o.use_tuned) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_tuned_locked();
+    auto it = g_tuned.find(TuneKey{p.m, p.n, p.k, o.kc, o.scaling});
+    if (it != g_tuned.end()) return it->second;
+  }
+  return ddk::kTile64x64;
+}
+
 dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes, bool internal_ws,
               hipStream_t s, bool fixed = false) {
   const int32_t algo = o.algo, kc = o.kc;
+  if (p.m == 0 || p.n == 0 || p.k == 0) return DD_OK;   // quick return: no device needed
   int dev = 0;
   dd_status st = check_device(&dev);
   if (st != DD_OK) return st;
-  if (p.m == 0 || p.n == 0 || p.k == 0) return DD_OK;
   if (algo == DD_ALGO_DD_VALU) {
     int64_t a_si, a_sp, b_sp, b_sj;
     strides(p, a_si, a_sp, b_sp, b_sj);
@@ -306,6 +374,39 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
     if (st != DD_OK) return st;
     if (pe.e1) (void)hipEventRecord(pe.e1, s);
     st = run_slices_product(p, L, ws, s);
+    if (pe.e2) {
+      (void)hipEventRecord(pe.e2, s);
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_prof_events.push_back(pe);
+    }
+    return st;
+  }
+  if (algo == DD_ALGO_CASCADE_ON_LOAD) {
+    // the row and column maxima, then the product kernel that splits as it stages
+    const CascadeLayout L = ddk::make_layout(p.m, p.n, p.k, kc, kTileM, kTileN);
+    const size_t need = L.off_apack;   // the maxima come first in the layout
+    char* ws = (char*)workspace;
+    if (internal_ws) {
+      void* w = nullptr;
+      st = cached_workspace(dev, s, need, &w);
+      if (st != DD_OK) return st;
+      ws = (char*)w;
+    } else if (ws_bytes < need || ((uintptr_t)ws & 255u) != 0) {
+      return DD_ERR_WORKSPACE;
+    }
+    int64_t a_si, a_sp, b_sp, b_sj;
+    strides(p, a_si, a_sp, b_sp, b_sj);
+    uint64_t* amax = (uint64_t*)(ws + L.off_amax);
+    uint64_t* bmax = (uint64_t*)(ws + L.off_bmax);
+    PhaseEvents pe = prof_begin(s, !fixed);
+    DD_TRY(ddk::launch_fill_u64(amax, L.mpad, 0, s));
+    DD_TRY(ddk::launch_fill_u64(bmax, L.npad, 0, s));
+    DD_TRY(ddk::launch_max_abs_bits(p.Ahi, p.m, p.k, a_si, a_sp, amax, s));
+    DD_TRY(ddk::launch_max_abs_bits(p.Bhi, p.n, p.k, b_sj, b_sp, bmax, s));
+    if (pe.e1) (void)hipEventRecord(pe.e1, s);
+    if (o.flags) DD_TRY(ddk::launch_fill_u32(o.flags, (p.m * p.n + 31) / 32, 0u, s));
+    st = hip_status(ddk::launch_cascade_onload(L, p.Ahi, p.Alo, a_si, a_sp, p.Bhi, p.Blo, b_sp, b_sj, amax, bmax,
+                                               p.Chi, p.Clo, p.ldc, o.flags, s));
     if (pe.e2) {
       (void)hipEventRecord(pe.e2, s);
       std::lock_guard<std::mutex> lk(g_mu);
@@ -346,7 +447,8 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
                                       (const double*)(ws + L.off_bpack),
                                       (const uint64_t*)(ws + L.off_amax),
                                       (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, o.flags, s,
-                                      (const int32_t*)(ws + L.off_aexp), (const int32_t*)(ws + L.off_bexp)));
+                                      (const int32_t*)(ws + L.off_aexp), (const int32_t*)(ws + L.off_bexp),
+                                      tile_shape(p, o)));
   if (pe.e2) {
     (void)hipEventRecord(pe.e2, s);
     std::lock_guard<std::mutex> lk(g_mu);
@@ -373,13 +475,21 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
 static bool read_opts(const dd_gemm_opts* o, Opts* out) {
   *out = Opts{};
   if (!o) return true;
-  if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_SIMPLE_UNFUSED) return false;
-  if (o->tile != 0) return false;
+  if (o->algo < DD_ALGO_CASCADE_F64 || o->algo > DD_ALGO_CASCADE_ON_LOAD) return false;
+  if (o->tile < 0 || o->tile > DD_TILE_64x32) return false;
+  if (o->tile != 0 && o->algo != DD_ALGO_CASCADE_F64 &&
+      !(o->algo == DD_ALGO_CASCADE_ON_LOAD && o->tile == DD_TILE_64x64)) return false;
+  if (o->use_tuned != 0 && o->use_tuned != 1) return false;
+  if (o->use_tuned && o->algo != DD_ALGO_CASCADE_F64) return false;
   if (o->scaling < 0 || o->scaling > (DD_SCALING_PANEL | DD_SCALING_BALANCE)) return false;
   out->algo = o->algo;
-  if (o->flags_out && o->algo != DD_ALGO_CASCADE_F64) return false;
+  const bool fused = o->algo == DD_ALGO_CASCADE_F64 || o->algo == DD_ALGO_CASCADE_ON_LOAD;
+  if (o->flags_out && !fused) return false;
   if (o->scaling != DD_SCALING_GLOBAL && o->algo != DD_ALGO_CASCADE_F64) return false;
   out->flags = o->flags_out;
+  out->tile = o->tile;
+  out->use_tuned = o->use_tuned != 0;
+  out->scaling = o->scaling;
   out->panels = (o->scaling & DD_SCALING_PANEL) != 0;
   out->balance = (o->scaling & DD_SCALING_BALANCE) != 0;
   if (out->slices()) {
@@ -396,11 +506,12 @@ static bool read_opts(const dd_gemm_opts* o, Opts* out) {
 static size_t workspace_bytes(int64_t m, int64_t n, int64_t k, const Opts& o) {
   if (m <= 0 || n <= 0 || k <= 0 || o.algo == DD_ALGO_DD_VALU) return 0;
   if (o.slices()) return ddk::make_slices_layout(m, n, k, o.S, o.w, o.fmt()).bytes;
+  if (o.algo == DD_ALGO_CASCADE_ON_LOAD) return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN).off_apack;
   return ddk::make_layout(m, n, k, o.kc, kTileM, kTileN, o.panels, o.balance,
                          o.algo == DD_ALGO_SIMPLE_UNFUSED).bytes;
 }
 
-size_t dd_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+size_t dd_gemm_workspace_size(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
                               const dd_gemm_opts* opts) {
   Opts o;
   if (!read_opts(opts, &o)) return 0;
@@ -408,7 +519,7 @@ size_t dd_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, 
   return workspace_bytes(m, n, k, o);
 }
 
-dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+dd_status dd_gemm_ex(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
                      const double* A_hi, const double* A_lo, int64_t lda,
                      const double* B_hi, const double* B_lo, int64_t ldb,
                      double* C_hi, double* C_lo, int64_t ldc,
@@ -425,7 +536,7 @@ dd_status dd_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k
   return run(p, o, workspace, ws_bytes, internal, stream);
 }
 
-dd_status dd_gemm_noalloc(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+dd_status dd_gemm_noalloc(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
                           const double* A_hi, const double* A_lo, int64_t lda,
                           const double* B_hi, const double* B_lo, int64_t ldb,
                           double* C_hi, double* C_lo, int64_t ldc,
@@ -438,10 +549,10 @@ dd_status dd_gemm_noalloc(dd_op transa, dd_op transb, int64_t m, int64_t n, int6
   if (!read_opts(opts, &o)) return -15;
   // the unfused form runs the vendor BLAS, whose handle and calls may allocate
   if (o.algo == DD_ALGO_SIMPLE_UNFUSED) return -15;
+  if (m == 0 || n == 0 || k == 0) return DD_OK;
   int dev = 0;
   dd_status st = check_device(&dev);
   if (st != DD_OK) return st;
-  if (m == 0 || n == 0 || k == 0) return DD_OK;
   if (workspace_bytes(m, n, k, o) > (size_t)DD_NOALLOC_SCRATCH_BYTES) return DD_ERR_WORKSPACE;
   char* ws = nullptr;
   st = scratch_address(dev, &ws);
@@ -449,7 +560,78 @@ dd_status dd_gemm_noalloc(dd_op transa, dd_op transb, int64_t m, int64_t n, int6
   return run(p, o, ws, (size_t)DD_NOALLOC_SCRATCH_BYTES, false, stream, true);
 }
 
-dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
+dd_status dd_tune(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                  const dd_gemm_opts* opts, int32_t repeats, int32_t* shapes_out, hipStream_t stream) {
+  if (count < 0) return -1;
+  if (count > 0 && !m) return -2;
+  if (count > 0 && !n) return -3;
+  if (count > 0 && !k) return -4;
+  Opts o;
+  if (!read_opts(opts, &o) || o.algo != DD_ALGO_CASCADE_F64 || o.tile != 0 || o.flags) return -5;
+  if (repeats < 1) return -6;
+  for (int32_t i = 0; i < count; ++i)
+    if (m[i] < 0 || n[i] < 0 || k[i] < 0) return -2;
+  int dev = 0;
+  dd_status st = check_device(&dev);
+  if (st != DD_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    if (e0) (void)hipEventDestroy(e0);
+    return DD_ERR_HIP;
+  }
+  for (int32_t i = 0; i < count && st == DD_OK; ++i) {
+    if (shapes_out) shapes_out[i] = 0;
+    if (m[i] == 0 || n[i] == 0 || k[i] == 0) continue;
+    // operands of the shape (zeros: the kernels' time does not depend on the values)
+    const size_t a = sizeof(double) * (size_t)m[i] * (size_t)k[i], b = sizeof(double) * (size_t)k[i] * (size_t)n[i];
+    const size_t c = sizeof(double) * (size_t)m[i] * (size_t)n[i];
+    const CascadeLayout L = ddk::make_layout(m[i], n[i], k[i], o.kc, kTileM, kTileN, o.panels, o.balance);
+    char* buf = nullptr;
+    const size_t wso = 2 * (a + b + c) + 1024, total = wso + L.bytes + 256;
+    if (hipMalloc(&buf, total) != hipSuccess) {
+      (void)hipGetLastError();
+      st = DD_ERR_WORKSPACE;
+      break;
+    }
+    if (hipMemsetAsync(buf, 0, wso, stream) != hipSuccess) st = DD_ERR_HIP;
+    Problem p{DD_OP_N, DD_OP_N, m[i], n[i], k[i],
+              (const double*)buf, (const double*)(buf + a), m[i],
+              (const double*)(buf + 2 * a), (const double*)(buf + 2 * a + b), k[i],
+              (double*)(buf + 2 * (a + b)), (double*)(buf + 2 * (a + b) + c), m[i]};
+    char* ws = buf + ddk::round_up((int64_t)wso, 256);
+    float best = 1e30f;
+    int32_t best_shape = ddk::kTile64x64;
+    for (int32_t shape = ddk::kTile64x64; shape <= ddk::kTile64x32 && st == DD_OK; ++shape) {
+      Opts q = o;
+      q.tile = shape;
+      st = run(p, q, ws, L.bytes, false, stream, true);   // warm-up
+      std::vector<float> t;
+      for (int32_t r = 0; r < repeats && st == DD_OK; ++r) {
+        (void)hipEventRecord(e0, stream);
+        st = run(p, q, ws, L.bytes, false, stream, true);
+        (void)hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess) { st = DD_ERR_HIP; break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t.push_back(ms);
+      }
+      if (st != DD_OK) break;
+      std::sort(t.begin(), t.end());
+      if (t[t.size() / 2] < best) { best = t[t.size() / 2]; best_shape = shape; }
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess && st == DD_OK) st = DD_ERR_HIP;
+    (void)hipFree(buf);
+    if (st != DD_OK) break;
+    record_tuned(TuneKey{m[i], n[i], k[i], o.kc, o.scaling}, best_shape);
+    if (shapes_out) shapes_out[i] = best_shape;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+dd_status dd_cascade_split(int32_t side, int32_t trans, int64_t rows, int64_t cols,
                            const double* X_hi, const double* X_lo, int64_t ldx,
                            int32_t kc, int32_t* exps, double* planes, hipStream_t stream) {
   if (side != 0 && side != 1) return -1;
@@ -499,7 +681,7 @@ dd_status dd_cascade_split(int32_t side, dd_op trans, int64_t rows, int64_t cols
   return DD_OK;
 }
 
-dd_status dd_slices_split(int32_t side, dd_op trans, int64_t rows, int64_t cols,
+dd_status dd_slices_split(int32_t side, int32_t trans, int64_t rows, int64_t cols,
                           const double* X_hi, const double* X_lo, int64_t ldx,
                           int32_t fmt, int32_t slices, int32_t slice_bits,
                           int32_t* exps, uint16_t* out, hipStream_t stream) {
@@ -679,14 +861,14 @@ const char* dd_status_string(dd_status s) {
 int32_t dd_version(void) { return 100; }
 
 // ------------------------------------------------------------------ FP64x3
-size_t td_gemm_workspace_size(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k, int32_t kc) {
+size_t td_gemm_workspace_size(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, int32_t kc) {
   if ((transa != DD_OP_N && transa != DD_OP_T) || (transb != DD_OP_N && transb != DD_OP_T)) return 0;
   if (m <= 0 || n <= 0 || k <= 0) return 0;
   if (kc != 0 && !valid_kc(kc)) return 0;
   return ddk::td_workspace_bytes(m, n, k, nullptr);
 }
 
-dd_status td_gemm_ex(dd_op transa, dd_op transb, int64_t m, int64_t n, int64_t k,
+dd_status td_gemm_ex(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
                      const double* A0, const double* A1, const double* A2, int64_t lda,
                      const double* B0, const double* B1, const double* B2, int64_t ldb,
                      double* C0, double* C1, double* C2, int64_t ldc,

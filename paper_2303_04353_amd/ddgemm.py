@@ -30,22 +30,27 @@ DD_ALGO_SLICES_BF16 = 2
 DD_ALGO_SLICES_F16 = 3
 DD_ALGO_SLICES_I8 = 4
 DD_ALGO_SIMPLE_UNFUSED = 5
+DD_ALGO_CASCADE_ON_LOAD = 6
 DD_SCALING_GLOBAL = 0
 DD_SCALING_PANEL = 1
 DD_SCALING_BALANCE = 2
 DD_NOALLOC_SCRATCH_BYTES = 128 << 20
+DD_TILE_AUTO = 0
+DD_TILE_64x64 = 1
+DD_TILE_32x64 = 2
+DD_TILE_64x32 = 3
 
 EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split", "dd_slices_split", "dd_dot",
             "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",
             "dd_batched_plan_schedule", "dd_batched_plan_info", "dd_batched_plan_destroy",
             "dd_gemm_batched", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version",
-            "td_gemm_workspace_size", "td_gemm_ex", "dd_gemm_noalloc", "dd_add")
+            "td_gemm_workspace_size", "td_gemm_ex", "dd_gemm_noalloc", "dd_add", "dd_tune")
 
 
 class dd_gemm_opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("kc", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("slices", ctypes.c_int32), ("slice_bits", ctypes.c_int32),
-                ("scaling", ctypes.c_int32), ("flags_out", ctypes.c_void_p)]
+                ("scaling", ctypes.c_int32), ("flags_out", ctypes.c_void_p), ("use_tuned", ctypes.c_int32)]
 
 
 class DDError(RuntimeError):
@@ -91,10 +96,10 @@ def lib():
         L.dd_gemm_batched_exec.restype = i32
         L.dd_batched_plan_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
         L.dd_batched_plan_tune.restype = i32
-        L.dd_batched_plan_schedule.argtypes = [vp, i32, i32, vp]
+        L.dd_batched_plan_schedule.argtypes = [vp, i32, i32, i32, vp]
         L.dd_batched_plan_schedule.restype = i32
         L.dd_batched_plan_info.argtypes = [vp, pi64, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                           ctypes.POINTER(sz)]
+                                           ctypes.POINTER(i32), ctypes.POINTER(sz)]
         L.dd_batched_plan_info.restype = i32
         L.dd_batched_plan_destroy.argtypes = [vp]
         L.dd_batched_plan_destroy.restype = i32
@@ -118,6 +123,8 @@ def lib():
         L.dd_gemm_noalloc.argtypes = [i32, i32, i64, i64, i64, vp, vp, i64, vp, vp, i64, vp, vp, i64,
                                       ctypes.POINTER(dd_gemm_opts), vp]
         L.dd_gemm_noalloc.restype = i32
+        L.dd_tune.argtypes = [i32, pi64, pi64, pi64, ctypes.POINTER(dd_gemm_opts), i32, ctypes.POINTER(i32), vp]
+        L.dd_tune.restype = i32
         _lib = L
     return _lib
 
@@ -243,16 +250,25 @@ def dd_batched_plan_tune(plan, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, repeats=3, st
                                           _ptr(C_hi), _ptr(C_lo), int(repeats), _stream(stream)))
 
 
-def dd_batched_plan_schedule(plan, dynamic, lpt, stream=None) -> int:
-    return int(lib().dd_batched_plan_schedule(plan, int(dynamic), int(lpt), _stream(stream)))
+def dd_batched_plan_schedule(plan, dynamic, lpt, tile_policy=0, stream=None) -> int:
+    return int(lib().dd_batched_plan_schedule(plan, int(dynamic), int(lpt), int(tile_policy), _stream(stream)))
 
 
 def dd_batched_plan_info(plan):
-    """Returns ``(status, ntiles, dynamic, lpt, device_bytes)``."""
-    nt, dy, lp, nb = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    """Returns ``(status, ntiles, dynamic, lpt, tile_policy, device_bytes)``."""
+    nt, dy, lp, tp, nb = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
     st = int(lib().dd_batched_plan_info(plan, ctypes.byref(nt), ctypes.byref(dy), ctypes.byref(lp),
-                                        ctypes.byref(nb)))
-    return st, nt.value, dy.value, lp.value, nb.value
+                                        ctypes.byref(tp), ctypes.byref(nb)))
+    return st, nt.value, dy.value, lp.value, tp.value, nb.value
+
+
+def dd_tune(m, n, k, opts=None, repeats=3, stream=None):
+    """Tile-shape tuner over the shapes (lists m, n, k); returns ``(status, shapes)``."""
+    count = len(m)
+    shapes = (ctypes.c_int32 * max(count, 1))()
+    st = int(lib().dd_tune(count, _i64arr(m), _i64arr(n), _i64arr(k), _opts(opts), int(repeats), shapes,
+                           _stream(stream)))
+    return st, [int(shapes[i]) for i in range(count)]
 
 
 def dd_batched_plan_destroy(plan) -> int:

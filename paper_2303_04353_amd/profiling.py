@@ -24,8 +24,16 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-PRODUCT_KERNEL = "cascade_kernel<false, false>"   # the headline form: no flags, global Sigma and T
+# the headline form of the product kernel: no flags, global Sigma and T, 64 x 64 tiles
+PRODUCT_KERNEL = "cascade_kernel<false, false, Shape<64, 64> >"
 PRODUCT_SOURCE = os.path.join(HERE, "csrc", "cascade.hip")
+
+
+def is_product_kernel(name: str) -> bool:
+    """True for the headline product kernel's name as rocprofv3 prints it
+    (namespaces of the template arguments dropped)."""
+    plain = name.replace("(anonymous namespace)::", "").replace("ddk::", "")
+    return PRODUCT_KERNEL in plain
 
 
 def source_hash(path: str = PRODUCT_SOURCE) -> str:
@@ -69,8 +77,8 @@ def traffic(fetch_csv: str, write_csv: str, copy_mib: int, m: int, n: int, k: in
     cal_w = max(v for name, v in write if "elementwise" in name)
     f_factor = copy_bytes / (cal_f * 1024.0)
     w_factor = copy_bytes / (cal_w * 1024.0)
-    pf = [v for name, v in fetch if PRODUCT_KERNEL in name]
-    pw = [v for name, v in write if PRODUCT_KERNEL in name]
+    pf = [v for name, v in fetch if is_product_kernel(name)]
+    pw = [v for name, v in write if is_product_kernel(name)]
     fb = sum(pf) / len(pf) * 1024.0 * f_factor
     wb = sum(pw) / len(pw) * 1024.0 * w_factor
     return {"kernel": PRODUCT_KERNEL, "source_sha256_16": source_hash(), "m": m, "n": n, "k": k,

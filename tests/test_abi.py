@@ -57,7 +57,7 @@ def test_ex_rejects_bad_ops_and_options():
     assert dg.dd_gemm_ex(0, 7, *base, stream=0) == -2
     assert dg.dd_gemm_ex(0, 0, *base, opts={"kc": 6}, stream=0) == -17
     assert dg.dd_gemm_ex(0, 0, *base, opts={"algo": 9}, stream=0) == -17
-    assert dg.dd_gemm_ex(0, 0, *base, opts={"tile": 3}, stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"tile": 7}, stream=0) == -17
     assert dg.dd_gemm_ex(0, 0, *base, workspace=None, ws_bytes=64, stream=0) == -15
 
 
@@ -157,7 +157,7 @@ def test_slices_options_and_workspace():
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": f16}) > 0
     for bad in ({"algo": bf, "slice_bits": 10}, {"algo": bf, "slices": 17}, {"algo": f16, "slice_bits": 10},
                 {"algo": bf, "kc": 256}, {"algo": 0, "slices": 4}, {"algo": 1, "slice_bits": 8},
-                {"algo": f16, "slice_bits": 12, "slices": 1}, {"algo": 6}):
+                {"algo": f16, "slice_bits": 12, "slices": 1}, {"algo": 7}):
         assert dg.dd_gemm_workspace_size(0, 0, m, n, k, bad) == 0, bad
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": f16, "slice_bits": 11, "slices": 1}) > 0
     # INT8: 16 slices of 7 bits, one byte each, k padded to 128, groups 3..5 of the upper pass
@@ -166,7 +166,7 @@ def test_slices_options_and_workspace():
     need8 = 8 * (mpad + npad) + 16 * (mpad + npad) * 384 + 4352 * (mpad // 32 + npad // 32) + 8 * 3 * mpad * npad
     assert need8 <= ws8 <= need8 + 6 * 256
     assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": i8, "slice_bits": 8}) == 0
-    assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": 6}) == 0
+    assert dg.dd_gemm_workspace_size(0, 0, m, n, k, {"algo": 7}) == 0
     base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
     assert dg.dd_gemm_ex(0, 0, *base, opts={"algo": bf, "slices": 20}, stream=0) == -17
 
@@ -214,3 +214,29 @@ def test_vector_calls_reject_bad_arguments_on_host():
     assert dg.dd_add(4, *x, 1, *y, 1, x[0] + 8, 1 << 25, 1, stream=0) == -8          # z_hi inside x_hi
     assert dg.dd_add(4, *x, 1, *y, 1, 1 << 24, y[1] + 16, 1, stream=0) == -9         # z_lo inside y_lo
     assert dg.dd_add(0, 0, 0, 0, 0, 0, 0, 0, 0, 0, stream=0) == 0
+
+
+def test_tile_and_tuner_options_checked_on_host():
+    base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"tile": 4}, stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"tile": -1}, stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"tile": 2, "algo": dg.DD_ALGO_DD_VALU}, stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"use_tuned": 2}, stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, opts={"use_tuned": 1, "algo": dg.DD_ALGO_SLICES_BF16}, stream=0) == -17
+    assert dg.dd_gemm_workspace_size(0, 0, 100, 70, 300, {"tile": 2}) == dg.dd_gemm_workspace_size(0, 0, 100, 70, 300)
+    assert dg.dd_tune([4], [4], [4], repeats=0, stream=0)[0] == -6
+    assert dg.dd_tune([4], [4], [4], opts={"algo": dg.DD_ALGO_SLICES_BF16}, stream=0)[0] == -5
+    assert dg.dd_tune([4], [4], [4], opts={"tile": 1}, stream=0)[0] == -5
+    assert dg.dd_tune([4], [-4], [4], stream=0)[0] == -2
+    assert dg.dd_tune([], [], [], stream=0)[0] in (0, dg.DD_ERR_HIP, dg.DD_ERR_UNSUPPORTED)
+
+
+def test_on_load_options_and_workspace():
+    base = (4, 4, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4, 1 << 24, 1 << 25, 4)
+    o = {"algo": dg.DD_ALGO_CASCADE_ON_LOAD}
+    assert dg.dd_gemm_ex(0, 0, *base, opts=dict(o, scaling=dg.DD_SCALING_PANEL), stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, opts=dict(o, tile=dg.DD_TILE_32x64), stream=0) == -17
+    assert dg.dd_gemm_ex(0, 0, *base, opts=dict(o, use_tuned=1), stream=0) == -17
+    # only the row and column maxima: 8 (mpad + npad) bytes, 256-byte aligned pieces
+    assert dg.dd_gemm_workspace_size(0, 0, 100, 70, 300, o) == 8 * 128 + 8 * 128
+    assert dg.dd_gemm_workspace_size(0, 0, 100, 70, 300, dict(o, tile=dg.DD_TILE_64x64)) == 8 * 256

@@ -78,23 +78,34 @@ SMALL = [(37, 50, 300), (1, 1, 1), (64, 64, 64), (0, 5, 7), (5, 0, 7), (6, 9, 0)
          (17, 200, 33), (128, 3, 257), (65, 65, 65), (200, 128, 520), (3, 3, 3)]
 
 
+# shapes where 32 x 64 or 64 x 32 tiles cut the padding, and where they do not
+MIXED = SMALL + [(80, 200, 300), (200, 90, 260), (33, 70, 257), (96, 96, 40), (160, 30, 600), (20, 150, 1)]
+
+
 @pytest.mark.parametrize("kc", [0, 128])
-def test_batch_equals_single_calls_bitwise_for_every_schedule(kc):
+def test_batch_equals_single_calls_bitwise_for_every_schedule_and_tile_policy(kc):
     import torch
-    b = Batch(SMALL)
+    b = Batch(MIXED)
     opts = {"kc": kc}
     want = b.singles(opts)
     plan = b.plan(opts)
     try:
-        for dyn in (1, 0):
-            for lpt in (1, 0):
-                log(f"batched small kc={kc} dynamic={dyn} lpt={lpt}")
-                dg.check(dg.dd_batched_plan_schedule(plan, dyn, lpt))
-                b.reset()
-                b.exec(plan)
-                torch.cuda.synchronize()
-                for i, (g, w) in enumerate(zip(b.results(), want)):
-                    assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1]), (i, dyn, lpt)
+        ntiles = {}
+        for policy in (0, 1, 2):
+            for dyn in (1, 0):
+                for lpt in (1, 0):
+                    log(f"batched small kc={kc} policy={policy} dynamic={dyn} lpt={lpt}")
+                    dg.check(dg.dd_batched_plan_schedule(plan, dyn, lpt, policy))
+                    b.reset()
+                    b.exec(plan)
+                    torch.cuda.synchronize()
+                    for i, (g, w) in enumerate(zip(b.results(), want)):
+                        assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1]), (i, policy, dyn, lpt)
+            st, nt, _, _, tp, _ = dg.dd_batched_plan_info(plan)
+            assert st == 0 and tp == policy
+            ntiles[policy] = nt
+        # smaller tiles where they cut padding: more (smaller) tiles under policies 1 and 2
+        assert ntiles[0] < ntiles[1] <= ntiles[2]
     finally:
         dg.dd_batched_plan_destroy(plan)
 
@@ -176,16 +187,17 @@ def test_tuner_records_choice(tmp_path):
         plan = b.plan()
         try:
             dg.check(dg.dd_batched_plan_tune(plan, b.pA[0], b.pA[1], b.pB[0], b.pB[1], b.pC[0], b.pC[1], 2))
-            st, nt, dyn, lpt, nbytes = dg.dd_batched_plan_info(plan)
-            assert st == 0 and nt > 0 and dyn in (0, 1) and lpt in (0, 1) and nbytes > 0
-            lines = open(tmp_path / "tune.txt").read().split()
-            assert len(lines) == 3 and int(lines[1]) == dyn and int(lines[2]) == lpt
+            st, nt, dyn, lpt, policy, nbytes = dg.dd_batched_plan_info(plan)
+            assert st == 0 and nt > 0 and dyn in (0, 1) and lpt in (0, 1) and policy in (0, 1, 2) and nbytes > 0
+            words = open(tmp_path / "tune.txt").read().split()
+            assert len(words) == 5 and words[0] == "b"
+            assert (int(words[2]), int(words[3]), int(words[4])) == (dyn, lpt, policy)
         finally:
             dg.dd_batched_plan_destroy(plan)
         plan2 = b.plan()   # a new plan of the same shapes starts from the recorded choice
         try:
-            st, nt, dyn2, lpt2, _ = dg.dd_batched_plan_info(plan2)
-            assert (dyn2, lpt2) == (dyn, lpt)
+            st, nt2, dyn2, lpt2, policy2, _ = dg.dd_batched_plan_info(plan2)
+            assert (dyn2, lpt2, policy2, nt2) == (dyn, lpt, policy, nt)
         finally:
             dg.dd_batched_plan_destroy(plan2)
         torch.cuda.synchronize()

@@ -25,6 +25,10 @@ def test_trace_table_names_and_units(tmp_path):
     assert t[3].startswith("| helper | 2 | 0.0 |")
 
 
+# the headline product kernel as rocprofv3 names it
+PROD = "void ddk::cascade_kernel<false, false, ddk::(anonymous namespace)::Shape<64, 64> >"
+
+
 def test_traffic_scales_by_the_calibration_copy(tmp_path):
     mib = 1024
     copy_bytes = mib << 20
@@ -32,11 +36,14 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
     # the copy reads each byte once but FETCH_SIZE counts half of it (x2),
     # WRITE_SIZE counts it all (x1); the product kernel fetches 10 GiB, writes 1 GiB
     fetch = [["vectorized_elementwise_kernel<copy>", "FETCH_SIZE", copy_bytes / 2 / 1024],
-             [pf.PRODUCT_KERNEL + "(double const*)", "FETCH_SIZE", 5 * (1 << 30) / 1024],
-             [pf.PRODUCT_KERNEL + "(double const*)", "FETCH_SIZE", 5 * (1 << 30) / 1024],
-             ["cascade_kernel<false, true>(double const*)", "FETCH_SIZE", 1.0]]
+             [PROD + "(double const*)", "FETCH_SIZE", 5 * (1 << 30) / 1024],
+             [PROD + "(double const*)", "FETCH_SIZE", 5 * (1 << 30) / 1024],
+             ["void ddk::cascade_kernel<false, true, ddk::(anonymous namespace)::Shape<64, 64> >(double const*)",
+              "FETCH_SIZE", 1.0],
+             ["void ddk::cascade_kernel<false, false, ddk::(anonymous namespace)::Shape<32, 64> >(double const*)",
+              "FETCH_SIZE", 1.0]]
     write = [["vectorized_elementwise_kernel<copy>", "WRITE_SIZE", copy_bytes / 1024],
-             [pf.PRODUCT_KERNEL + "(double const*)", "WRITE_SIZE", (1 << 30) / 1024]]
+             [PROD + "(double const*)", "WRITE_SIZE", (1 << 30) / 1024]]
     _write(tmp_path / "f.csv", hdr, fetch)
     _write(tmp_path / "w.csv", hdr, write)
     r = pf.traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), mib, 8, 8, 8)
