@@ -575,6 +575,16 @@ def main():
 
     torch.cuda.set_device(0)
     dg.lib()  # fails loudly if the HIP library is missing
+    if args.copy_calibration > 0:
+        # the reference for scaling HBM byte counters: one elementwise kernel
+        # that reads and writes the given size once
+        nel = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nel * 8} bytes read and written by one elementwise kernel")
+        del src, dst
     if args.slices_only:
         sres, samples, IJ = bench_slices(torch, dg, torch.cuda.current_stream(), reps=max(1, args.steps))
         if not args.no_cpu_baseline:
@@ -637,14 +647,6 @@ def main():
     log(f"{ms_per_step:.2f} ms/step, {value:.1f} GFLOP/s effective; product kernel {prod_avg_ms:.2f} ms "
         f"({achieved:.2f} TFLOP/s FP64 MFMA), phase one {split_avg_ms:.2f} ms")
 
-    if args.copy_calibration > 0:
-        nel = args.copy_calibration * (1 << 20) // 8
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        log(f"copy calibration: {nel * 8} bytes read and written by one elementwise kernel")
-        del src, dst
 
     from paper_2303_04353_amd.profiling import load_traffic
     traffic = load_traffic(args.traffic, m, n, k)
