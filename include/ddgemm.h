@@ -181,6 +181,13 @@ typedef struct {
  * kc = 256 and a workspace that the library allocates and keeps per device
  * and stream (grown on demand; calls that overlap on one stream are ordered
  * by the stream).  m = 0 or n = 0 is a no-op; k = 0 leaves C unchanged.
+ * Graph capture: a call on a stream being captured uses the cached
+ * workspace if it is large enough (make one call of the largest size on
+ * that stream first) and returns DD_ERR_WORKSPACE otherwise, since it can
+ * neither allocate nor wait.  A buffer handed to a captured call is never
+ * freed, so replays of the graph stay valid when later calls grow the
+ * cache.  Calls issued on one stream from several host threads at once
+ * must be ordered by the caller (a call may replace the stream's buffer).
  */
 dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
                   const double* A_hi, const double* A_lo, int64_t lda,
@@ -209,9 +216,9 @@ size_t dd_gemm_workspace_size(int32_t transa, int32_t transb,
  * lda >= max(1, rows of A as stored), likewise ldb; ldc >= max(1, m).
  * `workspace` is caller-owned device memory of at least
  * dd_gemm_workspace_size(...) bytes, 256-byte aligned; passing NULL with
- * ws_bytes = 0 makes the library use its own cached workspace (which may
- * allocate, so not under graph capture).  The workspace is in use until the
- * call's work on `stream` has finished.
+ * ws_bytes = 0 makes the library use its own cached workspace, as dd_gemm
+ * does (under graph capture only if it is already large enough).  The
+ * workspace is in use until the call's work on `stream` has finished.
  */
 dd_status dd_gemm_ex(int32_t transa, int32_t transb,
                      int64_t m, int64_t n, int64_t k,

@@ -47,19 +47,38 @@ dd_status check_device(int* dev_out) {
 // ------------------------------------------------------ cached workspaces
 struct WsKey { int dev; hipStream_t stream; bool operator<(const WsKey& o) const {
   return dev != o.dev ? dev < o.dev : (uintptr_t)stream < (uintptr_t)o.stream; } };
-struct WsBuf { void* ptr = nullptr; size_t bytes = 0; };
+// `captured`: the buffer was handed to a call made while its stream was
+// being captured into a HIP graph.  Replays of that graph read it at any
+// later time, so it is never freed: when the cache grows past it, it is
+// kept (g_ws_kept) until the process ends.
+struct WsBuf { void* ptr = nullptr; size_t bytes = 0; bool captured = false; };
 std::map<WsKey, WsBuf> g_ws;
+std::vector<void*> g_ws_kept;
 
 dd_status cached_workspace(int dev, hipStream_t stream, size_t bytes, void** out) {
   std::lock_guard<std::mutex> lk(g_mu);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return DD_ERR_HIP;
+  }
+  const bool capturing = cs != hipStreamCaptureStatusNone;
   WsBuf& b = g_ws[WsKey{dev, stream}];
   if (b.bytes < bytes) {
+    // a stream being captured can neither wait nor take a new allocation:
+    // the caller warms the cache up before capturing, or passes a workspace
+    if (capturing) return DD_ERR_WORKSPACE;
     if (b.ptr) {
-      // earlier work on this stream may still use the old buffer
-      if (hipStreamSynchronize(stream) != hipSuccess) return DD_ERR_HIP;
-      (void)hipFree(b.ptr);
+      if (b.captured) {
+        g_ws_kept.push_back(b.ptr);
+      } else {
+        // earlier work on this stream may still use the old buffer
+        if (hipStreamSynchronize(stream) != hipSuccess) return DD_ERR_HIP;
+        (void)hipFree(b.ptr);
+      }
       b.ptr = nullptr;
       b.bytes = 0;
+      b.captured = false;
     }
     size_t want = bytes + bytes / 8;
     if (hipMalloc(&b.ptr, want) != hipSuccess) {
@@ -69,6 +88,7 @@ dd_status cached_workspace(int dev, hipStream_t stream, size_t bytes, void** out
     }
     b.bytes = want;
   }
+  if (capturing) b.captured = true;
   *out = b.ptr;
   return DD_OK;
 }

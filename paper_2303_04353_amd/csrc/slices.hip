@@ -181,15 +181,28 @@ __device__ __forceinline__ void mfma_group(int n) {
   }
 }
 
-// A scheduling group of n vector-memory reads (n in 1..3).
+// A scheduling group of n vector-memory reads (n in 1..10).
 __device__ __forceinline__ void vmem_group(int n) {
   switch (n) {
     case 1: __builtin_amdgcn_sched_group_barrier(0x020, 1, 0); break;
     case 2: __builtin_amdgcn_sched_group_barrier(0x020, 2, 0); break;
     case 3: __builtin_amdgcn_sched_group_barrier(0x020, 3, 0); break;
+    case 4: __builtin_amdgcn_sched_group_barrier(0x020, 4, 0); break;
+    case 5: __builtin_amdgcn_sched_group_barrier(0x020, 5, 0); break;
+    case 6: __builtin_amdgcn_sched_group_barrier(0x020, 6, 0); break;
+    case 7: __builtin_amdgcn_sched_group_barrier(0x020, 7, 0); break;
+    case 8: __builtin_amdgcn_sched_group_barrier(0x020, 8, 0); break;
+    case 9: __builtin_amdgcn_sched_group_barrier(0x020, 9, 0); break;
+    case 10: __builtin_amdgcn_sched_group_barrier(0x020, 10, 0); break;
     default: break;
   }
 }
+
+// Next-step B slices loaded per iteration of a step: B_j goes out in
+// iteration j / BPER, so the last one has most of the step to arrive.  The
+// final pass (levels 0..8, few products per step) loads them sooner than
+// the upper pass, whose longer steps already cover the wait.
+constexpr int kBPerLower = 4, kBPerUpper = 2;
 
 struct ProductArgs {
   const u32x4* Apack;
@@ -228,6 +241,8 @@ __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
   constexpr bool kFlushes = FMT != kI8;
   constexpr int NL = LE - LB;
   constexpr int G0 = LB / kGroup, NGP = (LE + kGroup - 1) / kGroup - G0;   // groups of this pass
+  constexpr int BPER = LB == 0 ? kBPerLower : kBPerUpper;
+  static_assert(BPER >= 1 && BPER <= 9, "a scheduling group holds up to 10 loads");
   using Acc = acc_t<FMT>;
   // the wave index is uniform: operand addresses are formed on the scalar unit
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -253,7 +268,7 @@ __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
   // slices 0 .. LE-1 of both operands take part (every one reaches level LE-1).
   // A_i is reloaded for the next step right after its products; B_0 is
   // needed until the end of a step, so B has two buffers: the next step's B
-  // loads early in the current step.
+  // loads early in the current step, BPER slices per iteration.
   u32x4 fa[LE], fb0[LE], fb1[LE];
   {
     // same order as the loads inside the loop, so the waits there can count
@@ -261,8 +276,8 @@ __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
       fa[i] = Ap[base + i * 64];
-      if (2 * i < LE) fb0[2 * i] = Bp[base + 2 * i * 64];
-      if (2 * i + 1 < LE) fb0[2 * i + 1] = Bp[base + (2 * i + 1) * 64];
+#pragma unroll
+      for (int j = i * BPER; j < (i + 1) * BPER && j < LE; ++j) fb0[j] = Bp[base + j * 64];
       asm volatile("" ::: "memory");
     }
   }
@@ -312,11 +327,11 @@ __global__ void __launch_bounds__(256, 1) slices_product(const ProductArgs a) {
         acc[L] = mma<FMT>(fa[i], fb[j], fresh ? zero : acc[L]);
         started[L] = true;
       }
-      // A_i is not needed again in this step; two of next step's B slices
+      // A_i is not needed again in this step; up to BPER of next step's B slices
       fa[i] = Ap[nxt + i * 64];
       int nl = 1;
-      if (2 * i < LE) { fbn[2 * i] = Bp[nxt + 2 * i * 64]; ++nl; }
-      if (2 * i + 1 < LE) { fbn[2 * i + 1] = Bp[nxt + (2 * i + 1) * 64]; ++nl; }
+#pragma unroll
+      for (int j = i * BPER; j < (i + 1) * BPER && j < LE; ++j, ++nl) fbn[j] = Bp[nxt + j * 64];
       // keep the loads here (not sunk below the flushes)
       asm volatile("" ::: "memory");
       mfma_group(nm);                                      // this iteration's MFMAs,

@@ -66,6 +66,7 @@ constexpr int kAStage3 = 4 * kFrag3;          // A part of an LDS stage: four 16
 constexpr int kStage3 = 2 * kAStage3;         // doubles per stage (24 KiB)
 constexpr int kNBuf3 = 3;
 constexpr int kPieces3 = kStage3 / 128;       // 1 KiB pieces per stage (24), three per wave
+static_assert(kPieces3 == 3 * kWaves3, "every wave stages three 1 KiB pieces of a stage");
 
 // Packed planes of one 16-row (16-column) block are contiguous over k; the
 // blocks are 4 KiB + 256 B further apart than their size (L2 sets).
