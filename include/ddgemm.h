@@ -323,12 +323,34 @@ dd_status dd_batched_plan_info(dd_batched_plan plan, int64_t* ntiles, int32_t* d
 /* Waits for the device, then frees the plan and its memory. */
 dd_status dd_batched_plan_destroy(dd_batched_plan plan);
 
-/* One-shot form: plan, execute, wait, free.  Synchronous. */
+/*
+ * One-shot form.  m, n, k, lda, ldb, ldc are host arrays, A_hi .. C_lo
+ * device arrays of device pointers, as for a plan; opts as for a plan.
+ *  - workspace = NULL, ws_bytes = 0: plan, execute, wait, free
+ *    (allocates; synchronous).
+ *  - workspace = caller-owned device memory, 256-byte aligned, of at least
+ *    dd_gemm_batched_workspace_size(count, m, n, k, opts) bytes: the call
+ *    launches its kernels on `stream` and returns (asynchronous; the
+ *    workspace is in use until they finish).  The plan's tables
+ *    (descriptors and tile list, a few hundred bytes per problem and 16 per
+ *    tile) are built and uploaded at the first call with these shapes on a
+ *    device and kept by the library until the process ends; later calls
+ *    with the same shapes allocate nothing and may be captured in a HIP
+ *    graph.  On a stream being captured, shapes seen for the first time
+ *    give DD_ERR_WORKSPACE and nothing is launched.  A workspace smaller
+ *    than needed gives DD_ERR_WORKSPACE.
+ */
 dd_status dd_gemm_batched(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
                           const double* const* A_hi, const double* const* A_lo, const int64_t* lda,
                           const double* const* B_hi, const double* const* B_lo, const int64_t* ldb,
                           double* const* C_hi, double* const* C_lo, const int64_t* ldc,
-                          const dd_gemm_opts* opts, hipStream_t stream);
+                          void* workspace, size_t ws_bytes, const dd_gemm_opts* opts, hipStream_t stream);
+
+/* Bytes of workspace dd_gemm_batched needs for these shapes (host arrays) and
+ * options: an atomic counter, the row and column exponents and the packed
+ * planes of every problem.  0 for invalid arguments. */
+size_t dd_gemm_batched_workspace_size(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                                      const dd_gemm_opts* opts);
 
 /*
  * The split of Appendix A on its own (phase one of Sec. 4), for inspection

@@ -42,6 +42,8 @@ struct dd_batched_plan_s {
   uint64_t key = 0;
   char* dmem = nullptr;          // one device allocation for everything below
   size_t dmem_bytes = 0;
+  size_t ws_bytes = 0;           // exponent words and packed planes of all problems
+  bool own_ws = true;            // false: d_counter and d_ws come with each call
   BatchDesc* d_desc = nullptr;
   int64_t *d_pexpA = nullptr, *d_pexpB = nullptr, *d_ppackA = nullptr, *d_ppackB = nullptr;
   BatchTile* d_tiles = nullptr;
@@ -149,13 +151,10 @@ dd_status upload_tiles(dd_batched_plan_s* P, hipStream_t s) {
   return hip_st(hipMemcpyAsync(P->d_tiles, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice, s));
 }
 
-}  // namespace
-
-extern "C" {
-
-dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
-                                 const int64_t* lda, const int64_t* ldb, const int64_t* ldc,
-                                 const dd_gemm_opts* opts, dd_batched_plan* plan) {
+// Argument checks of a plan (numbers as in dd_batched_plan_create); kc out.
+dd_status check_plan_args(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                          const int64_t* lda, const int64_t* ldb, const int64_t* ldc, const dd_gemm_opts* opts,
+                          int32_t* kc_out) {
   if (count < 0) return -1;
   if (count > 0 && (!m)) return -2;
   if (count > 0 && (!n)) return -3;
@@ -163,12 +162,10 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
   if (count > 0 && (!lda)) return -5;
   if (count > 0 && (!ldb)) return -6;
   if (count > 0 && (!ldc)) return -7;
-  if (!plan) return -9;
-  *plan = nullptr;
   int32_t kc = 256;
   if (opts) {
     if (opts->algo != DD_ALGO_CASCADE_F64 || opts->tile != 0 || opts->slices != 0 || opts->slice_bits != 0 ||
-        opts->scaling != 0 || opts->flags_out != nullptr)
+        opts->scaling != 0 || opts->flags_out != nullptr || opts->use_tuned != 0)
       return -8;
     if (opts->kc != 0) {
       if (opts->kc < 4 || opts->kc > 4096 || opts->kc % 4 != 0) return -8;
@@ -181,6 +178,46 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
     if (ldb[p] < std::max<int64_t>(1, k[p])) return -6;
     if (ldc[p] < std::max<int64_t>(1, m[p])) return -7;
   }
+  *kc_out = kc;
+  return DD_OK;
+}
+
+// Bytes of the exponent words and packed planes of a batch; fills the
+// descriptors' layout fields when desc is given.
+size_t batch_ws_bytes(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k, int32_t kc,
+                      BatchDesc* desc) {
+  int64_t nexps = 0;
+  for (int32_t p = 0; p < count; ++p) {
+    const bool active = m[p] > 0 && n[p] > 0 && k[p] > 0;
+    if (active) nexps += ddk::round_up(m[p], kTile) + ddk::round_up(n[p], kTile);
+  }
+  size_t off = (size_t)ddk::round_up(nexps * 8, 256);
+  int64_t eoff = 0;
+  for (int32_t p = 0; p < count; ++p) {
+    if (!(m[p] > 0 && n[p] > 0 && k[p] > 0)) continue;
+    const ddk::CascadeLayout L = ddk::make_layout(m[p], n[p], k[p], kc, kTile, kTile);
+    BatchDesc tmp;
+    BatchDesc& d = desc ? desc[p] : tmp;
+    d.K4 = L.K4; d.mpad = L.mpad; d.npad = L.npad;
+    d.tiles_m = L.mpad / kTile; d.tiles_n = L.npad / kTile;
+    d.kcq = L.kcq; d.c0 = L.c[0]; d.c1 = L.c[1]; d.c2 = L.c[2];
+    d.off_amax = eoff * 8; eoff += d.mpad;
+    d.off_bmax = eoff * 8; eoff += d.npad;
+    d.off_apack = (int64_t)off;
+    off += (size_t)ddk::round_up((int64_t)(sizeof(double) * (d.mpad / 16) * ddk::a_block_stride(L.K4)), 256);
+    d.off_bpack = (int64_t)off;
+    off += (size_t)ddk::round_up((int64_t)(sizeof(double) * (d.npad / 16) * ddk::b_block_stride(L.K4)), 256);
+  }
+  return off;
+}
+
+// A plan of checked arguments.  With own_ws, its one device allocation also
+// holds the atomic counter and the workspace; otherwise only the tables
+// (descriptors, prefix sums, tiles), and each execution brings the rest.
+dd_status plan_create(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                      const int64_t* lda, const int64_t* ldb, const int64_t* ldc, int32_t kc, bool own_ws,
+                      dd_batched_plan* plan) {
+  *plan = nullptr;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return DD_ERR_HIP;
   hipDeviceProp_t prop;
@@ -195,31 +232,18 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
   P->desc.resize(count);
   std::vector<int64_t> pexpA(count + 1, 0), pexpB(count + 1, 0), ppackA(count + 1, 0), ppackB(count + 1, 0);
   // workspace: all exponent words first (zeroed with one fill), then the packed planes
-  int64_t nexps = 0;
-  for (int32_t p = 0; p < count; ++p) {
-    const int64_t mp = m[p] > 0 ? ddk::round_up(m[p], kTile) : 0, np = n[p] > 0 ? ddk::round_up(n[p], kTile) : 0;
-    nexps += mp + np;
-  }
-  size_t off = (size_t)ddk::round_up(nexps * 8, 256);
-  int64_t eoff = 0;
   for (int32_t p = 0; p < count; ++p) {
     BatchDesc& d = P->desc[p];
     std::memset(&d, 0, sizeof(d));
     d.m = m[p]; d.n = n[p]; d.k = k[p];
     d.lda = lda[p]; d.ldb = ldb[p]; d.ldc = ldc[p];
+  }
+  const size_t off = batch_ws_bytes(count, m, n, k, kc, P->desc.data());
+  int64_t eoff = 0;
+  for (int32_t p = 0; p < count; ++p) {
+    BatchDesc& d = P->desc[p];
     const bool active = m[p] > 0 && n[p] > 0 && k[p] > 0;
-    if (active) {
-      ddk::CascadeLayout L = ddk::make_layout(m[p], n[p], k[p], kc, kTile, kTile);
-      d.K4 = L.K4; d.mpad = L.mpad; d.npad = L.npad;
-      d.tiles_m = L.mpad / kTile; d.tiles_n = L.npad / kTile;
-      d.kcq = L.kcq; d.c0 = L.c[0]; d.c1 = L.c[1]; d.c2 = L.c[2];
-      d.off_amax = eoff * 8; eoff += d.mpad;
-      d.off_bmax = eoff * 8; eoff += d.npad;
-      d.off_apack = (int64_t)off;
-      off += (size_t)ddk::round_up((int64_t)(sizeof(double) * (d.mpad / 16) * ddk::a_block_stride(L.K4)), 256);
-      d.off_bpack = (int64_t)off;
-      off += (size_t)ddk::round_up((int64_t)(sizeof(double) * (d.npad / 16) * ddk::b_block_stride(L.K4)), 256);
-    }
+    if (active) eoff += d.mpad + d.npad;
     pexpA[p + 1] = pexpA[p] + (active ? cdiv(d.m, 256) * cdiv(d.k, 256) : 0);
     pexpB[p + 1] = pexpB[p] + (active ? cdiv(d.n, 4) * cdiv(d.k, 4096) : 0);
     ppackA[p + 1] = ppackA[p] + (active ? cdiv((d.mpad / 16) * d.K4, 4) : 0);
@@ -242,17 +266,18 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
     build_tiles(P, q);
     P->max_tiles = std::max(P->max_tiles, P->ntiles);
   }
-  const size_t ws_bytes = off;
+  P->ws_bytes = off;
+  P->own_ws = own_ws;
 
-  // device memory: descriptors, prefix arrays, tiles, counter, workspace
+  // device memory: descriptors, prefix arrays, tiles (and counter, workspace)
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = (size_t)ddk::round_up((int64_t)(o + bytes), 256); return r; };
   const size_t o_desc = take(sizeof(BatchDesc) * std::max(count, 1));
   const size_t o_pa = take(sizeof(int64_t) * (count + 1)), o_pb = take(sizeof(int64_t) * (count + 1));
   const size_t o_qa = take(sizeof(int64_t) * (count + 1)), o_qb = take(sizeof(int64_t) * (count + 1));
   const size_t o_tiles = take(sizeof(BatchTile) * std::max<int64_t>(P->max_tiles, 1));
-  const size_t o_ctr = take(sizeof(uint64_t));
-  const size_t o_ws = take(std::max<size_t>(ws_bytes, 256));
+  const size_t o_ctr = own_ws ? take(sizeof(uint64_t)) : 0;
+  const size_t o_ws = own_ws ? take(std::max<size_t>(P->ws_bytes, 256)) : 0;
   P->dmem_bytes = o;
   if (hipMalloc(&P->dmem, P->dmem_bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -265,8 +290,8 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
   P->d_ppackA = (int64_t*)(P->dmem + o_qa);
   P->d_ppackB = (int64_t*)(P->dmem + o_qb);
   P->d_tiles = (BatchTile*)(P->dmem + o_tiles);
-  P->d_counter = (uint32_t*)(P->dmem + o_ctr);
-  P->d_ws = P->dmem + o_ws;
+  P->d_counter = own_ws ? (uint32_t*)(P->dmem + o_ctr) : nullptr;
+  P->d_ws = own_ws ? P->dmem + o_ws : nullptr;
 
   // key of the tuning cache: device, kc and every shape
   uint64_t key = fnv1a(prop.gcnArchName, std::strlen(prop.gcnArchName));
@@ -300,10 +325,11 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
   return DD_OK;
 }
 
-dd_status dd_gemm_batched_exec(dd_batched_plan P, const double* const* A_hi, const double* const* A_lo,
-                               const double* const* B_hi, const double* const* B_lo,
-                               double* const* C_hi, double* const* C_lo, hipStream_t stream) {
-  if (!P) return -1;
+// One execution with the given workspace and counter (argument numbers as
+// in dd_gemm_batched_exec).
+dd_status plan_exec(dd_batched_plan P, const double* const* A_hi, const double* const* A_lo,
+                    const double* const* B_hi, const double* const* B_lo, double* const* C_hi,
+                    double* const* C_lo, char* ws, uint32_t* counter, hipStream_t stream) {
   if (P->ntiles == 0) return DD_OK;
   if (!A_hi) return -2;
   if (!A_lo) return -3;
@@ -316,10 +342,66 @@ dd_status dd_gemm_batched_exec(dd_batched_plan P, const double* const* A_hi, con
   if (dev != P->device) return DD_ERR_UNSUPPORTED;
   hipError_t e = ddk::launch_batched_phase_one(P->d_desc, P->count, P->d_pexpA, P->d_pexpB, P->units_exp,
                                                P->d_ppackA, P->d_ppackB, P->units_pack, A_hi, A_lo, B_hi, B_lo,
-                                               P->d_ws, (uint64_t*)P->d_ws, P->nexps, stream);
+                                               ws, (uint64_t*)ws, P->nexps, stream);
   if (e != hipSuccess) return hip_st(e);
-  return hip_st(ddk::launch_cascade_batched(P->d_desc, P->d_tiles, P->ntiles, C_hi, C_lo, P->d_ws,
-                                            P->d_counter, P->grid, P->dynamic != 0, stream));
+  return hip_st(ddk::launch_cascade_batched(P->d_desc, P->d_tiles, P->ntiles, C_hi, C_lo, ws, counter, P->grid,
+                                            P->dynamic != 0, stream));
+}
+
+// Tables of the one-shot form with a caller workspace, kept per device, kc
+// and shapes until the process ends (read-only once built).
+struct TableKey {
+  int dev;
+  int32_t kc;
+  std::vector<int64_t> shapes;   // m, n, k, lda, ldb, ldc of every problem
+  bool operator<(const TableKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (kc != o.kc) return kc < o.kc;
+    return shapes < o.shapes;
+  }
+};
+std::mutex g_tables_mu;
+std::map<TableKey, dd_batched_plan_s*> g_tables;
+
+}  // namespace
+
+extern "C" {
+
+dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                                 const int64_t* lda, const int64_t* ldb, const int64_t* ldc,
+                                 const dd_gemm_opts* opts, dd_batched_plan* plan) {
+  int32_t kc = 256;
+  const dd_status st = check_plan_args(count, m, n, k, lda, ldb, ldc, opts, &kc);
+  if (st != DD_OK) return st;
+  if (!plan) return -9;
+  return plan_create(count, m, n, k, lda, ldb, ldc, kc, true, plan);
+}
+
+dd_status dd_gemm_batched_exec(dd_batched_plan P, const double* const* A_hi, const double* const* A_lo,
+                               const double* const* B_hi, const double* const* B_lo,
+                               double* const* C_hi, double* const* C_lo, hipStream_t stream) {
+  if (!P) return -1;
+  if (!P->own_ws) return -1;
+  return plan_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, P->d_ws, P->d_counter, stream);
+}
+
+size_t dd_gemm_batched_workspace_size(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                                      const dd_gemm_opts* opts) {
+  if (count < 0 || (count > 0 && (!m || !n || !k))) return 0;
+  int32_t kc = 256;
+  if (opts) {
+    if (opts->algo != DD_ALGO_CASCADE_F64 || opts->tile != 0 || opts->slices != 0 || opts->slice_bits != 0 ||
+        opts->scaling != 0 || opts->flags_out != nullptr || opts->use_tuned != 0)
+      return 0;
+    if (opts->kc != 0) {
+      if (opts->kc < 4 || opts->kc > 4096 || opts->kc % 4 != 0) return 0;
+      kc = opts->kc;
+    }
+  }
+  for (int32_t p = 0; p < count; ++p)
+    if (m[p] < 0 || n[p] < 0 || k[p] < 0) return 0;
+  // the atomic counter, then the exponent words and packed planes
+  return 256 + std::max<size_t>(batch_ws_bytes(count, m, n, k, kc, nullptr), 256);
 }
 
 dd_status dd_batched_plan_tune(dd_batched_plan P, const double* const* A_hi, const double* const* A_lo,
@@ -408,23 +490,58 @@ dd_status dd_gemm_batched(int32_t count, const int64_t* m, const int64_t* n, con
                           const double* const* A_hi, const double* const* A_lo, const int64_t* lda,
                           const double* const* B_hi, const double* const* B_lo, const int64_t* ldb,
                           double* const* C_hi, double* const* C_lo, const int64_t* ldc,
-                          const dd_gemm_opts* opts, hipStream_t stream) {
+                          void* workspace, size_t ws_bytes, const dd_gemm_opts* opts, hipStream_t stream) {
+  // argument numbers of the plan calls mapped onto this prototype
+  static const int pos[] = {0, 1, 2, 3, 4, 7, 10, 13, 16, 0};
+  static const int pos2[] = {0, 0, 5, 6, 8, 9, 11, 12};
   if (count < 0) return -1;
+  if (!workspace && ws_bytes != 0) return -15;
+  if (workspace && ((uintptr_t)workspace & 255u) != 0) return -14;
+  int32_t kc = 256;
+  dd_status st = check_plan_args(count, m, n, k, lda, ldb, ldc, opts, &kc);
+  if (st != DD_OK) return st < 0 && -st < 10 ? -pos[-st] : st;
   if (count == 0) return DD_OK;
+  if (!workspace) {
+    dd_batched_plan P = nullptr;
+    st = plan_create(count, m, n, k, lda, ldb, ldc, kc, true, &P);
+    if (st != DD_OK) return st;
+    st = plan_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, P->d_ws, P->d_counter, stream);
+    if (st < 0) st = -pos2[-st];
+    const dd_status st2 = dd_batched_plan_destroy(P);  // waits for the work to finish
+    return st != DD_OK ? st : st2;
+  }
+  // caller workspace: the tables of these shapes, built once per device
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return DD_ERR_HIP;
+  TableKey key{dev, kc, {}};
+  key.shapes.reserve((size_t)count * 6);
+  for (int32_t p = 0; p < count; ++p) {
+    const int64_t v[6] = {m[p], n[p], k[p], lda[p], ldb[p], ldc[p]};
+    key.shapes.insert(key.shapes.end(), v, v + 6);
+  }
   dd_batched_plan P = nullptr;
-  dd_status st = dd_batched_plan_create(count, m, n, k, lda, ldb, ldc, opts, &P);
-  if (st != DD_OK) {
-    // map the plan's argument numbers onto this prototype
-    static const int pos[] = {0, 1, 2, 3, 4, 7, 10, 13, 14, 0};
-    return st < 0 && -st < 10 ? -pos[-st] : st;
+  {
+    std::lock_guard<std::mutex> lk(g_tables_mu);
+    auto it = g_tables.find(key);
+    if (it != g_tables.end()) {
+      P = it->second;
+    } else {
+      // building them allocates and waits: not on a stream being captured
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return DD_ERR_HIP;
+      }
+      if (cs != hipStreamCaptureStatusNone) return DD_ERR_WORKSPACE;
+      st = plan_create(count, m, n, k, lda, ldb, ldc, kc, false, &P);
+      if (st != DD_OK) return st;
+      g_tables.emplace(std::move(key), P);
+    }
   }
-  st = dd_gemm_batched_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, stream);
-  if (st < 0) {
-    static const int pos2[] = {0, 0, 5, 6, 8, 9, 11, 12};
-    st = -pos2[-st];
-  }
-  dd_status st2 = dd_batched_plan_destroy(P);  // waits for the work to finish
-  return st != DD_OK ? st : st2;
+  if (ws_bytes < 256 + std::max<size_t>(P->ws_bytes, 256)) return DD_ERR_WORKSPACE;
+  char* w = (char*)workspace;
+  st = plan_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, w + 256, (uint32_t*)w, stream);
+  return st < 0 ? -pos2[-st] : st;
 }
 
 }  // extern "C"

@@ -44,7 +44,8 @@ EXPORTED = ("dd_gemm", "dd_gemm_workspace_size", "dd_gemm_ex", "dd_cascade_split
             "dd_scal", "dd_batched_plan_create", "dd_gemm_batched_exec", "dd_batched_plan_tune",
             "dd_batched_plan_schedule", "dd_batched_plan_info", "dd_batched_plan_destroy",
             "dd_gemm_batched", "dd_profile_enable", "dd_phase_times", "dd_status_string", "dd_version",
-            "td_gemm_workspace_size", "td_gemm_ex", "dd_gemm_noalloc", "dd_add", "dd_tune")
+            "td_gemm_workspace_size", "td_gemm_ex", "dd_gemm_noalloc", "dd_add", "dd_tune",
+            "dd_gemm_batched_workspace_size")
 
 
 class dd_gemm_opts(ctypes.Structure):
@@ -104,8 +105,10 @@ def lib():
         L.dd_batched_plan_destroy.argtypes = [vp]
         L.dd_batched_plan_destroy.restype = i32
         L.dd_gemm_batched.argtypes = [i32, pi64, pi64, pi64, vp, vp, pi64, vp, vp, pi64, vp, vp, pi64,
-                                      ctypes.POINTER(dd_gemm_opts), vp]
+                                      vp, sz, ctypes.POINTER(dd_gemm_opts), vp]
         L.dd_gemm_batched.restype = i32
+        L.dd_gemm_batched_workspace_size.argtypes = [i32, pi64, pi64, pi64, ctypes.POINTER(dd_gemm_opts)]
+        L.dd_gemm_batched_workspace_size.restype = sz
         L.dd_profile_enable.argtypes = [i32]
         L.dd_profile_enable.restype = i32
         L.dd_phase_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -275,11 +278,17 @@ def dd_batched_plan_destroy(plan) -> int:
     return int(lib().dd_batched_plan_destroy(plan))
 
 
-def dd_gemm_batched(count, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc, opts=None,
-                    stream=None) -> int:
+def dd_gemm_batched(count, m, n, k, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc, workspace=None,
+                    ws_bytes=0, opts=None, stream=None) -> int:
     return int(lib().dd_gemm_batched(int(count), _i64arr(m), _i64arr(n), _i64arr(k), _ptr(A_hi), _ptr(A_lo),
                                      _i64arr(lda), _ptr(B_hi), _ptr(B_lo), _i64arr(ldb), _ptr(C_hi),
-                                     _ptr(C_lo), _i64arr(ldc), _opts(opts), _stream(stream)))
+                                     _ptr(C_lo), _i64arr(ldc), _ptr(workspace), int(ws_bytes), _opts(opts),
+                                     _stream(stream)))
+
+
+def dd_gemm_batched_workspace_size(count, m, n, k, opts=None) -> int:
+    return int(lib().dd_gemm_batched_workspace_size(int(count), _i64arr(m), _i64arr(n), _i64arr(k),
+                                                    _opts(opts)))
 
 
 def dd_profile_enable(enable) -> int:

@@ -240,3 +240,32 @@ def test_on_load_options_and_workspace():
     # only the row and column maxima: 8 (mpad + npad) bytes, 256-byte aligned pieces
     assert dg.dd_gemm_workspace_size(0, 0, 100, 70, 300, o) == 8 * 128 + 8 * 128
     assert dg.dd_gemm_workspace_size(0, 0, 100, 70, 300, dict(o, tile=dg.DD_TILE_64x64)) == 8 * 256
+
+
+def test_one_shot_batched_checks_on_host_and_workspace_size():
+    m, n, k = [64, 100], [32, 70], [16, 300]
+    ld = [128, 128]
+    ptrs = (1 << 20, 1 << 21, ld, 1 << 22, 1 << 23, ld, 1 << 24, 1 << 25, ld)
+    assert dg.dd_gemm_batched(-1, m, n, k, *ptrs, stream=0) == -1
+    assert dg.dd_gemm_batched(2, m, n, k, *ptrs, workspace=None, ws_bytes=4096, stream=0) == -15
+    assert dg.dd_gemm_batched(2, m, n, k, *ptrs, workspace=(1 << 26) + 8, ws_bytes=1 << 30, stream=0) == -14
+    assert dg.dd_gemm_batched(2, m, n, k, *ptrs, opts={"kc": 6}, stream=0) == -16
+    assert dg.dd_gemm_batched(2, m, n, k, *ptrs, opts={"scaling": dg.DD_SCALING_PANEL}, stream=0) == -16
+    assert dg.dd_gemm_batched(2, [64, -1], n, k, *ptrs, stream=0) == -2
+    assert dg.dd_gemm_batched(2, m, n, k, 1 << 20, 1 << 21, [63, 128], 1 << 22, 1 << 23, ld, 1 << 24, 1 << 25, ld,
+                              stream=0) == -7
+    # workspace: a 256-byte counter, the exponent words of both problems
+    # (rows and columns rounded up to 64), then the packed planes, which
+    # equal the single-GEMM cascade's
+    ws = dg.dd_gemm_batched_workspace_size(2, m, n, k)
+    exps = 8 * (64 + 64 + 128 + 128)
+    planes = 0
+    for mi, ni, ki in zip(m, n, k):
+        single = dg.dd_gemm_workspace_size(0, 0, mi, ni, ki)
+        planes += single - 8 * (-(-mi // 64) * 64 + -(-ni // 64) * 64)
+    assert ws >= 256 + exps + planes - 2 * 256 and ws <= 256 + exps + planes + 4 * 256
+    assert dg.dd_gemm_batched_workspace_size(2, m, n, [16, 600]) > ws
+    assert dg.dd_gemm_batched_workspace_size(2, m, n, k, opts={"kc": 6}) == 0
+    assert dg.dd_gemm_batched_workspace_size(-1, m, n, k) == 0
+    # problems with a zero dimension take no room
+    assert dg.dd_gemm_batched_workspace_size(3, m + [500], n + [0], k + [500]) == ws

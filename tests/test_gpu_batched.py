@@ -6,7 +6,9 @@
   the FP64x2 oracle on sampled entries of every problem;
 * a HIP graph of one execution, replayed several times with eager work in
   between, reproduces the eager result every time;
-* the tuner picks a schedule and records it in the cache file.
+* the tuner picks a schedule and records it in the cache file;
+* the one-shot call with a caller workspace: bit-identical to single calls,
+  a workspace too small refused, graph capture once its shapes are known.
 """
 import os
 
@@ -120,6 +122,90 @@ def test_one_shot_entry_point():
     torch.cuda.synchronize()
     for g, w in zip(b.results(), want):
         assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1])
+
+
+def _one_shot(b, ws, nbytes, stream=None, opts=None):
+    return dg.dd_gemm_batched(len(b.shapes), b.m, b.n, b.k, b.pA[0], b.pA[1], b.lda, b.pB[0], b.pB[1], b.ldb,
+                              b.pC[0], b.pC[1], b.ldc, workspace=ws, ws_bytes=nbytes, opts=opts, stream=stream)
+
+
+@pytest.mark.parametrize("kc", [0, 128])
+def test_one_shot_with_caller_workspace(kc):
+    import torch
+    log(f"batched one-shot with a caller workspace, kc={kc}")
+    b = Batch(MIXED, cfg=34)
+    opts = {"kc": kc}
+    want = b.singles(opts)
+    need = dg.dd_gemm_batched_workspace_size(len(b.shapes), b.m, b.n, b.k, opts)
+    assert need > 256
+    # the workspace arrives full of junk: the call must clear what it uses
+    ws = torch.full((need // 8 + 1,), float("nan"), dtype=torch.float64, device="cuda")
+    # too small: refused, C untouched
+    assert _one_shot(b, ws, need - 8, opts=opts) == dg.DD_ERR_WORKSPACE
+    torch.cuda.synchronize()
+    for g, c0 in zip(b.results(), b.C0):
+        assert np.array_equal(g[0], c0[0].cpu().numpy()) and np.array_equal(g[1], c0[1].cpu().numpy())
+    for r in range(2):   # the second call takes the kept tables
+        b.reset()
+        dg.check(_one_shot(b, ws, need, opts=opts), "dd_gemm_batched")
+        torch.cuda.synchronize()
+        for i, (g, w) in enumerate(zip(b.results(), want)):
+            assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1]), (r, i)
+
+
+def test_one_shot_with_workspace_under_graph_capture():
+    import ctypes
+    import torch
+    b = Batch(SMALL, cfg=35)
+    want = b.singles()
+    need = dg.dd_gemm_batched_workspace_size(len(b.shapes), b.m, b.n, b.k)
+    ws = torch.empty(need // 8 + 1, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        dg.check(_one_shot(b, ws, need, stream=s), "dd_gemm_batched warm-up")   # builds the tables
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            dg.check(_one_shot(b, ws, need, stream=s), "captured dd_gemm_batched")
+    torch.cuda.synchronize()
+    for r in range(3):
+        b.reset()
+        x = torch.randn(500, 500, device="cuda", dtype=torch.float64)   # eager work between replays
+        (x @ x).sum().item()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, (gg, w) in enumerate(zip(b.results(), want)):
+            assert np.array_equal(gg[0], w[0]) and np.array_equal(gg[1], w[1]), (r, i)
+    del g
+    # shapes never seen before cannot be prepared under capture: refused, nothing launched
+    b2 = Batch([(40, 41, 42), (43, 44, 45)], cfg=36)
+    need2 = dg.dd_gemm_batched_workspace_size(2, b2.m, b2.n, b2.k)
+    ws2 = torch.empty(need2 // 8 + 1, dtype=torch.float64, device="cuda")
+    hip = ctypes.CDLL("libamdhip64.so")
+    raw = ctypes.c_void_p()
+    assert hip.hipStreamCreate(ctypes.byref(raw)) == 0
+    try:
+        s2 = torch.cuda.ExternalStream(raw.value)
+        y = torch.zeros(8, device="cuda", dtype=torch.float64)
+        torch.cuda.synchronize()
+        g2 = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s2):
+            with torch.cuda.graph(g2, stream=s2):
+                st = _one_shot(b2, ws2, need2, stream=s2)
+                y.add_(1.0)   # the graph holds this op only
+        torch.cuda.synchronize()
+        assert st == dg.DD_ERR_WORKSPACE
+        g2.replay()
+        torch.cuda.synchronize()
+        assert float(y.sum()) == 8.0
+        for gg, c0 in zip(b2.results(), b2.C0):
+            assert np.array_equal(gg[0], c0[0].cpu().numpy()) and np.array_equal(gg[1], c0[1].cpu().numpy())
+        del g2
+    finally:
+        torch.cuda.synchronize()
+        hip.hipStreamDestroy(raw)
 
 
 def test_uneven_batch_512_against_oracle_and_singles():
