@@ -163,12 +163,16 @@ typedef struct {
                           other algorithms and for the batched calls.           */
   uint32_t* flags_out; /* cascade only, may be NULL: device bitmap of ceil(m n / 32)
                           words, bit (i + j m) for entry (i, j) of C.  The call
-                          zeroes it, then sets the bit of every entry at risk of
-                          cancellation: in some rank-kc block the exact bin 0
-                          (the leading digits' product, Sec. 3.7 and Sec. 4.4)
-                          is zero while a lower bin of that block is not.  No
-                          correction is applied.  Must be NULL for the other
-                          algorithms and for the batched calls.                  */
+                          zeroes it (also when k = 0), then sets the bit of
+                          every entry at risk of cancellation: in some rank-kc
+                          block the exact bin 0 (the leading digits' product,
+                          Sec. 3.7 and Sec. 4.4) is zero while a lower bin of
+                          that block is not.  No correction is applied.  Must
+                          be NULL for the other algorithms.  Batched calls: one
+                          bitmap for all problems, problem p's from word
+                          sum over q < p of ceil(m_q n_q / 32); every execution
+                          zeroes all of it (a plan keeps the pointer given at
+                          its creation).                                        */
   int32_t use_tuned;   /* cascade, 0 or 1: with tile = DD_TILE_AUTO, take the tile
                           shape dd_tune recorded for (m, n, k, kc, scaling), if
                           any (must be 0 for the other algorithms)              */

@@ -44,6 +44,8 @@ struct dd_batched_plan_s {
   size_t dmem_bytes = 0;
   size_t ws_bytes = 0;           // exponent words and packed planes of all problems
   bool own_ws = true;            // false: d_counter and d_ws come with each call
+  uint32_t* flags = nullptr;     // cancellation bitmaps (opts.flags_out), or null
+  int64_t flag_words = 0;        // words of all problems' bitmaps
   BatchDesc* d_desc = nullptr;
   int64_t *d_pexpA = nullptr, *d_pexpB = nullptr, *d_ppackA = nullptr, *d_ppackB = nullptr;
   BatchTile* d_tiles = nullptr;
@@ -165,7 +167,7 @@ dd_status check_plan_args(int32_t count, const int64_t* m, const int64_t* n, con
   int32_t kc = 256;
   if (opts) {
     if (opts->algo != DD_ALGO_CASCADE_F64 || opts->tile != 0 || opts->slices != 0 || opts->slice_bits != 0 ||
-        opts->scaling != 0 || opts->flags_out != nullptr || opts->use_tuned != 0)
+        opts->scaling != 0 || opts->use_tuned != 0)
       return -8;
     if (opts->kc != 0) {
       if (opts->kc < 4 || opts->kc > 4096 || opts->kc % 4 != 0) return -8;
@@ -216,7 +218,7 @@ size_t batch_ws_bytes(int32_t count, const int64_t* m, const int64_t* n, const i
 // (descriptors, prefix sums, tiles), and each execution brings the rest.
 dd_status plan_create(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
                       const int64_t* lda, const int64_t* ldb, const int64_t* ldc, int32_t kc, bool own_ws,
-                      dd_batched_plan* plan) {
+                      uint32_t* flags, dd_batched_plan* plan) {
   *plan = nullptr;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return DD_ERR_HIP;
@@ -232,12 +234,17 @@ dd_status plan_create(int32_t count, const int64_t* m, const int64_t* n, const i
   P->desc.resize(count);
   std::vector<int64_t> pexpA(count + 1, 0), pexpB(count + 1, 0), ppackA(count + 1, 0), ppackB(count + 1, 0);
   // workspace: all exponent words first (zeroed with one fill), then the packed planes
+  int64_t fw = 0;
   for (int32_t p = 0; p < count; ++p) {
     BatchDesc& d = P->desc[p];
     std::memset(&d, 0, sizeof(d));
     d.m = m[p]; d.n = n[p]; d.k = k[p];
     d.lda = lda[p]; d.ldb = ldb[p]; d.ldc = ldc[p];
+    d.off_flags = fw;
+    fw += cdiv(m[p] * n[p], 32);
   }
+  P->flags = flags;
+  P->flag_words = fw;
   const size_t off = batch_ws_bytes(count, m, n, k, kc, P->desc.data());
   int64_t eoff = 0;
   for (int32_t p = 0; p < count; ++p) {
@@ -329,7 +336,12 @@ dd_status plan_create(int32_t count, const int64_t* m, const int64_t* n, const i
 // in dd_gemm_batched_exec).
 dd_status plan_exec(dd_batched_plan P, const double* const* A_hi, const double* const* A_lo,
                     const double* const* B_hi, const double* const* B_lo, double* const* C_hi,
-                    double* const* C_lo, char* ws, uint32_t* counter, hipStream_t stream) {
+                    double* const* C_lo, char* ws, uint32_t* counter, uint32_t* flags, hipStream_t stream) {
+  if (flags && P->flag_words > 0) {
+    // every problem's bitmap starts cleared, also those with nothing to compute
+    const hipError_t e = ddk::launch_fill_u32(flags, P->flag_words, 0u, stream);
+    if (e != hipSuccess) return hip_st(e);
+  }
   if (P->ntiles == 0) return DD_OK;
   if (!A_hi) return -2;
   if (!A_lo) return -3;
@@ -345,7 +357,7 @@ dd_status plan_exec(dd_batched_plan P, const double* const* A_hi, const double* 
                                                ws, (uint64_t*)ws, P->nexps, stream);
   if (e != hipSuccess) return hip_st(e);
   return hip_st(ddk::launch_cascade_batched(P->d_desc, P->d_tiles, P->ntiles, C_hi, C_lo, ws, counter, P->grid,
-                                            P->dynamic != 0, stream));
+                                            P->dynamic != 0, flags, stream));
 }
 
 // Tables of the one-shot form with a caller workspace, kept per device, kc
@@ -374,7 +386,7 @@ dd_status dd_batched_plan_create(int32_t count, const int64_t* m, const int64_t*
   const dd_status st = check_plan_args(count, m, n, k, lda, ldb, ldc, opts, &kc);
   if (st != DD_OK) return st;
   if (!plan) return -9;
-  return plan_create(count, m, n, k, lda, ldb, ldc, kc, true, plan);
+  return plan_create(count, m, n, k, lda, ldb, ldc, kc, true, opts ? opts->flags_out : nullptr, plan);
 }
 
 dd_status dd_gemm_batched_exec(dd_batched_plan P, const double* const* A_hi, const double* const* A_lo,
@@ -382,7 +394,7 @@ dd_status dd_gemm_batched_exec(dd_batched_plan P, const double* const* A_hi, con
                                double* const* C_hi, double* const* C_lo, hipStream_t stream) {
   if (!P) return -1;
   if (!P->own_ws) return -1;
-  return plan_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, P->d_ws, P->d_counter, stream);
+  return plan_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, P->d_ws, P->d_counter, P->flags, stream);
 }
 
 size_t dd_gemm_batched_workspace_size(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
@@ -391,7 +403,7 @@ size_t dd_gemm_batched_workspace_size(int32_t count, const int64_t* m, const int
   int32_t kc = 256;
   if (opts) {
     if (opts->algo != DD_ALGO_CASCADE_F64 || opts->tile != 0 || opts->slices != 0 || opts->slice_bits != 0 ||
-        opts->scaling != 0 || opts->flags_out != nullptr || opts->use_tuned != 0)
+        opts->scaling != 0 || opts->use_tuned != 0)
       return 0;
     if (opts->kc != 0) {
       if (opts->kc < 4 || opts->kc > 4096 || opts->kc % 4 != 0) return 0;
@@ -501,11 +513,12 @@ dd_status dd_gemm_batched(int32_t count, const int64_t* m, const int64_t* n, con
   dd_status st = check_plan_args(count, m, n, k, lda, ldb, ldc, opts, &kc);
   if (st != DD_OK) return st < 0 && -st < 10 ? -pos[-st] : st;
   if (count == 0) return DD_OK;
+  uint32_t* const flags = opts ? opts->flags_out : nullptr;
   if (!workspace) {
     dd_batched_plan P = nullptr;
-    st = plan_create(count, m, n, k, lda, ldb, ldc, kc, true, &P);
+    st = plan_create(count, m, n, k, lda, ldb, ldc, kc, true, flags, &P);
     if (st != DD_OK) return st;
-    st = plan_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, P->d_ws, P->d_counter, stream);
+    st = plan_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, P->d_ws, P->d_counter, flags, stream);
     if (st < 0) st = -pos2[-st];
     const dd_status st2 = dd_batched_plan_destroy(P);  // waits for the work to finish
     return st != DD_OK ? st : st2;
@@ -533,14 +546,14 @@ dd_status dd_gemm_batched(int32_t count, const int64_t* m, const int64_t* n, con
         return DD_ERR_HIP;
       }
       if (cs != hipStreamCaptureStatusNone) return DD_ERR_WORKSPACE;
-      st = plan_create(count, m, n, k, lda, ldb, ldc, kc, false, &P);
+      st = plan_create(count, m, n, k, lda, ldb, ldc, kc, false, nullptr, &P);
       if (st != DD_OK) return st;
       g_tables.emplace(std::move(key), P);
     }
   }
   if (ws_bytes < 256 + std::max<size_t>(P->ws_bytes, 256)) return DD_ERR_WORKSPACE;
   char* w = (char*)workspace;
-  st = plan_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, w + 256, (uint32_t*)w, stream);
+  st = plan_exec(P, A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, w + 256, (uint32_t*)w, flags, stream);
   return st < 0 ? -pos2[-st] : st;
 }
 

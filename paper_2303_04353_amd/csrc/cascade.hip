@@ -587,11 +587,14 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
 // Persistent form for a batch of GEMMs: every workgroup takes tiles from the
 // list (in list order: the list is sorted by decreasing cost) until none is
 // left, either with a fixed stride or from an atomic counter.  Each tile
-// carries its shape (all tiles of one problem have the same).
+// carries its shape (all tiles of one problem have the same).  With kFlags,
+// problem p's cancellation bits go to its bitmap at flags + off_flags.
+template <bool kFlags>
 __global__ void __launch_bounds__(kWaves * 64)
 cascade_batched_kernel(const BatchDesc* __restrict__ desc, const BatchTile* __restrict__ tiles,
                        int64_t ntiles, double* const* __restrict__ Chi, double* const* __restrict__ Clo,
-                       const char* __restrict__ ws, unsigned long long* __restrict__ counter, int dynamic) {
+                       const char* __restrict__ ws, unsigned long long* __restrict__ counter, int dynamic,
+                       uint32_t* __restrict__ flags) {
   __shared__ __attribute__((aligned(16))) double lds[kLdsDoubles];
   __shared__ unsigned long long next;
   int64_t w = blockIdx.x;
@@ -609,15 +612,16 @@ cascade_batched_kernel(const BatchDesc* __restrict__ desc, const BatchTile* __re
     const double* Bp = (const double*)(ws + d.off_bpack);
     const uint64_t* am = (const uint64_t*)(ws + d.off_amax);
     const uint64_t* bm = (const uint64_t*)(ws + d.off_bmax);
+    uint32_t* fl = kFlags ? flags + d.off_flags : nullptr;
     if (t.shape == kTile32x64) {
-      cascade_tile<false, false, Shape32x64>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
-                                             Clo[t.p], d.ldc, nullptr);
+      cascade_tile<kFlags, false, Shape32x64>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
+                                              Clo[t.p], d.ldc, fl);
     } else if (t.shape == kTile64x32) {
-      cascade_tile<false, false, Shape64x32>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
-                                             Clo[t.p], d.ldc, nullptr);
+      cascade_tile<kFlags, false, Shape64x32>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
+                                              Clo[t.p], d.ldc, fl);
     } else {
-      cascade_tile<false, false, Shape64x64>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
-                                             Clo[t.p], d.ldc, nullptr);
+      cascade_tile<kFlags, false, Shape64x64>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
+                                              Clo[t.p], d.ldc, fl);
     }
     __syncthreads();  // the next tile reuses the staging buffers
     if (!dynamic) w += gridDim.x;
@@ -626,15 +630,21 @@ cascade_batched_kernel(const BatchDesc* __restrict__ desc, const BatchTile* __re
 
 hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles, int64_t ntiles,
                                   double* const* Chi, double* const* Clo, const char* ws,
-                                  uint32_t* counter, int grid, bool dynamic, hipStream_t s) {
+                                  uint32_t* counter, int grid, bool dynamic, uint32_t* flags, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (grid < 1) return hipErrorInvalidValue;
   if (dynamic) {
     hipError_t e = launch_fill_u64((uint64_t*)counter, 1, 0, s);
     if (e != hipSuccess) return e;
   }
-  cascade_batched_kernel<<<grid, kWaves * 64, 0, s>>>(desc, tiles, ntiles, Chi, Clo, ws,
-                                                      (unsigned long long*)counter, dynamic ? 1 : 0);
+  if (flags) {
+    cascade_batched_kernel<true><<<grid, kWaves * 64, 0, s>>>(desc, tiles, ntiles, Chi, Clo, ws,
+                                                              (unsigned long long*)counter, dynamic ? 1 : 0, flags);
+  } else {
+    cascade_batched_kernel<false><<<grid, kWaves * 64, 0, s>>>(desc, tiles, ntiles, Chi, Clo, ws,
+                                                               (unsigned long long*)counter, dynamic ? 1 : 0,
+                                                               nullptr);
+  }
   return hipGetLastError();
 }
 

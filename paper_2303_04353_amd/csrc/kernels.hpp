@@ -43,10 +43,12 @@ hipError_t launch_batched_phase_one(const BatchDesc* desc, int count, const int6
 
 // The product kernel over a list of tiles of a batch, `grid` persistent
 // workgroups; `dynamic` takes tiles from an atomic counter (zeroed here)
-// instead of a fixed stride.
+// instead of a fixed stride.  `flags` (may be null): the cancellation
+// bitmaps of all problems, problem p's from word desc[p].off_flags, zeroed
+// by the caller.
 hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles, int64_t ntiles,
                                   double* const* Chi, double* const* Clo, const char* ws,
-                                  uint32_t* counter, int grid, bool dynamic, hipStream_t s);
+                                  uint32_t* counter, int grid, bool dynamic, uint32_t* flags, hipStream_t s);
 
 // The fused product kernel: ten FP64 MFMA products per rank-kc block, bins
 // combined in FP64x2, Sigma/T applied, C := C + result.  `flags` (may be

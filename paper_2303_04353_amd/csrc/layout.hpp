@@ -66,6 +66,7 @@ struct BatchDesc {
   int64_t m, n, k, K4, mpad, npad, tiles_m, tiles_n;
   int64_t lda, ldb, ldc;
   int64_t off_amax, off_bmax, off_apack, off_bpack;
+  int64_t off_flags;   // first word of this problem's cancellation bitmap
   int32_t kcq, c0, c1, c2;
 };
 

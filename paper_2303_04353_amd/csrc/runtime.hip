@@ -368,7 +368,15 @@ int32_t tile_shape(const Problem& p, const Opts& o) {
 dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes, bool internal_ws,
               hipStream_t s, bool fixed = false) {
   const int32_t algo = o.algo, kc = o.kc;
-  if (p.m == 0 || p.n == 0 || p.k == 0) return DD_OK;   // quick return: no device needed
+  if (p.m == 0 || p.n == 0) return DD_OK;   // quick return: no device needed
+  if (p.k == 0) {
+    // C stays as it is; a cancellation bitmap is still cleared (no entry is at risk)
+    if (!o.flags) return DD_OK;
+    int dev = 0;
+    const dd_status st = check_device(&dev);
+    if (st != DD_OK) return st;
+    return hip_status(ddk::launch_fill_u32(o.flags, (p.m * p.n + 31) / 32, 0u, s));
+  }
   int dev = 0;
   dd_status st = check_device(&dev);
   if (st != DD_OK) return st;

@@ -8,7 +8,9 @@
   between, reproduces the eager result every time;
 * the tuner picks a schedule and records it in the cache file;
 * the one-shot call with a caller workspace: bit-identical to single calls,
-  a workspace too small refused, graph capture once its shapes are known.
+  a workspace too small refused, graph capture once its shapes are known;
+* cancellation flags of a batch: every problem's bitmap equal to its single
+  call's.
 """
 import os
 
@@ -26,10 +28,13 @@ pytestmark = pytest.mark.gpu
 class Batch:
     """Device copies of a list of problems plus the pointer arrays."""
 
-    def __init__(self, shapes, cfg=30):
+    def __init__(self, shapes, cfg=30, prepare=None):
         import torch
         self.shapes = shapes
         self.P = [make_problem(m, n, k, cfg=cfg, salt=i) for i, (m, n, k) in enumerate(shapes)]
+        if prepare:
+            for i, p in enumerate(self.P):
+                prepare(i, p)
         self.A = [(up(p["A"][0]), up(p["A"][1])) for p in self.P]
         self.B = [(up(p["B"][0]), up(p["B"][1])) for p in self.P]
         self.C0 = [(up(p["C"][0]), up(p["C"][1])) for p in self.P]
@@ -206,6 +211,71 @@ def test_one_shot_with_workspace_under_graph_capture():
     finally:
         torch.cuda.synchronize()
         hip.hipStreamDestroy(raw)
+
+
+def _plant_cancellation(i, P):
+    """In every other problem, rows 1 and m-1 of A against columns 0 and n-1
+    of B cancel in the leading digits of every block (as in the single-call
+    flags test)."""
+    A, B = P["A"], P["B"]
+    m, k = A[0].shape
+    n = B[0].shape[1]
+    if i % 2 or m < 2 or n < 1 or k < 2:
+        return
+    for r in (1, m - 1):
+        A[0][r, :] = 0.75
+        A[0][r, 1::2] = 0.75 + 2.0 ** -30
+        A[1][r, :] = 0.0
+    for c in (0, n - 1):
+        B[0][:, c] = 0.5
+        B[0][1::2, c] = -0.5
+        B[1][:, c] = 0.0
+
+
+def test_batched_cancellation_flags_equal_single_calls():
+    import torch
+    log("batched cancellation flags")
+    b = Batch(MIXED, cfg=37, prepare=_plant_cancellation)
+    words = [-(-m * n // 32) for m, n, _ in b.shapes]
+    off = np.concatenate([[0], np.cumsum(words)]).astype(np.int64)
+    # single calls: each problem's bitmap and result
+    want, want_bits = [], []
+    for i, (m, n, k) in enumerate(b.shapes):
+        ch, cl = b.C0[i][0].clone(), b.C0[i][1].clone()
+        fw = torch.full((max(1, words[i]),), -1, dtype=torch.int32, device="cuda")
+        dg.check(dg.dd_gemm_ex(0, 0, m, n, k, b.A[i][0], b.A[i][1], b.lda[i], b.B[i][0], b.B[i][1], b.ldb[i],
+                               ch, cl, b.ldc[i], opts={"flags_out": fw if words[i] else None}), "dd_gemm_ex")
+        torch.cuda.synchronize()
+        want.append((ch.cpu().numpy(), cl.cpu().numpy()))
+        want_bits.append(fw.cpu().numpy()[:words[i]])
+    assert sum(int(np.unpackbits(w.view(np.uint8)).sum()) for w in want_bits) >= 8
+    # a plan with flags, then the one-shot call with a caller workspace and flags
+    flags = torch.full((int(off[-1]),), -1, dtype=torch.int32, device="cuda")   # the calls zero it
+    st, plan = dg.dd_batched_plan_create(len(b.shapes), b.m, b.n, b.k, b.lda, b.ldb, b.ldc, {"flags_out": flags})
+    dg.check(st, "dd_batched_plan_create")
+    try:
+        for policy in (0, 2):
+            b.reset()
+            flags.fill_(-1)
+            dg.check(dg.dd_batched_plan_schedule(plan, 1, 1, policy))
+            b.exec(plan)
+            torch.cuda.synchronize()
+            got = flags.cpu().numpy()
+            for i, (g, w) in enumerate(zip(b.results(), want)):
+                assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1]), (policy, i)
+                assert np.array_equal(got[off[i]:off[i + 1]], want_bits[i]), (policy, i)
+    finally:
+        dg.dd_batched_plan_destroy(plan)
+    need = dg.dd_gemm_batched_workspace_size(len(b.shapes), b.m, b.n, b.k, {"flags_out": flags})
+    ws = torch.empty(need // 8 + 1, dtype=torch.float64, device="cuda")
+    b.reset()
+    flags.fill_(-1)
+    dg.check(_one_shot(b, ws, need, opts={"flags_out": flags}), "dd_gemm_batched flags")
+    torch.cuda.synchronize()
+    got = flags.cpu().numpy()
+    for i, (g, w) in enumerate(zip(b.results(), want)):
+        assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1]), i
+        assert np.array_equal(got[off[i]:off[i + 1]], want_bits[i]), i
 
 
 def test_uneven_batch_512_against_oracle_and_singles():
