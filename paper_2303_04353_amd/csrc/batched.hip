@@ -253,8 +253,8 @@ dd_status plan_create(int32_t count, const int64_t* m, const int64_t* n, const i
     if (active) eoff += d.mpad + d.npad;
     pexpA[p + 1] = pexpA[p] + (active ? cdiv(d.m, 256) * cdiv(d.k, 256) : 0);
     pexpB[p + 1] = pexpB[p] + (active ? cdiv(d.n, 4) * cdiv(d.k, 4096) : 0);
-    ppackA[p + 1] = ppackA[p] + (active ? cdiv((d.mpad / 16) * d.K4, 4) : 0);
-    ppackB[p + 1] = ppackB[p] + (active ? cdiv((d.npad / 16) * d.K4, 4) : 0);
+    ppackA[p + 1] = ppackA[p] + (active ? cdiv((d.mpad / 16) * d.K4, 4 * ddk::kPackFragsPerWave) : 0);
+    ppackB[p + 1] = ppackB[p] + (active ? cdiv((d.npad / 16) * d.K4, 4 * ddk::kPackFragsPerWave) : 0);
     // the smaller tile (32 x 64 or 64 x 32) with the least padded area, if
     // that is less than the 64 x 64 tiles'
     int32_t small = 0;

@@ -70,6 +70,10 @@ struct BatchDesc {
   int32_t kcq, c0, c1, c2;
 };
 
+// Fragments of packed planes one wave of the packing kernels fills (a
+// batched plan's units are 4 waves' worth).
+constexpr int kPackFragsPerWave = 4;
+
 // Output tile shapes of the product kernel (rows x columns per workgroup);
 // every shape computes every entry with the same arithmetic.
 constexpr int kTile64x64 = 1, kTile32x64 = 2, kTile64x32 = 3;

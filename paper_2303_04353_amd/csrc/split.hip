@@ -73,6 +73,7 @@ max_abs_bits_red_contig(const double* __restrict__ X, const double* __restrict__
     int64_t r0 = c * chunk;
     int64_t r1 = r0 + chunk < red ? r0 + chunk : red;
     uint64_t mx = 0;
+#pragma unroll 4
     for (int64_t r = r0 + lane; r < r1; r += 64) {
       double v = col_lo ? col[r] + col_lo[r] : col[r];
       if (rscale) v = __builtin_ldexp(v, rsign * rscale[r]);
@@ -103,80 +104,129 @@ __device__ __forceinline__ SplitParams make_params(int c0, int c1, int c2) {
   return sp;
 }
 
-// One 64-lane fragment of the packed A planes: op(A)(i, p) = A[i*si + p*sp_].
-// The exponent of entry (i, p) is amax[i] (pstride = 0), or with per-panel
-// Sigma amax[i + (p / plen) * pstride]; likewise for B.  With gexp, the
-// entry is first multiplied by 2^gexp[p] (A) or 2^-gexp[p] (B): the
-// diagonal balancing of the inner dimension.
-__device__ __forceinline__ void pack_a_frag(const double* __restrict__ Ahi, const double* __restrict__ Alo,
-                                            int64_t si, int64_t sp_, int64_t m, int64_t k, int64_t K4,
-                                            int64_t frag, int lane, const uint64_t* __restrict__ amax,
-                                            int c0, int c1, int c2, double* __restrict__ Apack,
-                                            int64_t plen = 1, int64_t pstride = 0,
-                                            const int32_t* __restrict__ gexp = nullptr) {
-  int64_t rb = frag / K4, kq = frag - rb * K4;
-  // position lane = s*16 + kk*4 + ii holds row rb*16 + s*4 + ii, inner index kq*4 + kk
-  int64_t i = rb * 16 + (lane >> 4) * 4 + (lane & 3), p = kq * 4 + ((lane >> 2) & 3);
-  double w[4] = {0.0, 0.0, 0.0, 0.0};
-  if (i < m && p < k) {
-    SplitParams spar = make_params(c0, c1, c2);
-    int64_t idx = i * si + p * sp_;
-    double xh, xl;
-    double h = Ahi[idx], l = Alo[idx];
-    if (gexp) { h = __builtin_ldexp(h, gexp[p]); l = __builtin_ldexp(l, gexp[p]); }
-    split_entry(h, l, exp_of_bits(amax[i + (p / plen) * pstride]), spar, w, xh, xl);
-  }
-  double* dst = Apack + rb * a_block_stride(K4) + kq * (kFragA * kLanes) + lane;
+// Packed A planes, F consecutive 64-lane fragments per wave: op(A)(i, p) =
+// A[i*si + p*sp_].  The exponent of entry (i, p) is amax[i] (pstride = 0),
+// or with per-panel Sigma amax[i + (p / plen) * pstride]; likewise for B.
+// With gexp, the entry is first multiplied by 2^gexp[p] (A) or 2^-gexp[p]
+// (B): the diagonal balancing of the inner dimension.  Every load of the F
+// fragments is issued before the first split, so a lane has 2F loads in
+// flight (one fragment's two would leave HBM half idle).  Fragments at or
+// past nfrag are skipped.
+template <int F>
+__device__ __forceinline__ void pack_a_frags(const double* __restrict__ Ahi, const double* __restrict__ Alo,
+                                             int64_t si, int64_t sp_, int64_t m, int64_t k, int64_t K4,
+                                             int64_t frag0, int64_t nfrag, int lane,
+                                             const uint64_t* __restrict__ amax, int c0, int c1, int c2,
+                                             double* __restrict__ Apack, int64_t plen = 1, int64_t pstride = 0,
+                                             const int32_t* __restrict__ gexp = nullptr) {
+  double h[F], l[F];
+  uint64_t mb[F];
+  int g[F];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) dst[t * kLanes] = w[t];
+  for (int f = 0; f < F; ++f) {
+    const int64_t frag = frag0 + f;
+    const int64_t rb = frag / K4, kq = frag - rb * K4;
+    // position lane = s*16 + kk*4 + ii holds row rb*16 + s*4 + ii, inner index kq*4 + kk
+    const int64_t i = rb * 16 + (lane >> 4) * 4 + (lane & 3), p = kq * 4 + ((lane >> 2) & 3);
+    h[f] = l[f] = 0.0;
+    mb[f] = 0;
+    g[f] = 0;
+    if (frag < nfrag && i < m && p < k) {
+      const int64_t idx = i * si + p * sp_;
+      h[f] = Ahi[idx];
+      l[f] = Alo[idx];
+      mb[f] = amax[i + (p / plen) * pstride];
+      if (gexp) g[f] = gexp[p];
+    }
+  }
+  const SplitParams spar = make_params(c0, c1, c2);
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    const int64_t frag = frag0 + f;
+    if (frag >= nfrag) break;
+    const int64_t rb = frag / K4, kq = frag - rb * K4;
+    const int64_t i = rb * 16 + (lane >> 4) * 4 + (lane & 3), p = kq * 4 + ((lane >> 2) & 3);
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < m && p < k) {
+      double xh, xl;
+      split_entry(__builtin_ldexp(h[f], g[f]), __builtin_ldexp(l[f], g[f]), exp_of_bits(mb[f]), spar, w, xh, xl);
+    }
+    double* dst = Apack + rb * a_block_stride(K4) + kq * (kFragA * kLanes) + lane;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dst[t * kLanes] = w[t];
+  }
 }
 
-// One 64-lane fragment of the packed B planes: op(B)(p, j) = B[p*sp_ + j*sj].
-__device__ __forceinline__ void pack_b_frag(const double* __restrict__ Bhi, const double* __restrict__ Blo,
-                                            int64_t sp_, int64_t sj, int64_t k, int64_t n, int64_t K4,
-                                            int64_t frag, int lane, const uint64_t* __restrict__ bmax,
-                                            int c0, int c1, int c2, double* __restrict__ Bpack,
-                                            int64_t plen = 1, int64_t pstride = 0,
-                                            const int32_t* __restrict__ gexp = nullptr) {
-  int64_t cb = frag / K4, kq = frag - cb * K4;
-  int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
-  double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (j < n && p < k) {
-    SplitParams spar = make_params(c0, c1, c2);
-    int64_t idx = p * sp_ + j * sj;
-    double yh, yl;
-    double h = Bhi[idx], l = Blo[idx];
-    if (gexp) { h = __builtin_ldexp(h, -gexp[p]); l = __builtin_ldexp(l, -gexp[p]); }
-    split_entry(h, l, exp_of_bits(bmax[j + (p / plen) * pstride]), spar, w, yh, yl);
-    w[4] = yh + yl;       // B6: the scaled entry itself, rounded once
-  }
-  double* dst = Bpack + cb * b_block_stride(K4) + kq * (kFragB * kLanes) + lane;
+// Packed B planes, F consecutive fragments per wave: op(B)(p, j) = B[p*sp_ + j*sj].
+template <int F>
+__device__ __forceinline__ void pack_b_frags(const double* __restrict__ Bhi, const double* __restrict__ Blo,
+                                             int64_t sp_, int64_t sj, int64_t k, int64_t n, int64_t K4,
+                                             int64_t frag0, int64_t nfrag, int lane,
+                                             const uint64_t* __restrict__ bmax, int c0, int c1, int c2,
+                                             double* __restrict__ Bpack, int64_t plen = 1, int64_t pstride = 0,
+                                             const int32_t* __restrict__ gexp = nullptr) {
+  double h[F], l[F];
+  uint64_t mb[F];
+  int g[F];
 #pragma unroll
-  for (int t = 0; t < 5; ++t) dst[t * kLanes] = w[t];
+  for (int f = 0; f < F; ++f) {
+    const int64_t frag = frag0 + f;
+    const int64_t cb = frag / K4, kq = frag - cb * K4;
+    const int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
+    h[f] = l[f] = 0.0;
+    mb[f] = 0;
+    g[f] = 0;
+    if (frag < nfrag && j < n && p < k) {
+      const int64_t idx = p * sp_ + j * sj;
+      h[f] = Bhi[idx];
+      l[f] = Blo[idx];
+      mb[f] = bmax[j + (p / plen) * pstride];
+      if (gexp) g[f] = gexp[p];   // negated where it is used: no wait here
+    }
+  }
+  const SplitParams spar = make_params(c0, c1, c2);
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    const int64_t frag = frag0 + f;
+    if (frag >= nfrag) break;
+    const int64_t cb = frag / K4, kq = frag - cb * K4;
+    const int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
+    double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (j < n && p < k) {
+      double yh, yl;
+      split_entry(__builtin_ldexp(h[f], -g[f]), __builtin_ldexp(l[f], -g[f]), exp_of_bits(mb[f]), spar, w, yh, yl);
+      w[4] = yh + yl;       // B6: the scaled entry itself, rounded once
+    }
+    double* dst = Bpack + cb * b_block_stride(K4) + kq * (kFragB * kLanes) + lane;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) dst[t * kLanes] = w[t];
+  }
 }
 
-// One wave per fragment (rb, kq).
+constexpr int kPF = kPackFragsPerWave;
+
+// kPF consecutive fragments (rb, kq) per wave.
 __global__ void __launch_bounds__(256)
 pack_a(const double* __restrict__ Ahi, const double* __restrict__ Alo, int64_t si, int64_t sp_,
        int64_t m, int64_t k, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ amax,
        int c0, int c1, int c2, double* __restrict__ Apack, int64_t plen, int64_t pstride,
        const int32_t* __restrict__ gexp) {
-  int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (frag >= nfrag) return;
-  pack_a_frag(Ahi, Alo, si, sp_, m, k, K4, frag, threadIdx.x & 63, amax, c0, c1, c2, Apack, plen, pstride,
-              gexp);
+  const int64_t frag0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kPF;
+  if (frag0 >= nfrag) return;
+  pack_a_frags<kPF>(Ahi, Alo, si, sp_, m, k, K4, frag0, nfrag, threadIdx.x & 63, amax, c0, c1, c2, Apack, plen,
+                    pstride, gexp);
 }
 
-// One wave per fragment (cb, kq).
+// kPF consecutive fragments (cb, kq) per wave.
 __global__ void __launch_bounds__(256)
 pack_b(const double* __restrict__ Bhi, const double* __restrict__ Blo, int64_t sp_, int64_t sj,
        int64_t k, int64_t n, int64_t K4, int64_t nfrag, const uint64_t* __restrict__ bmax,
        int c0, int c1, int c2, double* __restrict__ Bpack, int64_t plen, int64_t pstride,
        const int32_t* __restrict__ gexp) {
-  int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (frag >= nfrag) return;
-  pack_b_frag(Bhi, Blo, sp_, sj, k, n, K4, frag, threadIdx.x & 63, bmax, c0, c1, c2, Bpack, plen, pstride,
-              gexp);
+  const int64_t frag0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kPF;
+  if (frag0 >= nfrag) return;
+  pack_b_frags<kPF>(Bhi, Blo, sp_, sj, k, n, K4, frag0, nfrag, threadIdx.x & 63, bmax, c0, c1, c2, Bpack, plen,
+                    pstride, gexp);
 }
 
 // ------------------------------------------------------------ batched phase one
@@ -254,18 +304,18 @@ batched_pack(const BatchDesc* __restrict__ desc, int count, const int64_t* __res
     if (u < totA) {
       const int p = find_problem(prefA, count, u);
       const BatchDesc d = desc[p];
-      const int64_t frag = (u - prefA[p]) * 4 + (threadIdx.x >> 6);
-      if (frag >= (d.mpad / 16) * d.K4) continue;
-      pack_a_frag(Ahi[p], Alo[p], 1, d.lda, d.m, d.k, d.K4, frag, lane,
-                  (const uint64_t*)(ws + d.off_amax), d.c0, d.c1, d.c2, (double*)(ws + d.off_apack));
+      const int64_t frag0 = ((u - prefA[p]) * 4 + (threadIdx.x >> 6)) * kPF, nfrag = (d.mpad / 16) * d.K4;
+      if (frag0 >= nfrag) continue;
+      pack_a_frags<kPF>(Ahi[p], Alo[p], 1, d.lda, d.m, d.k, d.K4, frag0, nfrag, lane,
+                        (const uint64_t*)(ws + d.off_amax), d.c0, d.c1, d.c2, (double*)(ws + d.off_apack));
     } else {
       const int64_t v = u - totA;
       const int p = find_problem(prefB, count, v);
       const BatchDesc d = desc[p];
-      const int64_t frag = (v - prefB[p]) * 4 + (threadIdx.x >> 6);
-      if (frag >= (d.npad / 16) * d.K4) continue;
-      pack_b_frag(Bhi[p], Blo[p], 1, d.ldb, d.k, d.n, d.K4, frag, lane,
-                  (const uint64_t*)(ws + d.off_bmax), d.c0, d.c1, d.c2, (double*)(ws + d.off_bpack));
+      const int64_t frag0 = ((v - prefB[p]) * 4 + (threadIdx.x >> 6)) * kPF, nfrag = (d.npad / 16) * d.K4;
+      if (frag0 >= nfrag) continue;
+      pack_b_frags<kPF>(Bhi[p], Blo[p], 1, d.ldb, d.k, d.n, d.K4, frag0, nfrag, lane,
+                        (const uint64_t*)(ws + d.off_bmax), d.c0, d.c1, d.c2, (double*)(ws + d.off_bpack));
     }
   }
 }
@@ -370,7 +420,7 @@ hipError_t launch_pack_a(const double* Ahi, const double* Alo, int64_t si, int64
                          const int32_t* gexp) {
   int64_t nfrag = (L.mpad / 16) * L.K4;
   const int64_t plen = 4 * (int64_t)L.kcq, pstride = L.npanel > 1 ? L.mpad : 0;
-  pack_a<<<blocks_for(nfrag, 4), 256, 0, s>>>(Ahi, Alo, si, sp, L.m, L.k, L.K4, nfrag, amax,
+  pack_a<<<blocks_for(nfrag, 4 * kPF), 256, 0, s>>>(Ahi, Alo, si, sp, L.m, L.k, L.K4, nfrag, amax,
                                               L.c[0], L.c[1], L.c[2], Apack, plen, pstride, gexp);
   return hipGetLastError();
 }
@@ -380,7 +430,7 @@ hipError_t launch_pack_b(const double* Bhi, const double* Blo, int64_t sp, int64
                          const int32_t* gexp) {
   int64_t nfrag = (L.npad / 16) * L.K4;
   const int64_t plen = 4 * (int64_t)L.kcq, pstride = L.npanel > 1 ? L.npad : 0;
-  pack_b<<<blocks_for(nfrag, 4), 256, 0, s>>>(Bhi, Blo, sp, sj, L.k, L.n, L.K4, nfrag, bmax,
+  pack_b<<<blocks_for(nfrag, 4 * kPF), 256, 0, s>>>(Bhi, Blo, sp, sj, L.k, L.n, L.K4, nfrag, bmax,
                                               L.c[0], L.c[1], L.c[2], Bpack, plen, pstride, gexp);
   return hipGetLastError();
 }
