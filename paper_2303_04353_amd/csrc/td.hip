@@ -330,8 +330,12 @@ td_cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ B
     for (int c = 0; c < 3; ++c) stg[c] = *(const d2*)(psrc[c] + st * kFrag3);
   };
   auto store_stage = [&](int buf) {
+    // every piece starts on a 16-byte boundary (pdst is even): say so, or
+    // the 16-byte writes get split into two 8-byte ones, which conflict in
+    // the LDS banks
 #pragma unroll
-    for (int c = 0; c < 3; ++c) *(d2*)(lds + buf * kStage3 + pdst[c]) = stg[c];
+    for (int c = 0; c < 3; ++c)
+      *(d2*)__builtin_assume_aligned(lds + buf * kStage3 + pdst[c], 16) = stg[c];
   };
   const int aoff = wm * kFrag3 + (lane >> 4) * 4 + (lane & 3);
   const int boff = kAStage3 + wn * kCG3 * kFrag3 + lane;
