@@ -292,6 +292,22 @@ def test_flags_rejected_for_other_algorithms():
         assert dg.dd_gemm_ex(0, 0, *base, opts={"algo": algo, "flags_out": words}) == -17
 
 
+def test_flags_cleared_when_k_is_zero():
+    import torch
+    m, n = 70, 33
+    P = make_problem(m, n, 1, cfg=18)
+    Ch, Cl = up(P["C"][0]), up(P["C"][1])
+    words = torch.full(((m * n + 31) // 32,), -1, dtype=torch.int32, device="cuda")
+    A = torch.zeros(8, dtype=torch.float64, device="cuda")   # m x 0 and 0 x n: never read
+    B = torch.zeros(8, dtype=torch.float64, device="cuda")
+    st = dg.dd_gemm_ex(0, 0, m, n, 0, A, A, m, B, B, 1, Ch, Cl, m, opts={"flags_out": words})
+    dg.check(st, "dd_gemm_ex k=0 flags")
+    torch.cuda.synchronize()
+    # nothing is at risk with no products; C stays as it was
+    assert int(words.abs().sum()) == 0
+    assert np.array_equal(down(Ch), P["C"][0]) and np.array_equal(down(Cl), P["C"][1])
+
+
 # --- Sigma and T per rank-kc panel ------------------------------------------------
 
 PANEL = dg.DD_SCALING_PANEL
