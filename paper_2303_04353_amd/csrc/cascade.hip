@@ -218,74 +218,6 @@ __device__ __forceinline__ void combine(Bins<CB>& B, double (&acc_h)[kSub][CB], 
 
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
-// The epilogue of a tile: Sigma and T (unless applied per block, kPanel),
-// then C + result in FP64x2, and the cancellation bits (kFlags).  Every
-// load comes before the first store: as far as the compiler knows a store
-// to C may alias a later load of C, so loads after stores would wait for
-// each other, one round trip to memory per entry.  C is addressed as
-// global memory (which it is): the batched kernel reads its pointers from
-// an array, and flat accesses would also count on the scalar-load counter
-// and so wait for unrelated scalar loads.
-typedef __attribute__((address_space(1))) double global_double;
-
-template <bool kFlags, bool kPanel, int CB>
-__device__ __forceinline__ void tile_epilogue(const double (&acc_h)[kSub][CB], const double (&acc_l)[kSub][CB],
-                                              uint32_t flg, int64_t rb0, int64_t cb0, int64_t m, int64_t n,
-                                              const uint64_t* __restrict__ amax,
-                                              const uint64_t* __restrict__ bmax, global_double* __restrict__ Chi,
-                                              global_double* __restrict__ Clo, int64_t ldc,
-                                              uint32_t* __restrict__ flags) {
-  const int lane = threadIdx.x & 63;
-  // the maxima's bits and C first; the exponents are formed after the loads
-  uint64_t mb_r[kSub], mb_c[CB];
-  double c_h[kSub][CB], c_l[kSub][CB];
-#pragma unroll
-  for (int g = 0; g < CB; ++g) {
-    const int64_t col = (cb0 + g) * 16 + (lane & 15);
-    mb_c[g] = (!kPanel && col < n) ? bmax[col] : 0;
-  }
-#pragma unroll
-  for (int i = 0; i < kSub; ++i) {
-    const int64_t row = rb0 * 16 + i * 4 + (lane >> 4);
-    mb_r[i] = (!kPanel && row < m) ? amax[row] : 0;
-#pragma unroll
-    for (int g = 0; g < CB; ++g) {
-      const int64_t col = (cb0 + g) * 16 + (lane & 15);
-      c_h[i][g] = c_l[i][g] = 0.0;
-      if (row < m && col < n) {
-        c_h[i][g] = Chi[row + col * ldc];
-        c_l[i][g] = Clo[row + col * ldc];
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < kSub; ++i) {
-    const int64_t row = rb0 * 16 + i * 4 + (lane >> 4);
-    if (row >= m) continue;
-#pragma unroll
-    for (int g = 0; g < CB; ++g) {
-      const int64_t col = (cb0 + g) * 16 + (lane & 15);
-      if (col >= n) continue;
-      // 0 with per-panel scaling (applied per block)
-      const int sh = kPanel ? 0 : exp_of_bits(mb_r[i]) + exp_of_bits(mb_c[g]);
-      const double h = __builtin_ldexp(acc_h[i][g], sh);
-      const double l = __builtin_ldexp(acc_l[i][g], sh);
-      const int64_t idx = row + col * ldc;
-      double rh, rl;
-      dd_add(c_h[i][g], c_l[i][g], h, l, rh, rl);
-      Chi[idx] = rh;
-      Clo[idx] = rl;
-      if constexpr (kFlags) {
-        if (flg & (1u << (i * CB + g))) {
-          const int64_t bit = row + col * m;
-          atomicOr(&flags[bit >> 5], 1u << (bit & 31));
-        }
-      }
-    }
-  }
-}
-
-
 }  // namespace
 
 // One TM x TN output tile (tile row tm, tile column tn) of one GEMM,
@@ -421,8 +353,32 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   }
   if (inblk != 0) block_done();
 
-  tile_epilogue<kFlags, kPanel, CB>(acc_h, acc_l, flg, rb0, cb0, m, n, amax, bmax, (global_double*)Chi,
-                                    (global_double*)Clo, ldc, flags);
+  // Epilogue: Sigma and T (unless applied per block), then C + result.
+#pragma unroll
+  for (int i = 0; i < kSub; ++i) {
+    const int64_t row = rb0 * 16 + i * 4 + (lane >> 4);
+    if (row >= m) continue;
+    const int er = kPanel ? 0 : exp_of_bits(amax[row]);
+#pragma unroll
+    for (int g = 0; g < CB; ++g) {
+      const int64_t col = (cb0 + g) * 16 + (lane & 15);
+      if (col >= n) continue;
+      const int sh = kPanel ? 0 : er + exp_of_bits(bmax[col]);
+      const double h = __builtin_ldexp(acc_h[i][g], sh);
+      const double l = __builtin_ldexp(acc_l[i][g], sh);
+      const int64_t idx = row + col * ldc;
+      double rh, rl;
+      dd_add(Chi[idx], Clo[idx], h, l, rh, rl);
+      Chi[idx] = rh;
+      Clo[idx] = rl;
+      if constexpr (kFlags) {
+        if (flg & (1u << (i * CB + g))) {
+          const int64_t bit = row + col * m;
+          atomicOr(&flags[bit >> 5], 1u << (bit & 31));
+        }
+      }
+    }
+  }
 }
 
 // Split on load (the paper cascades while it packs, Sec. 4.3): the same
@@ -552,8 +508,32 @@ __device__ __forceinline__ void cascade_tile_onload(double* __restrict__ lds, co
     if (++inblk == kcq) { inblk = 0; block_done(); }
   }
   if (inblk != 0) block_done();
-  tile_epilogue<kFlags, false, CB>(acc_h, acc_l, flg, rb0, cb0, m, n, amax, bmax, (global_double*)Chi,
-                                   (global_double*)Clo, ldc, flags);
+
+#pragma unroll
+  for (int i = 0; i < kSub; ++i) {
+    const int64_t r = rb0 * 16 + i * 4 + (lane >> 4);
+    if (r >= m) continue;
+    const int er = exp_of_bits(amax[r]);
+#pragma unroll
+    for (int g = 0; g < CB; ++g) {
+      const int64_t c = (cb0 + g) * 16 + (lane & 15);
+      if (c >= n) continue;
+      const int sh = er + exp_of_bits(bmax[c]);
+      const double h = __builtin_ldexp(acc_h[i][g], sh);
+      const double l = __builtin_ldexp(acc_l[i][g], sh);
+      const int64_t idx = r + c * ldc;
+      double rh, rl;
+      dd_add(Chi[idx], Clo[idx], h, l, rh, rl);
+      Chi[idx] = rh;
+      Clo[idx] = rl;
+      if constexpr (kFlags) {
+        if (flg & (1u << (i * CB + g))) {
+          const int64_t bit = r + c * m;
+          atomicOr(&flags[bit >> 5], 1u << (bit & 31));
+        }
+      }
+    }
+  }
 }
 
 template <bool kFlags>
