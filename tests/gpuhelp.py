@@ -51,7 +51,7 @@ def dd_diff(G, O):
     return np.abs((G[0] - O[0]) + (G[1] - O[1]))
 
 
-def north_star_bound(A, B, k):
+def fp64x2_tolerance(A, B, k):
     """64 k 2^-104 (|A||B|)_ij with |A||B| from the high words in FP64."""
     AB = np.abs(np.asarray(A[0])) @ np.abs(np.asarray(B[0]))
     return 64.0 * max(k, 1) * 2.0 ** -104 * AB

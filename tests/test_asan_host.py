@@ -8,7 +8,7 @@
   invalid arguments must give the documented statuses, and valid calls must
   fail cleanly without a GPU.
 
-Skipped on a machine with a GPU: the driver's valid calls use dummy
+Skipped on a machine with a GPU: abi_check.c's valid calls use dummy
 pointers and would reach the device there.
 """
 import glob

@@ -16,7 +16,7 @@ from oracle.illcond import ill_conditioned
 from oracle.ref import exact_entries
 from paper_2303_04353_amd import ddgemm as dg
 from paper_2303_04353_amd.inputs import make_problem
-from tests.gpuhelp import log, north_star_bound, run_gemm
+from tests.gpuhelp import log, fp64x2_tolerance, run_gemm
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def _rel_errors(P, R, n):
 def test_errors_against_the_exact_product(name, n):
     log(f"accuracy workload {name} n={n}")
     P = _workload(name, n)
-    tol = north_star_bound(P["A"], P["B"], n)
+    tol = fp64x2_tolerance(P["A"], P["B"], n)
     rel = {}
     for algo, kw in ALGOS.items():
         R = run_gemm(P["A"], P["B"], P["C"], **kw)

@@ -22,7 +22,7 @@ from oracle import cascade as cz
 from oracle.ref import dd_gemm_ref, dd_gemm_ref_entries
 from paper_2303_04353_amd import ddgemm as dg
 from paper_2303_04353_amd.inputs import make_problem, sample_entries
-from tests.gpuhelp import (cascade_order_bound, dd_diff, down, log, north_star_bound, panel_order_bound,
+from tests.gpuhelp import (cascade_order_bound, dd_diff, down, log, fp64x2_tolerance, panel_order_bound,
                            run_gemm, up)
 
 pytestmark = pytest.mark.gpu
@@ -81,7 +81,7 @@ def test_cascade_matches_oracles(m, n, k, variant, kc):
     O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc)
     assert np.all(dd_diff(G, O) <= cascade_order_bound(P["A"], P["B"], O, k, kc))
     R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
-    assert np.all(dd_diff(G, R) <= north_star_bound(P["A"], P["B"], k))
+    assert np.all(dd_diff(G, R) <= fp64x2_tolerance(P["A"], P["B"], k))
 
 
 def test_plain_entry_point_equals_ex_default():
@@ -156,7 +156,7 @@ def test_non_finite_rows_become_nan_only_there():
     assert np.all(np.isfinite(G[0][~bad]))
     R = dd_gemm_ref((A[0][~bad], A[1][~bad]), P["B"], (P["C"][0][~bad], P["C"][1][~bad]))[:2]
     Ag = (A[0][~bad], A[1][~bad])
-    assert np.all(dd_diff((G[0][~bad], G[1][~bad]), R) <= north_star_bound(Ag, P["B"], 40))
+    assert np.all(dd_diff((G[0][~bad], G[1][~bad]), R) <= fp64x2_tolerance(Ag, P["B"], 40))
 
 
 def test_workspace_variant_and_errors():
@@ -323,7 +323,7 @@ def test_panel_scaling_matches_oracles(m, n, k, kc):
     O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc, scaling="panel")
     assert np.all(dd_diff(G, O) <= panel_order_bound(P["A"], P["B"], O, k, kc))
     R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
-    assert np.all(dd_diff(G, R) <= north_star_bound(P["A"], P["B"], k))
+    assert np.all(dd_diff(G, R) <= fp64x2_tolerance(P["A"], P["B"], k))
 
 
 def test_panel_scaling_equals_global_for_one_block():
@@ -356,7 +356,7 @@ def test_panel_scaling_meets_the_tolerance_where_global_does_not():
     B = (np.asfortranarray(Bhi), np.asfortranarray(Bhi * 2.0 ** -53 * rng.uniform(-1, 1, (k, n))))
     C = (np.zeros((m, n), order="F"), np.zeros((m, n), order="F"))
     R = dd_gemm_ref(A, B, C)[:2]
-    tol = north_star_bound(A, B, k)
+    tol = fp64x2_tolerance(A, B, k)
     Gp = run_gemm(A, B, C, kc=kc, scaling=PANEL)
     Gg = run_gemm(A, B, C, kc=kc)
     assert np.all(dd_diff(Gp, R) <= tol)
@@ -420,7 +420,7 @@ def test_balancing_matches_oracles(m, n, k, kc, panel):
     bound = (panel_order_bound if panel else cascade_order_bound)(Ab, Bb, O, k, kc)
     assert np.all(dd_diff(G, O) <= bound)
     R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
-    assert np.all(dd_diff(G, R) <= north_star_bound(P["A"], P["B"], k))
+    assert np.all(dd_diff(G, R) <= fp64x2_tolerance(P["A"], P["B"], k))
 
 
 def test_balancing_is_invariant_to_power_of_two_diagonal_scaling():
@@ -439,7 +439,7 @@ def test_balancing_meets_the_tolerance_on_skewed_operands():
     m, n, k = 96, 80, 512
     P = make_problem(m, n, k, cfg=22, variant="skewed")
     R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
-    tol = north_star_bound(P["A"], P["B"], k) + 64 * k * 2.0 ** -104 * np.abs(P["C"][0])
+    tol = fp64x2_tolerance(P["A"], P["B"], k) + 64 * k * 2.0 ** -104 * np.abs(P["C"][0])
     Gb = run_gemm(P["A"], P["B"], P["C"], scaling=BAL)
     Gu = run_gemm(P["A"], P["B"], P["C"])
     assert np.all(dd_diff(Gb, R) <= tol)
@@ -491,7 +491,7 @@ def test_simple_unfused_matches_oracles(m, n, k, variant, kc):
     O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc)
     assert np.all(dd_diff(G, O) <= cascade_order_bound(P["A"], P["B"], O, k, kc))
     R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
-    assert np.all(dd_diff(G, R) <= north_star_bound(P["A"], P["B"], k))
+    assert np.all(dd_diff(G, R) <= fp64x2_tolerance(P["A"], P["B"], k))
 
 
 def test_simple_unfused_integer_matrices_exact_and_transposes():
