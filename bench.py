@@ -190,7 +190,56 @@ def bench_slices(torch, dg, stream, n=4096, reps=3):
             del Ch, Cl
         samples[("problem", variant)] = P
         del Ah, Al, Bh, Bl, C0h, C0l
+    out["vendor_gemm"] = [vendor_narrow_rates(torch, v) for v in (n, 2 * n)]
     return out, samples, (I, J)
+
+
+def vendor_narrow_rates(torch, n=4096, seconds=0.012):
+    """The vendor library's BF16, FP16 and INT8 GEMMs at n^3 (torch.matmul,
+    torch._int_mm), launched back to back for about as long as one slices
+    product runs, so that the clock settles the way it does under the
+    slices kernels.  A reference point for what the matrix cores sustain on
+    these formats; it computes nothing of the FP64x2 product."""
+    out = {"library": f"torch ({torch.backends.cuda.preferred_blas_library()})", "n": n}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    for fmt in ("bf16", "f16", "i8"):
+        try:
+            if fmt == "i8":
+                a = torch.randint(-64, 64, (n, n), device="cuda", dtype=torch.int8, generator=g)
+                b = torch.randint(-64, 64, (n, n), device="cuda", dtype=torch.int8, generator=g)
+                c = torch.empty(n, n, device="cuda", dtype=torch.int32)
+                call = lambda: torch._int_mm(a, b, out=c)  # noqa: E731
+                peak = PEAK_I8_MFMA_TOPS
+            else:
+                dt = torch.bfloat16 if fmt == "bf16" else torch.float16
+                a = torch.randn(n, n, device="cuda", dtype=dt, generator=g)
+                b = torch.randn(n, n, device="cuda", dtype=dt, generator=g)
+                c = torch.empty(n, n, device="cuda", dtype=dt)
+                call = lambda: torch.matmul(a, b, out=c)  # noqa: E731
+                peak = PEAK_BF16_MFMA_TFLOPS
+            for _ in range(5):
+                call()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            call()
+            e1.record()
+            torch.cuda.synchronize()
+            reps = max(10, int(seconds * 1e3 / max(e0.elapsed_time(e1), 1e-3)))
+            e0.record()
+            for _ in range(reps):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rate = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+            out[fmt] = {"launches": reps, "ms_per_gemm": round(ms, 4), "matrix_tops": round(rate, 1),
+                        "pct_of_matrix_peak": round(100 * rate / peak, 1)}
+            del a, b, c
+        except Exception as exc:   # a format the library does not offer here
+            out[fmt] = {"error": f"{type(exc).__name__}: {exc}"[:200]}
+    return out
 
 
 def slices_accuracy(out, samples, IJ, n=4096):
