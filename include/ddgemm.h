@@ -23,6 +23,8 @@
  * - Every call is stream ordered and asynchronous on `stream` (NULL = the
  *   default stream).  Argument errors are detected on the host and returned
  *   before anything is launched; a launch error is returned as DD_ERR_HIP.
+ *   A leading dimension for which the matrix's extent in bytes would not fit
+ *   in int64 is invalid like one below the row count.
  *   No C++ exception and no process exit crosses this interface.
  * - Non-finite inputs: an output entry whose row of op(A) or column of op(B)
  *   holds an Inf or NaN becomes NaN (the split has no finite digits for it).

@@ -153,6 +153,20 @@ dd_status upload_tiles(dd_batched_plan_s* P, hipStream_t s) {
   return hip_st(hipMemcpyAsync(P->d_tiles, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice, s));
 }
 
+// Options a batch accepts (the cascade with global scaling and the library's
+// tiles; kc and the cancellation flags may be set); kc out.
+bool batched_opts(const dd_gemm_opts* opts, int32_t* kc) {
+  if (!opts) return true;
+  if (opts->algo != DD_ALGO_CASCADE_F64 || opts->tile != 0 || opts->slices != 0 || opts->slice_bits != 0 ||
+      opts->scaling != 0 || opts->use_tuned != 0)
+    return false;
+  if (opts->kc != 0) {
+    if (opts->kc < 4 || opts->kc > 4096 || opts->kc % 4 != 0) return false;
+    *kc = opts->kc;
+  }
+  return true;
+}
+
 // Argument checks of a plan (numbers as in dd_batched_plan_create); kc out.
 dd_status check_plan_args(int32_t count, const int64_t* m, const int64_t* n, const int64_t* k,
                           const int64_t* lda, const int64_t* ldb, const int64_t* ldc, const dd_gemm_opts* opts,
@@ -165,15 +179,7 @@ dd_status check_plan_args(int32_t count, const int64_t* m, const int64_t* n, con
   if (count > 0 && (!ldb)) return -6;
   if (count > 0 && (!ldc)) return -7;
   int32_t kc = 256;
-  if (opts) {
-    if (opts->algo != DD_ALGO_CASCADE_F64 || opts->tile != 0 || opts->slices != 0 || opts->slice_bits != 0 ||
-        opts->scaling != 0 || opts->use_tuned != 0)
-      return -8;
-    if (opts->kc != 0) {
-      if (opts->kc < 4 || opts->kc > 4096 || opts->kc % 4 != 0) return -8;
-      kc = opts->kc;
-    }
-  }
+  if (!batched_opts(opts, &kc)) return -8;
   for (int32_t p = 0; p < count; ++p) {
     if (m[p] < 0 || n[p] < 0 || k[p] < 0) return -2;
     if (lda[p] < std::max<int64_t>(1, m[p])) return -5;
@@ -401,15 +407,7 @@ size_t dd_gemm_batched_workspace_size(int32_t count, const int64_t* m, const int
                                       const dd_gemm_opts* opts) {
   if (count < 0 || (count > 0 && (!m || !n || !k))) return 0;
   int32_t kc = 256;
-  if (opts) {
-    if (opts->algo != DD_ALGO_CASCADE_F64 || opts->tile != 0 || opts->slices != 0 || opts->slice_bits != 0 ||
-        opts->scaling != 0 || opts->use_tuned != 0)
-      return 0;
-    if (opts->kc != 0) {
-      if (opts->kc < 4 || opts->kc > 4096 || opts->kc % 4 != 0) return 0;
-      kc = opts->kc;
-    }
-  }
+  if (!batched_opts(opts, &kc)) return 0;
   for (int32_t p = 0; p < count; ++p)
     if (m[p] < 0 || n[p] < 0 || k[p] < 0) return 0;
   // the atomic counter, then the exponent words and packed planes
@@ -423,8 +421,12 @@ dd_status dd_batched_plan_tune(dd_batched_plan P, const double* const* A_hi, con
   if (!P) return -1;
   if (repeats < 1) return -8;
   if (P->ntiles == 0) return DD_OK;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DD_ERR_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    if (e0) (void)hipEventDestroy(e0);
+    return DD_ERR_HIP;
+  }
   float best = 1e30f;
   int best_dyn = P->dynamic, best_lpt = P->lpt, best_policy = P->policy;
   dd_status st = DD_OK;

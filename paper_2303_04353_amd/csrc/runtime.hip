@@ -128,17 +128,52 @@ struct PhaseEvents { hipEvent_t e0, e1, e2; };
 bool g_prof = false;
 std::vector<PhaseEvents> g_prof_events;
 
-PhaseEvents prof_begin(hipStream_t s, bool allowed = true) {
-  PhaseEvents pe{nullptr, nullptr, nullptr};
-  if (!g_prof || !allowed) return pe;
-  if (hipEventCreate(&pe.e0) != hipSuccess || hipEventCreate(&pe.e1) != hipSuccess ||
-      hipEventCreate(&pe.e2) != hipSuccess) {
-    (void)hipGetLastError();
-    return PhaseEvents{nullptr, nullptr, nullptr};
+// Events around the two phases of one call while timing is enabled: `split`
+// marks the end of phase one, `done` the end of the product and keeps the
+// events for dd_phase_times.  A call that returns without `done` (an error)
+// destroys them.
+class PhaseTimer {
+ public:
+  PhaseTimer(hipStream_t s, bool allowed) : s_(s) {
+    if (!allowed) return;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      if (!g_prof) return;
+    }
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    for (hipEvent_t& x : e)
+      if (hipEventCreate(&x) != hipSuccess) {
+        (void)hipGetLastError();
+        for (hipEvent_t y : e)
+          if (y) (void)hipEventDestroy(y);
+        return;
+      }
+    pe_ = PhaseEvents{e[0], e[1], e[2]};
+    (void)hipEventRecord(pe_.e0, s_);
   }
-  (void)hipEventRecord(pe.e0, s);
-  return pe;
-}
+  PhaseTimer(const PhaseTimer&) = delete;
+  PhaseTimer& operator=(const PhaseTimer&) = delete;
+  ~PhaseTimer() {
+    if (!pe_.e0) return;
+    (void)hipEventDestroy(pe_.e0);
+    (void)hipEventDestroy(pe_.e1);
+    (void)hipEventDestroy(pe_.e2);
+  }
+  void split() {
+    if (pe_.e1) (void)hipEventRecord(pe_.e1, s_);
+  }
+  void done() {
+    if (!pe_.e2) return;
+    (void)hipEventRecord(pe_.e2, s_);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof_events.push_back(pe_);
+    pe_ = PhaseEvents{nullptr, nullptr, nullptr};
+  }
+
+ private:
+  hipStream_t s_;
+  PhaseEvents pe_{nullptr, nullptr, nullptr};
+};
 
 // ------------------------------------------------------------ arguments
 struct Problem {
@@ -163,6 +198,14 @@ size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
   return (size_t)((cols - 1) * ld + rows) * sizeof(double);
 }
 
+// The bytes a rows x cols matrix with leading dimension ld (>= rows) spans
+// fit in an int64 (false for leading dimensions no allocation can have).
+bool span_fits(int64_t rows, int64_t cols, int64_t ld) {
+  if (rows <= 0 || cols <= 1) return true;
+  const int64_t lim = INT64_MAX / (int64_t)sizeof(double);
+  return ld <= (lim - rows) / (cols - 1);
+}
+
 Arg validate(const Problem& p) {
   if (p.transa != DD_OP_N && p.transa != DD_OP_T) return ARG_TRANSA;
   if (p.transb != DD_OP_N && p.transb != DD_OP_T) return ARG_TRANSB;
@@ -174,6 +217,9 @@ Arg validate(const Problem& p) {
   if (p.lda < (arows > 1 ? arows : 1)) return ARG_LDA;
   if (p.ldb < (brows > 1 ? brows : 1)) return ARG_LDB;
   if (p.ldc < (p.m > 1 ? p.m : 1)) return ARG_LDC;
+  if (!span_fits(arows, acols, p.lda)) return ARG_LDA;
+  if (!span_fits(brows, bcols, p.ldb)) return ARG_LDB;
+  if (!span_fits(p.m, p.n, p.ldc)) return ARG_LDC;
   if (p.m == 0 || p.n == 0) return ARG_OK;
   if (!p.Chi) return ARG_CHI;
   if (!p.Clo) return ARG_CLO;
@@ -301,8 +347,6 @@ dd_status run_slices_product(const Problem& p, const ddk::SlicesLayout& L, char*
   return DD_OK;
 }
 
-// With `fixed` the workspace is the caller's (or the scratch array) and the
-// call creates nothing: no phase-timing events either.
 // ------------------------------------------------------ tuned tile shapes
 // Output tile shapes recorded by dd_tune, per (m, n, k, kc, scaling); kept
 // in memory and, when DDGEMM_TUNE_CACHE names a file, appended to it as
@@ -365,6 +409,9 @@ int32_t tile_shape(const Problem& p, const Opts& o) {
   return ddk::kTile64x64;
 }
 
+// One GEMM after validation.  With `fixed` the workspace is the caller's (or
+// the scratch array) and the call creates nothing: no phase-timing events
+// either.
 dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes, bool internal_ws,
               hipStream_t s, bool fixed = false) {
   const int32_t algo = o.algo, kc = o.kc;
@@ -397,16 +444,12 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
     } else if (ws_bytes < L.bytes || ((uintptr_t)ws & 255u) != 0) {
       return DD_ERR_WORKSPACE;
     }
-    PhaseEvents pe = prof_begin(s, !fixed);
+    PhaseTimer timer(s, !fixed);
     st = run_slices_split(p, L, ws, s);
     if (st != DD_OK) return st;
-    if (pe.e1) (void)hipEventRecord(pe.e1, s);
+    timer.split();
     st = run_slices_product(p, L, ws, s);
-    if (pe.e2) {
-      (void)hipEventRecord(pe.e2, s);
-      std::lock_guard<std::mutex> lk(g_mu);
-      g_prof_events.push_back(pe);
-    }
+    if (st == DD_OK) timer.done();
     return st;
   }
   if (algo == DD_ALGO_CASCADE_ON_LOAD) {
@@ -426,20 +469,16 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
     strides(p, a_si, a_sp, b_sp, b_sj);
     uint64_t* amax = (uint64_t*)(ws + L.off_amax);
     uint64_t* bmax = (uint64_t*)(ws + L.off_bmax);
-    PhaseEvents pe = prof_begin(s, !fixed);
+    PhaseTimer timer(s, !fixed);
     DD_TRY(ddk::launch_fill_u64(amax, L.mpad, 0, s));
     DD_TRY(ddk::launch_fill_u64(bmax, L.npad, 0, s));
     DD_TRY(ddk::launch_max_abs_bits(p.Ahi, p.m, p.k, a_si, a_sp, amax, s));
     DD_TRY(ddk::launch_max_abs_bits(p.Bhi, p.n, p.k, b_sj, b_sp, bmax, s));
-    if (pe.e1) (void)hipEventRecord(pe.e1, s);
+    timer.split();
     if (o.flags) DD_TRY(ddk::launch_fill_u32(o.flags, (p.m * p.n + 31) / 32, 0u, s));
     st = hip_status(ddk::launch_cascade_onload(L, p.Ahi, p.Alo, a_si, a_sp, p.Bhi, p.Blo, b_sp, b_sj, amax, bmax,
                                                p.Chi, p.Clo, p.ldc, o.flags, s));
-    if (pe.e2) {
-      (void)hipEventRecord(pe.e2, s);
-      std::lock_guard<std::mutex> lk(g_mu);
-      g_prof_events.push_back(pe);
-    }
+    if (st == DD_OK) timer.done();
     return st;
   }
   const bool simple = algo == DD_ALGO_SIMPLE_UNFUSED;
@@ -453,18 +492,14 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
   } else if (ws_bytes < L.bytes || ((uintptr_t)ws & 255u) != 0) {
     return DD_ERR_WORKSPACE;
   }
-  PhaseEvents pe = prof_begin(s, !fixed);
+  PhaseTimer timer(s, !fixed);
   st = run_split(p, L, ws, s);
   if (st != DD_OK) return st;
-  if (pe.e1) (void)hipEventRecord(pe.e1, s);
+  timer.split();
   if (simple) {
     st = hip_status(ddk::run_simple_products(L, ws, (const uint64_t*)(ws + L.off_amax),
                                              (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, s));
-    if (pe.e2) {
-      (void)hipEventRecord(pe.e2, s);
-      std::lock_guard<std::mutex> lk(g_mu);
-      g_prof_events.push_back(pe);
-    }
+    if (st == DD_OK) timer.done();
     return st;
   }
   if (o.flags) {
@@ -477,11 +512,7 @@ dd_status run(const Problem& p, const Opts& o, void* workspace, size_t ws_bytes,
                                       (const uint64_t*)(ws + L.off_bmax), p.Chi, p.Clo, p.ldc, o.flags, s,
                                       (const int32_t*)(ws + L.off_aexp), (const int32_t*)(ws + L.off_bexp),
                                       tile_shape(p, o)));
-  if (pe.e2) {
-    (void)hipEventRecord(pe.e2, s);
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_prof_events.push_back(pe);
-  }
+  if (st == DD_OK) timer.done();
   return st;
 }
 
@@ -911,6 +942,9 @@ dd_status td_gemm_ex(int32_t transa, int32_t transb, int64_t m, int64_t n, int64
   if (lda < (arows > 1 ? arows : 1)) return -9;
   if (ldb < (brows > 1 ? brows : 1)) return -13;
   if (ldc < (m > 1 ? m : 1)) return -17;
+  if (!span_fits(arows, acols, lda)) return -9;
+  if (!span_fits(brows, bcols, ldb)) return -13;
+  if (!span_fits(m, n, ldc)) return -17;
   if (kc != 0 && !valid_kc(kc)) return -20;
   const bool internal = workspace == nullptr && ws_bytes == 0;
   if (!internal && workspace == nullptr) return -18;

@@ -46,6 +46,9 @@ def test_status_strings_and_version():
     ((4, 4, 4, 8, 8, 4, 16, 16, 4, 0, 1 << 31, 4), -10),          # C_hi NULL
     ((4, 4, 4, 8, 16, 4, 1 << 20, 1 << 21, 4, 8, 1 << 22, 4), -10),  # C_hi overlaps A_hi
     ((4, 4, 4, 8, 16, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 22, 4), -11),  # C_lo overlaps C_hi
+    ((4, 4, 4, 8, 16, 1 << 61, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 4), -6),   # A's extent overflows
+    ((4, 4, 4, 8, 16, 4, 1 << 20, 1 << 21, 1 << 61, 1 << 22, 1 << 23, 4), -9),   # B's extent overflows
+    ((4, 4, 4, 8, 16, 4, 1 << 20, 1 << 21, 4, 1 << 22, 1 << 23, 1 << 61), -12),  # C's extent overflows
 ])
 def test_invalid_arguments_rejected_on_host(args, want):
     assert dg.dd_gemm(*args, stream=0) == want
@@ -123,6 +126,7 @@ def test_td_workspace_and_argument_checks():
                              kc=a.get("kc", 0), stream=0)
     assert call(transa=3) == -1 and call(transb=3) == -2 and call(m=-1) == -3 and call(k=-2) == -5
     assert call(lda=3) == -9 and call(ldb=3) == -13 and call(ldc=3) == -17 and call(kc=10) == -20
+    assert call(lda=1 << 61) == -9 and call(ldb=1 << 61) == -13 and call(ldc=1 << 61) == -17
     assert call(A1=0) == -7 and call(B2=0) == -12 and call(C0=0) == -14
     assert call(C1=7 * p + 8) == -15          # C planes overlap
     assert call(C2=2 * p) == -16              # C overlaps A
