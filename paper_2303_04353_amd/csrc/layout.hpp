@@ -16,9 +16,9 @@
 //      they are used, with the same two FP64 additions:
 //        Bpack[cb*b_block_stride(K4) + (kq*5 + t)*64 + kk*16 + c]
 // Rows/columns are padded with zeros up to the workgroup tile and the inner
-// dimension up to a multiple of 8 (two groups of 4, one LDS stage of the
-// product kernel), so the product kernel needs no bounds checks in its main
-// loop.
+// dimension up to a multiple of 16 (two LDS stages of the product kernel, 8
+// inner indices each, which its main loop takes in pairs), so the product
+// kernel needs no bounds checks in its main loop.
 #pragma once
 
 #include <stddef.h>

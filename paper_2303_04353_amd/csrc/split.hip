@@ -5,8 +5,10 @@
 //    |fl(hi + lo)| when the lo plane is given) as a bit pattern (non-negative
 //    doubles order like their bits), reduced with atomicMax; the exponent
 //    e = frexp_exp(max) is taken where it is used.
-//  * pack_a / pack_b: one wave per 64-lane fragment, each lane splits one
-//    entry and writes its 4 (A) or 7 (B) planes; zero padding outside m, n, k.
+//  * pack_a / pack_b: four consecutive 64-lane fragments per wave, each lane
+//    splits one entry of each and writes its 4 (A) or 5 (B: B0'..B3' and
+//    B6'; B4' and B5' are formed in the product kernel) planes; zero padding
+//    outside m, n, k.
 //  * unpack_*: diagnostic copy of the packed planes into plain column-major
 //    planes (used by dd_cascade_split).
 #include <hip/hip_runtime.h>
@@ -292,7 +294,8 @@ batched_max_abs(const BatchDesc* __restrict__ desc, int count, const int64_t* __
   }
 }
 
-// Units: 4 fragments (one per wave) of the packed A planes, then of B.
+// Units: 4 x kPF fragments (kPF consecutive ones per wave) of the packed A
+// planes, then of B.
 __global__ void __launch_bounds__(256)
 batched_pack(const BatchDesc* __restrict__ desc, int count, const int64_t* __restrict__ prefA,
              const int64_t* __restrict__ prefB, const double* const* __restrict__ Ahi,
