@@ -84,6 +84,20 @@ def test_cascade_matches_oracles(m, n, k, variant, kc):
     assert np.all(dd_diff(G, R) <= fp64x2_tolerance(P["A"], P["B"], k))
 
 
+@pytest.mark.parametrize("variant", ["uniform", "scaled"])
+def test_long_inner_dimension(variant):
+    """k = 2^17 + 5: 513 rank-256 blocks (the last one of 5 indices) summed
+    in the FP64x2 accumulator, against both oracles."""
+    m, n, k = 70, 33, (1 << 17) + 5
+    log(f"cascade long k: m={m} n={n} k={k} variant={variant}")
+    P = make_problem(m, n, k, cfg=16, variant=variant)
+    G = run_gemm(P["A"], P["B"], P["C"])
+    O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=256)
+    assert np.all(dd_diff(G, O) <= cascade_order_bound(P["A"], P["B"], O, k, 256))
+    R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
+    assert np.all(dd_diff(G, R) <= fp64x2_tolerance(P["A"], P["B"], k))
+
+
 def test_plain_entry_point_equals_ex_default():
     P = make_problem(96, 80, 300, cfg=12)
     G1 = run_gemm(P["A"], P["B"], P["C"], plain=True)
