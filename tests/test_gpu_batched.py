@@ -117,6 +117,28 @@ def test_batch_equals_single_calls_bitwise_for_every_schedule_and_tile_policy(kc
         dg.dd_batched_plan_destroy(plan)
 
 
+def test_batch_with_a_long_inner_dimension_equals_single_calls():
+    """One problem of 513 rank-256 blocks among small ones: the persistent
+    kernel's tiles of it take far longer than the rest (LPT puts them
+    first); every problem still equals its single call bit for bit."""
+    import torch
+    shapes = [(64, 64, 64), (70, 33, (1 << 17) + 5), (1, 1, 1), (130, 70, 1000), (33, 96, 300)]
+    log(f"batched long k: {shapes}")
+    b = Batch(shapes, cfg=34)
+    want = b.singles()
+    plan = b.plan()
+    try:
+        for dyn in (1, 0):
+            dg.check(dg.dd_batched_plan_schedule(plan, dyn, 1, 2))
+            b.reset()
+            b.exec(plan)
+            torch.cuda.synchronize()
+            for i, (g, w) in enumerate(zip(b.results(), want)):
+                assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1]), (i, dyn)
+    finally:
+        dg.dd_batched_plan_destroy(plan)
+
+
 def test_one_shot_entry_point():
     import torch
     b = Batch(SMALL[:6], cfg=31)

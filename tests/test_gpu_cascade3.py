@@ -65,6 +65,17 @@ def test_td_matches_the_oracle(m, n, k, kc, variant):
     assert np.all(np.abs(G[1]) <= np.spacing(np.abs(G[0]))) and np.all(np.abs(G[2]) <= np.spacing(np.abs(G[1])) + 1e-300)
 
 
+def test_td_long_inner_dimension():
+    """k = 20003: 79 rank-256 blocks (the last one of 35 indices), each added
+    to the triple-word accumulator."""
+    m, n, k = 40, 24, 20003
+    log(f"td long k: m={m} n={n} k={k}")
+    P = make_problem3(m, n, k, cfg=9)
+    G = run_td(P["A"], P["B"], P["C"])
+    O = c3.cascade3_gemm(P["A"], P["B"], P["C"], kc=256)
+    assert np.all(_diff(G, O) <= _order_bound(P["A"], P["B"], O, k, 256))
+
+
 def test_td_against_exact_rationals():
     m, n, k = 4, 3, 40
     P = make_problem3(m, n, k, cfg=31)
