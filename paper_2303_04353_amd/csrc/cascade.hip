@@ -27,9 +27,12 @@
 // group 1 and, at their end, the LDS writes of the next stage; group 1's
 // MFMAs carry, first, the global loads of the stage after that, then the
 // reads of the next stage's group 0.  Both waves of a SIMD meet at the
-// barrier, so nothing but the wait for the writes is left there.  FP64
-// vector work does not overlap the matrix cores on gfx950, so the loop
-// keeps vector instructions to the two additions that form B4' and B5'.
+// barrier, so nothing but the wait for the writes is left there.  Vector
+// instructions, integer ones included, do not overlap the matrix cores on
+// gfx950, so the loop keeps them to the two additions that form B4' and
+// B5': staging addresses are wave-uniform (scalar) bases plus the lane's 16
+// bytes, and the loop takes two stages at a time so LDS buffer offsets are
+// constants.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -262,39 +265,45 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   // Piece d of a stage (d = wave, wave + 8, ...): d < kPieceA is chunk d%4
   // of 16-row block d/4 of A, otherwise chunk e%5 of 16-column block e/5 of
   // B (e = d - kPieceA).  The packed planes of one block are contiguous over k.
+  // Every wave moves kPiecesMax pieces; a wave with fewer repeats piece 0
+  // (the same data to the same place), so the code has no branch.  A
+  // piece's source, stride and LDS place are the same for all lanes of the
+  // wave (scalar registers); each lane adds its own 16 bytes.  Vector
+  // instructions in this loop take issue cycles from the matrix cores, so
+  // the per-stage address work is kept scalar.
   constexpr int kRem = SH::kPieces % kWaves;
+  __builtin_assume(wave >= 0 && wave < kWaves);   // 8 waves per workgroup
   const int npiece = (kRem == 0 || wave < kRem) ? kPiecesMax : kPiecesMax - 1;
-  const double* psrc[kPiecesMax];
+  const int64_t strideA = kStageQ * kFragA * kLanes, strideB = kStageQ * kFragB * kLanes;
+  const double* pbase[kPiecesMax];
+  int64_t pstride[kPiecesMax];
   int pdst[kPiecesMax];
 #pragma unroll
   for (int c = 0; c < kPiecesMax; ++c) {
     const int d = c < npiece ? wave + c * kWaves : wave;   // unused slots repeat piece 0
     if (d < kPieceA) {
       const int blk = d >> 2, i = d & 3;
-      psrc[c] = Apack + (tm * SH::kRB + blk) * a_block_stride(K4) + i * 128 + lane * 2;
-      pdst[c] = blk * (kStageQ * kFragA * kLanes) + i * 128 + lane * 2;
+      pbase[c] = Apack + (tm * SH::kRB + blk) * a_block_stride(K4) + i * 128;
+      pstride[c] = strideA;
+      pdst[c] = blk * (kStageQ * kFragA * kLanes) + i * 128;
     } else {
       const int e = d - kPieceA, blk = e / 5, i = e % 5;
-      psrc[c] = Bpack + (tn * SH::kCB + blk) * b_block_stride(K4) + i * 128 + lane * 2;
-      pdst[c] = kAStage + blk * (kStageQ * kFragB * kLanes) + i * 128 + lane * 2;
+      pbase[c] = Bpack + (tn * SH::kCB + blk) * b_block_stride(K4) + i * 128;
+      pstride[c] = strideB;
+      pdst[c] = kAStage + blk * (kStageQ * kFragB * kLanes) + i * 128;
     }
   }
-  const int64_t strideA = kStageQ * kFragA * kLanes, strideB = kStageQ * kFragB * kLanes;
   d2 stg[kPiecesMax];
-  // every wave moves kPiecesMax pieces; a wave with fewer repeats piece 0
-  // (the same data to the same place), so the code has no branch
-  int64_t pstride[kPiecesMax];
-#pragma unroll
-  for (int c = 0; c < kPiecesMax; ++c) pstride[c] = pdst[c] < kAStage ? strideA : strideB;
   auto load_stage = [&](int64_t st) {
 #pragma unroll
-    for (int c = 0; c < kPiecesMax; ++c) stg[c] = *(const d2*)(psrc[c] + st * pstride[c]);
+    for (int c = 0; c < kPiecesMax; ++c) stg[c] = *(const d2*)(pbase[c] + st * pstride[c] + lane * 2);
   };
-  auto store_stage = [&](int64_t st) {
-    double* buf = lds + (int)(st % kNBuf) * kStage;
+  auto store_buf = [&](int b) {   // into stage buffer b
+    double* buf = lds + b * kStage + lane * 2;
 #pragma unroll
     for (int c = 0; c < kPiecesMax; ++c) *(d2*)(buf + pdst[c]) = stg[c];
   };
+  auto store_stage = [&](int64_t st) { store_buf((int)(st % kNBuf)); };
 
   auto a_ptr = [&](int64_t st) {
     return lds + (int)(st % kNBuf) * kStage + wm * (kStageQ * kFragA * kLanes)
@@ -321,7 +330,9 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   // whose last reads ended before the previous barrier; after the barrier
   // group 1's products (oy) run while group 0 of stage st+1 is read into ox
   // and stage st+2 is loaded.  The last iteration writes, reads and loads
-  // in-bounds copies that are not used.
+  // in-bounds copies that are not used.  The loop takes two stages at a
+  // time (nst is even), so each stage's buffer is known at compile time and
+  // every LDS address is a fixed offset from the lane's own.
   int32_t inblk = 0, blk = 0;
   auto block_done = [&]() {
     const int32_t* ea = nullptr;
@@ -335,21 +346,30 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
     combine<kFlags, kPanel, CB>(bins, acc_h, acc_l, flg, ea, fb);
     ++blk;
   };
-  for (int64_t st = 0; st < nst; ++st) {
-    read_ops(oy, a_ptr(st), b_ptr(st), 1);
+  const double* a0 = a_ptr(0);
+  const double* b0 = b_ptr(0);
+  auto one_stage = [&](int64_t st, int b) {   // stage st, in buffer b
+    read_ops(oy, a0 + b * kStage, b0 + b * kStage, 1);
     derive_b(ox);
-    store_stage(st + 1);
+    store_buf(b ^ 1);
     ten_products(bins, ox);
     interleave_reads_writes<CB, kPiecesMax>();
     if (++inblk == kcq) { inblk = 0; block_done(); }
     derive_b(oy);
     lds_reads_done();
     lds_barrier();
-    read_ops(ox, a_ptr(st + 1), b_ptr(st + 1), 0);
-    load_stage(st + 2 <= last ? st + 2 : last);
+    read_ops(ox, a0 + (b ^ 1) * kStage, b0 + (b ^ 1) * kStage, 0);
+    // stage numbers fit in 32 bits (the planes of 2^31 stages would not fit
+    // in memory), and the 32-bit compare is a scalar one
+    const int32_t s2 = (int32_t)st + 2;
+    load_stage(s2 <= (int32_t)last ? s2 : (int32_t)last);
     ten_products(bins, oy);
     interleave_reads_loads<CB, kPiecesMax>();
     if (++inblk == kcq) { inblk = 0; block_done(); }
+  };
+  for (int64_t st = 0; st < nst; st += 2) {
+    one_stage(st, 0);
+    one_stage(st + 1, 1);
   }
   if (inblk != 0) block_done();
 

@@ -37,17 +37,20 @@
 // previous barrier.
 //
 // Triple words: three VecSum passes (Ogita, Rump and Oishi) over the terms,
-// least significant first, the last element the first word, two more
-// passes over the rest for the second word, the plain sum of what remains
-// the third, one renormalising TwoSum chain.  It stands in for rounding the
-// exact sum to three words, within a few units of 2^-158 of the sum plus
-// 2^-200 of the terms' magnitudes.
+// roughly least significant first, the last element the first word, two
+// more passes over the rest for the second word, the plain sum of what
+// remains the third, one renormalising TwoSum chain.  It stands in for
+// rounding the exact sum to three words, within a few units of 2^-158 of
+// the sum plus 2^-200 of the terms' magnitudes.  Per rank-kc block one such
+// sum takes the six bins and the accumulator's three words (nine terms); the
+// epilogue takes the result and the three words of C (six).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <array>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 #include "dd_device.hpp"
@@ -147,26 +150,31 @@ td_pack_b(const double* __restrict__ X0, const double* __restrict__ X1, const do
   for (int t = 0; t < kP3; ++t) dst[t * kLanes] = out[t];
 }
 
-__device__ __forceinline__ void vec_sum6(double a[6]) {
+template <int N>
+__device__ __forceinline__ void vec_sum_n(double (&a)[N]) {
 #pragma unroll
-  for (int i = 1; i < 6; ++i) two_sum(a[i], a[i - 1], a[i], a[i - 1]);
-}
-__device__ __forceinline__ void vec_sum5(double a[5]) {
-#pragma unroll
-  for (int i = 1; i < 5; ++i) two_sum(a[i], a[i - 1], a[i], a[i - 1]);
+  for (int i = 1; i < N; ++i) two_sum(a[i], a[i - 1], a[i], a[i - 1]);
 }
 
-// The triple word of six terms given least significant first.
-__device__ __forceinline__ void td_from6(double a[6], double& r0, double& r1, double& r2) {
-  vec_sum6(a);
-  vec_sum6(a);
-  vec_sum6(a);
-  r0 = a[5];
-  double rest[5] = {a[0], a[1], a[2], a[3], a[4]};
-  vec_sum5(rest);
-  vec_sum5(rest);
-  r1 = rest[4];
-  r2 = ((rest[0] + rest[1]) + rest[2]) + rest[3];
+// The triple word of N terms given roughly least significant first: three
+// VecSum passes, the last element the first word; two more passes over the
+// rest, its last element the second word; the plain sum of what remains the
+// third; one renormalising TwoSum chain.
+template <int N>
+__device__ __forceinline__ void td_from_n(double (&a)[N], double& r0, double& r1, double& r2) {
+  vec_sum_n(a);
+  vec_sum_n(a);
+  vec_sum_n(a);
+  r0 = a[N - 1];
+  double rest[N - 1];
+#pragma unroll
+  for (int i = 0; i < N - 1; ++i) rest[i] = a[i];
+  vec_sum_n(rest);
+  vec_sum_n(rest);
+  r1 = rest[N - 2];
+  r2 = rest[0];
+#pragma unroll
+  for (int i = 1; i < N - 2; ++i) r2 = r2 + rest[i];
   two_sum(r1, r2, r1, r2);
   two_sum(r0, r1, r0, r1);
   two_sum(r1, r2, r1, r2);
@@ -264,18 +272,18 @@ __device__ __forceinline__ void interleave_second_half() {
   }
 }
 
-// Bins of a rank-kc block to a triple word, added to the accumulator; bins reset.
+// Bins of a rank-kc block added to the triple-word accumulator; bins reset.
 __device__ __forceinline__ void combine3(Bins3& B, double (&r0)[kSub3][kCG3], double (&r1)[kSub3][kCG3],
                                          double (&r2)[kSub3][kCG3]) {
 #pragma unroll
   for (int s = 0; s < kSub3; ++s)
 #pragma unroll
     for (int g = 0; g < kCG3; ++g) {
-      double t[6] = {B.b[kTail][s][g], B.b[4][s][g], B.b[3][s][g], B.b[2][s][g], B.b[1][s][g], B.b[0][s][g]};
-      double w0, w1, w2;
-      td_from6(t, w0, w1, w2);
-      double u[6] = {r2[s][g], w2, r1[s][g], w1, r0[s][g], w0};
-      td_from6(u, r0[s][g], r1[s][g], r2[s][g]);
+      // the block's six bins and the accumulator's three words in one sum,
+      // roughly by magnitude
+      double t[9] = {B.b[kTail][s][g], r2[s][g], B.b[4][s][g], B.b[3][s][g], r1[s][g],
+                     B.b[2][s][g],     B.b[1][s][g], B.b[0][s][g], r0[s][g]};
+      td_from_n(t, r0[s][g], r1[s][g], r2[s][g]);
 #pragma unroll
       for (int L = 0; L < 6; ++L) B.b[L][s][g] = 0.0;
     }
@@ -308,34 +316,38 @@ td_cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ B
   // Piece d of a stage (d = wave, wave + 8, wave + 16): d < 12 is chunk d%3
   // of 16-row block d/3 of A, else chunk e%3 of 16-column block e/3 of B
   // (e = d - 12).  A block's group is 384 contiguous doubles, 3 pieces.
-  const double* psrc[3];
+  // A piece's source and LDS place are the same for all lanes of the wave
+  // (scalar registers); each lane adds its own 16 bytes.  Vector
+  // instructions in the loop take issue cycles from the matrix cores.
+  __builtin_assume(wave >= 0 && wave < kWaves3);
+  const double* pbase[3];
   int pdst[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int d = wave + c * kWaves3;
     if (d < 12) {
       const int blk = d / 3, i = d % 3;
-      psrc[c] = Apack + (tm * 4 + blk) * td_block_stride(K4) + i * 128 + lane * 2;
-      pdst[c] = blk * kFrag3 + i * 128 + lane * 2;
+      pbase[c] = Apack + (tm * 4 + blk) * td_block_stride(K4) + i * 128;
+      pdst[c] = blk * kFrag3 + i * 128;
     } else {
       const int e = d - 12, blk = e / 3, i = e % 3;
-      psrc[c] = Bpack + (tn * 4 + blk) * td_block_stride(K4) + i * 128 + lane * 2;
-      pdst[c] = kAStage3 + blk * kFrag3 + i * 128 + lane * 2;
+      pbase[c] = Bpack + (tn * 4 + blk) * td_block_stride(K4) + i * 128;
+      pdst[c] = kAStage3 + blk * kFrag3 + i * 128;
     }
   }
   d2 stg[3];
   const int64_t last = K4 - 1;
   auto load_stage = [&](int64_t st) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) stg[c] = *(const d2*)(psrc[c] + st * kFrag3);
+    for (int c = 0; c < 3; ++c) stg[c] = *(const d2*)(pbase[c] + st * kFrag3 + lane * 2);
   };
   auto store_stage = [&](int buf) {
-    // every piece starts on a 16-byte boundary (pdst is even): say so, or
-    // the 16-byte writes get split into two 8-byte ones, which conflict in
-    // the LDS banks
+    // every piece starts on a 16-byte boundary: say so, or the 16-byte
+    // writes get split into two 8-byte ones, which conflict in the LDS banks
+    double* dst = lds + buf * kStage3 + lane * 2;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      *(d2*)__builtin_assume_aligned(lds + buf * kStage3 + pdst[c], 16) = stg[c];
+      *(d2*)__builtin_assume_aligned(dst + pdst[c], 16) = stg[c];
   };
   const int aoff = wm * kFrag3 + (lane >> 4) * 4 + (lane & 3);
   const int boff = kAStage3 + wn * kCG3 * kFrag3 + lane;
@@ -352,13 +364,16 @@ td_cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ B
   read_a(ax0, lds + aoff, 0);
 
   int32_t inblk = 0;
-  int cur = 0;                                 // buffer of the current group
   // One group: bc / ac0 hold its B planes and A_0'; bn / an0 receive the
   // next group's.  The last group reads and loads in-bounds copies that are
   // not used.
-  auto group = [&](int64_t st, double (&bc)[kP3][kCG3], double (&ac0)[kSub3], double (&bn)[kP3][kCG3],
+  // The buffer of a group is a template constant: the loop below runs six
+  // groups (two rounds of the three buffers) at a time, so every LDS
+  // address is a fixed offset from the lane's own.
+  auto group = [&](auto curc, int64_t st, double (&bc)[kP3][kCG3], double (&ac0)[kSub3], double (&bn)[kP3][kCG3],
                    double (&an0)[kSub3]) {
-    const int nxt = cur == kNBuf3 - 1 ? 0 : cur + 1;
+    constexpr int cur = decltype(curc)::value;
+    constexpr int nxt = cur == kNBuf3 - 1 ? 0 : cur + 1;
     const double* sA = lds + cur * kStage3 + aoff;
     double a1[kSub3], a2[kSub3], a3[kSub3], a4[kSub3], a5[kSub3];
     double u[kCG3];
@@ -385,7 +400,9 @@ td_cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ B
     lds_barrier();
     // second half: A_2'..A_5'; the next group's operands from the stage
     // just written, the stage after it from memory
-    load_stage(st + 2 <= last ? st + 2 : last);
+    // group numbers fit in 32 bits; the 32-bit compare is a scalar one
+    const int32_t s2 = (int32_t)st + 2;
+    load_stage(s2 <= (int32_t)last ? s2 : (int32_t)last);
     read_a(a3, sA, 3);
     read_a(a4, sA, 4);
     read_a(a5, sA, 5);
@@ -406,15 +423,31 @@ td_cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ B
     read_b(bn, lds + nxt * kStage3 + boff);
     read_a(an0, lds + nxt * kStage3 + aoff, 0);
     interleave_second_half();
-    cur = nxt;
     if (++inblk == kcq) {
       inblk = 0;
       combine3(bins, r0, r1, r2);
     }
   };
-  for (int64_t st = 0; st < K4; st += 2) {
-    group(st, bx, ax0, by, ay0);
-    group(st + 1, by, ay0, bx, ax0);
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
+  using B2 = std::integral_constant<int, 2>;
+  int64_t st = 0;
+  for (; st + 6 <= K4; st += 6) {
+    group(B0{}, st, bx, ax0, by, ay0);
+    group(B1{}, st + 1, by, ay0, bx, ax0);
+    group(B2{}, st + 2, bx, ax0, by, ay0);
+    group(B0{}, st + 3, by, ay0, bx, ax0);
+    group(B1{}, st + 4, bx, ax0, by, ay0);
+    group(B2{}, st + 5, by, ay0, bx, ax0);
+  }
+  // K4 is even: 0, 2 or 4 groups remain, starting again in buffer 0
+  if (st < K4) {
+    group(B0{}, st, bx, ax0, by, ay0);
+    group(B1{}, st + 1, by, ay0, bx, ax0);
+    if (st + 2 < K4) {
+      group(B2{}, st + 2, bx, ax0, by, ay0);
+      group(B0{}, st + 3, by, ay0, bx, ax0);
+    }
   }
   if (inblk != 0) combine3(bins, r0, r1, r2);
 
@@ -433,7 +466,7 @@ td_cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ B
       double u[6] = {C2[c], __builtin_ldexp(r2[s][g], sh), C1[c], __builtin_ldexp(r1[s][g], sh), C0[c],
                      __builtin_ldexp(r0[s][g], sh)};
       double w0, w1, w2;
-      td_from6(u, w0, w1, w2);
+      td_from_n(u, w0, w1, w2);
       C0[c] = w0;
       C1[c] = w1;
       C2[c] = w2;
