@@ -98,6 +98,18 @@ def test_long_inner_dimension(variant):
     assert np.all(dd_diff(G, R) <= fp64x2_tolerance(P["A"], P["B"], k))
 
 
+@pytest.mark.parametrize("kc", [12, 20, 36])
+def test_blocks_ending_mid_iteration(kc):
+    """kc / 4 = 3, 5, 9 groups per rank-kc block: the combines fall at every
+    position of the product loop's two-stage (four-group) iteration."""
+    m, n, k = 70, 96, 397
+    log(f"cascade kc={kc} (blocks of {kc // 4} groups) m={m} n={n} k={k}")
+    P = make_problem(m, n, k, cfg=17)
+    G = run_gemm(P["A"], P["B"], P["C"], kc=kc)
+    O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=kc)
+    assert np.all(dd_diff(G, O) <= cascade_order_bound(P["A"], P["B"], O, k, kc))
+
+
 def test_plain_entry_point_equals_ex_default():
     P = make_problem(96, 80, 300, cfg=12)
     G1 = run_gemm(P["A"], P["B"], P["C"], plain=True)

@@ -76,6 +76,18 @@ def test_td_long_inner_dimension():
     assert np.all(_diff(G, O) <= _order_bound(P["A"], P["B"], O, k, 256))
 
 
+@pytest.mark.parametrize("kc", [12, 20, 28])
+def test_td_blocks_ending_mid_iteration(kc):
+    """kc / 4 = 3, 5, 7 groups per block: the combines fall at every position
+    of the product loop's six-group iteration and of its tail."""
+    m, n, k = 40, 70, 230
+    log(f"td kc={kc} m={m} n={n} k={k}")
+    P = make_problem3(m, n, k, cfg=10)
+    G = run_td(P["A"], P["B"], P["C"], kc=kc)
+    O = c3.cascade3_gemm(P["A"], P["B"], P["C"], kc=kc)
+    assert np.all(_diff(G, O) <= _order_bound(P["A"], P["B"], O, k, kc))
+
+
 def test_td_against_exact_rationals():
     m, n, k = 4, 3, 40
     P = make_problem3(m, n, k, cfg=31)
