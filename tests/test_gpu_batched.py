@@ -89,7 +89,7 @@ SMALL = [(37, 50, 300), (1, 1, 1), (64, 64, 64), (0, 5, 7), (5, 0, 7), (6, 9, 0)
 MIXED = SMALL + [(80, 200, 300), (200, 90, 260), (33, 70, 257), (96, 96, 40), (160, 30, 600), (20, 150, 1)]
 
 
-@pytest.mark.parametrize("kc", [0, 128])
+@pytest.mark.parametrize("kc", [0, 128, 20])
 def test_batch_equals_single_calls_bitwise_for_every_schedule_and_tile_policy(kc):
     import torch
     b = Batch(MIXED)
