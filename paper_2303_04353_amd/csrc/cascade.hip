@@ -36,6 +36,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dd_device.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
@@ -231,7 +233,7 @@ __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? 
 // bexp[b * bstride + j] and are applied to each block's result; otherwise
 // the maxima amax[i], bmax[j] give the exponents that scale the sum.  The
 // arithmetic of every output entry is the same for every tile shape.
-template <bool kFlags, bool kPanel, class SH>
+template <bool kFlags, bool kPanel, class SH, bool kBuf = false>
 __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const double* __restrict__ Apack,
                                              const double* __restrict__ Bpack,
                                              const uint64_t* __restrict__ amax,
@@ -298,6 +300,33 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
 #pragma unroll
     for (int c = 0; c < kPiecesMax; ++c) stg[c] = *(const d2*)(pbase[c] + st * pstride[c] + lane * 2);
   };
+  // With kBuf the loop loads through buffer resources over the tile's A and
+  // B blocks: the piece's offset, stage included, is scalar and the lane's
+  // 16 bytes are the only vector part, so no vector instruction forms an
+  // address (32-bit offsets: the host takes this form while the tile's
+  // blocks span less than 2 GiB).
+  const char* tileA = (const char*)(Apack + tm * SH::kRB * a_block_stride(K4));
+  const char* tileB = (const char*)(Bpack + tn * SH::kCB * b_block_stride(K4));
+  // dword 3 of a raw buffer resource on gfx9 parts: 32-bit data, no swizzle
+  const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)tileA, (short)0, kBuf ? (int)(SH::kRB * a_block_stride(K4) * 8) : 0, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)tileB, (short)0, kBuf ? (int)(SH::kCB * b_block_stride(K4) * 8) : 0, 0x00020000);
+  bool isA[kPiecesMax];
+  uint32_t poff[kPiecesMax];   // byte offset of the piece's stage-0 chunk in its tile
+#pragma unroll
+  for (int c = 0; c < kPiecesMax; ++c) {
+    isA[c] = pstride[c] == strideA;
+    poff[c] = kBuf ? (uint32_t)((const char*)pbase[c] - (isA[c] ? tileA : tileB)) : 0u;
+  }
+  const uint32_t loff = (uint32_t)lane * 16u;
+  auto load_stage_buf = [&](int32_t st) {
+#pragma unroll
+    for (int c = 0; c < kPiecesMax; ++c) {
+      const uint32_t so = poff[c] + (uint32_t)st * (uint32_t)(pstride[c] * 8);
+      stg[c] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(isA[c] ? rA : rB, loff, so, 0));
+    }
+  };
   auto store_buf = [&](int b) {   // into stage buffer b
     double* buf = lds + b * kStage + lane * 2;
 #pragma unroll
@@ -362,7 +391,11 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
     // stage numbers fit in 32 bits (the planes of 2^31 stages would not fit
     // in memory), and the 32-bit compare is a scalar one
     const int32_t s2 = (int32_t)st + 2;
-    load_stage(s2 <= (int32_t)last ? s2 : (int32_t)last);
+    if constexpr (kBuf) {
+      load_stage_buf(s2 <= (int32_t)last ? s2 : (int32_t)last);
+    } else {
+      load_stage(s2 <= (int32_t)last ? s2 : (int32_t)last);
+    }
     ten_products(bins, oy);
     interleave_reads_loads<CB, kPiecesMax>();
     if (++inblk == kcq) { inblk = 0; block_done(); }
@@ -590,7 +623,7 @@ hipError_t launch_cascade_onload(const CascadeLayout& L, const double* Ahi, cons
   return hipGetLastError();
 }
 
-template <bool kFlags, bool kPanel, class SH>
+template <bool kFlags, bool kPanel, class SH, bool kBuf>
 __global__ void __launch_bounds__(kWaves * 64)
 cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpack,
                const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax,
@@ -600,8 +633,8 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
   __shared__ __attribute__((aligned(16))) double lds[kNBuf * SH::kStage];
   int64_t tm, tn;
   tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  cascade_tile<kFlags, kPanel, SH>(lds, Apack, Bpack, amax, bmax, K4, kcq, m, n, tm, tn, Chi, Clo, ldc, flags,
-                                   aexp, bexp, mpad, npad);
+  cascade_tile<kFlags, kPanel, SH, kBuf>(lds, Apack, Bpack, amax, bmax, K4, kcq, m, n, tm, tn, Chi, Clo, ldc,
+                                         flags, aexp, bexp, mpad, npad);
 }
 
 // Persistent form for a batch of GEMMs: every workgroup takes tiles from the
@@ -681,22 +714,26 @@ hipError_t launch_shape(const CascadeLayout& L, const double* Apack, const doubl
   if (tiles <= 0 || tiles > 0x7fffffff) return hipErrorInvalidValue;
   const unsigned g = (unsigned)tiles;
   const bool panel = L.npanel > 1;
-  if (flags && panel) {
-    cascade_kernel<true, true, SH><<<g, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
-                                                             tiles_m, tiles_n, Chi, Clo, ldc, flags, aexp, bexp,
-                                                             L.mpad, L.npad);
-  } else if (flags) {
-    cascade_kernel<true, false, SH><<<g, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
-                                                              tiles_m, tiles_n, Chi, Clo, ldc, flags, aexp,
-                                                              bexp, L.mpad, L.npad);
-  } else if (panel) {
-    cascade_kernel<false, true, SH><<<g, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n,
-                                                              tiles_m, tiles_n, Chi, Clo, ldc, nullptr, aexp,
-                                                              bexp, L.mpad, L.npad);
+  // the buffer-load form while a tile's A and B blocks span less than 2 GiB
+  const bool buf = SH::kRB * a_block_stride(L.K4) * 8 < (int64_t(1) << 31) &&
+                   SH::kCB * b_block_stride(L.K4) * 8 < (int64_t(1) << 31);
+  auto go = [&](auto fl, auto pn, auto bf) {
+    cascade_kernel<decltype(fl)::value, decltype(pn)::value, SH, decltype(bf)::value><<<g, kWaves * 64, 0, s>>>(
+        Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m, L.n, tiles_m, tiles_n, Chi, Clo, ldc,
+        decltype(fl)::value ? flags : nullptr, aexp, bexp, L.mpad, L.npad);
+  };
+  using T = std::true_type;
+  using F = std::false_type;
+  if (buf) {
+    if (flags && panel) go(T{}, T{}, T{});
+    else if (flags) go(T{}, F{}, T{});
+    else if (panel) go(F{}, T{}, T{});
+    else go(F{}, F{}, T{});
   } else {
-    cascade_kernel<false, false, SH><<<g, kWaves * 64, 0, s>>>(Apack, Bpack, amax, bmax, L.K4, L.kcq, L.m,
-                                                               L.n, tiles_m, tiles_n, Chi, Clo, ldc, nullptr,
-                                                               aexp, bexp, L.mpad, L.npad);
+    if (flags && panel) go(T{}, T{}, F{});
+    else if (flags) go(T{}, F{}, F{});
+    else if (panel) go(F{}, T{}, F{});
+    else go(F{}, F{}, F{});
   }
   return hipGetLastError();
 }

@@ -98,6 +98,20 @@ def test_long_inner_dimension(variant):
     assert np.all(dd_diff(G, R) <= fp64x2_tolerance(P["A"], P["B"], k))
 
 
+def test_inner_dimension_beyond_the_buffer_load_range():
+    """k = 2^20 + 3: a 64 x 64 tile's packed B blocks span 2.5 GiB, past the
+    32-bit offsets of the buffer-load form, so the product kernel stages with
+    64-bit global addresses; against both oracles."""
+    m, n, k = 20, 33, (1 << 20) + 3
+    log(f"cascade global-address staging: m={m} n={n} k={k}")
+    P = make_problem(m, n, k, cfg=18)
+    G = run_gemm(P["A"], P["B"], P["C"])
+    O = cz.cascade_gemm(P["A"], P["B"], P["C"], kc=256)
+    assert np.all(dd_diff(G, O) <= cascade_order_bound(P["A"], P["B"], O, k, 256))
+    R = dd_gemm_ref(P["A"], P["B"], P["C"])[:2]
+    assert np.all(dd_diff(G, R) <= fp64x2_tolerance(P["A"], P["B"], k))
+
+
 @pytest.mark.parametrize("kc", [12, 20, 36])
 def test_blocks_ending_mid_iteration(kc):
     """kc / 4 = 3, 5, 9 groups per rank-kc block: the combines fall at every
