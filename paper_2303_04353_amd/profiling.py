@@ -31,8 +31,9 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# the headline form of the product kernel: no flags, global Sigma and T, 64 x 64 tiles
-PRODUCT_KERNEL = "cascade_kernel<false, false, Shape<64, 64> >"
+# the headline form of the product kernel: no flags, global Sigma and T, 64 x 64
+# tiles (either staging form: the last template argument is left open)
+PRODUCT_KERNEL = "cascade_kernel<false, false, Shape<64, 64>"
 PRODUCT_SOURCE = os.path.join(HERE, "csrc", "cascade.hip")
 
 
@@ -86,9 +87,12 @@ def traffic(fetch_csv: str, write_csv: str, copy_mib: int, m: int, n: int, k: in
     w_factor = copy_bytes / (cal_w * 1024.0)
     pf = [v for name, v in fetch if is_product_kernel(name)]
     pw = [v for name, v in write if is_product_kernel(name)]
+    if not pf or not pw:
+        raise ValueError("no dispatch of the product kernel %r in the counter files" % PRODUCT_KERNEL)
     fb = sum(pf) / len(pf) * 1024.0 * f_factor
     wb = sum(pw) / len(pw) * 1024.0 * w_factor
-    return {"kernel": PRODUCT_KERNEL, "source_sha256_16": source_hash(), "m": m, "n": n, "k": k,
+    kname = next(_short(name).replace("ddk::", "") for name, _ in fetch if is_product_kernel(name))
+    return {"kernel": kname, "source_sha256_16": source_hash(), "m": m, "n": n, "k": k,
             "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
             "bytes_per_launch": fb + wb, "fetch_scale": f_factor, "write_scale": w_factor,
             "calibration_copy_bytes": copy_bytes, "dispatches": [len(pf), len(pw)]}

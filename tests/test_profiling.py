@@ -25,8 +25,8 @@ def test_trace_table_names_and_units(tmp_path):
     assert t[3].startswith("| helper | 2 | 0.0 |")
 
 
-# the headline product kernel as rocprofv3 names it
-PROD = "void ddk::cascade_kernel<false, false, ddk::(anonymous namespace)::Shape<64, 64> >"
+# the headline product kernel as rocprofv3 names it (buffer-load staging form)
+PROD = "void ddk::cascade_kernel<false, false, ddk::(anonymous namespace)::Shape<64, 64>, true>"
 
 
 def test_traffic_scales_by_the_calibration_copy(tmp_path):
@@ -51,6 +51,7 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
     assert abs(r["fetch_bytes_per_launch"] - 10 * (1 << 30)) < 1
     assert abs(r["bytes_per_launch"] - 11 * (1 << 30)) < 1
     assert r["dispatches"] == [2, 1] and r["source_sha256_16"] == pf.source_hash()
+    assert r["kernel"] == "cascade_kernel<false, false, Shape<64, 64>, true>"
     # a stored measurement counts only for the same shape and kernel source
     out = tmp_path / "t.json"
     out.write_text(json.dumps(r))
