@@ -737,7 +737,7 @@ def main():
                      # the minimum: A and B as hi/lo planes read once, C read and written
                      "algorithmic_bytes": 16 * (m * k + k * n) + 32 * m * n,
                      # what the kernel must at least read as designed: 4 + 5 packed digit planes, C
-                     "packed_plane_bytes": (4 + 5) * 8 * (m * k + k * n) + 32 * m * n},
+                     "packed_plane_bytes": 8 * (4 * m * k + 7 * k * n) + 32 * m * n},
     }
     rf = result["roofline"]
     if traffic is not None:

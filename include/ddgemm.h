@@ -205,7 +205,7 @@ dd_status dd_gemm(int64_t m, int64_t n, int64_t k,
  * (0 for DD_ALGO_DD_VALU).  Returns 0 as well for invalid arguments.
  * DD_ALGO_SIMPLE_UNFUSED needs, besides the cascade's, 8 (4 m k + 7 k n +
  * 6 m n) bytes of plain planes, bins and accumulator.
- * The cascade needs 32 mpad kpad + 40 npad kpad bytes of packed digit planes
+ * The cascade needs 32 mpad kpad + 56 npad kpad bytes of packed digit planes
  * (mpad, npad rounded up to 64, kpad to 16) plus 4352 bytes of padding per
  * 16 rows and columns.  The slices variants need b s (mpad + npad) kpad
  * bytes of packed slices (b = 2 for BF16/FP16, 1 for INT8; kpad rounded up
@@ -263,7 +263,7 @@ dd_status dd_tune(int32_t count, const int64_t* m, const int64_t* n, const int64
  * DD_ALGO_SIMPLE_UNFUSED is rejected (-15).  A problem whose
  * dd_gemm_workspace_size exceeds DD_NOALLOC_SCRATCH_BYTES is rejected with
  * DD_ERR_WORKSPACE before anything is launched: 1024 x 1024 x 1024 with the
- * cascade needs about 73 MiB; square cascades fit up to m = n = k = 1344.
+ * cascade needs about 89 MiB; square cascades fit up to m = n = k = 1216.
  * Every call on one device shares that device's array and leaves its
  * contents behind (each call clears what must start at zero), so calls that
  * overlap on one device, on any streams, race on it: order them on one

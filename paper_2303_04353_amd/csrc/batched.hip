@@ -56,6 +56,7 @@ struct dd_batched_plan_s {
   int dynamic = 1;
   int lpt = 1;
   int policy = 0;                     // tile policy, 0..2
+  bool buf = true;                    // every problem's tiles take the buffer-load staging
 };
 
 namespace {
@@ -214,7 +215,7 @@ size_t batch_ws_bytes(int32_t count, const int64_t* m, const int64_t* n, const i
     d.off_apack = (int64_t)off;
     off += (size_t)ddk::round_up((int64_t)(sizeof(double) * (d.mpad / 16) * ddk::a_block_stride(L.K4)), 256);
     d.off_bpack = (int64_t)off;
-    off += (size_t)ddk::round_up((int64_t)(sizeof(double) * (d.npad / 16) * ddk::b_block_stride(L.K4)), 256);
+    off += (size_t)ddk::round_up((int64_t)(sizeof(double) * (d.npad / 16) * ddk::b_block_stride(L.K4, ddk::kFragBBatched)), 256);
   }
   return off;
 }
@@ -252,6 +253,8 @@ dd_status plan_create(int32_t count, const int64_t* m, const int64_t* n, const i
   P->flags = flags;
   P->flag_words = fw;
   const size_t off = batch_ws_bytes(count, m, n, k, kc, P->desc.data());
+  for (int32_t p = 0; p < count; ++p)
+    if (m[p] > 0 && n[p] > 0 && k[p] > 0 && !ddk::buffer_staging_fits(P->desc[p].K4)) P->buf = false;
   int64_t eoff = 0;
   for (int32_t p = 0; p < count; ++p) {
     BatchDesc& d = P->desc[p];
@@ -363,7 +366,7 @@ dd_status plan_exec(dd_batched_plan P, const double* const* A_hi, const double* 
                                                ws, (uint64_t*)ws, P->nexps, stream);
   if (e != hipSuccess) return hip_st(e);
   return hip_st(ddk::launch_cascade_batched(P->d_desc, P->d_tiles, P->ntiles, C_hi, C_lo, ws, counter, P->grid,
-                                            P->dynamic != 0, flags, stream));
+                                            P->dynamic != 0, flags, P->buf, stream));
 }
 
 // Tables of the one-shot form with a caller workspace, kept per device, kc

@@ -15,11 +15,11 @@
 // the other's LDS reads.
 //
 // Operand staging: per LDS stage (2 groups of 4 inner indices) the
-// workgroup's 64 rows of A (4 planes) and 64 columns of B (5 stored planes),
-// 36 KiB, are loaded from the packed planes into registers (16-byte loads,
-// 36 pieces of 1 KiB dealt round robin to the 8 waves; a wave with four
-// pieces moves its first one twice, so every wave runs the same branch-free
-// code), then written to the other of two LDS buffers; one barrier per
+// workgroup's 64 rows of A (4 planes) and 64 columns of B (7 planes), 44
+// KiB, are loaded from the packed planes into registers (16-byte loads, 44
+// pieces of 1 KiB dealt round robin to the 8 waves; a wave with five pieces
+// moves its first one twice, so every wave runs the same branch-free code),
+// then written to the other of two LDS buffers; one barrier per
 // stage.  (Direct global-to-LDS copies would save the registers, but their
 // completion is tracked with the LDS counter as well, so every wait for an
 // operand read would also wait for the copies in flight.)  Every memory
@@ -29,10 +29,13 @@
 // reads of the next stage's group 0.  Both waves of a SIMD meet at the
 // barrier, so nothing but the wait for the writes is left there.  Vector
 // instructions, integer ones included, do not overlap the matrix cores on
-// gfx950, so the loop keeps them to the two additions that form B4' and
-// B5': staging addresses are wave-uniform (scalar) bases plus the lane's 16
-// bytes, and the loop takes two stages at a time so LDS buffer offsets are
-// constants.
+// gfx950, so the loop has next to none: B4' and B5' are stored planes
+// rather than sums formed here, staging addresses are wave-uniform (scalar)
+// bases plus the lane's 16 bytes, and the loop takes two stages at a time
+// so LDS buffer offsets are constants.  Batched plans, whose short-k tiles
+// gain less from this than their packing pays for two more planes, and the
+// split-on-load kernel store five B planes and form B4' and B5' with two
+// additions per column group.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -54,18 +57,20 @@ constexpr int kNBuf = 2;                // stage buffers in LDS
 // A workgroup tile of TM x TN outputs (64 x 64, 32 x 64 or 64 x 32): the
 // 16-row blocks and 16-column groups are dealt to the 8 waves, 16 rows by
 // kWaveCB column groups each (two for 64 x 64, one otherwise).  LDS stage:
-// A [16-row block][group h][plane 4][64], B [16-col block][h][plane 5][64].
-template <int TM, int TN>
+// A [16-row block][group h][plane 4][64], B [16-col block][h][plane FB][64],
+// FB the stored B planes (7, or 5 in batched plans: B4', B5' formed here).
+template <int TM, int TN, int FB = kFragB>
 struct Shape {
+  static constexpr int kFB = FB;
   static constexpr int kRB = TM / 16;                        // 16-row blocks
   static constexpr int kCB = TN / 16;                        // 16-column groups
   static constexpr int kWaveCB = kRB * kCB / kWaves;         // column groups per wave
   static constexpr int kWavesN = kCB / kWaveCB;              // waves along a row of the tile
   static constexpr int kAStage = kRB * kStageQ * kFragA * kLanes;   // doubles
-  static constexpr int kBStage = kCB * kStageQ * kFragB * kLanes;
+  static constexpr int kBStage = kCB * kStageQ * FB * kLanes;
   static constexpr int kStage = kAStage + kBStage;
   static constexpr int kPieceA = kRB * 4;                    // 1 KiB pieces per stage
-  static constexpr int kPieceB = kCB * 5;
+  static constexpr int kPieceB = kCB * FB;
   static constexpr int kPieces = kPieceA + kPieceB;          // piece d goes to wave d % 8
   static constexpr int kPiecesMax = (kPieces + kWaves - 1) / kWaves;
   static_assert(kWaveCB >= 1 && kRB * kCB == kWaves * kWaveCB, "8 waves cover the tile");
@@ -73,7 +78,10 @@ struct Shape {
 using Shape64x64 = Shape<64, 64>;
 using Shape32x64 = Shape<32, 64>;
 using Shape64x32 = Shape<64, 32>;
-constexpr int kLdsDoubles = kNBuf * Shape64x64::kStage;      // 72 KiB, the largest shape's
+using BShape64x64 = Shape<64, 64, kFragBBatched>;   // batched plans
+using BShape32x64 = Shape<32, 64, kFragBBatched>;
+using BShape64x32 = Shape<64, 32, kFragBBatched>;
+constexpr int kLdsBatched = kNBuf * BShape64x64::kStage;    // 72 KiB, the largest batched shape's
 
 typedef double d2 __attribute__((ext_vector_type(2)));
 
@@ -86,12 +94,14 @@ __device__ __forceinline__ void lds_reads_done() { asm volatile("s_waitcnt lgkmc
 
 // The scheduler's order for the MFMAs of one group (80 with two column
 // groups per wave, 40 with one) and the memory instructions issued among
-// them (the LDS reads of the next operand set are 13 two-word reads, or 11).
+// them (the LDS reads of the next operand set are 15 two-word reads, or 12,
+// with 7 stored B planes; 13 or 11 with 5).
 // Group 0: the reads of the next operands, then the LDS writes of the staged
 // stage, spread over the MFMAs.
-template <int CB, int NP>
+template <int CB, int NP, int FB>
 __device__ __forceinline__ void interleave_reads_writes() {
-  constexpr int R = CB == 2 ? 13 : 11, MR = CB == 2 ? 4 : 2, MW = CB == 2 ? 5 : 4;
+  constexpr int R = CB == 2 ? (FB == 7 ? 15 : 13) : (FB == 7 ? 12 : 11), MR = CB == 2 ? 4 : 2;
+  constexpr int MW = FB == 7 ? 3 : (CB == 2 ? 5 : 4);
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
@@ -105,9 +115,10 @@ __device__ __forceinline__ void interleave_reads_writes() {
 }
 
 // Group 1: the global loads of a later stage, then the reads.
-template <int CB, int NP>
+template <int CB, int NP, int FB>
 __device__ __forceinline__ void interleave_reads_loads() {
-  constexpr int R = CB == 2 ? 13 : 11, ML = CB == 2 ? 3 : 2, MR = CB == 2 ? 5 : 2;
+  constexpr int R = CB == 2 ? (FB == 7 ? 15 : 13) : (FB == 7 ? 12 : 11), ML = CB == 2 ? 3 : 2;
+  constexpr int MR = CB == 2 ? (FB == 7 ? 4 : 5) : 2;
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
     __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // VMEM read
@@ -122,14 +133,15 @@ __device__ __forceinline__ void interleave_reads_loads() {
 
 // Operands of one group of 4 inner indices.  A register (sub-block s, plane
 // t) of lane 16k + 4b + i holds position s*16 + k*4 + i of the wave's 16-row
-// block; B registers hold the planes B0'..B6' (B4', B5' formed here).
+// block; B registers hold the planes B0'..B6' (with 5 stored planes, B4'
+// and B5' formed by derive_b).
 template <int CB>
 struct Ops {
   double a[4][kSub];
   double b[7][CB];
 };
 
-template <int CB>
+template <int CB, int FB>
 __device__ __forceinline__ void read_ops(Ops<CB>& o, const double* sA, const double* sB, int h) {
 #pragma unroll
   for (int t = 0; t < 4; ++t)
@@ -137,21 +149,27 @@ __device__ __forceinline__ void read_ops(Ops<CB>& o, const double* sA, const dou
     for (int s = 0; s < kSub; ++s) o.a[t][s] = sA[h * (kFragA * kLanes) + t * kLanes + s * 16];
 #pragma unroll
   for (int g = 0; g < CB; ++g) {
-    const double* b = sB + (g * kStageQ + h) * (kFragB * kLanes);
-    o.b[0][g] = b[0 * kLanes];
-    o.b[1][g] = b[1 * kLanes];
-    o.b[2][g] = b[2 * kLanes];
-    o.b[3][g] = b[3 * kLanes];
-    o.b[6][g] = b[4 * kLanes];
+    const double* b = sB + (g * kStageQ + h) * (FB * kLanes);
+    if constexpr (FB == 7) {
+#pragma unroll
+      for (int t = 0; t < 7; ++t) o.b[t][g] = b[t * kLanes];
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) o.b[t][g] = b[t * kLanes];
+      o.b[6][g] = b[4 * kLanes];
+    }
   }
 }
 
-template <int CB>
+// B4' and B5' of operands read from 5 stored planes.
+template <int CB, int FB>
 __device__ __forceinline__ void derive_b(Ops<CB>& o) {
+  if constexpr (FB == 5) {
 #pragma unroll
-  for (int g = 0; g < CB; ++g) {
-    o.b[4][g] = o.b[2][g] + o.b[3][g];   // sigma_2 B4 = B2' + B3'
-    o.b[5][g] = o.b[1][g] + o.b[4][g];   // sigma_1 B5 = B1' + B2' + B3'
+    for (int g = 0; g < CB; ++g) {
+      o.b[4][g] = o.b[2][g] + o.b[3][g];   // sigma_2 B4 = B2' + B3'
+      o.b[5][g] = o.b[1][g] + o.b[4][g];   // sigma_1 B5 = B1' + B2' + B3'
+    }
   }
 }
 
@@ -244,7 +262,7 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
                                              const int32_t* __restrict__ aexp = nullptr,
                                              const int32_t* __restrict__ bexp = nullptr,
                                              int64_t astride = 0, int64_t bstride = 0) {
-  constexpr int CB = SH::kWaveCB;
+  constexpr int CB = SH::kWaveCB, FB = SH::kFB;
   constexpr int kPiecesMax = SH::kPiecesMax, kPieceA = SH::kPieceA, kAStage = SH::kAStage;
   constexpr int kStage = SH::kStage;
   uint32_t flg = 0;
@@ -276,7 +294,7 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   constexpr int kRem = SH::kPieces % kWaves;
   __builtin_assume(wave >= 0 && wave < kWaves);   // 8 waves per workgroup
   const int npiece = (kRem == 0 || wave < kRem) ? kPiecesMax : kPiecesMax - 1;
-  const int64_t strideA = kStageQ * kFragA * kLanes, strideB = kStageQ * kFragB * kLanes;
+  const int64_t strideA = kStageQ * kFragA * kLanes, strideB = kStageQ * FB * kLanes;
   const double* pbase[kPiecesMax];
   int64_t pstride[kPiecesMax];
   int pdst[kPiecesMax];
@@ -289,10 +307,10 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
       pstride[c] = strideA;
       pdst[c] = blk * (kStageQ * kFragA * kLanes) + i * 128;
     } else {
-      const int e = d - kPieceA, blk = e / 5, i = e % 5;
-      pbase[c] = Bpack + (tn * SH::kCB + blk) * b_block_stride(K4) + i * 128;
+      const int e = d - kPieceA, blk = e / FB, i = e % FB;
+      pbase[c] = Bpack + (tn * SH::kCB + blk) * b_block_stride(K4, FB) + i * 128;
       pstride[c] = strideB;
-      pdst[c] = kAStage + blk * (kStageQ * kFragB * kLanes) + i * 128;
+      pdst[c] = kAStage + blk * (kStageQ * FB * kLanes) + i * 128;
     }
   }
   d2 stg[kPiecesMax];
@@ -306,12 +324,12 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   // address (32-bit offsets: the host takes this form while the tile's
   // blocks span less than 2 GiB).
   const char* tileA = (const char*)(Apack + tm * SH::kRB * a_block_stride(K4));
-  const char* tileB = (const char*)(Bpack + tn * SH::kCB * b_block_stride(K4));
+  const char* tileB = (const char*)(Bpack + tn * SH::kCB * b_block_stride(K4, FB));
   // dword 3 of a raw buffer resource on gfx9 parts: 32-bit data, no swizzle
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
       (void*)tileA, (short)0, kBuf ? (int)(SH::kRB * a_block_stride(K4) * 8) : 0, 0x00020000);
   const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)tileB, (short)0, kBuf ? (int)(SH::kCB * b_block_stride(K4) * 8) : 0, 0x00020000);
+      (void*)tileB, (short)0, kBuf ? (int)(SH::kCB * b_block_stride(K4, FB) * 8) : 0, 0x00020000);
   bool isA[kPiecesMax];
   uint32_t poff[kPiecesMax];   // byte offset of the piece's stage-0 chunk in its tile
 #pragma unroll
@@ -339,7 +357,7 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
            + (lane >> 4) * 4 + (lane & 3);
   };
   auto b_ptr = [&](int64_t st) {
-    return lds + (int)(st % kNBuf) * kStage + kAStage + (wn * CB) * (kStageQ * kFragB * kLanes)
+    return lds + (int)(st % kNBuf) * kStage + kAStage + (wn * CB) * (kStageQ * FB * kLanes)
            + lane;
   };
 
@@ -352,7 +370,7 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   lds_reads_done();
   lds_barrier();
   Ops<CB> ox, oy;
-  read_ops(ox, a_ptr(0), b_ptr(0), 0);
+  read_ops<CB, FB>(ox, a_ptr(0), b_ptr(0), 0);
 
   // Per stage st: group 0's products (ox) run while group 1 is read into oy
   // and stage st+1 (staged in registers) is written to the other buffer,
@@ -378,16 +396,16 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
   const double* a0 = a_ptr(0);
   const double* b0 = b_ptr(0);
   auto one_stage = [&](int64_t st, int b) {   // stage st, in buffer b
-    read_ops(oy, a0 + b * kStage, b0 + b * kStage, 1);
-    derive_b(ox);
+    read_ops<CB, FB>(oy, a0 + b * kStage, b0 + b * kStage, 1);
+    derive_b<CB, FB>(ox);
     store_buf(b ^ 1);
     ten_products(bins, ox);
-    interleave_reads_writes<CB, kPiecesMax>();
+    interleave_reads_writes<CB, kPiecesMax, FB>();
     if (++inblk == kcq) { inblk = 0; block_done(); }
-    derive_b(oy);
+    derive_b<CB, FB>(oy);
     lds_reads_done();
     lds_barrier();
-    read_ops(ox, a0 + (b ^ 1) * kStage, b0 + (b ^ 1) * kStage, 0);
+    read_ops<CB, FB>(ox, a0 + (b ^ 1) * kStage, b0 + (b ^ 1) * kStage, 0);
     // stage numbers fit in 32 bits (the planes of 2^31 stages would not fit
     // in memory), and the 32-bit compare is a scalar one
     const int32_t s2 = (int32_t)st + 2;
@@ -397,7 +415,7 @@ __device__ __forceinline__ void cascade_tile(double* __restrict__ lds, const dou
       load_stage(s2 <= (int32_t)last ? s2 : (int32_t)last);
     }
     ten_products(bins, oy);
-    interleave_reads_loads<CB, kPiecesMax>();
+    interleave_reads_loads<CB, kPiecesMax, FB>();
     if (++inblk == kcq) { inblk = 0; block_done(); }
   };
   for (int64_t st = 0; st < nst; st += 2) {
@@ -455,8 +473,9 @@ __device__ __forceinline__ void cascade_tile_onload(double* __restrict__ lds, co
                                                     int64_t tm, int64_t tn, double* __restrict__ Chi,
                                                     double* __restrict__ Clo, int64_t ldc,
                                                     uint32_t* __restrict__ flags) {
-  using SH = Shape64x64;
-  constexpr int CB = SH::kWaveCB, kStage = SH::kStage, kAStage = SH::kAStage;
+  // five B planes in LDS, B4' and B5' formed from them (registers are short here)
+  using SH = BShape64x64;
+  constexpr int CB = SH::kWaveCB, kStage = SH::kStage, kAStage = SH::kAStage, FB = SH::kFB;
   uint32_t flg = 0;
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -487,7 +506,7 @@ __device__ __forceinline__ void cascade_tile_onload(double* __restrict__ lds, co
   // group pb/4, plane p at p*64 + kk*16 + c (c = jb%16, kk = pb%4)
   const int adst = (ia >> 4) * (kStageQ * kFragA * kLanes) + (pa >> 2) * (kFragA * kLanes)
                    + ((ia & 15) >> 2) * 16 + (pa & 3) * 4 + (ia & 3);
-  const int bdst = kAStage + (jb >> 4) * (kStageQ * kFragB * kLanes) + (pb >> 2) * (kFragB * kLanes)
+  const int bdst = kAStage + (jb >> 4) * (kStageQ * FB * kLanes) + (pb >> 2) * (FB * kLanes)
                    + (pb & 3) * 16 + (jb & 15);
   SplitParams sp;
   {
@@ -530,7 +549,7 @@ __device__ __forceinline__ void cascade_tile_onload(double* __restrict__ lds, co
     return lds + (int)(st % kNBuf) * kStage + wm * (kStageQ * kFragA * kLanes) + (lane >> 4) * 4 + (lane & 3);
   };
   auto b_ptr = [&](int64_t st) {
-    return lds + (int)(st % kNBuf) * kStage + kAStage + (wn * CB) * (kStageQ * kFragB * kLanes) + lane;
+    return lds + (int)(st % kNBuf) * kStage + kAStage + (wn * CB) * (kStageQ * FB * kLanes) + lane;
   };
 
   const int64_t nst = K4 / kStageQ;
@@ -541,23 +560,23 @@ __device__ __forceinline__ void cascade_tile_onload(double* __restrict__ lds, co
   lds_reads_done();
   lds_barrier();
   Ops<CB> ox, oy;
-  read_ops(ox, a_ptr(0), b_ptr(0), 0);
+  read_ops<CB, FB>(ox, a_ptr(0), b_ptr(0), 0);
   int32_t inblk = 0;
   auto block_done = [&]() { combine<kFlags, false, CB>(bins, acc_h, acc_l, flg, nullptr, nullptr); };
   for (int64_t st = 0; st < nst; ++st) {
-    read_ops(oy, a_ptr(st), b_ptr(st), 1);
-    derive_b(ox);
+    read_ops<CB, FB>(oy, a_ptr(st), b_ptr(st), 1);
+    derive_b<CB, FB>(ox);
     store_stage(st + 1);
     ten_products(bins, ox);
-    interleave_reads_writes<CB, 9>();
+    interleave_reads_writes<CB, kFragA + FB, FB>();
     if (++inblk == kcq) { inblk = 0; block_done(); }
-    derive_b(oy);
+    derive_b<CB, FB>(oy);
     lds_reads_done();
     lds_barrier();
-    read_ops(ox, a_ptr(st + 1), b_ptr(st + 1), 0);
+    read_ops<CB, FB>(ox, a_ptr(st + 1), b_ptr(st + 1), 0);
     load_stage(st + 2 <= last ? st + 2 : last);
     ten_products(bins, oy);
-    interleave_reads_loads<CB, 4>();
+    interleave_reads_loads<CB, 4, FB>();
     if (++inblk == kcq) { inblk = 0; block_done(); }
   }
   if (inblk != 0) block_done();
@@ -596,7 +615,7 @@ cascade_onload_kernel(const double* __restrict__ Ahi, const double* __restrict__
                       const uint64_t* __restrict__ amax, const uint64_t* __restrict__ bmax, int c0, int c1, int c2,
                       int64_t K4, int32_t kcq, int64_t m, int64_t n, int64_t k, int64_t tiles_m, int64_t tiles_n,
                       double* __restrict__ Chi, double* __restrict__ Clo, int64_t ldc, uint32_t* __restrict__ flags) {
-  __shared__ __attribute__((aligned(16))) double lds[kNBuf * Shape64x64::kStage];
+  __shared__ __attribute__((aligned(16))) double lds[kNBuf * BShape64x64::kStage];
   int64_t tm, tn;
   tile_of_block(blockIdx.x, tiles_m, tiles_n, tm, tn);
   cascade_tile_onload<kFlags>(lds, Ahi, Alo, a_si, a_sp, Bhi, Blo, b_sp, b_sj, amax, bmax, c0, c1, c2, K4, kcq, m,
@@ -642,13 +661,14 @@ cascade_kernel(const double* __restrict__ Apack, const double* __restrict__ Bpac
 // left, either with a fixed stride or from an atomic counter.  Each tile
 // carries its shape (all tiles of one problem have the same).  With kFlags,
 // problem p's cancellation bits go to its bitmap at flags + off_flags.
-template <bool kFlags>
+// kBuf: stage through buffer loads (every problem's blocks span < 2 GiB).
+template <bool kFlags, bool kBuf>
 __global__ void __launch_bounds__(kWaves * 64)
 cascade_batched_kernel(const BatchDesc* __restrict__ desc, const BatchTile* __restrict__ tiles,
                        int64_t ntiles, double* const* __restrict__ Chi, double* const* __restrict__ Clo,
                        const char* __restrict__ ws, unsigned long long* __restrict__ counter, int dynamic,
                        uint32_t* __restrict__ flags) {
-  __shared__ __attribute__((aligned(16))) double lds[kLdsDoubles];
+  __shared__ __attribute__((aligned(16))) double lds[kLdsBatched];
   __shared__ unsigned long long next;
   int64_t w = blockIdx.x;
   for (;;) {
@@ -667,13 +687,13 @@ cascade_batched_kernel(const BatchDesc* __restrict__ desc, const BatchTile* __re
     const uint64_t* bm = (const uint64_t*)(ws + d.off_bmax);
     uint32_t* fl = kFlags ? flags + d.off_flags : nullptr;
     if (t.shape == kTile32x64) {
-      cascade_tile<kFlags, false, Shape32x64>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
+      cascade_tile<kFlags, false, BShape32x64, kBuf>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
                                               Clo[t.p], d.ldc, fl);
     } else if (t.shape == kTile64x32) {
-      cascade_tile<kFlags, false, Shape64x32>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
+      cascade_tile<kFlags, false, BShape64x32, kBuf>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
                                               Clo[t.p], d.ldc, fl);
     } else {
-      cascade_tile<kFlags, false, Shape64x64>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
+      cascade_tile<kFlags, false, BShape64x64, kBuf>(lds, Ap, Bp, am, bm, d.K4, d.kcq, d.m, d.n, t.tm, t.tn, Chi[t.p],
                                               Clo[t.p], d.ldc, fl);
     }
     __syncthreads();  // the next tile reuses the staging buffers
@@ -683,22 +703,33 @@ cascade_batched_kernel(const BatchDesc* __restrict__ desc, const BatchTile* __re
 
 hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles, int64_t ntiles,
                                   double* const* Chi, double* const* Clo, const char* ws,
-                                  uint32_t* counter, int grid, bool dynamic, uint32_t* flags, hipStream_t s) {
+                                  uint32_t* counter, int grid, bool dynamic, uint32_t* flags, bool buf,
+                                  hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (grid < 1) return hipErrorInvalidValue;
   if (dynamic) {
     hipError_t e = launch_fill_u64((uint64_t*)counter, 1, 0, s);
     if (e != hipSuccess) return e;
   }
+  auto go = [&](auto fl, auto bf) {
+    cascade_batched_kernel<decltype(fl)::value, decltype(bf)::value><<<grid, kWaves * 64, 0, s>>>(
+        desc, tiles, ntiles, Chi, Clo, ws, (unsigned long long*)counter, dynamic ? 1 : 0, flags);
+  };
+  using T = std::true_type;
+  using F = std::false_type;
   if (flags) {
-    cascade_batched_kernel<true><<<grid, kWaves * 64, 0, s>>>(desc, tiles, ntiles, Chi, Clo, ws,
-                                                              (unsigned long long*)counter, dynamic ? 1 : 0, flags);
+    if (buf) go(T{}, T{});
+    else go(T{}, F{});
   } else {
-    cascade_batched_kernel<false><<<grid, kWaves * 64, 0, s>>>(desc, tiles, ntiles, Chi, Clo, ws,
-                                                               (unsigned long long*)counter, dynamic ? 1 : 0,
-                                                               nullptr);
+    if (buf) go(F{}, T{});
+    else go(F{}, F{});
   }
   return hipGetLastError();
+}
+
+bool buffer_staging_fits(int64_t K4) {
+  return 4 * a_block_stride(K4) * 8 < (int64_t(1) << 31) &&
+         4 * b_block_stride(K4, kFragBBatched) * 8 < (int64_t(1) << 31);
 }
 
 namespace {

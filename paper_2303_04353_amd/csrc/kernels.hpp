@@ -48,7 +48,11 @@ hipError_t launch_batched_phase_one(const BatchDesc* desc, int count, const int6
 // by the caller.
 hipError_t launch_cascade_batched(const BatchDesc* desc, const BatchTile* tiles, int64_t ntiles,
                                   double* const* Chi, double* const* Clo, const char* ws,
-                                  uint32_t* counter, int grid, bool dynamic, uint32_t* flags, hipStream_t s);
+                                  uint32_t* counter, int grid, bool dynamic, uint32_t* flags, bool buf,
+                                  hipStream_t s);
+// Whether the packed blocks of a 64 x 64 tile at this K4 span less than the
+// 2 GiB that the product kernels' buffer-load staging addresses.
+bool buffer_staging_fits(int64_t K4);
 
 // The fused product kernel: ten FP64 MFMA products per rank-kc block, bins
 // combined in FP64x2, Sigma/T applied, C := C + result.  `flags` (may be

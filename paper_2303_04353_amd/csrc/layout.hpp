@@ -10,11 +10,13 @@
 //      index kk and row i sit at s*16 + kk*4 + i (16 values per 4-row
 //      sub-block, read by all four MFMA blocks at once):
 //        Apack[rb*a_block_stride(K4) + (kq*4 + t)*64 + s*16 + kk*4 + i]
-//   B: for each 16-column block cb, five planes B0', B1', B2', B3', B6' (in
-//      that order), one 64-lane operand each (lane kk*16 + c holds inner index
-//      kk, column c); B4' = B2' + B3' and B5' = B1' + B4' are formed where
-//      they are used, with the same two FP64 additions:
-//        Bpack[cb*b_block_stride(K4) + (kq*5 + t)*64 + kk*16 + c]
+//   B: for each 16-column block cb, FB planes, one 64-lane operand each
+//      (lane kk*16 + c holds inner index kk, column c).  Single GEMMs store
+//      all seven, B0', ..., B6' (FB = 7: B4' = B2' + B3' and B5' = B1' + B4'
+//      computed by the split); batched plans store B0', B1', B2', B3', B6'
+//      (FB = 5), and their product loop forms B4' and B5' with the same two
+//      FP64 additions:
+//        Bpack[cb*b_block_stride(K4, FB) + (kq*FB + t)*64 + kk*16 + c]
 // Rows/columns are padded with zeros up to the workgroup tile and the inner
 // dimension up to a multiple of 16 (two LDS stages of the product kernel, 8
 // inner indices each, which its main loop takes in pairs), so the product
@@ -27,8 +29,9 @@
 namespace ddk {
 
 constexpr int kFragA = 4;   // planes of op(A)
-constexpr int kFragB = 5;   // stored planes of op(B): B0', B1', B2', B3', B6'
-constexpr int kPlanesB = 7; // planes of op(B) in the products (with B4', B5')
+constexpr int kFragB = 7;   // stored planes of op(B) for single GEMMs: B0', B1', ..., B6'
+constexpr int kFragBBatched = 5;   // in batched plans: B0', B1', B2', B3', B6'
+constexpr int kPlanesB = 7; // planes of op(B) in the products
 constexpr int kLanes = 64;
 
 // The packed planes of one 16-row block of op(A) (16-column block of op(B))
@@ -38,7 +41,7 @@ constexpr int kLanes = 64;
 // blocks, and those of neighbouring tiles, fall on the same L2 sets.
 constexpr int64_t kBlockPad = 544;   // 4 KiB + 256 B
 constexpr int64_t a_block_stride(int64_t K4) { return K4 * kFragA * kLanes + kBlockPad; }
-constexpr int64_t b_block_stride(int64_t K4) { return K4 * kFragB * kLanes + kBlockPad; }
+constexpr int64_t b_block_stride(int64_t K4, int fb = kFragB) { return K4 * fb * kLanes + kBlockPad; }
 
 struct CascadeLayout {
   int64_t m, n, k;

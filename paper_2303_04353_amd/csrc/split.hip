@@ -160,7 +160,8 @@ __device__ __forceinline__ void pack_a_frags(const double* __restrict__ Ahi, con
 }
 
 // Packed B planes, F consecutive fragments per wave: op(B)(p, j) = B[p*sp_ + j*sj].
-template <int F>
+// FB stored planes per fragment: 7 (B0'..B6') or 5 (B0'..B3', B6').
+template <int F, int FB = kFragB>
 __device__ __forceinline__ void pack_b_frags(const double* __restrict__ Bhi, const double* __restrict__ Blo,
                                              int64_t sp_, int64_t sj, int64_t k, int64_t n, int64_t K4,
                                              int64_t frag0, int64_t nfrag, int lane,
@@ -193,15 +194,24 @@ __device__ __forceinline__ void pack_b_frags(const double* __restrict__ Bhi, con
     if (frag >= nfrag) break;
     const int64_t cb = frag / K4, kq = frag - cb * K4;
     const int64_t j = cb * 16 + (lane & 15), p = kq * 4 + (lane >> 4);
-    double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double w[kFragB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (j < n && p < k) {
       double yh, yl;
       split_entry(__builtin_ldexp(h[f], -g[f]), __builtin_ldexp(l[f], -g[f]), exp_of_bits(mb[f]), spar, w, yh, yl);
-      w[4] = yh + yl;       // B6: the scaled entry itself, rounded once
+      w[4] = w[2] + w[3];   // sigma_2 B4 = B2' + B3'
+      w[5] = w[1] + w[4];   // sigma_1 B5 = B1' + B2' + B3'
+      w[6] = yh + yl;       // B6: the scaled entry itself, rounded once
     }
-    double* dst = Bpack + cb * b_block_stride(K4) + kq * (kFragB * kLanes) + lane;
+    double* dst = Bpack + cb * b_block_stride(K4, FB) + kq * (FB * kLanes) + lane;
+    if constexpr (FB == kFragB) {
 #pragma unroll
-    for (int t = 0; t < 5; ++t) dst[t * kLanes] = w[t];
+      for (int t = 0; t < kFragB; ++t) dst[t * kLanes] = w[t];
+    } else {
+      static_assert(FB == kFragBBatched, "5 or 7 stored planes");
+#pragma unroll
+      for (int t = 0; t < 4; ++t) dst[t * kLanes] = w[t];
+      dst[4 * kLanes] = w[6];
+    }
   }
 }
 
@@ -317,7 +327,7 @@ batched_pack(const BatchDesc* __restrict__ desc, int count, const int64_t* __res
       const BatchDesc d = desc[p];
       const int64_t frag0 = ((v - prefB[p]) * 4 + (threadIdx.x >> 6)) * kPF, nfrag = (d.npad / 16) * d.K4;
       if (frag0 >= nfrag) continue;
-      pack_b_frags<kPF>(Bhi[p], Blo[p], 1, d.ldb, d.k, d.n, d.K4, frag0, nfrag, lane,
+      pack_b_frags<kPF, kFragBBatched>(Bhi[p], Blo[p], 1, d.ldb, d.k, d.n, d.K4, frag0, nfrag, lane,
                         (const uint64_t*)(ws + d.off_bmax), d.c0, d.c1, d.c2, (double*)(ws + d.off_bpack));
     }
   }
@@ -340,17 +350,7 @@ unpack_planes(const double* __restrict__ pack, int side, int64_t rows, int64_t c
   } else {
     int64_t blk = cidx / 16, q = r / 4, kk = r % 4;
     const double* src = pack + blk * b_block_stride(K4) + q * (int64_t)(kFragB * kLanes) + kk * 16 + (cidx % 16);
-    double b[5];
-    for (int t = 0; t < kFragB; ++t) b[t] = src[t * kLanes];
-    const double b4 = b[2] + b[3];   // the same additions as the product kernel
-    const double b5 = b[1] + b4;
-    planes[0 * plane + idx] = b[0];
-    planes[1 * plane + idx] = b[1];
-    planes[2 * plane + idx] = b[2];
-    planes[3 * plane + idx] = b[3];
-    planes[4 * plane + idx] = b4;
-    planes[5 * plane + idx] = b5;
-    planes[6 * plane + idx] = b[4];
+    for (int t = 0; t < kFragB; ++t) planes[t * plane + idx] = src[t * kLanes];
   }
 }
 

@@ -76,8 +76,8 @@ def test_without_a_gpu_valid_calls_fail_cleanly():
 def test_workspace_size_formula():
     ws = dg.dd_gemm_workspace_size(0, 0, 100, 70, 300)
     mpad, npad, kpad = 128, 128, 304
-    # packed planes: per 16-row (16-column) block 4 (5) planes over kpad, plus 544 doubles of padding
-    need = 8 * (mpad + npad) + 8 * (mpad // 16) * (4 * 16 * kpad + 544) + 8 * (npad // 16) * (5 * 16 * kpad + 544)
+    # packed planes: per 16-row (16-column) block 4 (7) planes over kpad, plus 544 doubles of padding
+    need = 8 * (mpad + npad) + 8 * (mpad // 16) * (4 * 16 * kpad + 544) + 8 * (npad // 16) * (7 * 16 * kpad + 544)
     assert need <= ws <= need + 4 * 256
     assert dg.dd_gemm_workspace_size(0, 0, 100, 70, 300, {"algo": dg.DD_ALGO_DD_VALU}) == 0
     assert dg.dd_gemm_workspace_size(3, 0, 100, 70, 300) == 0
@@ -197,8 +197,8 @@ def test_noalloc_rejects_bad_arguments_on_host():
     assert dg.dd_gemm_noalloc(0, 0, *base, opts={"algo": dg.DD_ALGO_SIMPLE_UNFUSED}, stream=0) == -15
     assert dg.DD_NOALLOC_SCRATCH_BYTES == 128 << 20
     # the largest square cascade the scratch array holds, and the first one it does not
-    assert dg.dd_gemm_workspace_size(0, 0, 1344, 1344, 1344) <= dg.DD_NOALLOC_SCRATCH_BYTES
-    assert dg.dd_gemm_workspace_size(0, 0, 1360, 1360, 1360) > dg.DD_NOALLOC_SCRATCH_BYTES
+    assert dg.dd_gemm_workspace_size(0, 0, 1216, 1216, 1216) <= dg.DD_NOALLOC_SCRATCH_BYTES
+    assert dg.dd_gemm_workspace_size(0, 0, 1217, 1217, 1217) > dg.DD_NOALLOC_SCRATCH_BYTES
 
 
 def test_vector_calls_reject_bad_arguments_on_host():
@@ -259,14 +259,18 @@ def test_one_shot_batched_checks_on_host_and_workspace_size():
     assert dg.dd_gemm_batched(2, m, n, k, 1 << 20, 1 << 21, [63, 128], 1 << 22, 1 << 23, ld, 1 << 24, 1 << 25, ld,
                               stream=0) == -7
     # workspace: a 256-byte counter, the exponent words of both problems
-    # (rows and columns rounded up to 64), then the packed planes, which
-    # equal the single-GEMM cascade's
+    # (rows and columns rounded up to 64), then the packed planes: per
+    # 16-row block of A the single GEMM's 4 planes, per 16-column block of B
+    # 5 (the single GEMM stores 7), over k rounded up to 16, plus 544
+    # doubles of padding per block
     ws = dg.dd_gemm_batched_workspace_size(2, m, n, k)
     exps = 8 * (64 + 64 + 128 + 128)
     planes = 0
     for mi, ni, ki in zip(m, n, k):
+        mp, np_, kp = -(-mi // 64) * 64, -(-ni // 64) * 64, -(-ki // 16) * 16
+        planes += 8 * (mp // 16) * (4 * 16 * kp + 544) + 8 * (np_ // 16) * (5 * 16 * kp + 544)
         single = dg.dd_gemm_workspace_size(0, 0, mi, ni, ki)
-        planes += single - 8 * (-(-mi // 64) * 64 + -(-ni // 64) * 64)
+        assert single - 8 * (mp + np_) == 8 * (mp // 16) * (4 * 16 * kp + 544) + 8 * (np_ // 16) * (7 * 16 * kp + 544)
     assert ws >= 256 + exps + planes - 2 * 256 and ws <= 256 + exps + planes + 4 * 256
     assert dg.dd_gemm_batched_workspace_size(2, m, n, [16, 600]) > ws
     assert dg.dd_gemm_batched_workspace_size(2, m, n, k, opts={"kc": 6}) == 0

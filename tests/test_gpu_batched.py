@@ -139,6 +139,28 @@ def test_batch_with_a_long_inner_dimension_equals_single_calls():
         dg.dd_batched_plan_destroy(plan)
 
 
+def test_batch_beyond_the_buffer_load_range_equals_single_calls():
+    """A problem with k = 2^20 + 3, whose 64 x 64 tiles' packed blocks span
+    more than the 2 GiB of the buffer-load form, makes the plan stage every
+    tile through 64-bit global addresses; every problem still equals its
+    single call (which stages the small ones through buffer loads) bit for
+    bit."""
+    import torch
+    shapes = [(20, 33, (1 << 20) + 3), (64, 64, 64), (130, 70, 1000), (5, 40, 9)]
+    log(f"batched global-address staging: {shapes}")
+    b = Batch(shapes, cfg=35)
+    want = b.singles()
+    plan = b.plan()
+    try:
+        b.reset()
+        b.exec(plan)
+        torch.cuda.synchronize()
+        for i, (g, w) in enumerate(zip(b.results(), want)):
+            assert np.array_equal(g[0], w[0]) and np.array_equal(g[1], w[1]), i
+    finally:
+        dg.dd_batched_plan_destroy(plan)
+
+
 def test_one_shot_entry_point():
     import torch
     b = Batch(SMALL[:6], cfg=31)

@@ -99,7 +99,7 @@ def test_long_inner_dimension(variant):
 
 
 def test_inner_dimension_beyond_the_buffer_load_range():
-    """k = 2^20 + 3: a 64 x 64 tile's packed B blocks span 2.5 GiB, past the
+    """k = 2^20 + 3: a 64 x 64 tile's packed B blocks span 3.5 GiB, past the
     32-bit offsets of the buffer-load form, so the product kernel stages with
     64-bit global addresses; against both oracles."""
     m, n, k = 20, 33, (1 << 20) + 3
