@@ -32,8 +32,9 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # the headline form of the product kernel: no flags, global Sigma and T, 64 x 64
-# tiles (either staging form: the last template argument is left open)
-PRODUCT_KERNEL = "cascade_kernel<false, false, Shape<64, 64>"
+# tiles with seven stored B planes (either staging form: the last template
+# argument is left open)
+PRODUCT_KERNEL = "cascade_kernel<false, false, Shape<64, 64, 7>"
 PRODUCT_SOURCE = os.path.join(HERE, "csrc", "cascade.hip")
 
 

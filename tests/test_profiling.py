@@ -26,7 +26,7 @@ def test_trace_table_names_and_units(tmp_path):
 
 
 # the headline product kernel as rocprofv3 names it (buffer-load staging form)
-PROD = "void ddk::cascade_kernel<false, false, ddk::(anonymous namespace)::Shape<64, 64>, true>"
+PROD = "void ddk::cascade_kernel<false, false, ddk::(anonymous namespace)::Shape<64, 64, 7>, true>"
 
 
 def test_traffic_scales_by_the_calibration_copy(tmp_path):
@@ -38,9 +38,9 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
     fetch = [["vectorized_elementwise_kernel<copy>", "FETCH_SIZE", copy_bytes / 2 / 1024],
              [PROD + "(double const*)", "FETCH_SIZE", 5 * (1 << 30) / 1024],
              [PROD + "(double const*)", "FETCH_SIZE", 5 * (1 << 30) / 1024],
-             ["void ddk::cascade_kernel<false, true, ddk::(anonymous namespace)::Shape<64, 64> >(double const*)",
+             ["void ddk::cascade_kernel<false, true, ddk::(anonymous namespace)::Shape<64, 64, 7>, true>(double const*)",
               "FETCH_SIZE", 1.0],
-             ["void ddk::cascade_kernel<false, false, ddk::(anonymous namespace)::Shape<32, 64> >(double const*)",
+             ["void ddk::cascade_kernel<false, false, ddk::(anonymous namespace)::Shape<32, 64, 7>, true>(double const*)",
               "FETCH_SIZE", 1.0]]
     write = [["vectorized_elementwise_kernel<copy>", "WRITE_SIZE", copy_bytes / 1024],
              [PROD + "(double const*)", "WRITE_SIZE", (1 << 30) / 1024]]
@@ -51,7 +51,7 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
     assert abs(r["fetch_bytes_per_launch"] - 10 * (1 << 30)) < 1
     assert abs(r["bytes_per_launch"] - 11 * (1 << 30)) < 1
     assert r["dispatches"] == [2, 1] and r["source_sha256_16"] == pf.source_hash()
-    assert r["kernel"] == "cascade_kernel<false, false, Shape<64, 64>, true>"
+    assert r["kernel"] == "cascade_kernel<false, false, Shape<64, 64, 7>, true>"
     # a stored measurement counts only for the same shape and kernel source
     out = tmp_path / "t.json"
     out.write_text(json.dumps(r))
