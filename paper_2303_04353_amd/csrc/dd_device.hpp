@@ -95,15 +95,17 @@ __device__ __forceinline__ void split_entry(double hi, double lo, int e, const S
 // Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD b % 8)
 // and each XCD has its own L2.  Give every XCD a contiguous range of tiles
 // and walk that range in groups of kGroupM tile rows, so the workgroups that
-// run together on one XCD share a few A and B strips in its L2.
+// run together on one XCD share a few A and B strips in its L2.  For T
+// blocks (b < T), XCD x runs ceil((T - x) / 8) of them; its range starts
+// after those of XCDs 0..x-1, so b -> L is a bijection on [0, T) for any T.
 constexpr int64_t kXcds = 8;
 constexpr int64_t kGroupM = 8;
 
 __device__ __forceinline__ void tile_of_block(int64_t b, int64_t tiles_m, int64_t tiles_n,
                                               int64_t& tm, int64_t& tn) {
   const int64_t T = tiles_m * tiles_n;
-  int64_t L = b;
-  if (T % kXcds == 0) L = (b % kXcds) * (T / kXcds) + b / kXcds;
+  const int64_t per_xcd = T / kXcds, extra = T % kXcds, x = b % kXcds;
+  const int64_t L = x * per_xcd + (x < extra ? x : extra) + b / kXcds;
   const int64_t per_group = kGroupM * tiles_n;
   const int64_t g = L / per_group;
   const int64_t first_m = g * kGroupM;
